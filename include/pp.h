@@ -1,0 +1,181 @@
+/*
+ * pp.h -- C ABI of libpp, the push/pull graph-sweep library for MI355X (gfx950).
+ *
+ * The library implements the per-iteration edge sweep of Besta et al., "To Push
+ * or To Pull: On Reducing Communication and Synchronization in Graph
+ * Computations" (HPDC'17), in its two forms:
+ *   - push: a vertex scatters updates to its out-neighbours' shared state
+ *     (write conflicts resolved with atomics; Sec. 3.8, Sec. 4.1 pushing line);
+ *   - pull: a vertex gathers from its in-neighbours into state only it writes
+ *     (no atomics; Sec. 3.8, Sec. 4.1 pulling line).
+ * The sweeps are instantiated as the PageRank power-iteration step (FP32,
+ * Sec. 3.1 equation, Sec. 4.1 listing) and the BFS frontier step (int32,
+ * Sec. 3.3, Sec. 4.3 listing: top-down = push, bottom-up = pull), plus the
+ * direction switch (Sec. 5 Generic-Switch; direction-optimising BFS cited in
+ * Sec. 1).  Batched personalised PageRank, its adjoint with respect to edge
+ * weights, and a many-graph launch sit on the same sweeps.
+ *
+ * Conventions shared by every entry point
+ *  - Graph representation: the adjacency array of Sec. 2.2.  CSR = out-
+ *    adjacency (row v lists targets of edges leaving v; used by push), CSC =
+ *    in-adjacency (row u lists sources of edges entering u; used by pull).  A
+ *    symmetric graph may pass the same arrays for both.  int32 offsets and
+ *    indices; nnz must fit in int32.
+ *  - Memory: every array argument is DEVICE memory owned by the caller unless
+ *    stated otherwise.  The library never allocates or frees device memory;
+ *    derived data lives in caller-provided workspaces whose size is queried
+ *    first.  A graph handle keeps the caller's pointers: they must outlive it.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = default
+ *    stream).  Compute calls enqueue work and return; results are valid once
+ *    the stream is synchronised.  Calls marked SYNC wait on the stream.
+ *  - Concurrency: calls that share a graph handle, a BFS state or a workspace
+ *    must be ordered on one stream; overlapping them races.
+ *  - Errors: every call returns a pp_status.  Arguments are validated on the
+ *    host before anything is launched; on error nothing is enqueued and
+ *    pp_last_error() (thread-local) describes the failure.  A HIP runtime error
+ *    maps to PP_E_HIP with the runtime's message.
+ */
+#ifndef PP_H
+#define PP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PP_ABI_VERSION 1
+
+typedef enum {
+    PP_OK = 0,
+    PP_E_NULL = -1,        /* a required pointer is NULL */
+    PP_E_SIZE = -2,        /* n, nnz, k or another size is out of range */
+    PP_E_RANGE = -3,       /* a scalar argument (f, root, iters, ...) is out of range */
+    PP_E_GRAPH = -4,       /* the graph arrays are malformed (pp_graph_check) */
+    PP_E_WORKSPACE = -5,   /* a workspace or state buffer is too small */
+    PP_E_HIP = -6,         /* the HIP runtime reported an error */
+    PP_E_UNSUPPORTED = -7  /* the combination of arguments is not supported */
+} pp_status;
+
+typedef enum { PP_PUSH = 0, PP_PULL = 1, PP_SWITCH = 2 } pp_dir;
+
+/* Graph flags. */
+#define PP_GRAPH_WEIGHTED 0x1u /* csr_w (and csc_to_csr) are given */
+
+typedef struct pp_graph_s* pp_graph;
+
+int pp_abi_version(void);
+const char* pp_last_error(void);
+
+/* ------------------------------------------------------------------ graph */
+/* Workspace bytes pp_graph_create needs for a graph of n vertices and nnz
+ * stored directed edges (0 when n or nnz is out of range). */
+size_t pp_graph_workspace_bytes(int32_t n, int64_t nnz, uint32_t flags);
+
+/* Registers a graph (Sec. 2.2 adjacency arrays) and derives, on the device,
+ * the out-degree d(v) (or out-strength s(v) = sum of weights when weighted),
+ * its reciprocal (0 when d(v) = 0), and the vertex lists binned by degree
+ * that the sweeps use to map rows of very different lengths onto lanes,
+ * wavefronts and workgroups.  csr_off/csc_off: int32[n+1]; csr_idx/csc_idx:
+ * int32[nnz]; csc may alias csr for symmetric graphs.  Weighted graphs
+ * (PP_GRAPH_WEIGHTED) pass csr_w (float[nnz], one weight per CSR slot, > 0)
+ * and csc_to_csr (int32[nnz], the CSR slot of each CSC slot).  ws: device
+ * workspace of at least pp_graph_workspace_bytes(n, nnz, flags) bytes, kept
+ * by the handle until pp_graph_destroy.  SYNC (reads back bin sizes). */
+pp_status pp_graph_create(int32_t n, int64_t nnz,
+                          const int32_t* csr_off, const int32_t* csr_idx,
+                          const int32_t* csc_off, const int32_t* csc_idx,
+                          const float* csr_w, const int32_t* csc_to_csr,
+                          uint32_t flags, void* ws, size_t ws_bytes, void* stream, pp_graph* out);
+
+/* Frees the host handle (device memory stays with the caller). */
+pp_status pp_graph_destroy(pp_graph g);
+
+/* Device-side validation: offsets start at 0, are monotone and end at nnz;
+ * every index lies in [0, n).  Returns PP_OK or PP_E_GRAPH.  SYNC. */
+pp_status pp_graph_check(pp_graph g, void* stream);
+
+/* Host copies of the degree-bin boundaries (for tests and tuning):
+ * counts[0..PP_NUM_BINS) of vertices per bin, for the pull (in-degree) or
+ * push (out-degree) lists. */
+#define PP_NUM_BINS 6
+pp_status pp_graph_bins(pp_graph g, pp_dir dir, int32_t* counts);
+
+/* Degree thresholds of the bins (upper bounds of bins 0..4; bin 5 is the
+ * rest) and the split chunk for the longest rows.  Defaults: 4, 16, 64, 1024,
+ * 16384; chunk 16384.  Takes effect at the next pp_graph_create. */
+pp_status pp_set_bin_thresholds(const int32_t* upper5, int32_t split_chunk);
+
+/* --------------------------------------------------------------- PageRank */
+/* One Jacobi step of the PageRank equation (Sec. 3.1):
+ *   y[u] = (1-f)/n + f * sum over edges (v,u) of P_uv * x[v],
+ * P_uv = 1/d(v) (unweighted) or w(v->u)/s(v) (weighted); a vertex with
+ * d(v) = 0 contributes nothing.  x, y: float[n], distinct.  pp_pr_push
+ * scatters along CSR rows with FP32 atomics (nnz atomic adds per call; the
+ * summation order, hence the last bits, may vary between runs); pp_pr_pull
+ * gathers along CSC rows with no atomics (bit-reproducible).  f in [0, 1).
+ * Uses the graph's scratch: calls on one graph must be ordered. */
+pp_status pp_pr_push(pp_graph g, const float* x, float* y, float f, void* stream);
+pp_status pp_pr_pull(pp_graph g, const float* x, float* y, float f, void* stream);
+
+/* iters Jacobi steps in direction dir (PP_PUSH or PP_PULL) starting from
+ * x_inout (float[n], x_0 in, x_iters out), with the contribution
+ * c[v] = f * x[v] * P-normaliser computed once per step in the fused
+ * epilogue of the previous step.  iters >= 0. */
+pp_status pp_pr_run(pp_graph g, pp_dir dir, int32_t iters, float f, float* x_inout, void* stream);
+
+/* -------------------------------------------------------------------- BFS */
+/* BFS state: frontier queues, frontier and visited bitmaps and counters
+ * (device memory, caller-owned).  Size in bytes for graph g. */
+size_t pp_bfs_state_bytes(pp_graph g);
+
+/* Statistics of one BFS run (host struct). */
+#define PP_BFS_MAX_LOG 64
+typedef struct {
+    int32_t levels;                   /* number of non-empty frontiers */
+    int32_t reached;                  /* vertices with level >= 0 */
+    int64_t edges_reached;            /* sum of out-degrees of reached vertices */
+    int8_t dir[PP_BFS_MAX_LOG];       /* direction used to expand frontier l */
+    int32_t frontier[PP_BFS_MAX_LOG]; /* |F| at level l */
+} pp_bfs_stats;
+
+/* Initialises a BFS from `root` (Sec. 3.3; Sec. 4.3 with every ready
+ * counter equal to one): level[] = parent[] = -1 (int32[n], caller-owned,
+ * kept by the state), level[root] = 0, parent[root] = root, F = {root}. */
+pp_status pp_bfs_init(pp_graph g, int32_t root, int32_t* level, int32_t* parent,
+                      void* state, size_t state_bytes, void* stream);
+
+/* Expands the frontier of level cur_level (the number of steps taken since
+ * pp_bfs_init) into level cur_level+1.  push = top-down: every frontier
+ * vertex claims its unvisited out-neighbours (one atomic OR on the visited
+ * bitmap per claim, wave-aggregated queue appends).  pull = bottom-up: every
+ * unvisited vertex scans its in-neighbours in stored order and stops at the
+ * first frontier member, which becomes its parent (no atomics on vertex
+ * state; one counter update per wavefront).  Either step may follow the
+ * other.  level/parent must be the arrays given to pp_bfs_init.  Enqueue
+ * only; the frontier size is read with pp_bfs_frontier.  A step on an empty
+ * frontier does nothing. */
+pp_status pp_bfs_step_push(pp_graph g, void* state, int32_t* level, int32_t* parent, int32_t cur_level,
+                           void* stream);
+pp_status pp_bfs_step_pull(pp_graph g, void* state, int32_t* level, int32_t* parent, int32_t cur_level,
+                           void* stream);
+
+/* Size of the frontier produced by the last step (SYNC). */
+pp_status pp_bfs_frontier(pp_graph g, void* state, int32_t* size, void* stream);
+
+/* Whole BFS from root.  policy PP_PUSH / PP_PULL forces one direction;
+ * PP_SWITCH chooses per level on the device: top-down -> bottom-up when
+ * m_f > m_u / alpha, bottom-up -> top-down when n_f < n / beta and the
+ * frontier shrinks (m_f: out-edges of the frontier, m_u: out-edges of
+ * unvisited vertices, n_f: frontier size).  alpha, beta > 0 (defaults 14, 24
+ * when <= 0 is passed).  Levels do not depend on the policy; parents are
+ * any valid BFS parents.  stats: host, nullable.  SYNC. */
+pp_status pp_bfs_run(pp_graph g, int32_t root, pp_dir policy, float alpha, float beta,
+                     int32_t* level, int32_t* parent, void* state, size_t state_bytes,
+                     pp_bfs_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PP_H */

@@ -1,0 +1,116 @@
+"""Push/pull graph sweeps on MI355X (gfx950): PageRank and BFS steps in their
+pushing and pulling forms (Besta et al., "To Push or To Pull", HPDC'17).
+
+The compute lives in ``libpp.so`` (hand-written HIP kernels behind the C ABI of
+``include/pp.h``).  ``_lib`` binds every entry point under its C name; this
+module adds thin conveniences that own the device tensors a call needs.
+PyTorch provides device memory and streams only.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+from ._lib import (PP_PULL, PP_PUSH, PP_SWITCH, PPError, BfsStats)  # noqa: F401
+from ._lib import *  # noqa: F401,F403  (the C names)
+
+__all__ = ["Graph", "BfsRun", "PPError", "PP_PUSH", "PP_PULL", "PP_SWITCH", "pagerank", "bfs"]
+
+
+class Graph:
+    """A graph registered with libpp: device adjacency arrays, the workspace of
+    derived data, and the library handle.
+
+    ``host`` is a ``graphgen.HostGraph``-like object with ``n``, ``off`` and
+    ``idx`` (CSR = out-adjacency), optional ``in_off``/``in_idx`` (CSC =
+    in-adjacency; the CSR is reused when the graph is symmetric), and optional
+    ``weights`` (per CSR slot) with ``in_to_out`` (CSR slot of each CSC slot).
+    """
+
+    def __init__(self, host, device="cuda", weighted=None, stream=None):
+        n = int(host.n)
+        nnz = int(host.off[-1])
+        if nnz > 2**31 - 1:
+            raise ValueError("nnz must fit in int32")
+        self.n, self.nnz = n, nnz
+        dev = torch.device(device)
+
+        def up(a, dt):
+            return torch.as_tensor(a).to(dtype=dt).to(dev).contiguous()
+
+        self.csr_off = up(host.off, torch.int32)
+        self.csr_idx = up(host.idx, torch.int32) if nnz else torch.zeros(1, dtype=torch.int32, device=dev)
+        in_off = getattr(host, "in_off", None)
+        if in_off is None or in_off is host.off:
+            if in_off is None and not getattr(host, "symmetric", False):
+                raise ValueError("a directed graph needs in_off/in_idx")
+            self.csc_off, self.csc_idx = self.csr_off, self.csr_idx  # symmetric: CSC = CSR
+        else:
+            self.csc_off = up(host.in_off, torch.int32)
+            self.csc_idx = up(host.in_idx, torch.int32) if nnz else self.csr_idx
+        if weighted is None:
+            weighted = getattr(host, "weights", None) is not None
+        self.weighted = bool(weighted)
+        flags = _lib.PP_GRAPH_WEIGHTED if self.weighted else 0
+        if self.weighted:
+            self.csr_w = up(host.weights, torch.float32)
+            self.csc_to_csr = up(host.in_to_out, torch.int32)
+        else:
+            self.csr_w = self.csc_to_csr = None
+        ws_bytes = _lib.pp_graph_workspace_bytes(n, nnz, flags)
+        if ws_bytes == 0:
+            raise ValueError("graph size out of range")
+        self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        self.handle = _lib.pp_graph_create(n, nnz, self.csr_off, self.csr_idx, self.csc_off, self.csc_idx,
+                                           self.csr_w, self.csc_to_csr, flags, self.ws, stream)
+        self.device = dev
+
+    def bins(self, direction=PP_PULL):
+        return _lib.pp_graph_bins(self.handle, direction)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            _lib.pp_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pagerank(g: Graph, iters=20, f=0.85, direction=PP_PULL, x0=None, stream=None):
+    """``iters`` Jacobi steps of the PageRank equation from x0 (default 1/n)."""
+    x = torch.full((g.n,), 1.0 / g.n, dtype=torch.float32, device=g.device) if x0 is None else x0.clone()
+    _lib.pp_pr_run(g.handle, direction, iters, f, x, stream)
+    return x
+
+
+class BfsRun:
+    """Device buffers of one BFS: level, parent and the library's state."""
+
+    def __init__(self, g: Graph):
+        self.g = g
+        self.level = torch.empty(g.n, dtype=torch.int32, device=g.device)
+        self.parent = torch.empty(g.n, dtype=torch.int32, device=g.device)
+        self.state = torch.empty(_lib.pp_bfs_state_bytes(g.handle), dtype=torch.uint8, device=g.device)
+
+    def run(self, root, policy=PP_SWITCH, alpha=14.0, beta=24.0, stream=None) -> BfsStats:
+        return _lib.pp_bfs_run(self.g.handle, root, policy, alpha, beta, self.level, self.parent, self.state, stream)
+
+    def init(self, root, stream=None):
+        _lib.pp_bfs_init(self.g.handle, root, self.level, self.parent, self.state, stream)
+
+    def step(self, cur_level, direction, stream=None):
+        fn = _lib.pp_bfs_step_push if direction == PP_PUSH else _lib.pp_bfs_step_pull
+        fn(self.g.handle, self.state, self.level, self.parent, cur_level, stream)
+
+    def frontier(self, stream=None) -> int:
+        return _lib.pp_bfs_frontier(self.g.handle, self.state, stream)
+
+
+def bfs(g: Graph, root, policy=PP_SWITCH, alpha=14.0, beta=24.0):
+    r = BfsRun(g)
+    stats = r.run(root, policy, alpha, beta)
+    return r.level, r.parent, stats

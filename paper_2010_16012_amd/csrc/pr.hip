@@ -1,0 +1,391 @@
+// PageRank power-iteration step in its pulling and pushing forms
+// (Sec. 3.1 equation; Sec. 4.1 listing, pushing and pulling lines).
+//
+// Both forms run over degree-binned vertex lists in ONE launch per sweep:
+// workgroups [block_off[b], block_off[b+1]) serve bin b, heaviest bin first.
+// A vertex of bin b is owned by kBinLanes[b] lanes (1, 4, 16, a wavefront,
+// a workgroup); bin 5 rows are cut into chunks of split_chunk edges.
+//
+// The contribution vector c[v] = f * x[v] / s(v) (s = out-degree or
+// out-strength) is produced by the previous step's epilogue, so a gather
+// reads ONE float per edge instead of the neighbour's rank and degree.
+#include <hip/hip_runtime.h>
+
+#include "pp_common.h"
+
+namespace pp {
+
+struct SweepPlan {
+    int32_t block_off[PP_NUM_BINS + 1];
+    int32_t list_off[PP_NUM_BINS + 1];
+};
+
+static SweepPlan sweep_plan(const BinPlan& p) {
+    SweepPlan s;
+    for (int b = 0; b <= PP_NUM_BINS; ++b) {
+        s.block_off[b] = p.block_off[b];
+        s.list_off[b] = p.list_off[b];
+    }
+    return s;
+}
+
+// Which bin does this workgroup serve?  Launch order is bin 5, 4, ..., 0.
+__device__ __forceinline__ int block_bin(const SweepPlan& sp, int32_t blk) {
+    int b = PP_NUM_BINS - 1;
+#pragma unroll
+    for (int i = PP_NUM_BINS - 1; i > 0; --i)
+        if (blk >= sp.block_off[i - 1]) b = i - 1;
+    return b;
+}
+
+template <int G>
+__device__ __forceinline__ float group_reduce(float v) {
+#pragma unroll
+    for (int s = G / 2; s > 0; s >>= 1) v += __shfl_xor(v, s);
+    return v;
+}
+
+// Deterministic workgroup sum (fixed order: wavefront tree, then waves 0..3).
+__device__ __forceinline__ float block_reduce(float v, float* red) {
+    v = group_reduce<kWave>(v);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+    __syncthreads();
+    float t = 0.f;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kBlock / kWave; ++i) t += red[i];
+    }
+    return t;  // valid in thread 0
+}
+
+// Sum of c[idx[j]] (times the slot weight) over j = b + lane, b + lane + G, ...
+// Four independent gathers in flight per lane.
+template <int G, bool W>
+__device__ __forceinline__ float gather_row(const int32_t* __restrict__ idx, const float* __restrict__ wt,
+                                            const float* __restrict__ c, int32_t b, int32_t e, int lane) {
+    float a0 = 0.f, a1 = 0.f;
+    int32_t j = b + lane;
+    for (; j + 3 * G < e; j += 4 * G) {
+        const int32_t i0 = idx[j], i1 = idx[j + G], i2 = idx[j + 2 * G], i3 = idx[j + 3 * G];
+        float v0 = c[i0], v1 = c[i1], v2 = c[i2], v3 = c[i3];
+        if (W) {
+            v0 *= wt[j];
+            v1 *= wt[j + G];
+            v2 *= wt[j + 2 * G];
+            v3 *= wt[j + 3 * G];
+        }
+        a0 += v0 + v1;
+        a1 += v2 + v3;
+    }
+    for (; j < e; j += G) {
+        float v = c[idx[j]];
+        if (W) v *= wt[j];
+        a0 += v;
+    }
+    return a0 + a1;
+}
+
+struct PullArgs {
+    SweepPlan sp;
+    const int32_t* off;    // CSC offsets
+    const int32_t* idx;    // CSC indices
+    const float* wt;       // weights in CSC slot order (weighted only)
+    const int32_t* list;   // vertices grouped by in-degree bin
+    const int32_t* tab;    // bin-5 chunk table (v | begin | end | first)
+    int32_t tab_cap;
+    float* part;           // bin-5 partial sums
+    const float* c;        // contributions of the current iterate
+    const float* inv_s;
+    float* c_next;         // contributions of the new iterate (nullable)
+    float* y;              // new iterate (nullable)
+    float base;            // (1-f)/n
+    float f;
+};
+
+// Owner of u writes y[u] = base + acc and the next contribution.
+__device__ __forceinline__ void pull_finish(const PullArgs& a, int32_t u, float acc) {
+    const float yv = a.base + acc;
+    if (a.y) a.y[u] = yv;
+    if (a.c_next) a.c_next[u] = a.f * yv * a.inv_s[u];
+}
+
+template <int G, bool W>
+__device__ __forceinline__ void pull_group(const PullArgs& a, int bin, int32_t local_blk) {
+    constexpr int per_block = kBlock / G;
+    const int32_t i = local_blk * per_block + threadIdx.x / G;
+    const int lane = threadIdx.x & (G - 1);
+    const int32_t count = a.sp.list_off[bin + 1] - a.sp.list_off[bin];
+    if (i >= count) return;  // whole groups leave together
+    const int32_t u = a.list[a.sp.list_off[bin] + i];
+    const int32_t b = a.off[u], e = a.off[u + 1];
+    float acc = gather_row<G, W>(a.idx, a.wt, a.c, b, e, lane);
+    acc = group_reduce<G>(acc);
+    if (lane == 0) pull_finish(a, u, acc);
+}
+
+template <bool W>
+__global__ __launch_bounds__(kBlock) void k_pr_pull(PullArgs a) {
+    __shared__ float red[kBlock / kWave];
+    const int32_t blk = blockIdx.x;
+    const int bin = block_bin(a.sp, blk);
+    const int32_t lb = blk - a.sp.block_off[bin];
+    switch (bin) {
+        case 5: {  // one chunk of a very long row -> partial sum, finished by k_pr_pull_fix
+            const int32_t b = a.tab[a.tab_cap + lb], e = a.tab[2 * a.tab_cap + lb];
+            float acc = gather_row<kBlock, W>(a.idx, a.wt, a.c, b, e, threadIdx.x);
+            acc = block_reduce(acc, red);
+            if (threadIdx.x == 0) a.part[lb] = acc;
+            break;
+        }
+        case 4: {  // one workgroup per row
+            const int32_t u = a.list[a.sp.list_off[4] + lb];
+            float acc = gather_row<kBlock, W>(a.idx, a.wt, a.c, a.off[u], a.off[u + 1], threadIdx.x);
+            acc = block_reduce(acc, red);
+            if (threadIdx.x == 0) pull_finish(a, u, acc);
+            break;
+        }
+        case 3: pull_group<64, W>(a, 3, lb); break;
+        case 2: pull_group<16, W>(a, 2, lb); break;
+        case 1: pull_group<4, W>(a, 1, lb); break;
+        default: pull_group<1, W>(a, 0, lb); break;
+    }
+}
+
+// Sums the chunk partials of every split row in chunk order (deterministic).
+__global__ void k_pr_pull_fix(PullArgs a, int32_t nsplit) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsplit) return;
+    const int32_t* first = a.tab + 3 * a.tab_cap;
+    float acc = 0.f;
+    for (int32_t e = first[i]; e < first[i + 1]; ++e) acc += a.part[e];
+    pull_finish(a, a.tab[first[i]], acc);
+}
+
+struct PushArgs {
+    SweepPlan sp;
+    const int32_t* off;    // CSR offsets
+    const int32_t* idx;    // CSR indices
+    const float* wt;       // weights in CSR slot order (weighted only)
+    const int32_t* list;   // vertices grouped by out-degree bin
+    const int32_t* tab;
+    int32_t tab_cap;
+    const float* c;        // contributions
+    float* y;              // accumulator, pre-set to (1-f)/n
+};
+
+// Scatter c[v] (times the slot weight) to every out-neighbour with FP32
+// atomic adds (global_atomic_add_f32, result unused).
+template <int G, bool W>
+__device__ __forceinline__ void scatter_row(const PushArgs& a, float cv, int32_t b, int32_t e, int lane) {
+    int32_t j = b + lane;
+    for (; j + G < e; j += 2 * G) {
+        const int32_t u0 = a.idx[j], u1 = a.idx[j + G];
+        unsafeAtomicAdd(&a.y[u0], W ? cv * a.wt[j] : cv);
+        unsafeAtomicAdd(&a.y[u1], W ? cv * a.wt[j + G] : cv);
+    }
+    if (j < e) unsafeAtomicAdd(&a.y[a.idx[j]], W ? cv * a.wt[j] : cv);
+}
+
+template <int G, bool W>
+__device__ __forceinline__ void push_group(const PushArgs& a, int bin, int32_t local_blk) {
+    constexpr int per_block = kBlock / G;
+    const int32_t i = local_blk * per_block + threadIdx.x / G;
+    const int lane = threadIdx.x & (G - 1);
+    const int32_t count = a.sp.list_off[bin + 1] - a.sp.list_off[bin];
+    if (i >= count) return;
+    const int32_t v = a.list[a.sp.list_off[bin] + i];
+    const float cv = a.c[v];
+    if (cv == 0.f) return;  // nothing to pass on
+    scatter_row<G, W>(a, cv, a.off[v], a.off[v + 1], lane);
+}
+
+template <bool W>
+__global__ __launch_bounds__(kBlock) void k_pr_push(PushArgs a) {
+    const int32_t blk = blockIdx.x;
+    const int bin = block_bin(a.sp, blk);
+    const int32_t lb = blk - a.sp.block_off[bin];
+    switch (bin) {
+        case 5: {
+            const int32_t v = a.tab[lb];
+            const int32_t b = a.tab[a.tab_cap + lb], e = a.tab[2 * a.tab_cap + lb];
+            const float cv = a.c[v];
+            if (cv != 0.f) scatter_row<kBlock, W>(a, cv, b, e, threadIdx.x);
+            break;
+        }
+        case 4: {
+            const int32_t v = a.list[a.sp.list_off[4] + lb];
+            const float cv = a.c[v];
+            if (cv != 0.f) scatter_row<kBlock, W>(a, cv, a.off[v], a.off[v + 1], threadIdx.x);
+            break;
+        }
+        case 3: push_group<64, W>(a, 3, lb); break;
+        case 2: push_group<16, W>(a, 2, lb); break;
+        case 1: push_group<4, W>(a, 1, lb); break;
+        default: push_group<1, W>(a, 0, lb); break;
+    }
+}
+
+// c[u] = f * x[u] / s(u); optionally y[u] = base (the push accumulator).
+__global__ void k_pr_prologue(int32_t n, const float* __restrict__ x, const float* __restrict__ inv_s, float f,
+                              float* __restrict__ c, float* __restrict__ y_init, float base) {
+    const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    c[u] = f * x[u] * inv_s[u];
+    if (y_init) y_init[u] = base;
+}
+
+// After a push sweep: c[u] = f * y[u] / s(u); reset the other accumulator to
+// base; copy the iterate out on the last step.
+__global__ void k_pr_push_epilogue(int32_t n, const float* __restrict__ y, const float* __restrict__ inv_s, float f,
+                                   float* __restrict__ c, float* __restrict__ y_reset, float base,
+                                   float* __restrict__ x_out) {
+    const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    const float yv = y[u];
+    c[u] = f * yv * inv_s[u];
+    if (y_reset) y_reset[u] = base;
+    if (x_out) x_out[u] = yv;
+}
+
+// ------------------------------------------------------------------ launchers
+static float teleport(int32_t n, float f) { return (float)((1.0 - (double)f) / (double)n); }
+
+static PullArgs pull_args(pp_graph g, const float* c, float* c_next, float* y, float f) {
+    PullArgs a;
+    a.sp = sweep_plan(g->pull_plan);
+    a.off = g->d.csc_off;
+    a.idx = g->d.csc_idx;
+    a.wt = g->d.csc_w;
+    a.list = g->d.pull_list;
+    a.tab_cap = g->split_cap;
+    a.tab = g->d.split_tab;
+    a.part = g->d.split_part;
+    a.c = c;
+    a.inv_s = g->d.inv_s;
+    a.c_next = c_next;
+    a.y = y;
+    a.base = teleport(g->d.n, f);
+    a.f = f;
+    return a;
+}
+
+}  // namespace pp
+
+namespace pp {
+
+pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float f, hipStream_t st) {
+    PullArgs a = pull_args(g, c, c_next, y, f);
+    const int32_t blocks = g->pull_plan.total_blocks;
+    if (blocks > 0) {
+        if (g->weighted) hipLaunchKernelGGL(k_pr_pull<true>, dim3(blocks), dim3(kBlock), 0, st, a);
+        else hipLaunchKernelGGL(k_pr_pull<false>, dim3(blocks), dim3(kBlock), 0, st, a);
+    }
+    const int32_t nsplit = g->pull_plan.count[5];
+    if (nsplit > 0) hipLaunchKernelGGL(k_pr_pull_fix, dim3(ceil_div(nsplit, 64)), dim3(64), 0, st, a, nsplit);
+    PP_LAUNCH_CHECK("k_pr_pull");
+    return PP_OK;
+}
+
+pp_status launch_push(pp_graph g, const float* c, float* y, hipStream_t st) {
+    PushArgs a;
+    a.sp = sweep_plan(g->push_plan);
+    a.off = g->d.csr_off;
+    a.idx = g->d.csr_idx;
+    a.wt = g->d.csr_w;
+    a.list = g->d.push_list;
+    a.tab_cap = g->split_cap;
+    a.tab = g->d.split_tab + 4 * (size_t)a.tab_cap + 1;
+    a.c = c;
+    a.y = y;
+    const int32_t blocks = g->push_plan.total_blocks;
+    if (blocks > 0) {
+        if (g->weighted) hipLaunchKernelGGL(k_pr_push<true>, dim3(blocks), dim3(kBlock), 0, st, a);
+        else hipLaunchKernelGGL(k_pr_push<false>, dim3(blocks), dim3(kBlock), 0, st, a);
+    }
+    PP_LAUNCH_CHECK("k_pr_push");
+    return PP_OK;
+}
+
+static pp_status check_pr_args(pp_graph g, const void* x, const void* y, float f) {
+    if (!g) return set_error(PP_E_NULL, "graph handle is NULL");
+    if (!x || !y) return set_error(PP_E_NULL, "x and y are required");
+    if (x == y) return set_error(PP_E_RANGE, "x and y must be distinct buffers");
+    if (!(f >= 0.f && f < 1.f)) return set_error(PP_E_RANGE, "f must lie in [0, 1)");
+    return PP_OK;
+}
+
+}  // namespace pp
+
+using namespace pp;
+
+PP_EXPORT pp_status pp_pr_pull(pp_graph g, const float* x, float* y, float f, void* stream) {
+    clear_error();
+    pp_status s = check_pr_args(g, x, y, f);
+    if (s != PP_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int32_t n = g->d.n;
+    hipLaunchKernelGGL(k_pr_prologue, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, x, g->d.inv_s, f, g->d.buf0,
+                       (float*)nullptr, 0.f);
+    PP_LAUNCH_CHECK("k_pr_prologue");
+    return launch_pull(g, g->d.buf0, nullptr, y, f, st);
+}
+
+PP_EXPORT pp_status pp_pr_push(pp_graph g, const float* x, float* y, float f, void* stream) {
+    clear_error();
+    pp_status s = check_pr_args(g, x, y, f);
+    if (s != PP_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int32_t n = g->d.n;
+    hipLaunchKernelGGL(k_pr_prologue, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, x, g->d.inv_s, f, g->d.buf0, y,
+                       teleport(n, f));
+    PP_LAUNCH_CHECK("k_pr_prologue");
+    return launch_push(g, g->d.buf0, y, st);
+}
+
+PP_EXPORT pp_status pp_pr_run(pp_graph g, pp_dir dir, int32_t iters, float f, float* x_inout, void* stream) {
+    clear_error();
+    if (!g) return set_error(PP_E_NULL, "graph handle is NULL");
+    if (!x_inout) return set_error(PP_E_NULL, "x_inout is required");
+    if (!(f >= 0.f && f < 1.f)) return set_error(PP_E_RANGE, "f must lie in [0, 1)");
+    if (iters < 0) return set_error(PP_E_RANGE, "iters must be >= 0");
+    if (dir != PP_PUSH && dir != PP_PULL) return set_error(PP_E_RANGE, "dir must be PP_PUSH or PP_PULL");
+    if (iters == 0) return PP_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int32_t n = g->d.n;
+    const float base = teleport(n, f);
+    const dim3 vb(ceil_div(n, 256)), vt(256);
+    if (dir == PP_PULL) {
+        float* c = g->d.buf0;
+        float* cn = g->d.buf1;
+        hipLaunchKernelGGL(k_pr_prologue, vb, vt, 0, st, n, (const float*)x_inout, g->d.inv_s, f, c, (float*)nullptr,
+                           0.f);
+        PP_LAUNCH_CHECK("k_pr_prologue");
+        for (int32_t t = 0; t < iters; ++t) {
+            const bool last = (t == iters - 1);
+            pp_status s = launch_pull(g, c, last ? nullptr : cn, last ? x_inout : nullptr, f, st);
+            if (s != PP_OK) return s;
+            float* tmp = c;
+            c = cn;
+            cn = tmp;
+        }
+        return PP_OK;
+    }
+    float* c = g->d.buf0;
+    float* ya = g->d.buf1;
+    float* yb = g->d.buf2;
+    hipLaunchKernelGGL(k_pr_prologue, vb, vt, 0, st, n, (const float*)x_inout, g->d.inv_s, f, c, ya, base);
+    PP_LAUNCH_CHECK("k_pr_prologue");
+    for (int32_t t = 0; t < iters; ++t) {
+        const bool last = (t == iters - 1);
+        pp_status s = launch_push(g, c, ya, st);
+        if (s != PP_OK) return s;
+        hipLaunchKernelGGL(k_pr_push_epilogue, vb, vt, 0, st, n, (const float*)ya, g->d.inv_s, f, c,
+                           last ? nullptr : yb, base, last ? x_inout : nullptr);
+        PP_LAUNCH_CHECK("k_pr_push_epilogue");
+        float* tmp = ya;
+        ya = yb;
+        yb = tmp;
+    }
+    return PP_OK;
+}

@@ -1,0 +1,144 @@
+"""BFS top-down (push), bottom-up (pull) and direction-switching runs on the
+GPU against the FP64 oracle's FIFO BFS.
+
+Bar: levels bit-identical to the oracle; parents checked for validity (a
+reached vertex's parent is an in-neighbour one level up), since several
+parents are correct.
+"""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+import paper_2010_16012_amd as pp
+from tests import helpers as H
+from tests.gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+POLICIES = [pp.PP_PUSH, pp.PP_PULL, pp.PP_SWITCH]
+POL_IDS = ["push", "pull", "switch"]
+
+
+def _run(g, root, policy):
+    r = pp.BfsRun(g)
+    st = r.run(root, policy)
+    torch.cuda.synchronize()
+    return r.level.cpu().numpy(), r.parent.cpu().numpy(), st
+
+
+def _check(host, roots, policies=POLICIES, fast=False):
+    g = pp.Graph(host)
+    for root in roots:
+        want, _, nlev = oracle.bfs(host.off, host.idx, int(root))
+        for pol, name in zip(POLICIES, POL_IDS):
+            if pol not in policies:
+                continue
+            announce(f"BFS {name} {host.name} root={root}")
+            lv, par, st = _run(g, int(root), pol)
+            assert np.array_equal(lv, want), f"{name} root {root}: levels differ"
+            viol = (H.bfs_violations_fast if fast else H.bfs_violations)(host, int(root), lv, par)
+            assert viol == [], f"{name} root {root}: {viol}"
+            assert st.levels == nlev
+            assert st.reached == int((want >= 0).sum())
+            deg = np.diff(host.off)
+            assert st.edges_reached == int(deg[want >= 0].sum())
+    g.close()
+
+
+@pytest.mark.parametrize("maker", [lambda: H.path(300), lambda: H.star(100), lambda: H.cycle(129),
+                                   lambda: H.complete(12), lambda: H.full_grid(20, 33)],
+                         ids=["path", "star", "cycle", "K12", "grid"])
+def test_small_graphs(maker):
+    host = maker()
+    _check(host, [0, host.n // 2, host.n - 1])
+
+
+def test_rmat14_from_vertex0_and_random_roots():
+    host = gg.workload("rmat14")
+    roots = [0] + list(gg.pick_vertices(host, 5, seed=3))
+    _check(host, roots)
+
+
+def test_disconnected_isolated_root_and_ragged():
+    host = gg.from_edges(1000, np.arange(0, 400), np.arange(1, 401), True)  # a path 0..400, rest isolated
+    _check(host, [0, 200, 999])
+    one = gg.from_edges(1, [], [], True)
+    _check(one, [0])
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_directed_graphs_td_uses_out_bu_uses_in(seed):
+    host = H.random_graph(4000, 9000, seed, symmetric=False)
+    host.ensure_transpose()
+    _check(host, [0, 17])
+
+
+def test_step_api_any_direction_sequence():
+    host = gg.workload("rmat14")
+    g = pp.Graph(host)
+    want, _, nlev = oracle.bfs(host.off, host.idx, 0)
+    rng = np.random.default_rng(4)
+    for trial in range(4):
+        r = pp.BfsRun(g)
+        r.init(0)
+        lvl = 0
+        while True:
+            r.step(lvl, pp.PP_PUSH if rng.random() < 0.5 else pp.PP_PULL)
+            lvl += 1
+            if r.frontier() == 0:
+                break
+        assert lvl == nlev
+        lv = r.level.cpu().numpy()
+        par = r.parent.cpu().numpy()
+        assert np.array_equal(lv, want)
+        assert H.bfs_violations(host, 0, lv, par) == []
+        # a step on an empty frontier changes nothing
+        r.step(lvl, pp.PP_PULL)
+        assert np.array_equal(r.level.cpu().numpy(), want)
+
+
+def test_bottom_up_parents_are_first_in_stored_order():
+    # pull scans in-neighbours in stored order and stops at the first frontier member
+    host = gg.workload("rmat14")
+    g = pp.Graph(host)
+    want, _, _ = oracle.bfs(host.off, host.idx, 0)
+    lv, par, _ = _run(g, 0, pp.PP_PULL)
+    for v in np.nonzero(want > 0)[0][:2000]:
+        row = host.idx[host.off[v]:host.off[v + 1]]
+        first = row[np.nonzero(want[row] == want[v] - 1)[0][0]]
+        assert par[v] == first
+
+
+def test_switch_policy_changes_direction_on_rmat():
+    host = gg.workload("rmat14")
+    g = pp.Graph(host)
+    lv, par, st = _run(g, 0, pp.PP_SWITCH)
+    dirs = [st.dir[i] for i in range(st.levels)]
+    assert pp.PP_PUSH in dirs and pp.PP_PULL in dirs, dirs
+
+
+def test_bad_root_raises():
+    g = pp.Graph(H.path(5))
+    with pytest.raises(pp.PPError):
+        pp.bfs(g, 5)
+    with pytest.raises(pp.PPError):
+        pp.bfs(g, -1)
+
+
+@pytest.mark.slow
+def test_rmat22_roots():
+    host = gg.workload("rmat22")
+    roots = gg.pick_vertices(host, 64, seed=1)
+    announce(f"BFS rmat22 nnz={host.nnz}")
+    # every policy on a few roots, the switch policy on more
+    _check(host, roots[:2], fast=True)
+    _check(host, roots[2:6], policies=[pp.PP_SWITCH], fast=True)
+
+
+@pytest.mark.slow
+def test_grid4096_corner_many_levels():
+    host = gg.workload("grid4096")
+    announce(f"BFS grid n={host.n}")
+    _check(host, [0], policies=[pp.PP_PUSH, pp.PP_SWITCH], fast=True)

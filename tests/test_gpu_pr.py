@@ -1,0 +1,191 @@
+"""PageRank push/pull sweeps on the GPU against the FP64 oracle.
+
+Bar: L1 distance <= 1e-6 between the FP32 GPU iterate and the FP64 oracle
+iterate after T steps (and per-element relative error reported), for push and
+pull, on closed-form graphs, directed graphs (push walks CSR, pull walks CSC),
+R-MAT scale 14, graphs forced through every degree bin, and at R-MAT scale 22
+via one-step sampled checks and the mass balance that holds at any size.
+"""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+import paper_2010_16012_amd as pp
+from paper_2010_16012_amd import _lib
+from tests import helpers as H
+from tests.gpu_util import F, PR_L1_TOL, announce, default_bins, pr_gpu, tiny_bins
+
+pytestmark = pytest.mark.gpu
+
+DIRS = [pp.PP_PULL, pp.PP_PUSH]
+DIR_IDS = ["pull", "push"]
+
+
+@pytest.fixture(autouse=True)
+def _bins():
+    default_bins()
+    yield
+    default_bins()
+
+
+def _check(host, iters=20, bins=None, tol=PR_L1_TOL):
+    if bins == "tiny":
+        tiny_bins()
+    g = pp.Graph(host)
+    want = oracle.pagerank(host.off, host.idx, F, iters)
+    for d, name in zip(DIRS, DIR_IDS):
+        announce(f"PR {name} {host.name} n={host.n} nnz={host.nnz} T={iters}")
+        got = pr_gpu(g, d, iters).astype(np.float64)
+        l1 = np.abs(got - want).sum()
+        assert l1 <= tol, f"{name}: L1 {l1:.3e} > {tol}"
+    g.close()
+
+
+@pytest.mark.parametrize("maker", [lambda: H.star(50), lambda: H.complete(9), lambda: H.cycle(257),
+                                   lambda: H.complete_bipartite(3, 70), lambda: H.full_grid(13, 17)],
+                         ids=["star", "K9", "cycle", "K3_70", "grid"])
+def test_closed_form_graphs(maker):
+    _check(maker())
+
+
+def test_rmat14_both_forms():
+    _check(gg.workload("rmat14"))
+
+
+def test_rmat14_every_bin_including_split_rows():
+    host = gg.workload("rmat14")
+    tiny_bins()
+    g = pp.Graph(host)
+    bins = g.bins(pp.PP_PULL)
+    assert all(b > 0 for b in bins), bins
+    want = oracle.pagerank(host.off, host.idx, F, 20)
+    for d in DIRS:
+        got = pr_gpu(g, d, 20).astype(np.float64)
+        assert np.abs(got - want).sum() <= PR_L1_TOL
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_directed_graph_push_uses_out_edges_pull_uses_in_edges(seed):
+    host = H.random_graph(3000, 20000, seed, symmetric=False)
+    host.ensure_transpose()
+    _check(host, bins=None)
+    _check(host, bins="tiny")
+
+
+def test_edge_cases_single_vertex_and_no_edges():
+    one = gg.from_edges(1, [], [], True)
+    _check(one, iters=5)
+    empty = gg.from_edges(100, [], [], True)
+    _check(empty, iters=3)
+    # ragged: vertex count not a multiple of any tile, with a few isolated vertices
+    _check(H.random_graph(1001, 1500, 3), iters=7)
+
+
+def test_zero_iterations_is_identity():
+    host = H.cycle(10)
+    g = pp.Graph(host)
+    x0 = torch.arange(10, dtype=torch.float32, device="cuda")
+    for d in DIRS:
+        x = pp.pagerank(g, 0, F, d, x0=x0)
+        assert torch.equal(x, x0)
+
+
+def test_pull_is_bit_reproducible_and_resumable():
+    host = gg.workload("rmat14")
+    g = pp.Graph(host)
+    a = pr_gpu(g, pp.PP_PULL, 20)
+    b = pr_gpu(g, pp.PP_PULL, 20)
+    assert np.array_equal(a, b)
+    half = pp.pagerank(g, 10, F, pp.PP_PULL)
+    full = pp.pagerank(g, 10, F, pp.PP_PULL, x0=half)
+    assert np.array_equal(full.cpu().numpy(), a)
+    # push is order-dependent in the last bits but resumes within tolerance
+    p_half = pp.pagerank(g, 10, F, pp.PP_PUSH)
+    p_full = pp.pagerank(g, 10, F, pp.PP_PUSH, x0=p_half).cpu().numpy().astype(np.float64)
+    assert np.abs(p_full - a).sum() <= PR_L1_TOL
+
+
+def test_step_api_matches_run_api():
+    host = H.random_graph(5000, 40000, 5, symmetric=False)
+    host.ensure_transpose()
+    g = pp.Graph(host)
+    x = torch.rand(g.n, device="cuda", dtype=torch.float32) / g.n
+    want = oracle.pagerank(host.off, host.idx, F, 1, x0=x.cpu().numpy().astype(np.float64))
+    for fn in (_lib.pp_pr_pull, _lib.pp_pr_push):
+        y = torch.empty_like(x)
+        fn(g.handle, x, y, F)
+        torch.cuda.synchronize()
+        assert np.abs(y.cpu().numpy() - want).sum() <= 1e-7
+    y_run = pp.pagerank(g, 1, F, pp.PP_PULL, x0=x)
+    y_step = torch.empty_like(x)
+    _lib.pp_pr_pull(g.handle, x, y_step, F)
+    assert torch.equal(y_run, y_step)
+
+
+def test_weighted_pagerank_matches_oracle_ppr_average():
+    # weighted uniform PageRank = mean over all sources of weighted PPR
+    host = H.random_graph(300, 1500, 8, symmetric=True)
+    gg.with_weights(host, seed=2)
+    g = pp.Graph(host)
+    X, _ = oracle.ppr(host.off, host.idx, np.arange(host.n), F, T=15, weights=host.weights)
+    want = X.mean(axis=1)
+    for d in DIRS:
+        got = pr_gpu(g, d, 15).astype(np.float64)
+        assert np.abs(got - want).sum() <= PR_L1_TOL
+
+
+def test_argument_errors_raise():
+    host = H.cycle(8)
+    g = pp.Graph(host)
+    x = torch.zeros(8, device="cuda")
+    with pytest.raises(pp.PPError):
+        _lib.pp_pr_pull(g.handle, x, x, F)        # aliasing
+    with pytest.raises(pp.PPError):
+        _lib.pp_pr_push(g.handle, x, torch.zeros(8, device="cuda"), 1.5)  # f out of range
+    with pytest.raises(pp.PPError):
+        _lib.pp_pr_run(g.handle, pp.PP_SWITCH, 3, F, x)
+    bad = gg.from_edges(4, [0, 1], [1, 2], True)
+    bad.idx = bad.idx.copy()
+    bad.idx[0] = 7  # out of range index
+    with pytest.raises(pp.PPError):
+        pp.Graph(bad)
+
+
+@pytest.mark.slow
+def test_rmat22_sampled_step_and_mass_balance():
+    host = gg.workload("rmat22")
+    announce(f"PR rmat22 n={host.n} nnz={host.nnz}")
+    g = pp.Graph(host)
+    deg = np.diff(host.off)
+    rng = np.random.default_rng(0)
+    verts = np.concatenate([np.arange(64), rng.integers(0, host.n, 4032)]).astype(np.int32)
+    for d, name in zip(DIRS, DIR_IDS):
+        x19 = pp.pagerank(g, 19, F, d)
+        x20 = pp.pagerank(g, 1, F, d, x0=x19)
+        torch.cuda.synchronize()
+        x19h = x19.cpu().numpy()
+        x20h = x20.cpu().numpy().astype(np.float64)
+        want = oracle.pagerank_step_at(host.off, host.idx, x19h, verts, F)
+        rel = np.abs(x20h[verts] - want) / np.abs(want)
+        assert rel.max() <= 1e-5, f"{name}: worst relative error {rel.max():.2e}"
+        # mass balance of one step, at every size
+        lhs = x20h.sum()
+        rhs = (1 - F) + F * x19h[deg > 0].astype(np.float64).sum()
+        assert abs(lhs - rhs) <= 1e-5, f"{name}: mass {lhs} vs {rhs}"
+        # isolated vertices sit exactly at the teleport value
+        iso = np.nonzero(deg == 0)[0][:1000]
+        assert np.all(x20h[iso] == np.float32((1 - F) / host.n))  # F is FP32-exact
+
+
+@pytest.mark.slow
+def test_rmat22_full_run_against_oracle():
+    host = gg.workload("rmat22")
+    g = pp.Graph(host)
+    want = oracle.pagerank(host.off, host.idx, F, 20)
+    for d, name in zip(DIRS, DIR_IDS):
+        announce(f"PR rmat22 full {name}")
+        got = pr_gpu(g, d, 20).astype(np.float64)
+        l1 = np.abs(got - want).sum()
+        assert l1 <= PR_L1_TOL, f"{name}: L1 {l1:.3e}"
