@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Push/pull sweep benchmark on one MI355X.
+
+One step = the whole hot path over the R-MAT scale-22 graph (edge factor 16,
+a,b,c = .57,.19,.19, seed 1, symmetrised, deduplicated, int32 CSR):
+  * PageRank, 20 Jacobi steps, pulling form (f = 0.85, FP32)
+  * PageRank, 20 Jacobi steps, pushing form
+  * BFS from 64 seeded non-isolated roots: top-down (push), bottom-up (pull)
+    and direction-switching.
+value = traversed edges per second over the step, in GTEPS: a PageRank step
+traverses nnz edges; a BFS traverses the undirected edges of the root's
+component (sum of reached degrees / 2).  Per-part rates are in "parts".
+
+The roofline object covers the pull sweep kernel: algorithmic bytes per launch
+(4*nnz + 16*n) over the average launch time measured with HIP
+events around the 20-step pull run.  The CPU baseline is the FP64 C oracle on
+a bounded sample (one PageRank step and two BFS roots).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+F = 0.85
+PR_ITERS = 20
+N_ROOTS = 64
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--scale", type=int, default=22)
+    p.add_argument("--roots", type=int, default=N_ROOTS)
+    p.add_argument("--only", default="", help="comma list of parts to run (pr_pull,pr_push,bfs_push,bfs_pull,bfs_switch)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
+    return p.parse_args()
+
+
+def source_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2010_16012_amd", "csrc", n), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_src_hash, launch_algo_bytes):
+    """HBM traffic per launch from a committed counter summary, if it still
+    describes the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "pr_pull_rmat22_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != kernel_src_hash:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sweep shards by vertex "
+              "ranges across GPUs, see DESIGN.md, but this build runs on one GPU only)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import scipy.sparse as sp
+    import scipy.sparse.csgraph as csg
+    import torch
+
+    import graphgen as gg
+    import paper_2010_16012_amd as pp
+
+    parts = ["pr_pull", "pr_push", "bfs_push", "bfs_pull", "bfs_switch"]
+    if args.only:
+        parts = [p for p in parts if p in args.only.split(",")]
+    dev = torch.device("cuda:0")
+    t_gen = time.time()
+    host = gg.rmat(args.scale, 16, seed=1)
+    n, nnz = host.n, host.nnz
+    roots = gg.pick_vertices(host, args.roots, seed=1)
+    print(f"# graph rmat{args.scale}: n={n} nnz={nnz} generated in {time.time() - t_gen:.1f}s", flush=True)
+    # edges of each root's component, from the host graph (independent of the GPU path)
+    A = sp.csr_matrix((np.ones(nnz, dtype=np.int8), host.idx, host.off), shape=(n, n))
+    ncomp, comp = csg.connected_components(A, directed=False)
+    deg = np.diff(host.off)
+    comp_edges = np.bincount(comp, weights=deg, minlength=ncomp)
+    root_edges = comp_edges[comp[roots]] / 2.0
+    del A
+
+    t_up = time.time()
+    g = pp.Graph(host, device=dev)
+    torch.cuda.synchronize()
+    print(f"# uploaded and registered in {time.time() - t_up:.1f}s", flush=True)
+    x = torch.empty(n, dtype=torch.float32, device=dev)
+    runs = {p: pp.BfsRun(g) for p in ("bfs_push", "bfs_pull", "bfs_switch")}
+    policy = {"bfs_push": pp.PP_PUSH, "bfs_pull": pp.PP_PULL, "bfs_switch": pp.PP_SWITCH}
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        return e
+
+    def step(times):
+        for p in parts:
+            e0 = ev()
+            if p.startswith("pr_"):
+                x.fill_(1.0 / n)
+                e0 = ev()  # the fill is not part of the sweep
+                pp.pagerank_into(g, x, PR_ITERS, F, pp.PP_PULL if p == "pr_pull" else pp.PP_PUSH)
+            else:
+                r = runs[p]
+                for root in roots:
+                    r.run(int(root), policy[p])
+            e1 = ev()
+            times.setdefault(p, []).append((e0, e1))
+
+    for _ in range(args.warmup):
+        step({})
+    torch.cuda.synchronize()
+    times = {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(times)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+
+    part_ms = {p: float(np.mean([a.elapsed_time(b) for a, b in times[p]])) for p in parts}
+    part_edges = {"pr_pull": PR_ITERS * nnz, "pr_push": PR_ITERS * nnz}
+    for p in ("bfs_push", "bfs_pull", "bfs_switch"):
+        part_edges[p] = float(root_edges.sum())
+    step_edges = sum(part_edges[p] for p in parts)
+    value = step_edges / (ms_step * 1e-3) / 1e9
+
+    out_parts = {}
+    for p in parts:
+        d = {"ms": round(part_ms[p], 4), "gteps": round(part_edges[p] / (part_ms[p] * 1e-3) / 1e9, 3)}
+        if p.startswith("bfs_"):
+            ms_root = part_ms[p] / len(roots)
+            per_root = root_edges / (ms_root * 1e-3) / 1e9
+            d["ms_per_root"] = round(ms_root, 4)
+            d["gteps_hmean_roots"] = round(float(len(per_root) / np.sum(1.0 / per_root)), 3)
+        else:
+            d["us_per_iter"] = round(part_ms[p] * 1e3 / PR_ITERS, 2)
+        out_parts[p] = d
+
+    roofline = None
+    if "pr_pull" in parts:
+        # one pull launch reads offsets (4n), indices (4 nnz), the gathered
+        # contribution (4n) and 1/d (4n), and writes the next contribution (4n)
+        algo = 4 * nnz + 16 * n
+        t_launch = part_ms["pr_pull"] * 1e-3 / PR_ITERS
+        achieved = algo / t_launch / 1e9
+        src_hash = source_hash("pr.hip")
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(src_hash, algo),
+                    "kernel": "k_pr_pull<false>", "algorithmic_bytes_per_launch": algo,
+                    "launch_us": round(t_launch * 1e6, 2)}
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.neg(a, out=b)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del a, b
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.perf_counter()
+        oracle.pagerank(host.off, host.idx, F, 1)
+        t_pr = time.perf_counter() - t
+        t = time.perf_counter()
+        for root in roots[:2]:
+            oracle.bfs(host.off, host.idx, int(root))
+        t_bfs = time.perf_counter() - t
+        e = nnz + float(root_edges[:2].sum())
+        cpu = {"value": round(e / (t_pr + t_bfs) / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": f"one FP64 PageRank step ({t_pr:.2f}s) + FIFO BFS from 2 of the 64 roots ({t_bfs:.2f}s) "
+                         f"on the same rmat{args.scale} graph, single thread"}
+
+    line = {
+        "metric": "GTEPS per PageRank iter & BFS, push vs pull; % of HBM roofline",
+        "value": round(value, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+i32",
+        "data": "synthetic",
+        "config": {"workload": f"rmat{args.scale}_ef16_seed1_sym: PageRank x{PR_ITERS} pull+push, "
+                               f"BFS from {len(roots)} roots push/pull/switch",
+                   "n": n, "nnz": nnz, "parts": parts},
+        "parts": out_parts,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -62,6 +62,8 @@ typedef enum { PP_PUSH = 0, PP_PULL = 1, PP_SWITCH = 2 } pp_dir;
 
 /* Graph flags. */
 #define PP_GRAPH_WEIGHTED 0x1u /* csr_w (and csc_to_csr) are given */
+#define PP_GRAPH_RELABEL 0x2u  /* renumber vertices by decreasing degree inside the
+                                  library (caller ids are kept at the ABI) */
 
 typedef struct pp_graph_s* pp_graph;
 
@@ -89,6 +91,15 @@ pp_status pp_graph_create(int32_t n, int64_t nnz,
                           const float* csr_w, const int32_t* csc_to_csr,
                           uint32_t flags, void* ws, size_t ws_bytes, void* stream, pp_graph* out);
 
+/* With PP_GRAPH_RELABEL the library keeps a renumbered copy of the adjacency
+ * arrays in the workspace: vertices sorted by floor(log2(d_out + d_in + 1)),
+ * heaviest first, ties in caller order.  Heavy rows then sit in one
+ * contiguous id range, which the push sweep privatises in LDS and which keeps
+ * the most-gathered entries in a compact, cache-resident prefix.  Every entry
+ * point still takes and returns vectors in caller ids.  perm: int32[n] device
+ * output, perm[i] = caller id of internal vertex i. */
+pp_status pp_graph_relabel_map(pp_graph g, int32_t* perm, void* stream);
+
 /* Frees the host handle (device memory stays with the caller). */
 pp_status pp_graph_destroy(pp_graph g);
 
@@ -106,6 +117,14 @@ pp_status pp_graph_bins(pp_graph g, pp_dir dir, int32_t* counts);
  * rest) and the split chunk for the longest rows.  Defaults: 4, 16, 64, 1024,
  * 16384; chunk 16384.  Takes effect at the next pp_graph_create. */
 pp_status pp_set_bin_thresholds(const int32_t* upper5, int32_t split_chunk);
+
+/* Push-sweep tuning: the first `hot` vertices (internal ids) are accumulated
+ * per workgroup in LDS and merged once per sweep (the Partition-Awareness
+ * strategy of Sec. 5 with a workgroup as the owner); the sweep runs on
+ * `push_blocks` persistent workgroups.  Defaults 8192 and 1024; hot in
+ * [0, 16384] (0 disables), push_blocks in [1, 65536].  Takes effect at the
+ * next pp_graph_create. */
+pp_status pp_set_push_tuning(int32_t hot, int32_t push_blocks);
 
 /* --------------------------------------------------------------- PageRank */
 /* One Jacobi step of the PageRank equation (Sec. 3.1):

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (PP_PULL, PP_PUSH, PP_SWITCH, PPError, BfsStats)  # noqa: F401
 from ._lib import *  # noqa: F401,F403  (the C names)
 
-__all__ = ["Graph", "BfsRun", "PPError", "PP_PUSH", "PP_PULL", "PP_SWITCH", "pagerank", "bfs"]
+__all__ = ["Graph", "BfsRun", "PPError", "PP_PUSH", "PP_PULL", "PP_SWITCH", "pagerank", "pagerank_into", "bfs"]
 
 
 class Graph:
@@ -27,7 +27,7 @@ class Graph:
     ``weights`` (per CSR slot) with ``in_to_out`` (CSR slot of each CSC slot).
     """
 
-    def __init__(self, host, device="cuda", weighted=None, stream=None):
+    def __init__(self, host, device="cuda", weighted=None, relabel=True, stream=None):
         n = int(host.n)
         nnz = int(host.off[-1])
         if nnz > 2**31 - 1:
@@ -51,7 +51,8 @@ class Graph:
         if weighted is None:
             weighted = getattr(host, "weights", None) is not None
         self.weighted = bool(weighted)
-        flags = _lib.PP_GRAPH_WEIGHTED if self.weighted else 0
+        flags = (_lib.PP_GRAPH_WEIGHTED if self.weighted else 0) | (_lib.PP_GRAPH_RELABEL if relabel else 0)
+        self.relabel = bool(relabel)
         if self.weighted:
             self.csr_w = up(host.weights, torch.float32)
             self.csc_to_csr = up(host.in_to_out, torch.int32)
@@ -64,6 +65,12 @@ class Graph:
         self.handle = _lib.pp_graph_create(n, nnz, self.csr_off, self.csr_idx, self.csc_off, self.csc_idx,
                                            self.csr_w, self.csc_to_csr, flags, self.ws, stream)
         self.device = dev
+
+    def relabel_map(self):
+        """perm[i] = caller id of internal vertex i (graphs registered with relabel)."""
+        perm = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        _lib.pp_graph_relabel_map(self.handle, perm)
+        return perm
 
     def bins(self, direction=PP_PULL):
         return _lib.pp_graph_bins(self.handle, direction)
@@ -83,6 +90,12 @@ class Graph:
 def pagerank(g: Graph, iters=20, f=0.85, direction=PP_PULL, x0=None, stream=None):
     """``iters`` Jacobi steps of the PageRank equation from x0 (default 1/n)."""
     x = torch.full((g.n,), 1.0 / g.n, dtype=torch.float32, device=g.device) if x0 is None else x0.clone()
+    _lib.pp_pr_run(g.handle, direction, iters, f, x, stream)
+    return x
+
+
+def pagerank_into(g: Graph, x, iters=20, f=0.85, direction=PP_PULL, stream=None):
+    """In place: x (float32[n] on the device) holds x_0 on entry, x_iters on exit."""
     _lib.pp_pr_run(g.handle, direction, iters, f, x, stream)
     return x
 

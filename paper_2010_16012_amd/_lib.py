@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpp.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2010_16012_amd.build`")
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_2010_16012_amd/build.py`")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -33,6 +33,7 @@ STATUS_NAMES = {0: "PP_OK", -1: "PP_E_NULL", -2: "PP_E_SIZE", -3: "PP_E_RANGE", 
 
 PP_PUSH, PP_PULL, PP_SWITCH = 0, 1, 2
 PP_GRAPH_WEIGHTED = 0x1
+PP_GRAPH_RELABEL = 0x2
 PP_NUM_BINS = 6
 PP_BFS_MAX_LOG = 64
 
@@ -64,6 +65,8 @@ _SIGS = {
     "pp_graph_check": ([_P, _P], ctypes.c_int),
     "pp_graph_bins": ([_P, ctypes.c_int, ctypes.POINTER(_I32)], ctypes.c_int),
     "pp_set_bin_thresholds": ([ctypes.POINTER(_I32), _I32], ctypes.c_int),
+    "pp_set_push_tuning": ([_I32, _I32], ctypes.c_int),
+    "pp_graph_relabel_map": ([_P, _P, _P], ctypes.c_int),
     "pp_pr_push": ([_P, _P, _P, _F32, _P], ctypes.c_int),
     "pp_pr_pull": ([_P, _P, _P, _F32, _P], ctypes.c_int),
     "pp_pr_run": ([_P, ctypes.c_int, _I32, _F32, _P, _P], ctypes.c_int),
@@ -153,6 +156,14 @@ def pp_graph_bins(h, direction: int):
 def pp_set_bin_thresholds(upper5, split_chunk: int) -> None:
     arr = (_I32 * 5)(*[int(u) for u in upper5])
     _check(_lib.pp_set_bin_thresholds(arr, split_chunk))
+
+
+def pp_set_push_tuning(hot: int, push_blocks: int) -> None:
+    _check(_lib.pp_set_push_tuning(hot, push_blocks))
+
+
+def pp_graph_relabel_map(h, perm, stream=None) -> None:
+    _check(_lib.pp_graph_relabel_map(h, _ptr(perm), _stream(stream)))
 
 
 def pp_pr_push(h, x, y, f: float, stream=None) -> None:

@@ -1,6 +1,7 @@
 """Builds libpp.so (HIP, gfx950) in-tree: one hipcc compile per source, then a link.
 
-Usage: python -m paper_2010_16012_amd.build   (or call build()).
+Usage: python paper_2010_16012_amd/build.py   (or call build()).  Run it by
+path: importing the package first would load a stale libpp.so.
 """
 from __future__ import annotations
 

@@ -1,5 +1,6 @@
-// Graph registration: error state, workspace layout, device-derived degree
-// data and the degree-binned vertex lists the sweeps are launched over.
+// Graph registration: error state, workspace layout, validation, the
+// optional degree-ordered relabelling, device-derived degree data and the
+// degree-binned vertex lists the sweeps are launched over.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,24 +31,206 @@ Tuning& tuning() {
     return t;
 }
 
-pp_status check_graph_handle(pp_graph g) {
-    if (!g) return set_error(PP_E_NULL, "graph handle is NULL");
-    return PP_OK;
-}
-
 // ------------------------------------------------------------------ kernels
-// Degree of v in an adjacency array.
+constexpr int kTile = 256;      // vertices per partition tile
+constexpr int kMaxKeys = 32;    // partition keys are 0..31
+constexpr int kScanTile = 1024; // elements per scan tile
+
 __device__ __forceinline__ int32_t row_len(const int32_t* off, int32_t v) { return off[v + 1] - off[v]; }
 
+// Degree bin of every vertex (keys for the bin partition).
 struct BinBounds {
     int32_t upper[PP_NUM_BINS - 1];
 };
 
-__device__ __forceinline__ int bin_of(int32_t d, const BinBounds& bb) {
+__global__ void k_bin_keys(int32_t n, const int32_t* __restrict__ off, BinBounds bb, uint8_t* __restrict__ key) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t d = row_len(off, v);
     int b = 0;
 #pragma unroll
     for (int i = 0; i < PP_NUM_BINS - 1; ++i) b += (d > bb.upper[i]);
-    return b;
+    key[v] = (uint8_t)b;
+}
+
+// Relabel key: heaviest vertices first, by floor(log2(d_out + d_in + 1)).
+__global__ void k_relabel_keys(int32_t n, const int32_t* __restrict__ off, const int32_t* __restrict__ in_off,
+                               uint8_t* __restrict__ key) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const uint32_t d = (uint32_t)row_len(off, v) + (uint32_t)row_len(in_off, v) + 1u;
+    key[v] = (uint8_t)(__clz(d));  // 31 - floor(log2 d): larger degree -> smaller key
+}
+
+// Stable partition of 0..n-1 by key: per-tile counts ...
+__global__ __launch_bounds__(kTile) void k_part_count(int32_t n, int nkeys, const uint8_t* __restrict__ key,
+                                                      int32_t* __restrict__ tile_counts) {
+    __shared__ int32_t cnt[kMaxKeys];
+    if (threadIdx.x < kMaxKeys) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int32_t v = blockIdx.x * kTile + threadIdx.x;
+    const int b = (v < n) ? key[v] : -1;
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int i = 0; i < nkeys; ++i) {
+        const uint64_t m = __ballot(b == i);
+        if (lane == 0 && m) atomicAdd(&cnt[i], __popcll(m));
+    }
+    __syncthreads();
+    if (threadIdx.x < nkeys) tile_counts[blockIdx.x * nkeys + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// ... an exclusive scan of the tile counts, key-major (one workgroup) ...
+__global__ __launch_bounds__(1024) void k_part_scan(int32_t tiles, int nkeys, int32_t* __restrict__ tile_counts,
+                                                    int32_t* __restrict__ totals) {
+    __shared__ int32_t part[1024];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int per = (tiles + 1023) / 1024;
+    for (int b = 0; b < nkeys; ++b) {
+        const int t0 = threadIdx.x * per;
+        int32_t s = 0;
+        for (int t = t0; t < t0 + per && t < tiles; ++t) s += tile_counts[t * nkeys + b];
+        part[threadIdx.x] = s;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            int32_t add = (threadIdx.x >= d) ? part[threadIdx.x - d] : 0;
+            __syncthreads();
+            part[threadIdx.x] += add;
+            __syncthreads();
+        }
+        int32_t run = carry + part[threadIdx.x] - s;
+        for (int t = t0; t < t0 + per && t < tiles; ++t) {
+            const int32_t c = tile_counts[t * nkeys + b];
+            tile_counts[t * nkeys + b] = run;
+            run += c;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) {
+            totals[b] = part[1023];
+            carry += part[1023];
+        }
+        __syncthreads();
+    }
+}
+
+// ... and a scatter that keeps vertex order within each key.
+__global__ __launch_bounds__(kTile) void k_part_scatter(int32_t n, int nkeys, const uint8_t* __restrict__ key,
+                                                        const int32_t* __restrict__ tile_base,
+                                                        int32_t* __restrict__ list) {
+    __shared__ int32_t wave_cnt[kTile / kWave][kMaxKeys];
+    const int32_t v = blockIdx.x * kTile + threadIdx.x;
+    const int b = (v < n) ? key[v] : -1;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    int rank = 0;
+    for (int i = 0; i < nkeys; ++i) {
+        const uint64_t m = __ballot(b == i);
+        if (b == i) rank = __popcll(m & below);
+        if (lane == 0) wave_cnt[w][i] = __popcll(m);
+    }
+    __syncthreads();
+    if (b >= 0) {
+        int pos = tile_base[blockIdx.x * nkeys + b] + rank;
+        for (int ww = 0; ww < w; ++ww) pos += wave_cnt[ww][b];
+        list[pos] = v;
+    }
+}
+
+// Exclusive scan of n int32 values into out[0..n] (out[n] = total):
+// per-tile scans ...
+__global__ __launch_bounds__(256) void k_scan_tiles(int32_t n, const int32_t* __restrict__ in,
+                                                    int32_t* __restrict__ out, int32_t* __restrict__ tsum) {
+    __shared__ int32_t part[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
+    int32_t v[4];
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        int32_t add = (threadIdx.x >= d) ? part[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int32_t run = part[threadIdx.x] - s;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 255) tsum[blockIdx.x] = part[255];
+}
+
+// ... a scan of the tile sums (one workgroup) ...
+__global__ __launch_bounds__(1024) void k_scan_sums(int32_t tiles, int32_t* __restrict__ tsum,
+                                                    int32_t* __restrict__ total) {
+    __shared__ int32_t part[1024];
+    const int per = (tiles + 1023) / 1024;
+    const int t0 = threadIdx.x * per;
+    int32_t s = 0;
+    for (int t = t0; t < t0 + per && t < tiles; ++t) s += tsum[t];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        int32_t add = (threadIdx.x >= d) ? part[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int32_t run = part[threadIdx.x] - s;
+    for (int t = t0; t < t0 + per && t < tiles; ++t) {
+        const int32_t c = tsum[t];
+        tsum[t] = run;
+        run += c;
+    }
+    if (threadIdx.x == 1023) *total = part[1023];
+}
+
+// ... and the tile offsets added back.
+__global__ void k_scan_add(int32_t n, int32_t* __restrict__ out, const int32_t* __restrict__ tsum,
+                           const int32_t* __restrict__ total) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += tsum[i / kScanTile];
+    if (i == n) out[n] = *total;
+}
+
+__global__ void k_invert_perm(int32_t n, const int32_t* __restrict__ perm, int32_t* __restrict__ iperm) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) iperm[perm[i]] = i;
+}
+
+__global__ void k_perm_degrees(int32_t n, const int32_t* __restrict__ perm, const int32_t* __restrict__ off,
+                               int32_t* __restrict__ deg) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) deg[i] = row_len(off, perm[i]);
+}
+
+// Row i of the relabelled array is row perm[i] of the caller's array with
+// every neighbour renamed (stored order kept).  Optional weights follow their
+// slots: wsrc is indexed by slot, or by map[slot] when map is given.
+__global__ __launch_bounds__(256) void k_relabel_rows(int32_t n, const int32_t* __restrict__ perm,
+                                                      const int32_t* __restrict__ iperm,
+                                                      const int32_t* __restrict__ off, const int32_t* __restrict__ idx,
+                                                      const int32_t* __restrict__ off_new, int32_t* __restrict__ idx_new,
+                                                      const float* __restrict__ wsrc, const int32_t* __restrict__ map,
+                                                      float* __restrict__ w_new) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t nw = gridDim.x * (blockDim.x / kWave);
+    for (int32_t i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < n; i += nw) {
+        const int32_t v = perm[i];
+        const int32_t b = off[v], e = off[v + 1], o = off_new[i];
+        for (int32_t j = b + lane; j < e; j += kWave) {
+            if (idx_new) idx_new[o + (j - b)] = iperm[idx[j]];
+            if (w_new) w_new[o + (j - b)] = map ? wsrc[map[j]] : wsrc[j];
+        }
+    }
 }
 
 // d(v), and the reciprocal of d(v) (or of the out-strength s(v) when
@@ -76,84 +259,23 @@ __global__ void k_gather_weights(int64_t nnz, const float* __restrict__ csr_w, c
     if (j < nnz) csc_w[j] = csr_w[map[j]];
 }
 
-// Stable partition of the vertices by degree bin: per-tile counts ...
-constexpr int kTile = 256;
-
-__global__ __launch_bounds__(kTile) void k_bin_count(int32_t n, const int32_t* __restrict__ off, BinBounds bb,
-                                                     int32_t* __restrict__ tile_counts) {
-    __shared__ int32_t cnt[PP_NUM_BINS];
-    if (threadIdx.x < PP_NUM_BINS) cnt[threadIdx.x] = 0;
-    __syncthreads();
-    const int32_t v = blockIdx.x * kTile + threadIdx.x;
-    const int b = (v < n) ? bin_of(row_len(off, v), bb) : -1;
-    const int lane = threadIdx.x & (kWave - 1);
+// Largest out- and in-row length.
+__global__ void k_max_deg(int32_t n, const int32_t* __restrict__ off, const int32_t* __restrict__ in_off,
+                          int32_t* __restrict__ out) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t a = 0, b = 0;
+    if (v < n) {
+        a = row_len(off, v);
+        b = row_len(in_off, v);
+    }
 #pragma unroll
-    for (int i = 0; i < PP_NUM_BINS; ++i) {
-        const uint64_t m = __ballot(b == i);
-        if (lane == 0 && m) atomicAdd(&cnt[i], __popcll(m));
+    for (int s = 32; s > 0; s >>= 1) {
+        a = max(a, __shfl_xor(a, s));
+        b = max(b, __shfl_xor(b, s));
     }
-    __syncthreads();
-    if (threadIdx.x < PP_NUM_BINS) tile_counts[blockIdx.x * PP_NUM_BINS + threadIdx.x] = cnt[threadIdx.x];
-}
-
-// ... an exclusive scan of the tile counts, bin-major (one workgroup) ...
-__global__ __launch_bounds__(1024) void k_bin_scan(int32_t tiles, int32_t* __restrict__ tile_counts,
-                                                   int32_t* __restrict__ totals) {
-    __shared__ int32_t part[1024];
-    __shared__ int32_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    const int per = (tiles + 1023) / 1024;
-    for (int b = 0; b < PP_NUM_BINS; ++b) {
-        const int t0 = threadIdx.x * per;
-        int32_t s = 0;
-        for (int t = t0; t < t0 + per && t < tiles; ++t) s += tile_counts[t * PP_NUM_BINS + b];
-        part[threadIdx.x] = s;
-        __syncthreads();
-        // Hillis-Steele inclusive scan over 1024 partial sums
-        for (int d = 1; d < 1024; d <<= 1) {
-            int32_t add = (threadIdx.x >= d) ? part[threadIdx.x - d] : 0;
-            __syncthreads();
-            part[threadIdx.x] += add;
-            __syncthreads();
-        }
-        int32_t run = carry + part[threadIdx.x] - s;  // exclusive prefix of this thread's range
-        for (int t = t0; t < t0 + per && t < tiles; ++t) {
-            const int32_t c = tile_counts[t * PP_NUM_BINS + b];
-            tile_counts[t * PP_NUM_BINS + b] = run;
-            run += c;
-        }
-        __syncthreads();
-        if (threadIdx.x == 1023) {
-            totals[b] = part[1023];
-            carry += part[1023];
-        }
-        __syncthreads();
-    }
-}
-
-// ... and a scatter that keeps vertex order inside each bin.
-__global__ __launch_bounds__(kTile) void k_bin_scatter(int32_t n, const int32_t* __restrict__ off, BinBounds bb,
-                                                       const int32_t* __restrict__ tile_base,
-                                                       int32_t* __restrict__ list) {
-    __shared__ int32_t wave_cnt[kTile / kWave][PP_NUM_BINS];
-    const int32_t v = blockIdx.x * kTile + threadIdx.x;
-    const int b = (v < n) ? bin_of(row_len(off, v), bb) : -1;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int w = threadIdx.x / kWave;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-    int rank = 0;
-#pragma unroll
-    for (int i = 0; i < PP_NUM_BINS; ++i) {
-        const uint64_t m = __ballot(b == i);
-        if (b == i) rank = __popcll(m & below);
-        if (lane == 0) wave_cnt[w][i] = __popcll(m);
-    }
-    __syncthreads();
-    if (b >= 0) {
-        int pos = tile_base[blockIdx.x * PP_NUM_BINS + b] + rank;
-        for (int ww = 0; ww < w; ++ww) pos += wave_cnt[ww][b];
-        list[pos] = v;
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&out[0], a);
+        atomicMax(&out[1], b);
     }
 }
 
@@ -176,10 +298,15 @@ __global__ void k_check_indices(int32_t n, int64_t nnz, const int32_t* __restric
     if (u < 0 || u >= n) atomicAdd(&err[1], 1);
 }
 
+__global__ void k_zero_i32(int32_t n, int32_t* p) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 // ------------------------------------------------------------------ host side
 struct WsLayout {
-    size_t inv_s, out_deg, pull_list, push_list, buf0, buf1, buf2, csc_w, split_tab, split_part, err, tiles,
-        total;
+    size_t inv_s, out_deg, pull_list, push_list, buf0, buf1, buf2, csc_w, split_tab, split_part, hot_part, err,
+        tiles, keys, perm, iperm, r_csr_off, r_csr_idx, r_csc_off, r_csc_idx, r_csr_w, total;
     int32_t split_cap;
 };
 
@@ -188,7 +315,8 @@ static int32_t split_capacity(int64_t nnz, const Tuning& t) {
     return (int32_t)std::min<int64_t>(cap, INT32_MAX / 4);
 }
 
-static WsLayout layout(int32_t n, int64_t nnz, uint32_t flags, const Tuning& t) {
+// `aliased`: the caller passes one array pair for CSR and CSC (symmetric graph).
+static WsLayout layout(int32_t n, int64_t nnz, uint32_t flags, const Tuning& t, bool aliased) {
     WsLayout L{};
     size_t p = 0;
     auto take = [&](size_t bytes) {
@@ -197,6 +325,9 @@ static WsLayout layout(int32_t n, int64_t nnz, uint32_t flags, const Tuning& t) 
         return at;
     };
     const size_t nn = (size_t)n;
+    const bool relabel = (flags & PP_GRAPH_RELABEL) != 0;
+    const bool weighted = (flags & PP_GRAPH_WEIGHTED) != 0;
+    const size_t nz = (size_t)std::max<int64_t>(nnz, 1);
     L.split_cap = split_capacity(nnz, t);
     L.inv_s = take(nn * 4);
     L.out_deg = take(nn * 4);
@@ -205,12 +336,26 @@ static WsLayout layout(int32_t n, int64_t nnz, uint32_t flags, const Tuning& t) 
     L.buf0 = take(nn * 4);
     L.buf1 = take(nn * 4);
     L.buf2 = take(nn * 4);
-    L.csc_w = (flags & PP_GRAPH_WEIGHTED) ? take((size_t)nnz * 4) : 0;
-    // split table: per entry (vertex, begin, end) + per split vertex first entry, for pull and push
-    L.split_tab = take((size_t)2 * (3 * (size_t)L.split_cap + (size_t)L.split_cap + 1) * 4);
+    L.csc_w = weighted ? take(nz * 4) : 0;
+    // split tables: per entry (vertex, begin, end) + per split vertex first entry, for pull and push
+    L.split_tab = take((size_t)2 * (4 * (size_t)L.split_cap + 1) * 4);
     L.split_part = take((size_t)L.split_cap * 4);
+    L.hot_part = take((size_t)t.push_blocks * (size_t)std::max(t.hot, 1) * 4);
     L.err = take(64 * 4);
-    L.tiles = take(((size_t)ceil_div(n, kTile) + 1) * PP_NUM_BINS * 4);
+    const size_t tiles = std::max<size_t>((size_t)ceil_div(n, kTile) * kMaxKeys, (size_t)ceil_div(n, kScanTile) + 1);
+    L.tiles = take(tiles * 4);
+    L.keys = take(nn);
+    if (relabel) {
+        L.perm = take(nn * 4);
+        L.iperm = take(nn * 4);
+        L.r_csr_off = take((nn + 1) * 4);
+        L.r_csr_idx = take(nz * 4);
+        if (!aliased) {
+            L.r_csc_off = take((nn + 1) * 4);
+            L.r_csc_idx = take(nz * 4);
+        }
+        if (weighted) L.r_csr_w = take(nz * 4);
+    }
     L.total = p;
     return L;
 }
@@ -236,47 +381,43 @@ static void make_plan(BinPlan& p, const int32_t* counts, int32_t split_chunks) {
     p.total_blocks = at;
 }
 
-}  // namespace pp
-
-using namespace pp;
-
-PP_EXPORT int pp_abi_version(void) { return PP_ABI_VERSION; }
-
-PP_EXPORT const char* pp_last_error(void) { return g_last_error.c_str(); }
-
-PP_EXPORT size_t pp_graph_workspace_bytes(int32_t n, int64_t nnz, uint32_t flags) {
-    if (n < 1 || nnz < 0 || nnz > INT32_MAX) return 0;
-    return layout(n, nnz, flags, tuning()).total;
-}
-
-PP_EXPORT pp_status pp_set_bin_thresholds(const int32_t* upper5, int32_t split_chunk) {
-    if (!upper5) return set_error(PP_E_NULL, "upper5 is NULL");
-    for (int i = 0; i < PP_NUM_BINS - 1; ++i) {
-        if (upper5[i] < 0 || (i > 0 && upper5[i] < upper5[i - 1]))
-            return set_error(PP_E_RANGE, "bin thresholds must be non-negative and non-decreasing");
+// Stable partition of the vertices by key (keys already computed); writes
+// list[] and, when host_totals is given, the per-key totals (host).
+static pp_status partition(int32_t n, int nkeys, const uint8_t* keys, int32_t* tile_counts, int32_t* dev_totals,
+                           int32_t* list, int32_t* host_totals, hipStream_t st) {
+    const int32_t tiles = ceil_div(n, kTile);
+    hipLaunchKernelGGL(k_part_count, dim3(tiles), dim3(kTile), 0, st, n, nkeys, keys, tile_counts);
+    hipLaunchKernelGGL(k_part_scan, dim3(1), dim3(1024), 0, st, tiles, nkeys, tile_counts, dev_totals);
+    hipLaunchKernelGGL(k_part_scatter, dim3(tiles), dim3(kTile), 0, st, n, nkeys, keys, tile_counts, list);
+    PP_LAUNCH_CHECK("vertex partition");
+    if (host_totals) {
+        PP_HIP(hipMemcpyAsync(host_totals, dev_totals, sizeof(int32_t) * nkeys, hipMemcpyDeviceToHost, st));
+        PP_HIP(hipStreamSynchronize(st));
     }
-    if (split_chunk < kBlock) return set_error(PP_E_RANGE, "split_chunk must be at least 256");
-    for (int i = 0; i < PP_NUM_BINS - 1; ++i) tuning().upper[i] = upper5[i];
-    tuning().split_chunk = split_chunk;
     return PP_OK;
 }
 
-namespace pp {
+static pp_status exclusive_scan(int32_t n, const int32_t* in, int32_t* out, int32_t* tsum, int32_t* total,
+                                hipStream_t st) {
+    const int32_t tiles = std::max(ceil_div(n, kScanTile), 1);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(256), 0, st, n, in, out, tsum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, tiles, tsum, total);
+    hipLaunchKernelGGL(k_scan_add, dim3(ceil_div((int64_t)n + 1, 256)), dim3(256), 0, st, n, out, tsum, total);
+    PP_LAUNCH_CHECK("exclusive scan");
+    return PP_OK;
+}
+
+// Degree-binned vertex list and plan for one adjacency array; for bin 5 also
+// the chunk table (built on the host from the bin-5 rows).
 static pp_status bins_for(pp_graph g, const int32_t* off, int32_t* list, int32_t* tab, int32_t split_cap,
-                          int32_t* tile_counts, BinPlan& plan, int32_t& entries, hipStream_t st) {
+                          int32_t* tile_counts, uint8_t* keys, BinPlan& plan, int32_t& entries, hipStream_t st) {
     const int32_t n = g->d.n;
-    const int32_t tiles = ceil_div(n, kTile);
     BinBounds bb;
     for (int i = 0; i < PP_NUM_BINS - 1; ++i) bb.upper[i] = g->tune.upper[i];
-    int32_t* totals = g->d.err + 8;
-    hipLaunchKernelGGL(k_bin_count, dim3(tiles), dim3(kTile), 0, st, n, off, bb, tile_counts);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, tiles, tile_counts, totals);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(tiles), dim3(kTile), 0, st, n, off, bb, tile_counts, list);
-    PP_LAUNCH_CHECK("degree binning");
+    hipLaunchKernelGGL(k_bin_keys, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, off, bb, keys);
     int32_t counts[PP_NUM_BINS];
-    PP_HIP(hipMemcpyAsync(counts, totals, sizeof(counts), hipMemcpyDeviceToHost, st));
-    PP_HIP(hipStreamSynchronize(st));
-    // bin 5: split every row into chunks of split_chunk edges (host-built table)
+    pp_status s = partition(n, PP_NUM_BINS, keys, tile_counts, g->d.err + 8, list, counts, st);
+    if (s != PP_OK) return s;
     const int32_t n5 = counts[5];
     std::vector<int32_t> verts(n5), offs((size_t)2 * n5);
     if (n5 > 0) {
@@ -315,9 +456,70 @@ static pp_status bins_for(pp_graph g, const int32_t* off, int32_t* list, int32_t
     make_plan(plan, counts, entries);
     return PP_OK;
 }
+
+static pp_status check_arrays(int32_t n, int64_t nnz, const int32_t* off, const int32_t* idx, int32_t* err,
+                              int32_t* host, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, 2, err);
+    hipLaunchKernelGGL(k_check_offsets, dim3(ceil_div((int64_t)n + 1, 256)), dim3(256), 0, st, n, nnz, off, err);
+    if (nnz > 0) hipLaunchKernelGGL(k_check_indices, dim3(ceil_div(nnz, 256)), dim3(256), 0, st, n, nnz, idx, err);
+    PP_LAUNCH_CHECK("graph check");
+    PP_HIP(hipMemcpyAsync(host, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    PP_HIP(hipStreamSynchronize(st));
+    return PP_OK;
+}
+
+static pp_status check_graph(pp_graph g, hipStream_t st) {
+    const GraphDev& d = g->d;
+    int32_t h[4] = {0, 0, 0, 0};
+    pp_status s = check_arrays(d.n, d.nnz, d.user_csr_off, d.user_csr_idx, d.err, h, st);
+    if (s != PP_OK) return s;
+    if (d.user_csc_off != d.user_csr_off || d.user_csc_idx != d.user_csr_idx) {
+        s = check_arrays(d.n, d.nnz, d.user_csc_off, d.user_csc_idx, d.err, h + 2, st);
+        if (s != PP_OK) return s;
+    }
+    if (h[0] || h[2]) return set_error(PP_E_GRAPH, "offsets are not monotone from 0 to nnz");
+    if (h[1] || h[3]) return set_error(PP_E_GRAPH, "an index lies outside [0, n)");
+    return PP_OK;
+}
+
+constexpr uint32_t kKnownFlags = PP_GRAPH_WEIGHTED | PP_GRAPH_RELABEL;
+
 }  // namespace pp
 
-PP_EXPORT pp_status pp_graph_check(pp_graph g, void* stream);
+using namespace pp;
+
+PP_EXPORT int pp_abi_version(void) { return PP_ABI_VERSION; }
+
+PP_EXPORT const char* pp_last_error(void) { return g_last_error.c_str(); }
+
+PP_EXPORT size_t pp_graph_workspace_bytes(int32_t n, int64_t nnz, uint32_t flags) {
+    if (n < 1 || nnz < 0 || nnz > INT32_MAX) return 0;
+    if (flags & ~kKnownFlags) return 0;
+    // sized for distinct CSR and CSC arrays, which also covers the aliased case
+    return layout(n, nnz, flags, tuning(), false).total;
+}
+
+PP_EXPORT pp_status pp_set_bin_thresholds(const int32_t* upper5, int32_t split_chunk) {
+    clear_error();
+    if (!upper5) return set_error(PP_E_NULL, "upper5 is NULL");
+    for (int i = 0; i < PP_NUM_BINS - 1; ++i) {
+        if (upper5[i] < 0 || (i > 0 && upper5[i] < upper5[i - 1]))
+            return set_error(PP_E_RANGE, "bin thresholds must be non-negative and non-decreasing");
+    }
+    if (split_chunk < kBlock) return set_error(PP_E_RANGE, "split_chunk must be at least 256");
+    for (int i = 0; i < PP_NUM_BINS - 1; ++i) tuning().upper[i] = upper5[i];
+    tuning().split_chunk = split_chunk;
+    return PP_OK;
+}
+
+PP_EXPORT pp_status pp_set_push_tuning(int32_t hot, int32_t push_blocks) {
+    clear_error();
+    if (hot < 0 || hot > kHotMax) return set_error(PP_E_RANGE, "hot must lie in [0, 16384]");
+    if (push_blocks < 1 || push_blocks > 65536) return set_error(PP_E_RANGE, "push_blocks must lie in [1, 65536]");
+    tuning().hot = hot;
+    tuning().push_blocks = push_blocks;
+    return PP_OK;
+}
 
 PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_off, const int32_t* csr_idx,
                                     const int32_t* csc_off, const int32_t* csc_idx, const float* csr_w,
@@ -331,11 +533,13 @@ PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_o
     if (!csr_off || !csc_off || !ws) return set_error(PP_E_NULL, "csr_off, csc_off and ws are required");
     if (nnz > 0 && (!csr_idx || !csc_idx)) return set_error(PP_E_NULL, "csr_idx and csc_idx are required when nnz > 0");
     const bool weighted = (flags & PP_GRAPH_WEIGHTED) != 0;
+    const bool relabel = (flags & PP_GRAPH_RELABEL) != 0;
     if (weighted && nnz > 0 && (!csr_w || !csc_to_csr))
         return set_error(PP_E_NULL, "weighted graph needs csr_w and csc_to_csr");
-    if (flags & ~PP_GRAPH_WEIGHTED) return set_error(PP_E_UNSUPPORTED, "unknown graph flag");
+    if (flags & ~kKnownFlags) return set_error(PP_E_UNSUPPORTED, "unknown graph flag");
+    const bool aliased = (csc_off == csr_off) && (csc_idx == csr_idx);
     const Tuning t = tuning();
-    const WsLayout L = layout(n, nnz, flags, t);
+    const WsLayout L = layout(n, nnz, flags, t, aliased);
     if (ws_bytes < L.total) return set_error(PP_E_WORKSPACE, "graph workspace too small");
     if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return set_error(PP_E_RANGE, "workspace must be 256-byte aligned");
 
@@ -343,92 +547,147 @@ PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_o
     if (!g) return set_error(PP_E_SIZE, "host allocation of the graph handle failed");
     g->flags = flags;
     g->weighted = weighted;
+    g->relabelled = relabel;
     g->tune = t;
     char* base = static_cast<char*>(ws);
+    auto at = [&](size_t off) { return static_cast<void*>(base + off); };
     GraphDev& d = g->d;
     d.n = n;
     d.nnz = nnz;
+    d.user_csr_off = csr_off;
+    d.user_csr_idx = csr_idx;
+    d.user_csc_off = csc_off;
+    d.user_csc_idx = csc_idx;
     d.csr_off = csr_off;
     d.csr_idx = csr_idx;
     d.csc_off = csc_off;
     d.csc_idx = csc_idx;
     d.csr_w = weighted ? csr_w : nullptr;
-    d.inv_s = reinterpret_cast<float*>(base + L.inv_s);
-    d.out_deg = reinterpret_cast<int32_t*>(base + L.out_deg);
-    d.pull_list = reinterpret_cast<int32_t*>(base + L.pull_list);
-    d.push_list = reinterpret_cast<int32_t*>(base + L.push_list);
-    d.buf0 = reinterpret_cast<float*>(base + L.buf0);
-    d.buf1 = reinterpret_cast<float*>(base + L.buf1);
-    d.buf2 = reinterpret_cast<float*>(base + L.buf2);
-    d.csc_w = weighted ? reinterpret_cast<float*>(base + L.csc_w) : nullptr;
-    d.split_tab = reinterpret_cast<int32_t*>(base + L.split_tab);
-    d.split_part = reinterpret_cast<float*>(base + L.split_part);
-    d.err = reinterpret_cast<int32_t*>(base + L.err);
-    int32_t* tile_counts = reinterpret_cast<int32_t*>(base + L.tiles);
+    d.perm = d.iperm = nullptr;
+    d.inv_s = static_cast<float*>(at(L.inv_s));
+    d.out_deg = static_cast<int32_t*>(at(L.out_deg));
+    d.pull_list = static_cast<int32_t*>(at(L.pull_list));
+    d.push_list = static_cast<int32_t*>(at(L.push_list));
+    d.buf0 = static_cast<float*>(at(L.buf0));
+    d.buf1 = static_cast<float*>(at(L.buf1));
+    d.buf2 = static_cast<float*>(at(L.buf2));
+    d.csc_w = weighted ? static_cast<float*>(at(L.csc_w)) : nullptr;
+    d.split_tab = static_cast<int32_t*>(at(L.split_tab));
+    d.split_part = static_cast<float*>(at(L.split_part));
+    d.hot_part = static_cast<float*>(at(L.hot_part));
+    d.err = static_cast<int32_t*>(at(L.err));
+    int32_t* tiles = static_cast<int32_t*>(at(L.tiles));
+    uint8_t* keys = static_cast<uint8_t*>(at(L.keys));
     hipStream_t st = static_cast<hipStream_t>(stream);
 
     auto fail = [&](pp_status s) {
         delete g;
         return s;
     };
-    {
-        // The sweeps trust the arrays, so malformed ones are rejected here.
-        pp_status s = pp_graph_check(g, stream);
+    // The sweeps trust the arrays, so malformed ones are rejected here.
+    pp_status s = check_graph(g, st);
+    if (s != PP_OK) return fail(s);
+
+    if (relabel) {
+        int32_t* perm = static_cast<int32_t*>(at(L.perm));
+        int32_t* iperm = static_cast<int32_t*>(at(L.iperm));
+        const dim3 vb(ceil_div(n, 256)), vt(256);
+        hipLaunchKernelGGL(k_relabel_keys, vb, vt, 0, st, n, csr_off, csc_off, keys);
+        s = partition(n, kMaxKeys, keys, tiles, d.err + 8, perm, nullptr, st);
         if (s != PP_OK) return fail(s);
-    }
-    hipLaunchKernelGGL(k_degrees, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, csr_off, d.csr_w, d.out_deg, d.inv_s);
-    if (weighted && nnz > 0)
+        hipLaunchKernelGGL(k_invert_perm, vb, vt, 0, st, n, perm, iperm);
+        int32_t* r_off = static_cast<int32_t*>(at(L.r_csr_off));
+        int32_t* r_idx = static_cast<int32_t*>(at(L.r_csr_idx));
+        int32_t* tmp_deg = d.out_deg;  // scratch until k_degrees fills it
+        float* r_w = weighted ? static_cast<float*>(at(L.r_csr_w)) : nullptr;
+        const int32_t row_blocks = std::max(std::min<int32_t>(ceil_div(n, 4), 16384), 1);
+        hipLaunchKernelGGL(k_perm_degrees, vb, vt, 0, st, n, perm, csr_off, tmp_deg);
+        s = exclusive_scan(n, tmp_deg, r_off, tiles, d.err + 40, st);
+        if (s != PP_OK) return fail(s);
+        hipLaunchKernelGGL(k_relabel_rows, dim3(row_blocks), dim3(256), 0, st, n, perm, iperm, csr_off, csr_idx,
+                           r_off, r_idx, csr_w, (const int32_t*)nullptr, r_w);
+        d.csr_off = r_off;
+        d.csr_idx = r_idx;
+        d.csr_w = r_w;
+        if (aliased) {
+            d.csc_off = r_off;
+            d.csc_idx = r_idx;
+            if (weighted)  // same slots as the CSR rows; weights arrive through the slot map
+                hipLaunchKernelGGL(k_relabel_rows, dim3(row_blocks), dim3(256), 0, st, n, perm, iperm, csc_off,
+                                   csc_idx, r_off, (int32_t*)nullptr, csr_w, csc_to_csr, d.csc_w);
+        } else {
+            int32_t* rc_off = static_cast<int32_t*>(at(L.r_csc_off));
+            int32_t* rc_idx = static_cast<int32_t*>(at(L.r_csc_idx));
+            hipLaunchKernelGGL(k_perm_degrees, vb, vt, 0, st, n, perm, csc_off, tmp_deg);
+            s = exclusive_scan(n, tmp_deg, rc_off, tiles, d.err + 40, st);
+            if (s != PP_OK) return fail(s);
+            hipLaunchKernelGGL(k_relabel_rows, dim3(row_blocks), dim3(256), 0, st, n, perm, iperm, csc_off, csc_idx,
+                               rc_off, rc_idx, csr_w, csc_to_csr, d.csc_w);
+            d.csc_off = rc_off;
+            d.csc_idx = rc_idx;
+        }
+        PP_LAUNCH_CHECK("relabel");
+        d.perm = perm;
+        d.iperm = iperm;
+    } else if (weighted && nnz > 0) {
         hipLaunchKernelGGL(k_gather_weights, dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz, csr_w, csc_to_csr,
                            d.csc_w);
+    }
+    hipLaunchKernelGGL(k_degrees, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, d.csr_off, d.csr_w, d.out_deg,
+                       d.inv_s);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, 2, d.err + 48);
+    hipLaunchKernelGGL(k_max_deg, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, d.csr_off, d.csc_off, d.err + 48);
     {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(hip_error(e, "graph degree kernels"));
     }
+    int32_t maxd[2];
+    {
+        hipError_t e = hipMemcpyAsync(maxd, d.err + 48, sizeof(maxd), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(hip_error(e, "reading degrees"));
+    }
+    g->max_out_deg = maxd[0];
+    g->max_in_deg = maxd[1];
     const int32_t cap = L.split_cap;
     g->split_cap = cap;
     int32_t* tab_pull = d.split_tab;
     int32_t* tab_push = d.split_tab + 4 * (size_t)cap + 1;
-    pp_status s = bins_for(g, csc_off, d.pull_list, tab_pull, cap, tile_counts, g->pull_plan, g->split_pull_entries, st);
+    s = bins_for(g, d.csc_off, d.pull_list, tab_pull, cap, tiles, keys, g->pull_plan, g->split_pull_entries, st);
     if (s != PP_OK) return fail(s);
-    s = bins_for(g, csr_off, d.push_list, tab_push, cap, tile_counts, g->push_plan, g->split_push_entries, st);
+    s = bins_for(g, d.csr_off, d.push_list, tab_push, cap, tiles, keys, g->push_plan, g->split_push_entries, st);
     if (s != PP_OK) return fail(s);
     *out = g;
     return PP_OK;
 }
 
 PP_EXPORT pp_status pp_graph_destroy(pp_graph g) {
+    clear_error();
     if (!g) return set_error(PP_E_NULL, "graph handle is NULL");
     delete g;
     return PP_OK;
 }
 
 PP_EXPORT pp_status pp_graph_bins(pp_graph g, pp_dir dir, int32_t* counts) {
+    clear_error();
     if (!g || !counts) return set_error(PP_E_NULL, "graph or counts is NULL");
-    const BinPlan& p = (dir == PP_PUSH) ? g->push_plan : g->pull_plan;
     if (dir != PP_PUSH && dir != PP_PULL) return set_error(PP_E_RANGE, "dir must be PP_PUSH or PP_PULL");
+    const BinPlan& p = (dir == PP_PUSH) ? g->push_plan : g->pull_plan;
     for (int b = 0; b < PP_NUM_BINS; ++b) counts[b] = p.count[b];
+    return PP_OK;
+}
+
+PP_EXPORT pp_status pp_graph_relabel_map(pp_graph g, int32_t* perm, void* stream) {
+    clear_error();
+    if (!g || !perm) return set_error(PP_E_NULL, "graph or perm is NULL");
+    if (!g->relabelled) return set_error(PP_E_UNSUPPORTED, "graph was registered without PP_GRAPH_RELABEL");
+    PP_HIP(hipMemcpyAsync(perm, g->d.perm, sizeof(int32_t) * g->d.n, hipMemcpyDeviceToDevice,
+                          static_cast<hipStream_t>(stream)));
     return PP_OK;
 }
 
 PP_EXPORT pp_status pp_graph_check(pp_graph g, void* stream) {
     clear_error();
     if (!g) return set_error(PP_E_NULL, "graph handle is NULL");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const GraphDev& d = g->d;
-    int32_t h[4] = {0, 0, 0, 0};
-    for (int pass = 0; pass < 2; ++pass) {
-        const int32_t* off = pass ? d.csc_off : d.csr_off;
-        const int32_t* idx = pass ? d.csc_idx : d.csr_idx;
-        PP_HIP(hipMemsetAsync(d.err, 0, 2 * sizeof(int32_t), st));
-        hipLaunchKernelGGL(k_check_offsets, dim3(ceil_div((int64_t)d.n + 1, 256)), dim3(256), 0, st, d.n, d.nnz, off,
-                           d.err);
-        if (d.nnz > 0)
-            hipLaunchKernelGGL(k_check_indices, dim3(ceil_div(d.nnz, 256)), dim3(256), 0, st, d.n, d.nnz, idx, d.err);
-        PP_LAUNCH_CHECK("graph check");
-        PP_HIP(hipMemcpyAsync(h + 2 * pass, d.err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        PP_HIP(hipStreamSynchronize(st));
-    }
-    if (h[0] || h[2]) return set_error(PP_E_GRAPH, "offsets are not monotone from 0 to nnz");
-    if (h[1] || h[3]) return set_error(PP_E_GRAPH, "an index lies outside [0, n)");
-    return PP_OK;
+    return check_graph(g, static_cast<hipStream_t>(stream));
 }

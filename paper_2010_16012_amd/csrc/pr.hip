@@ -1,14 +1,18 @@
 // PageRank power-iteration step in its pulling and pushing forms
 // (Sec. 3.1 equation; Sec. 4.1 listing, pushing and pulling lines).
 //
-// Both forms run over degree-binned vertex lists in ONE launch per sweep:
-// workgroups [block_off[b], block_off[b+1]) serve bin b, heaviest bin first.
-// A vertex of bin b is owned by kBinLanes[b] lanes (1, 4, 16, a wavefront,
-// a workgroup); bin 5 rows are cut into chunks of split_chunk edges.
+// Work is described by degree-binned vertex lists: bin b owns a contiguous
+// range of work units, heaviest bin first.  A vertex of bin b is owned by
+// kBinLanes[b] lanes (1, 4, 16, a wavefront, a workgroup); bin 5 rows are
+// cut into chunks of split_chunk edges.
 //
-// The contribution vector c[v] = f * x[v] / s(v) (s = out-degree or
-// out-strength) is produced by the previous step's epilogue, so a gather
-// reads ONE float per edge instead of the neighbour's rank and degree.
+// The contribution c[v] = f * x[v] / s(v) (s = out-degree or out-strength)
+// is produced by the previous step's epilogue, so a gather reads ONE float
+// per edge instead of the neighbour's rank and degree.
+//
+// Vectors the caller sees (x, y) are in caller ids; c, the push accumulator
+// and everything per-edge are in internal ids (equal to caller ids unless the
+// graph was relabelled): the first gather and the last write go through perm.
 #include <hip/hip_runtime.h>
 
 #include "pp_common.h"
@@ -29,8 +33,8 @@ static SweepPlan sweep_plan(const BinPlan& p) {
     return s;
 }
 
-// Which bin does this workgroup serve?  Launch order is bin 5, 4, ..., 0.
-__device__ __forceinline__ int block_bin(const SweepPlan& sp, int32_t blk) {
+// Which bin does work unit `blk` belong to?  Units run bin 5, 4, ..., 0.
+__device__ __forceinline__ int unit_bin(const SweepPlan& sp, int32_t blk) {
     int b = PP_NUM_BINS - 1;
 #pragma unroll
     for (int i = PP_NUM_BINS - 1; i > 0; --i)
@@ -56,7 +60,8 @@ __device__ __forceinline__ float block_reduce(float v, float* red) {
 #pragma unroll
         for (int i = 0; i < kBlock / kWave; ++i) t += red[i];
     }
-    return t;  // valid in thread 0
+    __syncthreads();  // red[] may be reused right after
+    return t;         // valid in thread 0
 }
 
 // Sum of c[idx[j]] (times the slot weight) over j = b + lane, b + lane + G, ...
@@ -86,6 +91,7 @@ __device__ __forceinline__ float gather_row(const int32_t* __restrict__ idx, con
     return a0 + a1;
 }
 
+// ------------------------------------------------------------------ pull
 struct PullArgs {
     SweepPlan sp;
     const int32_t* off;    // CSC offsets
@@ -97,16 +103,17 @@ struct PullArgs {
     float* part;           // bin-5 partial sums
     const float* c;        // contributions of the current iterate
     const float* inv_s;
+    const int32_t* perm;   // internal -> caller id (nullable)
     float* c_next;         // contributions of the new iterate (nullable)
-    float* y;              // new iterate (nullable)
+    float* y;              // new iterate, caller ids (nullable)
     float base;            // (1-f)/n
     float f;
 };
 
-// Owner of u writes y[u] = base + acc and the next contribution.
+// Owner of u writes y = base + acc and the next contribution.
 __device__ __forceinline__ void pull_finish(const PullArgs& a, int32_t u, float acc) {
     const float yv = a.base + acc;
-    if (a.y) a.y[u] = yv;
+    if (a.y) a.y[user_id(a.perm, u)] = yv;
     if (a.c_next) a.c_next[u] = a.f * yv * a.inv_s[u];
 }
 
@@ -124,11 +131,12 @@ __device__ __forceinline__ void pull_group(const PullArgs& a, int bin, int32_t l
     if (lane == 0) pull_finish(a, u, acc);
 }
 
+// One workgroup per work unit.  No atomics: every output has one writer.
 template <bool W>
 __global__ __launch_bounds__(kBlock) void k_pr_pull(PullArgs a) {
     __shared__ float red[kBlock / kWave];
     const int32_t blk = blockIdx.x;
-    const int bin = block_bin(a.sp, blk);
+    const int bin = unit_bin(a.sp, blk);
     const int32_t lb = blk - a.sp.block_off[bin];
     switch (bin) {
         case 5: {  // one chunk of a very long row -> partial sum, finished by k_pr_pull_fix
@@ -162,6 +170,7 @@ __global__ void k_pr_pull_fix(PullArgs a, int32_t nsplit) {
     pull_finish(a, a.tab[first[i]], acc);
 }
 
+// ------------------------------------------------------------------ push
 struct PushArgs {
     SweepPlan sp;
     const int32_t* off;    // CSR offsets
@@ -170,88 +179,128 @@ struct PushArgs {
     const int32_t* list;   // vertices grouped by out-degree bin
     const int32_t* tab;
     int32_t tab_cap;
+    int32_t units;         // work units (= blocks of the one-shot layout)
+    int32_t hot;           // targets below this id go to LDS first
+    float* hot_part;       // [gridDim.x][hot] per-workgroup partial sums
     const float* c;        // contributions
-    float* y;              // accumulator, pre-set to (1-f)/n
+    float* y;              // accumulator (internal ids), pre-set to (1-f)/n
 };
 
-// Scatter c[v] (times the slot weight) to every out-neighbour with FP32
-// atomic adds (global_atomic_add_f32, result unused).
-template <int G, bool W>
-__device__ __forceinline__ void scatter_row(const PushArgs& a, float cv, int32_t b, int32_t e, int lane) {
+// Adds val to target u: LDS for privatised (hot) targets, else a global FP32
+// atomic add (global_atomic_add_f32, result unused).
+template <bool HOT>
+__device__ __forceinline__ void push_to(const PushArgs& a, float* s_hot, int32_t u, float val) {
+    if (HOT && u < a.hot) atomicAdd(&s_hot[u], val);
+    else unsafeAtomicAdd(&a.y[u], val);
+}
+
+template <int G, bool W, bool HOT>
+__device__ __forceinline__ void scatter_row(const PushArgs& a, float* s_hot, float cv, int32_t b, int32_t e,
+                                            int lane) {
     int32_t j = b + lane;
     for (; j + G < e; j += 2 * G) {
         const int32_t u0 = a.idx[j], u1 = a.idx[j + G];
-        unsafeAtomicAdd(&a.y[u0], W ? cv * a.wt[j] : cv);
-        unsafeAtomicAdd(&a.y[u1], W ? cv * a.wt[j + G] : cv);
+        push_to<HOT>(a, s_hot, u0, W ? cv * a.wt[j] : cv);
+        push_to<HOT>(a, s_hot, u1, W ? cv * a.wt[j + G] : cv);
     }
-    if (j < e) unsafeAtomicAdd(&a.y[a.idx[j]], W ? cv * a.wt[j] : cv);
+    if (j < e) push_to<HOT>(a, s_hot, a.idx[j], W ? cv * a.wt[j] : cv);
 }
 
-template <int G, bool W>
-__device__ __forceinline__ void push_group(const PushArgs& a, int bin, int32_t local_blk) {
+template <int G, bool W, bool HOT>
+__device__ __forceinline__ void push_group(const PushArgs& a, float* s_hot, int bin, int32_t local_blk) {
     constexpr int per_block = kBlock / G;
     const int32_t i = local_blk * per_block + threadIdx.x / G;
     const int lane = threadIdx.x & (G - 1);
     const int32_t count = a.sp.list_off[bin + 1] - a.sp.list_off[bin];
-    if (i >= count) return;
-    const int32_t v = a.list[a.sp.list_off[bin] + i];
-    const float cv = a.c[v];
-    if (cv == 0.f) return;  // nothing to pass on
-    scatter_row<G, W>(a, cv, a.off[v], a.off[v + 1], lane);
-}
-
-template <bool W>
-__global__ __launch_bounds__(kBlock) void k_pr_push(PushArgs a) {
-    const int32_t blk = blockIdx.x;
-    const int bin = block_bin(a.sp, blk);
-    const int32_t lb = blk - a.sp.block_off[bin];
-    switch (bin) {
-        case 5: {
-            const int32_t v = a.tab[lb];
-            const int32_t b = a.tab[a.tab_cap + lb], e = a.tab[2 * a.tab_cap + lb];
-            const float cv = a.c[v];
-            if (cv != 0.f) scatter_row<kBlock, W>(a, cv, b, e, threadIdx.x);
-            break;
-        }
-        case 4: {
-            const int32_t v = a.list[a.sp.list_off[4] + lb];
-            const float cv = a.c[v];
-            if (cv != 0.f) scatter_row<kBlock, W>(a, cv, a.off[v], a.off[v + 1], threadIdx.x);
-            break;
-        }
-        case 3: push_group<64, W>(a, 3, lb); break;
-        case 2: push_group<16, W>(a, 2, lb); break;
-        case 1: push_group<4, W>(a, 1, lb); break;
-        default: push_group<1, W>(a, 0, lb); break;
+    if (i < count) {
+        const int32_t v = a.list[a.sp.list_off[bin] + i];
+        const float cv = a.c[v];
+        if (cv != 0.f) scatter_row<G, W, HOT>(a, s_hot, cv, a.off[v], a.off[v + 1], lane);
     }
 }
 
-// c[u] = f * x[u] / s(u); optionally y[u] = base (the push accumulator).
-__global__ void k_pr_prologue(int32_t n, const float* __restrict__ x, const float* __restrict__ inv_s, float f,
-                              float* __restrict__ c, float* __restrict__ y_init, float base) {
+// Persistent: workgroup b takes units b, b + gridDim.x, ...  With HOT, LDS
+// holds this workgroup's sums for targets [0, hot), written out at the end.
+template <bool W, bool HOT>
+__global__ __launch_bounds__(kBlock) void k_pr_push(PushArgs a) {
+    extern __shared__ float s_hot[];
+    if (HOT) {
+        for (int32_t i = threadIdx.x; i < a.hot; i += kBlock) s_hot[i] = 0.f;
+        __syncthreads();
+    }
+    for (int32_t unit = blockIdx.x; unit < a.units; unit += gridDim.x) {
+        const int bin = unit_bin(a.sp, unit);
+        const int32_t lb = unit - a.sp.block_off[bin];
+        switch (bin) {
+            case 5: {
+                const int32_t v = a.tab[lb];
+                const int32_t b = a.tab[a.tab_cap + lb], e = a.tab[2 * a.tab_cap + lb];
+                const float cv = a.c[v];
+                if (cv != 0.f) scatter_row<kBlock, W, HOT>(a, s_hot, cv, b, e, threadIdx.x);
+                break;
+            }
+            case 4: {
+                const int32_t v = a.list[a.sp.list_off[4] + lb];
+                const float cv = a.c[v];
+                if (cv != 0.f) scatter_row<kBlock, W, HOT>(a, s_hot, cv, a.off[v], a.off[v + 1], threadIdx.x);
+                break;
+            }
+            case 3: push_group<64, W, HOT>(a, s_hot, 3, lb); break;
+            case 2: push_group<16, W, HOT>(a, s_hot, 2, lb); break;
+            case 1: push_group<4, W, HOT>(a, s_hot, 1, lb); break;
+            default: push_group<1, W, HOT>(a, s_hot, 0, lb); break;
+        }
+    }
+    if (HOT) {
+        __syncthreads();
+        float* dst = a.hot_part + (size_t)blockIdx.x * a.hot;
+        for (int32_t i = threadIdx.x; i < a.hot; i += kBlock) dst[i] = s_hot[i];
+    }
+}
+
+// y[u] += sum over workgroups of their LDS partials, u < hot (one writer per
+// u; fixed summation order).  Block: 64 targets x 4 partial-row groups.
+__global__ __launch_bounds__(256) void k_pr_push_hot_reduce(int32_t hot, int32_t parts,
+                                                            const float* __restrict__ hot_part,
+                                                            float* __restrict__ y) {
+    __shared__ float s[4][64];
+    const int32_t u = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int r = threadIdx.x >> 6;
+    float acc = 0.f;
+    if (u < hot)
+        for (int32_t b = r; b < parts; b += 4) acc += hot_part[(size_t)b * hot + u];
+    s[r][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (r == 0 && u < hot) y[u] += (s[0][threadIdx.x] + s[1][threadIdx.x]) + (s[2][threadIdx.x] + s[3][threadIdx.x]);
+}
+
+// c[u] = f * x[caller id of u] / s(u); optionally y[u] = base (push accumulator).
+__global__ void k_pr_prologue(int32_t n, const float* __restrict__ x, const int32_t* __restrict__ perm,
+                              const float* __restrict__ inv_s, float f, float* __restrict__ c,
+                              float* __restrict__ y_init, float base) {
     const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
-    c[u] = f * x[u] * inv_s[u];
+    c[u] = f * x[user_id(perm, u)] * inv_s[u];
     if (y_init) y_init[u] = base;
 }
 
 // After a push sweep: c[u] = f * y[u] / s(u); reset the other accumulator to
-// base; copy the iterate out on the last step.
+// base; copy the iterate out (caller ids) on the last step.
 __global__ void k_pr_push_epilogue(int32_t n, const float* __restrict__ y, const float* __restrict__ inv_s, float f,
                                    float* __restrict__ c, float* __restrict__ y_reset, float base,
-                                   float* __restrict__ x_out) {
+                                   float* __restrict__ x_out, const int32_t* __restrict__ perm) {
     const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
     const float yv = y[u];
-    c[u] = f * yv * inv_s[u];
+    if (c) c[u] = f * yv * inv_s[u];
     if (y_reset) y_reset[u] = base;
-    if (x_out) x_out[u] = yv;
+    if (x_out) x_out[user_id(perm, u)] = yv;
 }
 
 // ------------------------------------------------------------------ launchers
 static float teleport(int32_t n, float f) { return (float)((1.0 - (double)f) / (double)n); }
 
-static PullArgs pull_args(pp_graph g, const float* c, float* c_next, float* y, float f) {
+pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float f, hipStream_t st) {
     PullArgs a;
     a.sp = sweep_plan(g->pull_plan);
     a.off = g->d.csc_off;
@@ -263,19 +312,11 @@ static PullArgs pull_args(pp_graph g, const float* c, float* c_next, float* y, f
     a.part = g->d.split_part;
     a.c = c;
     a.inv_s = g->d.inv_s;
+    a.perm = g->d.perm;
     a.c_next = c_next;
     a.y = y;
     a.base = teleport(g->d.n, f);
     a.f = f;
-    return a;
-}
-
-}  // namespace pp
-
-namespace pp {
-
-pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float f, hipStream_t st) {
-    PullArgs a = pull_args(g, c, c_next, y, f);
     const int32_t blocks = g->pull_plan.total_blocks;
     if (blocks > 0) {
         if (g->weighted) hipLaunchKernelGGL(k_pr_pull<true>, dim3(blocks), dim3(kBlock), 0, st, a);
@@ -287,6 +328,7 @@ pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float
     return PP_OK;
 }
 
+// Accumulates the push sweep of c into y (internal ids, pre-set to base).
 pp_status launch_push(pp_graph g, const float* c, float* y, hipStream_t st) {
     PushArgs a;
     a.sp = sweep_plan(g->push_plan);
@@ -296,13 +338,24 @@ pp_status launch_push(pp_graph g, const float* c, float* y, hipStream_t st) {
     a.list = g->d.push_list;
     a.tab_cap = g->split_cap;
     a.tab = g->d.split_tab + 4 * (size_t)a.tab_cap + 1;
+    a.units = g->push_plan.total_blocks;
+    a.hot = std::min(g->tune.hot, g->d.n);
+    a.hot_part = g->d.hot_part;
     a.c = c;
     a.y = y;
-    const int32_t blocks = g->push_plan.total_blocks;
-    if (blocks > 0) {
-        if (g->weighted) hipLaunchKernelGGL(k_pr_push<true>, dim3(blocks), dim3(kBlock), 0, st, a);
-        else hipLaunchKernelGGL(k_pr_push<false>, dim3(blocks), dim3(kBlock), 0, st, a);
+    if (a.units == 0) return PP_OK;
+    const int32_t grid = std::min(a.units, g->tune.push_blocks);
+    const bool hot = a.hot > 0;
+    const size_t lds = hot ? (size_t)a.hot * sizeof(float) : 0;
+    if (g->weighted) {
+        if (hot) hipLaunchKernelGGL((k_pr_push<true, true>), dim3(grid), dim3(kBlock), lds, st, a);
+        else hipLaunchKernelGGL((k_pr_push<true, false>), dim3(grid), dim3(kBlock), 0, st, a);
+    } else {
+        if (hot) hipLaunchKernelGGL((k_pr_push<false, true>), dim3(grid), dim3(kBlock), lds, st, a);
+        else hipLaunchKernelGGL((k_pr_push<false, false>), dim3(grid), dim3(kBlock), 0, st, a);
     }
+    if (hot) hipLaunchKernelGGL(k_pr_push_hot_reduce, dim3(ceil_div(a.hot, 64)), dim3(256), 0, st, a.hot, grid,
+                                (const float*)a.hot_part, y);
     PP_LAUNCH_CHECK("k_pr_push");
     return PP_OK;
 }
@@ -325,8 +378,8 @@ PP_EXPORT pp_status pp_pr_pull(pp_graph g, const float* x, float* y, float f, vo
     if (s != PP_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int32_t n = g->d.n;
-    hipLaunchKernelGGL(k_pr_prologue, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, x, g->d.inv_s, f, g->d.buf0,
-                       (float*)nullptr, 0.f);
+    hipLaunchKernelGGL(k_pr_prologue, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, x, g->d.perm, g->d.inv_s, f,
+                       g->d.buf0, (float*)nullptr, 0.f);
     PP_LAUNCH_CHECK("k_pr_prologue");
     return launch_pull(g, g->d.buf0, nullptr, y, f, st);
 }
@@ -337,10 +390,16 @@ PP_EXPORT pp_status pp_pr_push(pp_graph g, const float* x, float* y, float f, vo
     if (s != PP_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int32_t n = g->d.n;
-    hipLaunchKernelGGL(k_pr_prologue, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, x, g->d.inv_s, f, g->d.buf0, y,
+    const dim3 vb(ceil_div(n, 256)), vt(256);
+    hipLaunchKernelGGL(k_pr_prologue, vb, vt, 0, st, n, x, g->d.perm, g->d.inv_s, f, g->d.buf0, g->d.buf1,
                        teleport(n, f));
     PP_LAUNCH_CHECK("k_pr_prologue");
-    return launch_push(g, g->d.buf0, y, st);
+    s = launch_push(g, g->d.buf0, g->d.buf1, st);
+    if (s != PP_OK) return s;
+    hipLaunchKernelGGL(k_pr_push_epilogue, vb, vt, 0, st, n, (const float*)g->d.buf1, g->d.inv_s, f, (float*)nullptr,
+                       (float*)nullptr, 0.f, y, g->d.perm);
+    PP_LAUNCH_CHECK("k_pr_push_epilogue");
+    return PP_OK;
 }
 
 PP_EXPORT pp_status pp_pr_run(pp_graph g, pp_dir dir, int32_t iters, float f, float* x_inout, void* stream) {
@@ -358,8 +417,8 @@ PP_EXPORT pp_status pp_pr_run(pp_graph g, pp_dir dir, int32_t iters, float f, fl
     if (dir == PP_PULL) {
         float* c = g->d.buf0;
         float* cn = g->d.buf1;
-        hipLaunchKernelGGL(k_pr_prologue, vb, vt, 0, st, n, (const float*)x_inout, g->d.inv_s, f, c, (float*)nullptr,
-                           0.f);
+        hipLaunchKernelGGL(k_pr_prologue, vb, vt, 0, st, n, (const float*)x_inout, g->d.perm, g->d.inv_s, f, c,
+                           (float*)nullptr, 0.f);
         PP_LAUNCH_CHECK("k_pr_prologue");
         for (int32_t t = 0; t < iters; ++t) {
             const bool last = (t == iters - 1);
@@ -374,14 +433,14 @@ PP_EXPORT pp_status pp_pr_run(pp_graph g, pp_dir dir, int32_t iters, float f, fl
     float* c = g->d.buf0;
     float* ya = g->d.buf1;
     float* yb = g->d.buf2;
-    hipLaunchKernelGGL(k_pr_prologue, vb, vt, 0, st, n, (const float*)x_inout, g->d.inv_s, f, c, ya, base);
+    hipLaunchKernelGGL(k_pr_prologue, vb, vt, 0, st, n, (const float*)x_inout, g->d.perm, g->d.inv_s, f, c, ya, base);
     PP_LAUNCH_CHECK("k_pr_prologue");
     for (int32_t t = 0; t < iters; ++t) {
         const bool last = (t == iters - 1);
         pp_status s = launch_push(g, c, ya, st);
         if (s != PP_OK) return s;
-        hipLaunchKernelGGL(k_pr_push_epilogue, vb, vt, 0, st, n, (const float*)ya, g->d.inv_s, f, c,
-                           last ? nullptr : yb, base, last ? x_inout : nullptr);
+        hipLaunchKernelGGL(k_pr_push_epilogue, vb, vt, 0, st, n, (const float*)ya, g->d.inv_s, f,
+                           last ? nullptr : c, last ? nullptr : yb, base, last ? x_inout : nullptr, g->d.perm);
         PP_LAUNCH_CHECK("k_pr_push_epilogue");
         float* tmp = ya;
         ya = yb;

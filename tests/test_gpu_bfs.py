@@ -28,8 +28,14 @@ def _run(g, root, policy):
     return r.level.cpu().numpy(), r.parent.cpu().numpy(), st
 
 
-def _check(host, roots, policies=POLICIES, fast=False):
-    g = pp.Graph(host)
+def _check(host, roots, policies=POLICIES, fast=False, relabel=(True, False)):
+    for rl in relabel:
+        g = pp.Graph(host, relabel=rl)
+        _check_graph(g, host, roots, policies, fast)
+        g.close()
+
+
+def _check_graph(g, host, roots, policies, fast):
     for root in roots:
         want, _, nlev = oracle.bfs(host.off, host.idx, int(root))
         for pol, name in zip(POLICIES, POL_IDS):
@@ -44,7 +50,6 @@ def _check(host, roots, policies=POLICIES, fast=False):
             assert st.reached == int((want >= 0).sum())
             deg = np.diff(host.off)
             assert st.edges_reached == int(deg[want >= 0].sum())
-    g.close()
 
 
 @pytest.mark.parametrize("maker", [lambda: H.path(300), lambda: H.star(100), lambda: H.cycle(129),
@@ -61,6 +66,15 @@ def test_rmat14_from_vertex0_and_random_roots():
     _check(host, roots)
 
 
+def test_long_rows_take_the_chunked_top_down_pass():
+    # rows longer than 1024 edges go through the second top-down kernel
+    host = H.star(5000)
+    _check(host, [0, 17])
+    host = gg.from_edges(9002, np.concatenate([np.zeros(3000), np.ones(3000), np.arange(2, 3002)]),
+                         np.concatenate([np.arange(2, 3002), np.arange(3002, 6002), np.arange(6002, 9002)]), True)
+    _check(host, [0, 1, 5000])
+
+
 def test_disconnected_isolated_root_and_ragged():
     host = gg.from_edges(1000, np.arange(0, 400), np.arange(1, 401), True)  # a path 0..400, rest isolated
     _check(host, [0, 200, 999])
@@ -75,9 +89,10 @@ def test_directed_graphs_td_uses_out_bu_uses_in(seed):
     _check(host, [0, 17])
 
 
-def test_step_api_any_direction_sequence():
+@pytest.mark.parametrize("relabel", [True, False])
+def test_step_api_any_direction_sequence(relabel):
     host = gg.workload("rmat14")
-    g = pp.Graph(host)
+    g = pp.Graph(host, relabel=relabel)
     want, _, nlev = oracle.bfs(host.off, host.idx, 0)
     rng = np.random.default_rng(4)
     for trial in range(4):
@@ -99,10 +114,11 @@ def test_step_api_any_direction_sequence():
         assert np.array_equal(r.level.cpu().numpy(), want)
 
 
-def test_bottom_up_parents_are_first_in_stored_order():
+@pytest.mark.parametrize("relabel", [True, False])
+def test_bottom_up_parents_are_first_in_stored_order(relabel):
     # pull scans in-neighbours in stored order and stops at the first frontier member
     host = gg.workload("rmat14")
-    g = pp.Graph(host)
+    g = pp.Graph(host, relabel=relabel)
     want, _, _ = oracle.bfs(host.off, host.idx, 0)
     lv, par, _ = _run(g, 0, pp.PP_PULL)
     for v in np.nonzero(want > 0)[0][:2000]:
@@ -133,12 +149,13 @@ def test_rmat22_roots():
     roots = gg.pick_vertices(host, 64, seed=1)
     announce(f"BFS rmat22 nnz={host.nnz}")
     # every policy on a few roots, the switch policy on more
-    _check(host, roots[:2], fast=True)
-    _check(host, roots[2:6], policies=[pp.PP_SWITCH], fast=True)
+    _check(host, roots[:2], fast=True, relabel=(True,))
+    _check(host, roots[2:6], policies=[pp.PP_SWITCH], fast=True, relabel=(True,))
+    _check(host, roots[6:7], fast=True, relabel=(False,))
 
 
 @pytest.mark.slow
 def test_grid4096_corner_many_levels():
     host = gg.workload("grid4096")
     announce(f"BFS grid n={host.n}")
-    _check(host, [0], policies=[pp.PP_PUSH, pp.PP_SWITCH], fast=True)
+    _check(host, [0], policies=[pp.PP_PUSH, pp.PP_SWITCH], fast=True, relabel=(True,))
