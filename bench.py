@@ -93,12 +93,14 @@ def main():
     roots = gg.pick_vertices(host, args.roots, seed=1)
     print(f"# graph rmat{args.scale}: n={n} nnz={nnz} generated in {time.time() - t_gen:.1f}s", flush=True)
     # edges of each root's component, from the host graph (independent of the GPU path)
-    A = sp.csr_matrix((np.ones(nnz, dtype=np.int8), host.idx, host.off), shape=(n, n))
-    ncomp, comp = csg.connected_components(A, directed=False)
-    deg = np.diff(host.off)
-    comp_edges = np.bincount(comp, weights=deg, minlength=ncomp)
-    root_edges = comp_edges[comp[roots]] / 2.0
-    del A
+    root_edges = np.zeros(len(roots))
+    if any(p.startswith("bfs_") for p in parts):
+        A = sp.csr_matrix((np.ones(nnz, dtype=np.int8), host.idx, host.off), shape=(n, n))
+        ncomp, comp = csg.connected_components(A, directed=False)
+        deg = np.diff(host.off)
+        comp_edges = np.bincount(comp, weights=deg, minlength=ncomp)
+        root_edges = comp_edges[comp[roots]] / 2.0
+        del A
 
     t_up = time.time()
     g = pp.Graph(host, device=dev)

@@ -115,7 +115,7 @@ pp_status pp_graph_bins(pp_graph g, pp_dir dir, int32_t* counts);
 
 /* Degree thresholds of the bins (upper bounds of bins 0..4; bin 5 is the
  * rest) and the split chunk for the longest rows.  Defaults: 4, 16, 64, 1024,
- * 16384; chunk 16384.  Takes effect at the next pp_graph_create. */
+ * 4096; chunk 4096.  Takes effect at the next pp_graph_create. */
 pp_status pp_set_bin_thresholds(const int32_t* upper5, int32_t split_chunk);
 
 /* Push-sweep tuning: the first `hot` vertices (internal ids) are accumulated
@@ -125,6 +125,14 @@ pp_status pp_set_bin_thresholds(const int32_t* upper5, int32_t split_chunk);
  * [0, 16384] (0 disables), push_blocks in [1, 65536].  Takes effect at the
  * next pp_graph_create. */
 pp_status pp_set_push_tuning(int32_t hot, int32_t push_blocks);
+
+/* Pull-sweep tuning: each workgroup of the persistent pull sweep stages the
+ * contributions of the first `pull_hot` vertices (internal ids; with
+ * PP_GRAPH_RELABEL the heaviest ones, which most gathers hit) in LDS, capped
+ * by the LDS one workgroup may use; pull_block threads per workgroup (256,
+ * 512 or 1024).  Defaults 32768 and 1024.  Takes effect at the next
+ * pp_graph_create. */
+pp_status pp_set_pull_tuning(int32_t pull_hot, int32_t pull_block);
 
 /* --------------------------------------------------------------- PageRank */
 /* One Jacobi step of the PageRank equation (Sec. 3.1):

@@ -66,6 +66,7 @@ _SIGS = {
     "pp_graph_bins": ([_P, ctypes.c_int, ctypes.POINTER(_I32)], ctypes.c_int),
     "pp_set_bin_thresholds": ([ctypes.POINTER(_I32), _I32], ctypes.c_int),
     "pp_set_push_tuning": ([_I32, _I32], ctypes.c_int),
+    "pp_set_pull_tuning": ([_I32, _I32], ctypes.c_int),
     "pp_graph_relabel_map": ([_P, _P, _P], ctypes.c_int),
     "pp_pr_push": ([_P, _P, _P, _F32, _P], ctypes.c_int),
     "pp_pr_pull": ([_P, _P, _P, _F32, _P], ctypes.c_int),
@@ -160,6 +161,10 @@ def pp_set_bin_thresholds(upper5, split_chunk: int) -> None:
 
 def pp_set_push_tuning(hot: int, push_blocks: int) -> None:
     _check(_lib.pp_set_push_tuning(hot, push_blocks))
+
+
+def pp_set_pull_tuning(pull_hot: int, pull_block: int) -> None:
+    _check(_lib.pp_set_pull_tuning(pull_hot, pull_block))
 
 
 def pp_graph_relabel_map(h, perm, stream=None) -> None:

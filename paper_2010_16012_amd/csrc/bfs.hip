@@ -27,6 +27,7 @@ namespace pp {
 
 constexpr int32_t kPage = 256;      // queue entries per page
 constexpr int32_t kBigRow = 1024;   // top-down rows longer than this are chunked
+constexpr int32_t kBigInRow = 2048; // bottom-up in-rows longer than this are chunked
 constexpr int kBfsMaxBlocks = 1024;
 
 struct BfsSlot {
@@ -54,7 +55,7 @@ struct BfsHdr {
 };
 
 struct BfsLayout {
-    size_t hdr, queue0, queue1, fill0, fill1, fb0, fb1, fb2, visited, items, total;
+    size_t hdr, queue0, queue1, fill0, fill1, fb0, fb1, fb2, visited, items, best, total;
     int32_t words, blocks, page_cap, item_cap;
 };
 
@@ -74,7 +75,7 @@ static BfsLayout bfs_layout(int32_t n, int64_t nnz) {
     // full pages hold at most n entries; each wavefront of each of the two
     // kernels of a level leaves at most one partial page
     L.page_cap = ceil_div(n, kPage) + 2 * waves + 2;
-    L.item_cap = (int32_t)std::min<int64_t>(2 * nnz / kBigRow + 64, INT32_MAX / 4);
+    L.item_cap = (int32_t)std::min<int64_t>(2 * nnz / std::min(kBigRow, kBigInRow) + 64, INT32_MAX / 4);
     L.hdr = take(sizeof(BfsHdr));
     L.queue0 = take((size_t)L.page_cap * kPage * 4);
     L.queue1 = take((size_t)L.page_cap * kPage * 4);
@@ -85,6 +86,7 @@ static BfsLayout bfs_layout(int32_t n, int64_t nnz) {
     L.fb2 = take((size_t)L.words * 8);
     L.visited = take((size_t)L.words * 8);
     L.items = take((size_t)L.item_cap * 3 * 4);
+    L.best = take((size_t)n * 4);
     L.total = p;
     return L;
 }
@@ -108,7 +110,8 @@ struct BfsArgs {
     int32_t* fill[2];
     uint64_t* fb[3];
     uint64_t* visited;
-    int32_t* items;         // (v, begin, end) chunk items of long top-down rows
+    int32_t* items;         // (v, begin, end) chunk items of long rows
+    int32_t* best;          // bottom-up: first hit position in a long in-row (INT32_MAX: none)
 };
 
 static BfsArgs bfs_args(pp_graph g, void* state, int32_t* level, int32_t* parent) {
@@ -138,6 +141,7 @@ static BfsArgs bfs_args(pp_graph g, void* state, int32_t* level, int32_t* parent
     a.fb[2] = reinterpret_cast<uint64_t*>(s + L.fb2);
     a.visited = reinterpret_cast<uint64_t*>(s + L.visited);
     a.items = reinterpret_cast<int32_t*>(s + L.items);
+    a.best = reinterpret_cast<int32_t*>(s + L.best);
     return a;
 }
 
@@ -234,6 +238,7 @@ __global__ void k_bfs_init(BfsArgs a, int32_t root_user, int64_t nnz) {
     for (int32_t v = t; v < a.n; v += stride) {
         a.level[v] = (v == root_user) ? 0 : -1;
         a.parent[v] = (v == root_user) ? root_user : -1;
+        a.best[v] = INT32_MAX;
     }
     const uint64_t rbit = 1ull << (root & 63);
     for (int32_t w = t; w < a.words; w += stride) {
@@ -259,6 +264,33 @@ __global__ void k_bfs_init(BfsArgs a, int32_t root_user, int64_t nnz) {
         h->overflow = 0;
         h->reached = 0;
         h->edges = 0;
+    }
+}
+
+// Queues (v, begin, end) chunk items of `chunk` edges for the lanes with
+// `huge` set.  Wave-collective; one counter atomic per call.
+__device__ __forceinline__ void queue_chunks(const BfsArgs& a, bool huge, int32_t v, int32_t rb, int32_t re,
+                                             int32_t chunk, BfsSlot* nxt, int lane) {
+    const int32_t nch = huge ? (re - rb + chunk - 1) / chunk : 0;
+    int32_t incl = nch;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
+    }
+    const int32_t tot = __shfl(incl, kWave - 1);
+    int32_t base = 0;
+    if (lane == 0) base = atomicAdd(&nxt->big, tot);
+    base = __shfl(base, 0);
+    for (int32_t k = 0; k < nch; ++k) {
+        const int32_t it = base + incl - nch + k;
+        if (it < a.item_cap) {
+            a.items[3 * it] = v;
+            a.items[3 * it + 1] = rb + k * chunk;
+            a.items[3 * it + 2] = min(re, rb + (k + 1) * chunk);
+        } else {
+            atomicOr(&a.hdr->overflow, 2);
+        }
     }
 }
 
@@ -316,32 +348,9 @@ __device__ void level_top_down(const BfsArgs& a, const TdCtx& cx, const int32_t*
             int32_t len = re - rb;
             // very long rows: queue chunks for the second kernel
             const bool huge = len > kBigRow;
-            const uint64_t hm = __ballot(huge);
-            if (hm) {
-                const int32_t nch = huge ? (len + kBigRow - 1) / kBigRow : 0;
-                int32_t incl = nch;
-#pragma unroll
-                for (int d = 1; d < kWave; d <<= 1) {
-                    const int32_t y = __shfl_up(incl, d);
-                    if (lane >= d) incl += y;
-                }
-                const int32_t tot = __shfl(incl, kWave - 1);
-                int32_t base = 0;
-                if (lane == 0) base = atomicAdd(&cx.nxt->big, tot);
-                base = __shfl(base, 0);
-                if (huge) {
-                    for (int32_t k = 0; k < nch; ++k) {
-                        const int32_t it = base + incl - nch + k;
-                        if (it < a.item_cap) {
-                            a.items[3 * it] = v;
-                            a.items[3 * it + 1] = rb + k * kBigRow;
-                            a.items[3 * it + 2] = min(re, rb + (k + 1) * kBigRow);
-                        } else {
-                            atomicOr(&a.hdr->overflow, 2);
-                        }
-                    }
-                    len = 0;
-                }
+            if (__ballot(huge)) {
+                queue_chunks(a, huge, v, rb, re, kBigRow, cx.nxt, lane);
+                if (huge) len = 0;
             }
             // medium rows: the whole wave walks one row at a time
             uint64_t big = __ballot(len >= kWave);
@@ -400,9 +409,15 @@ __device__ void level_bottom_up(const BfsArgs& a, int32_t lvl, const uint64_t* f
         const bool unvisited = (v < a.n) && !((vis >> lane) & 1ull);
         if (__ballot(unvisited) == 0) continue;
         const int32_t rb = unvisited ? a.csc_off[v] : 0;
-        const int32_t re = unvisited ? a.csc_off[v + 1] : 0;
+        int32_t re = unvisited ? a.csc_off[v + 1] : 0;
         bool found = false;
         int32_t par = -1;
+        // very long in-rows: chunks scanned grid-wide by k_bfs_bu_big
+        const bool huge = (re - rb) > kBigInRow;
+        if (__ballot(huge)) {
+            queue_chunks(a, huge, v, rb, re, kBigInRow, nxt, lane);
+            if (huge) re = rb;
+        }
         // long in-rows: the wave scans 64 in-neighbours at a time, stops at the first hit
         const bool coop = (re - rb) >= 32;
         uint64_t big = __ballot(coop);
@@ -514,6 +529,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a, int32_t lvl, in
 __global__ __launch_bounds__(kBlock) void k_bfs_td_big(BfsArgs a, int32_t lvl) {
     BfsHdr* h = a.hdr;
     const int sn = (lvl + 1) % 3;
+    if (h->slot[sn].dir_prev != PP_PUSH) return;
     const int32_t items = min(h->slot[sn].big, a.item_cap);
     if (items == 0) return;
     const int lane = threadIdx.x & (kWave - 1);
@@ -534,6 +550,82 @@ __global__ __launch_bounds__(kBlock) void k_bfs_td_big(BfsArgs a, int32_t lvl) {
     flush_stats(cnt, deg, &h->slot[sn]);
 }
 
+// Bottom-up pass over the chunks of very long in-rows, one wavefront per
+// chunk: the first frontier member in a chunk lowers best[v] to its slot.
+// A chunk stops early once an earlier slot of the same row has a hit.
+__global__ __launch_bounds__(kBlock) void k_bfs_bu_big(BfsArgs a, int32_t lvl) {
+    BfsHdr* h = a.hdr;
+    const int sc = lvl % 3, sn = (lvl + 1) % 3;
+    if (h->slot[sn].dir_prev != PP_PULL) return;
+    const int32_t items = min(h->slot[sn].big, a.item_cap);
+    const uint64_t* fb_cur = a.fb[sc];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t gwave = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int32_t nwaves = gridDim.x * (kBlock / kWave);
+    for (int32_t it = gwave; it < items; it += nwaves) {
+        const int32_t v = a.items[3 * it], b = a.items[3 * it + 1], e = a.items[3 * it + 2];
+        for (int32_t jb = b; jb < e; jb += kWave) {
+            if (__shfl(lane == 0 ? a.best[v] : 0, 0) < jb) break;  // an earlier slot already hit
+            const int32_t j = jb + lane;
+            const int32_t u = (j < e) ? a.csc_idx[j] : -1;
+            const bool hit = (u >= 0) && ((fb_cur[u >> 6] >> (u & 63)) & 1ull);
+            const uint64_t hm = __ballot(hit);
+            if (hm) {
+                if (lane == 0) atomicMin(&a.best[v], jb + __ffsll((long long)hm) - 1);
+                break;
+            }
+        }
+    }
+}
+
+// Finishes the long in-row vertices: one item per vertex (its first chunk)
+// records the parent at best[v], sets the bitmaps and appends the vertex.
+__global__ __launch_bounds__(kBlock) void k_bfs_bu_fin(BfsArgs a, int32_t lvl) {
+    BfsHdr* h = a.hdr;
+    const int sn = (lvl + 1) % 3;
+    if (h->slot[sn].dir_prev != PP_PULL) return;
+    const int32_t items = min(h->slot[sn].big, a.item_cap);
+    if (items == 0) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    int32_t cnt = 0;
+    int64_t deg = 0;
+    Pager pg{-1, 0};
+    int32_t* q_next = a.queue[(lvl + 1) & 1];
+    int32_t* fill_next = a.fill[(lvl + 1) & 1];
+    const int32_t nthreads = gridDim.x * blockDim.x;
+    const int32_t t0 = blockIdx.x * blockDim.x + threadIdx.x;
+    // wave-uniform trip count so page_append stays wave-collective
+    const int32_t trips = (items + nthreads - 1) / nthreads;
+    for (int32_t r = 0; r < trips; ++r) {
+        const int32_t it = t0 + r * nthreads;
+        bool found = false;
+        int32_t v = -1;
+        if (it < items) {
+            v = a.items[3 * it];
+            if (a.items[3 * it + 1] == a.csc_off[v]) {  // first chunk of v
+                const int32_t pos = a.best[v];
+                if (pos != INT32_MAX) {
+                    found = true;
+                    const int32_t vu = user_id(a.perm, v);
+                    a.level[vu] = lvl + 1;
+                    a.parent[vu] = user_id(a.perm, a.csc_idx[pos]);
+                    const uint64_t bit = 1ull << (v & 63);
+                    atomicOr(reinterpret_cast<unsigned long long*>(&a.visited[v >> 6]), (unsigned long long)bit);
+                    atomicOr(reinterpret_cast<unsigned long long*>(&a.fb[sn][v >> 6]), (unsigned long long)bit);
+                    a.best[v] = INT32_MAX;
+                    cnt += 1;
+                    deg += a.out_deg[v];
+                }
+            }
+        }
+        const uint64_t fm = __ballot(found);
+        if (fm) page_append(a, pg, found, v, __popcll(fm & lanes_below(lane)), __popcll(fm), q_next, fill_next,
+                            &h->slot[sn], lane);
+    }
+    page_close(pg, fill_next, lane);
+    flush_stats(cnt, deg, &h->slot[sn]);
+}
+
 static pp_status check_state(pp_graph g, void* state, size_t bytes) {
     if (!g) return set_error(PP_E_NULL, "graph handle is NULL");
     if (!state) return set_error(PP_E_NULL, "state is NULL");
@@ -548,6 +640,10 @@ static pp_status launch_level(pp_graph g, const BfsArgs& a, int32_t lvl, int32_t
     hipLaunchKernelGGL(k_bfs_level, dim3(blocks), dim3(kBlock), 0, st, a, lvl, policy, alpha, beta);
     if (policy != PP_PULL && g->max_out_deg > kBigRow)
         hipLaunchKernelGGL(k_bfs_td_big, dim3(blocks), dim3(kBlock), 0, st, a, lvl);
+    if (policy != PP_PUSH && g->max_in_deg > kBigInRow) {
+        hipLaunchKernelGGL(k_bfs_bu_big, dim3(blocks), dim3(kBlock), 0, st, a, lvl);
+        hipLaunchKernelGGL(k_bfs_bu_fin, dim3(blocks), dim3(kBlock), 0, st, a, lvl);
+    }
     PP_LAUNCH_CHECK("k_bfs_level");
     return PP_OK;
 }

@@ -379,6 +379,16 @@ static void make_plan(BinPlan& p, const int32_t* counts, int32_t split_chunks) {
     }
     p.block_off[PP_NUM_BINS] = at;  // unused sentinel
     p.total_blocks = at;
+    int32_t waves[PP_NUM_BINS];
+    waves[5] = split_chunks;
+    for (int b = 0; b < PP_NUM_BINS - 1; ++b) waves[b] = ceil_div(counts[b], kWave / kPullLanes[b]);
+    at = 0;
+    for (int b = PP_NUM_BINS - 1; b >= 0; --b) {
+        p.wave_off[b] = at;
+        at += waves[b];
+    }
+    p.wave_off[PP_NUM_BINS] = at;
+    p.total_wave_units = at;
 }
 
 // Stable partition of the vertices by key (keys already computed); writes
@@ -507,6 +517,8 @@ PP_EXPORT pp_status pp_set_bin_thresholds(const int32_t* upper5, int32_t split_c
             return set_error(PP_E_RANGE, "bin thresholds must be non-negative and non-decreasing");
     }
     if (split_chunk < kBlock) return set_error(PP_E_RANGE, "split_chunk must be at least 256");
+    if (upper5[PP_NUM_BINS - 2] < upper5[PP_NUM_BINS - 3])
+        return set_error(PP_E_RANGE, "bin thresholds must be non-decreasing");
     for (int i = 0; i < PP_NUM_BINS - 1; ++i) tuning().upper[i] = upper5[i];
     tuning().split_chunk = split_chunk;
     return PP_OK;
@@ -518,6 +530,16 @@ PP_EXPORT pp_status pp_set_push_tuning(int32_t hot, int32_t push_blocks) {
     if (push_blocks < 1 || push_blocks > 65536) return set_error(PP_E_RANGE, "push_blocks must lie in [1, 65536]");
     tuning().hot = hot;
     tuning().push_blocks = push_blocks;
+    return PP_OK;
+}
+
+PP_EXPORT pp_status pp_set_pull_tuning(int32_t pull_hot, int32_t pull_block) {
+    clear_error();
+    if (pull_hot < 0 || pull_hot > (1 << 20)) return set_error(PP_E_RANGE, "pull_hot must lie in [0, 2^20]");
+    if (pull_block != 256 && pull_block != 512 && pull_block != 1024)
+        return set_error(PP_E_RANGE, "pull_block must be 256, 512 or 1024");
+    tuning().pull_hot = pull_hot;
+    tuning().pull_block = pull_block;
     return PP_OK;
 }
 
@@ -649,6 +671,18 @@ PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_o
     }
     g->max_out_deg = maxd[0];
     g->max_in_deg = maxd[1];
+    {
+        int dev = 0, cus = 0, lds = 0, lds_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+        if (e != hipSuccess) return fail(hip_error(e, "device attributes"));
+        g->num_cu = std::max(cus, 1);
+        g->max_lds = lds;
+        g->lds_per_cu = std::max(lds_cu, lds);
+    }
     const int32_t cap = L.split_cap;
     g->split_cap = cap;
     int32_t* tab_pull = d.split_tab;

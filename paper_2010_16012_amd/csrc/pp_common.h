@@ -20,15 +20,23 @@ constexpr int kBlock = 256;  // threads per workgroup for the sweep kernels
 //   bin 4: one workgroup   bin 5: the row is split into chunks, one workgroup each
 constexpr int kBinLanes[PP_NUM_BINS] = {1, 4, 16, 64, kBlock, kBlock};
 
+// The persistent pull sweep gives each row fewer lanes and each lane more
+// loads in flight: lanes per row and loads per lane for bins 0..5 (bin 5 =
+// one split chunk).  A wavefront therefore keeps 64 / lanes rows in flight.
+constexpr int kPullLanes[PP_NUM_BINS] = {1, 1, 4, 16, 64, 64};
+constexpr int kPullLoads[PP_NUM_BINS] = {4, 16, 16, 16, 16, 16};
+
 // Push privatisation: the first kHotMax internal vertices can be accumulated
 // in LDS by each workgroup of the persistent push sweep.
 constexpr int kHotMax = 16384;
 
 struct Tuning {
-    int32_t upper[PP_NUM_BINS - 1] = {4, 16, 64, 1024, 16384};
-    int32_t split_chunk = 16384;
+    int32_t upper[PP_NUM_BINS - 1] = {4, 16, 64, 1024, 4096};
+    int32_t split_chunk = 4096;
     int32_t hot = 8192;          // vertices privatised in LDS by the push sweep (0 = off)
     int32_t push_blocks = 1024;  // workgroups of the persistent push sweep
+    int32_t pull_hot = 32768;    // contributions staged in LDS by the pull sweep (0 = off)
+    int32_t pull_block = 1024;   // threads per workgroup of the persistent pull sweep
 };
 Tuning& tuning();
 
@@ -40,6 +48,10 @@ struct BinPlan {
     int32_t block_off[PP_NUM_BINS + 1] = {}; // first work unit of each bin (launch order)
     int32_t split_chunks = 0;                // units used by bin 5
     int32_t total_blocks = 0;
+    // the same work cut into wavefront-sized units (bins 3 and 4: one row per
+    // wavefront; bin 5: one chunk per wavefront), heaviest bin first
+    int32_t wave_off[PP_NUM_BINS + 1] = {};
+    int32_t total_wave_units = 0;
 };
 
 struct GraphDev {
@@ -91,6 +103,9 @@ struct pp_graph_s {
     int32_t split_cap;           // capacity of each split table
     int32_t max_out_deg;
     int32_t max_in_deg;
+    int32_t num_cu;              // compute units of the device the graph lives on
+    int32_t max_lds;             // LDS bytes one workgroup may allocate
+    int32_t lds_per_cu;          // LDS bytes of one compute unit
     pp::Tuning tune;
 };
 

@@ -65,35 +65,66 @@ __device__ __forceinline__ float block_reduce(float v, float* red) {
 }
 
 // Sum of c[idx[j]] (times the slot weight) over j = b + lane, b + lane + G, ...
-// Four independent gathers in flight per lane.
-template <int G, bool W>
+// U index loads and then U gathers are issued back to back per lane (indices
+// past the row end are clamped to its last slot and their values masked), so
+// a row of up to U*G edges costs two dependent memory round trips.
+// With HOT, entries below `hot` are read from the LDS copy s_c of c.
+template <int G, int U, bool W, bool HOT = false>
 __device__ __forceinline__ float gather_row(const int32_t* __restrict__ idx, const float* __restrict__ wt,
-                                            const float* __restrict__ c, int32_t b, int32_t e, int lane) {
-    float a0 = 0.f, a1 = 0.f;
-    int32_t j = b + lane;
-    for (; j + 3 * G < e; j += 4 * G) {
-        const int32_t i0 = idx[j], i1 = idx[j + G], i2 = idx[j + 2 * G], i3 = idx[j + 3 * G];
-        float v0 = c[i0], v1 = c[i1], v2 = c[i2], v3 = c[i3];
-        if (W) {
-            v0 *= wt[j];
-            v1 *= wt[j + G];
-            v2 *= wt[j + 2 * G];
-            v3 *= wt[j + 3 * G];
+                                            const float* __restrict__ c, int32_t b, int32_t e, int lane,
+                                            const float* s_c = nullptr, int32_t hot = 0) {
+    float acc[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) acc[k] = 0.f;
+    for (int32_t j0 = b + lane; j0 < e; j0 += U * G) {
+        int32_t jj[U], ii[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) jj[k] = min(j0 + k * G, e - 1);
+#pragma unroll
+        for (int k = 0; k < U; ++k) ii[k] = idx[jj[k]];
+        float v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (HOT) {
+                // Two separate loads: an LDS read (index clamped into the
+                // staged range) and a global load only on lanes that need
+                // it.  A single conditional load would be merged into a flat
+                // load, which occupies the vector-memory path even for LDS.
+                const float lv = s_c[min(ii[k], hot - 1)];
+                float gv = 0.f;
+                if (ii[k] >= hot) gv = c[ii[k]];
+                v[k] = (ii[k] < hot) ? lv : gv;
+            } else {
+                v[k] = c[ii[k]];
+            }
         }
-        a0 += v0 + v1;
-        a1 += v2 + v3;
+        if (W) {
+#pragma unroll
+            for (int k = 0; k < U; ++k) v[k] *= wt[jj[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) acc[k] += (j0 + k * G < e) ? v[k] : 0.f;
     }
-    for (; j < e; j += G) {
-        float v = c[idx[j]];
-        if (W) v *= wt[j];
-        a0 += v;
+#pragma unroll
+    for (int s = U / 2; s > 0; s >>= 1) {
+#pragma unroll
+        for (int k = 0; k < s; ++k) acc[k] += acc[k + s];
     }
-    return a0 + a1;
+    return acc[0];
+}
+
+// loads in flight per lane for a group of G lanes
+template <int G>
+constexpr int unroll_for() {
+    return G >= 64 ? 8 : 4;
 }
 
 // ------------------------------------------------------------------ pull
 struct PullArgs {
     SweepPlan sp;
+    int32_t wave_off[PP_NUM_BINS + 1];  // wavefront units per bin (persistent sweep)
+    int32_t units;
+    int32_t hot;           // contributions below this id are staged in LDS
     const int32_t* off;    // CSC offsets
     const int32_t* idx;    // CSC indices
     const float* wt;       // weights in CSC slot order (weighted only)
@@ -117,46 +148,60 @@ __device__ __forceinline__ void pull_finish(const PullArgs& a, int32_t u, float 
     if (a.c_next) a.c_next[u] = a.f * yv * a.inv_s[u];
 }
 
-template <int G, bool W>
-__device__ __forceinline__ void pull_group(const PullArgs& a, int bin, int32_t local_blk) {
-    constexpr int per_block = kBlock / G;
-    const int32_t i = local_blk * per_block + threadIdx.x / G;
-    const int lane = threadIdx.x & (G - 1);
-    const int32_t count = a.sp.list_off[bin + 1] - a.sp.list_off[bin];
-    if (i >= count) return;  // whole groups leave together
-    const int32_t u = a.list[a.sp.list_off[bin] + i];
-    const int32_t b = a.off[u], e = a.off[u + 1];
-    float acc = gather_row<G, W>(a.idx, a.wt, a.c, b, e, lane);
-    acc = group_reduce<G>(acc);
-    if (lane == 0) pull_finish(a, u, acc);
+// Which bin does wavefront unit `u` belong to?  Units run bin 5, 4, ..., 0.
+__device__ __forceinline__ int wave_unit_bin(const int32_t* wo, int32_t u) {
+    int b = PP_NUM_BINS - 1;
+#pragma unroll
+    for (int i = PP_NUM_BINS - 1; i > 0; --i)
+        if (u >= wo[i - 1]) b = i - 1;
+    return b;
 }
 
-// One workgroup per work unit.  No atomics: every output has one writer.
-template <bool W>
-__global__ __launch_bounds__(kBlock) void k_pr_pull(PullArgs a) {
-    __shared__ float red[kBlock / kWave];
-    const int32_t blk = blockIdx.x;
-    const int bin = unit_bin(a.sp, blk);
-    const int32_t lb = blk - a.sp.block_off[bin];
-    switch (bin) {
-        case 5: {  // one chunk of a very long row -> partial sum, finished by k_pr_pull_fix
-            const int32_t b = a.tab[a.tab_cap + lb], e = a.tab[2 * a.tab_cap + lb];
-            float acc = gather_row<kBlock, W>(a.idx, a.wt, a.c, b, e, threadIdx.x);
-            acc = block_reduce(acc, red);
-            if (threadIdx.x == 0) a.part[lb] = acc;
-            break;
+// Unit lu of bin `bin`: kWave/G rows, G lanes each, U loads per lane.
+template <int BIN, bool W, bool HOT>
+__device__ __forceinline__ void pull_unit(const PullArgs& a, int32_t lu, int lane, const float* s_c) {
+    constexpr int G = kPullLanes[BIN];
+    constexpr int U = kPullLoads[BIN];
+    const int32_t i = lu * (kWave / G) + lane / G;
+    const int32_t count = a.sp.list_off[BIN + 1] - a.sp.list_off[BIN];
+    if (i >= count) return;  // whole groups leave together
+    const int32_t u = a.list[a.sp.list_off[BIN] + i];
+    const int gl = lane & (G - 1);
+    float acc = gather_row<G, U, W, HOT>(a.idx, a.wt, a.c, a.off[u], a.off[u + 1], gl, s_c, a.hot);
+    acc = group_reduce<G>(acc);
+    if (gl == 0) pull_finish(a, u, acc);
+}
+
+// Persistent pull sweep: every workgroup first copies c[0, hot) -- the
+// contributions of the heaviest vertices, which most gathers hit -- into
+// LDS, then its wavefronts take units w, w + W, ... (W = wavefronts in the
+// grid).  No atomics: every output has exactly one writer.
+template <bool W, bool HOT>
+__global__ __launch_bounds__(1024) void k_pr_pull(PullArgs a) {
+    extern __shared__ float s_c[];
+    if (HOT) {
+        for (int32_t i = threadIdx.x; i < a.hot; i += blockDim.x) s_c[i] = a.c[i];
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t nw = gridDim.x * (blockDim.x / kWave);
+    for (int32_t unit = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; unit < a.units; unit += nw) {
+        const int bin = wave_unit_bin(a.wave_off, unit);
+        const int32_t lu = unit - a.wave_off[bin];
+        switch (bin) {
+            case 5: {  // one chunk of a very long row -> partial sum, finished by k_pr_pull_fix
+                const int32_t b = a.tab[a.tab_cap + lu], e = a.tab[2 * a.tab_cap + lu];
+                float acc = gather_row<kPullLanes[5], kPullLoads[5], W, HOT>(a.idx, a.wt, a.c, b, e, lane, s_c, a.hot);
+                acc = group_reduce<kWave>(acc);
+                if (lane == 0) a.part[lu] = acc;
+                break;
+            }
+            case 4: pull_unit<4, W, HOT>(a, lu, lane, s_c); break;
+            case 3: pull_unit<3, W, HOT>(a, lu, lane, s_c); break;
+            case 2: pull_unit<2, W, HOT>(a, lu, lane, s_c); break;
+            case 1: pull_unit<1, W, HOT>(a, lu, lane, s_c); break;
+            default: pull_unit<0, W, HOT>(a, lu, lane, s_c); break;
         }
-        case 4: {  // one workgroup per row
-            const int32_t u = a.list[a.sp.list_off[4] + lb];
-            float acc = gather_row<kBlock, W>(a.idx, a.wt, a.c, a.off[u], a.off[u + 1], threadIdx.x);
-            acc = block_reduce(acc, red);
-            if (threadIdx.x == 0) pull_finish(a, u, acc);
-            break;
-        }
-        case 3: pull_group<64, W>(a, 3, lb); break;
-        case 2: pull_group<16, W>(a, 2, lb); break;
-        case 1: pull_group<4, W>(a, 1, lb); break;
-        default: pull_group<1, W>(a, 0, lb); break;
     }
 }
 
@@ -194,16 +239,24 @@ __device__ __forceinline__ void push_to(const PushArgs& a, float* s_hot, int32_t
     else unsafeAtomicAdd(&a.y[u], val);
 }
 
+// U index loads issued back to back, then the U adds.
 template <int G, bool W, bool HOT>
 __device__ __forceinline__ void scatter_row(const PushArgs& a, float* s_hot, float cv, int32_t b, int32_t e,
                                             int lane) {
-    int32_t j = b + lane;
-    for (; j + G < e; j += 2 * G) {
-        const int32_t u0 = a.idx[j], u1 = a.idx[j + G];
-        push_to<HOT>(a, s_hot, u0, W ? cv * a.wt[j] : cv);
-        push_to<HOT>(a, s_hot, u1, W ? cv * a.wt[j + G] : cv);
+    constexpr int U = unroll_for<G>();
+    for (int32_t j0 = b + lane; j0 < e; j0 += U * G) {
+        int32_t jj[U], uu[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) jj[k] = min(j0 + k * G, e - 1);
+#pragma unroll
+        for (int k = 0; k < U; ++k) uu[k] = a.idx[jj[k]];
+        float val[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) val[k] = W ? cv * a.wt[jj[k]] : cv;
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (j0 + k * G < e) push_to<HOT>(a, s_hot, uu[k], val[k]);
     }
-    if (j < e) push_to<HOT>(a, s_hot, a.idx[j], W ? cv * a.wt[j] : cv);
 }
 
 template <int G, bool W, bool HOT>
@@ -317,10 +370,32 @@ pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float
     a.y = y;
     a.base = teleport(g->d.n, f);
     a.f = f;
-    const int32_t blocks = g->pull_plan.total_blocks;
-    if (blocks > 0) {
-        if (g->weighted) hipLaunchKernelGGL(k_pr_pull<true>, dim3(blocks), dim3(kBlock), 0, st, a);
-        else hipLaunchKernelGGL(k_pr_pull<false>, dim3(blocks), dim3(kBlock), 0, st, a);
+    for (int b = 0; b <= PP_NUM_BINS; ++b) a.wave_off[b] = g->pull_plan.wave_off[b];
+    a.units = g->pull_plan.total_wave_units;
+    const int32_t tpb = g->tune.pull_block;
+    const int32_t lds_cap = std::max(g->max_lds, 0) / (int32_t)sizeof(float);
+    a.hot = std::min(std::min(g->tune.pull_hot, g->d.n), lds_cap);
+    if (a.units > 0) {
+        // one workgroup per compute unit (more when they are small), never more than the work
+        const bool hot = a.hot > 0;
+        const size_t lds = hot ? (size_t)a.hot * sizeof(float) : 0;
+        // as many workgroups per compute unit as 32 wavefronts and the LDS allow
+        int32_t per_cu = std::max(2048 / tpb, 1);
+        if (lds > 0) per_cu = std::max(1, std::min<int32_t>(per_cu, (int32_t)(g->lds_per_cu / lds)));
+        const int32_t grid = std::max(1, std::min(g->num_cu * per_cu, ceil_div(a.units, tpb / kWave)));
+        if (lds > 65536) {  // allow the LDS beyond the default 64 KiB (no-op where not needed)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_pull<true, true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_pull<false, true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        }
+        if (g->weighted) {
+            if (hot) hipLaunchKernelGGL((k_pr_pull<true, true>), dim3(grid), dim3(tpb), lds, st, a);
+            else hipLaunchKernelGGL((k_pr_pull<true, false>), dim3(grid), dim3(tpb), 0, st, a);
+        } else {
+            if (hot) hipLaunchKernelGGL((k_pr_pull<false, true>), dim3(grid), dim3(tpb), lds, st, a);
+            else hipLaunchKernelGGL((k_pr_pull<false, false>), dim3(grid), dim3(tpb), 0, st, a);
+        }
     }
     const int32_t nsplit = g->pull_plan.count[5];
     if (nsplit > 0) hipLaunchKernelGGL(k_pr_pull_fix, dim3(ceil_div(nsplit, 64)), dim3(64), 0, st, a, nsplit);

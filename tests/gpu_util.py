@@ -11,7 +11,9 @@ PR_L1_TOL = 1e-6  # FP32 sweep vs FP64 oracle, L1 over the whole vector
 
 
 def default_bins():
-    _lib.pp_set_bin_thresholds([4, 16, 64, 1024, 16384], 16384)
+    _lib.pp_set_bin_thresholds([4, 16, 64, 1024, 4096], 4096)
+    _lib.pp_set_push_tuning(8192, 1024)
+    _lib.pp_set_pull_tuning(32768, 1024)
 
 
 def tiny_bins():

@@ -87,6 +87,21 @@ def test_push_privatisation_settings(hot, blocks):
         _lib.pp_set_push_tuning(8192, 1024)
 
 
+@pytest.mark.parametrize("hot,block", [(0, 1024), (1, 256), (300, 512), (1 << 20, 1024)])
+def test_pull_lds_staging_settings(hot, block):
+    # no staging, a single staged entry, a partial prefix, everything that fits in LDS
+    host = gg.workload("rmat14")
+    want = oracle.pagerank(host.off, host.idx, F, 20)
+    _lib.pp_set_pull_tuning(hot, block)
+    try:
+        for rl in (True, False):
+            g = pp.Graph(host, relabel=rl)
+            got = pr_gpu(g, pp.PP_PULL, 20).astype(np.float64)
+            assert np.abs(got - want).sum() <= PR_L1_TOL, (hot, block, rl)
+    finally:
+        _lib.pp_set_pull_tuning(32768, 1024)
+
+
 def test_relabel_map_is_a_degree_ordered_permutation():
     host = gg.workload("rmat14")
     g = pp.Graph(host, relabel=True)
