@@ -202,6 +202,43 @@ pp_status pp_bfs_run(pp_graph g, int32_t root, pp_dir policy, float alpha, float
                      int32_t* level, int32_t* parent, void* state, size_t state_bytes,
                      pp_bfs_stats* stats, void* stream);
 
+/* ------------------------------------------------------ personalised PR */
+/* Scratch bytes for pp_ppr_run / pp_ppr_adjoint with k columns processed in
+ * tiles of k_tile (0 when an argument is invalid). */
+size_t pp_ppr_scratch_bytes(pp_graph g, int32_t k, int32_t k_tile);
+
+/* Personalised PageRank for k sources at once (the PageRank equation of
+ * Sec. 3.1 with its teleport term put on one vertex; not defined in the
+ * paper): for column j, x_0 = e_{s_j} and
+ *   x_{t+1}(u) = (1-f)[u == s_j] + f * sum over edges (v,u) of P_uv x_t(v).
+ * sources: device int32[k], caller ids.  X: device float[n*k], row-major,
+ * caller ids (output).  Columns run in tiles of k_tile (8, 16, 32, 64; the
+ * last tile may be partial); a tile's rows hold k_tile contiguous values so every edge
+ * moves one coalesced k_tile-float row.  dir PP_PULL gathers along CSC (no
+ * atomics, deterministic), PP_PUSH scatters along CSR with FP32 atomics.
+ * Runs `iters` sweeps per tile, or stops a tile early once the L1 change of
+ * its iterate in one sweep falls below tol (tol = 0: exactly iters; each
+ * check synchronises the stream).  iters_done (host, nullable): most sweeps
+ * any tile ran.  SYNC when tol > 0 (and once to validate the sources). */
+pp_status pp_ppr_run(pp_graph g, pp_dir dir, int32_t k, const int32_t* sources, int32_t iters, float tol,
+                     float f, int32_t k_tile, float* X, void* scratch, size_t scratch_bytes,
+                     int32_t* iters_done, void* stream);
+
+/* Adjoint of personalised PageRank with respect to the edge weights, at the
+ * fixed point X of pp_ppr_run (float[n*k], caller layout).  dLdX: float[n*k]
+ * (caller layout).  Lambda (output, float[n*k]) solves
+ *   Lambda = dLdX + f P^T Lambda,  (P^T z)(v) = (1/s(v)) sum over out-edges
+ * (v,u) of w(v->u) z(u),
+ * which is the transposed sweep: PP_PULL gathers along the CSR rows (the rows
+ * the forward push scatters along), PP_PUSH scatters along CSC.  grad_w
+ * (output, float[nnz], the caller's CSR slot order):
+ *   dL/dw(v->u) = (f/s(v)) sum_j X[v,j] (Lambda[u,j] - (P^T Lambda)[v,j]).
+ * Unweighted graphs differentiate with respect to implicit unit weights.
+ * iters/tol as in pp_ppr_run. */
+pp_status pp_ppr_adjoint(pp_graph g, pp_dir dir, int32_t k, const float* X, const float* dLdX, int32_t iters,
+                         float tol, float f, int32_t k_tile, float* Lambda, float* grad_w, void* scratch,
+                         size_t scratch_bytes, int32_t* iters_done, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,8 @@ from . import _lib
 from ._lib import (PP_PULL, PP_PUSH, PP_SWITCH, PPError, BfsStats)  # noqa: F401
 from ._lib import *  # noqa: F401,F403  (the C names)
 
-__all__ = ["Graph", "BfsRun", "PPError", "PP_PUSH", "PP_PULL", "PP_SWITCH", "pagerank", "pagerank_into", "bfs"]
+__all__ = ["Graph", "BfsRun", "PPError", "PP_PUSH", "PP_PULL", "PP_SWITCH", "pagerank", "pagerank_into", "bfs",
+           "ppr", "ppr_adjoint", "PPRFunction"]
 
 
 class Graph:
@@ -127,3 +128,63 @@ def bfs(g: Graph, root, policy=PP_SWITCH, alpha=14.0, beta=24.0):
     r = BfsRun(g)
     stats = r.run(root, policy, alpha, beta)
     return r.level, r.parent, stats
+
+
+def _scratch(g: Graph, k: int, k_tile: int):
+    nbytes = _lib.pp_ppr_scratch_bytes(g.handle, k, k_tile)
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=g.device)
+
+
+def ppr(g: Graph, sources, iters=30, f=0.85, k_tile=32, direction=PP_PULL, tol=0.0, stream=None):
+    """Personalised PageRank for every source (caller ids): returns X (n x k,
+    column j = PageRank personalised on sources[j]) and the sweeps run."""
+    src = torch.as_tensor(sources, dtype=torch.int32, device=g.device).contiguous()
+    k = src.numel()
+    X = torch.empty((g.n, k), dtype=torch.float32, device=g.device)
+    done = _lib.pp_ppr_run(g.handle, direction, k, src, iters, tol, f, k_tile, X, _scratch(g, k, k_tile), stream)
+    return X, done
+
+
+def ppr_adjoint(g: Graph, X, dLdX, iters=2000, f=0.85, k_tile=32, direction=PP_PULL, tol=0.0, stream=None):
+    """Adjoint solve and edge-weight gradient at the fixed point X:
+    returns (Lambda n x k, grad[nnz] in CSR slot order, sweeps run)."""
+    X = X.contiguous()
+    dLdX = dLdX.contiguous()
+    k = X.shape[1]
+    lam = torch.empty_like(X)
+    grad = torch.empty(max(g.nnz, 1), dtype=torch.float32, device=g.device)
+    done = _lib.pp_ppr_adjoint(g.handle, direction, k, X, dLdX, iters, tol, f, k_tile, lam, grad,
+                               _scratch(g, k, k_tile), stream)
+    return lam, grad[: g.nnz], done
+
+
+class PPRFunction(torch.autograd.Function):
+    """X = PPR(w): personalised PageRank at convergence as a function of the
+    per-slot edge weights w (CSR slot order of `structure`, a HostGraph-like
+    object).  backward() runs the library's adjoint: the transposed sweep
+    solves (I - f P^T) Lambda = dL/dX and a per-slot kernel forms dL/dw.
+
+    ``forward_dir`` / ``adjoint_dir`` pick push or pull for each solve (the
+    adjoint of a forward push is a pull over the same CSR rows, and vice
+    versa)."""
+
+    @staticmethod
+    def forward(ctx, w, structure, sources, f=0.85, iters=3000, tol=1e-9, k_tile=32,
+                forward_dir=PP_PULL, adjoint_dir=PP_PULL, relabel=True):
+        import copy
+        host = copy.copy(structure)
+        host.weights = w.detach().float().cpu().numpy()
+        host.ensure_transpose()
+        g = Graph(host, device=w.device, weighted=True, relabel=relabel)
+        X, _ = ppr(g, sources, iters=iters, f=f, k_tile=k_tile, direction=forward_dir, tol=tol)
+        ctx.g = g
+        ctx.cfg = (f, iters, tol, k_tile, adjoint_dir)
+        ctx.save_for_backward(X)
+        return X
+
+    @staticmethod
+    def backward(ctx, dX):
+        (X,) = ctx.saved_tensors
+        f, iters, tol, k_tile, adir = ctx.cfg
+        _, grad, _ = ppr_adjoint(ctx.g, X, dX.float(), iters=iters, f=f, k_tile=k_tile, direction=adir, tol=tol)
+        return grad, None, None, None, None, None, None, None, None, None

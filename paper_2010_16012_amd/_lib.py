@@ -77,6 +77,11 @@ _SIGS = {
     "pp_bfs_step_pull": ([_P, _P, _P, _P, _I32, _P], ctypes.c_int),
     "pp_bfs_frontier": ([_P, _P, ctypes.POINTER(_I32), _P], ctypes.c_int),
     "pp_bfs_run": ([_P, _I32, ctypes.c_int, _F32, _F32, _P, _P, _P, _SZ, ctypes.POINTER(BfsStats), _P], ctypes.c_int),
+    "pp_ppr_scratch_bytes": ([_P, _I32, _I32], _SZ),
+    "pp_ppr_run": ([_P, ctypes.c_int, _I32, _P, _I32, _F32, _F32, _I32, _P, _P, _SZ, ctypes.POINTER(_I32), _P],
+                   ctypes.c_int),
+    "pp_ppr_adjoint": ([_P, ctypes.c_int, _I32, _P, _P, _I32, _F32, _F32, _I32, _P, _P, _P, _SZ,
+                        ctypes.POINTER(_I32), _P], ctypes.c_int),
 }
 
 EXPORTS = tuple(_SIGS)
@@ -210,3 +215,21 @@ def pp_bfs_run(h, root, policy, alpha, beta, level, parent, state, stream=None) 
     _check(_lib.pp_bfs_run(h, root, policy, alpha, beta, _ptr(level), _ptr(parent), _ptr(state), state.numel(),
                            ctypes.byref(st), _stream(stream)))
     return st
+
+
+def pp_ppr_scratch_bytes(h, k: int, k_tile: int) -> int:
+    return _lib.pp_ppr_scratch_bytes(h, k, k_tile)
+
+
+def pp_ppr_run(h, direction, k, sources, iters, tol, f, k_tile, X, scratch, stream=None) -> int:
+    done = _I32()
+    _check(_lib.pp_ppr_run(h, direction, k, _ptr(sources), iters, tol, f, k_tile, _ptr(X), _ptr(scratch),
+                           scratch.numel(), ctypes.byref(done), _stream(stream)))
+    return done.value
+
+
+def pp_ppr_adjoint(h, direction, k, X, dLdX, iters, tol, f, k_tile, Lambda, grad_w, scratch, stream=None) -> int:
+    done = _I32()
+    _check(_lib.pp_ppr_adjoint(h, direction, k, _ptr(X), _ptr(dLdX), iters, tol, f, k_tile, _ptr(Lambda),
+                               _ptr(grad_w), _ptr(scratch), scratch.numel(), ctypes.byref(done), _stream(stream)))
+    return done.value

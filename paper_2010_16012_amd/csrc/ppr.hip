@@ -1,0 +1,803 @@
+// Batched personalised PageRank (k source columns) and its adjoint with
+// respect to the edge weights, on the push/pull sweeps.
+//
+// Forward, per column j with source s_j (the PageRank equation of Sec. 3.1
+// with the teleport term concentrated on s_j):
+//   x_{t+1}(u) = (1-f)[u == s_j] + f * sum over edges (v,u) of P_uv x_t(v),
+//   P_uv = w(v->u)/s(v),  x_0 = e_{s_j}.
+// Adjoint of L(X) at the fixed point (not in the paper): Lambda solves
+// Lambda = dL/dX + f P^T Lambda, with (P^T z)(v) = (1/s(v)) sum over
+// out-edges (v,u) of w(v->u) z(u) -- a gather along the CSR rows, i.e. the
+// transposed sweep: the forward pull gathers along CSC and pushes along CSR;
+// the adjoint pull gathers along CSR and pushes along CSC.  The gradient of
+// the weight of slot (v->u) is
+//   g = (f/s(v)) sum_j X[v,j] (Lambda[u,j] - (P^T Lambda)[v,j]).
+//
+// Columns are processed in tiles of KT (8, 16, 32 or 64) columns; a tile's
+// state is stored tile-major (row u holds its KT values contiguously), so one
+// neighbour costs one coalesced KT-float read.  A group of KT lanes owns a
+// row (lane = column).  Rows are distributed with the degree bins of the
+// graph: short rows one group each, long rows one workgroup each (groups take
+// strided neighbours, reduced through LDS in a fixed order), and the longest
+// rows in chunks finished by a fix-up kernel.  Pull sweeps use no atomics
+// and are deterministic; push sweeps use FP32 atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "pp_common.h"
+
+namespace pp {
+
+constexpr int kKtMax = 64;
+
+struct KPlan {
+    int32_t unit_off[PP_NUM_BINS + 1];  // units per bin, launch order 5, 4, ..., 0
+    int32_t list_off[PP_NUM_BINS + 1];
+    int32_t units;
+};
+
+// Units of a KT-column sweep over a binned vertex list: bins 0-2 put
+// kBlock/KT rows in a unit, bins 3-4 one row, bin 5 one chunk.
+static KPlan kplan(const BinPlan& p, int kt) {
+    KPlan k;
+    int32_t u[PP_NUM_BINS];
+    for (int b = 0; b < 3; ++b) u[b] = ceil_div(p.count[b], kBlock / kt);
+    u[3] = p.count[3];
+    u[4] = p.count[4];
+    u[5] = p.split_chunks;
+    int32_t at = 0;
+    for (int b = PP_NUM_BINS - 1; b >= 0; --b) {
+        k.unit_off[b] = at;
+        at += u[b];
+    }
+    k.unit_off[PP_NUM_BINS] = at;
+    k.units = at;
+    for (int b = 0; b <= PP_NUM_BINS; ++b) k.list_off[b] = p.list_off[b];
+    return k;
+}
+
+__device__ __forceinline__ int kunit_bin(const KPlan& kp, int32_t u) {
+    int b = PP_NUM_BINS - 1;
+#pragma unroll
+    for (int i = PP_NUM_BINS - 1; i > 0; --i)
+        if (u >= kp.unit_off[i - 1]) b = i - 1;
+    return b;
+}
+
+enum EpiKind { kEpiForward = 0, kEpiAdjoint = 1, kEpiPtl = 2 };
+
+// Everything a k-column gather sweep needs.  `src` is the tile being gathered
+// (n x KT); the epilogue turns a row's gathered sums into the next state.
+struct KArgs {
+    KPlan kp;
+    const int32_t* off;
+    const int32_t* idx;
+    const float* wt;        // per-slot weight in the walked order (nullable)
+    const int32_t* list;
+    const int32_t* tab;     // bin-5 chunk table (v | begin | end | first)
+    int32_t tab_cap;
+    float* part;            // bin-5 partials, entries x KT
+    const float* src;       // gathered tile
+    // epilogue
+    int32_t kind;
+    const float* inv_s;
+    const int32_t* perm;    // internal -> caller id (nullable)
+    float f;
+    int32_t k;              // total columns (caller layout row length)
+    int32_t col0;           // first column of the tile
+    const int32_t* src_int; // forward: internal id of each column's source (length k)
+    const float* prev;      // previous iterate (residual), tile layout (nullable)
+    float* out_tile;        // new iterate, tile layout
+    float* out_scaled;      // forward: c = f * x / s (tile layout, nullable)
+    const float* g_caller;  // adjoint: dL/dX, caller layout n x k
+    float* out_caller;      // last iteration: caller layout n x k (nullable)
+    float* resid_part;      // per-unit-group residual partials (nullable)
+};
+
+template <int KT>
+__device__ __forceinline__ float kt_epilogue(const KArgs& a, int32_t u, int lane, float acc) {
+    float val;
+    if (a.kind == kEpiForward) {
+        val = acc + ((a.src_int[a.col0 + lane] == u) ? 1.0f - a.f : 0.f);
+        if (a.out_scaled) a.out_scaled[(size_t)u * KT + lane] = a.f * val * a.inv_s[u];
+    } else if (a.kind == kEpiAdjoint) {
+        const int32_t uc = user_id(a.perm, u);
+        const float gv = (a.col0 + lane < a.k) ? a.g_caller[(size_t)uc * a.k + a.col0 + lane] : 0.f;
+        val = gv + a.f * a.inv_s[u] * acc;
+    } else {
+        val = a.inv_s[u] * acc;  // (P^T Lambda)(u)
+    }
+    a.out_tile[(size_t)u * KT + lane] = val;
+    if (a.out_caller && a.col0 + lane < a.k) a.out_caller[(size_t)user_id(a.perm, u) * a.k + a.col0 + lane] = val;
+    return a.prev ? fabsf(val - a.prev[(size_t)u * KT + lane]) : 0.f;
+}
+
+// One group of KT lanes sums src[idx[j]] (x wt[j]) over j = b + g, b + g + stride, ...
+template <int KT, bool W>
+__device__ __forceinline__ float kt_gather(const KArgs& a, int32_t b, int32_t e, int32_t g, int32_t stride, int lane) {
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    int32_t j = b + g;
+    for (; j + 3 * stride < e; j += 4 * stride) {
+        const int32_t v0 = a.idx[j], v1 = a.idx[j + stride], v2 = a.idx[j + 2 * stride], v3 = a.idx[j + 3 * stride];
+        float x0 = a.src[(size_t)v0 * KT + lane], x1 = a.src[(size_t)v1 * KT + lane];
+        float x2 = a.src[(size_t)v2 * KT + lane], x3 = a.src[(size_t)v3 * KT + lane];
+        if (W) {
+            x0 *= a.wt[j];
+            x1 *= a.wt[j + stride];
+            x2 *= a.wt[j + 2 * stride];
+            x3 *= a.wt[j + 3 * stride];
+        }
+        a0 += x0;
+        a1 += x1;
+        a2 += x2;
+        a3 += x3;
+    }
+    for (; j < e; j += stride) {
+        float x = a.src[(size_t)a.idx[j] * KT + lane];
+        if (W) x *= a.wt[j];
+        a0 += x;
+    }
+    return (a0 + a1) + (a2 + a3);
+}
+
+// Sum over the groups of a workgroup, in group order (thread (0, lane) holds it).
+template <int KT>
+__device__ __forceinline__ float kt_block_sum(float v, float* red) {
+    constexpr int G = kBlock / KT;
+    red[threadIdx.x] = v;
+    __syncthreads();
+    float t = 0.f;
+    if (threadIdx.x < KT) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) t += red[g * KT + threadIdx.x];
+    }
+    __syncthreads();
+    return t;
+}
+
+template <int KT, bool W>
+__global__ __launch_bounds__(kBlock) void k_kcol_pull(KArgs a) {
+    __shared__ float red[kBlock];
+    constexpr int G = kBlock / KT;
+    const int lane = threadIdx.x % KT;
+    const int grp = threadIdx.x / KT;
+    const int32_t unit = blockIdx.x;
+    const int bin = kunit_bin(a.kp, unit);
+    const int32_t lu = unit - a.kp.unit_off[bin];
+    float res = 0.f;
+    if (bin <= 2) {
+        const int32_t i = lu * G + grp;
+        if (i < a.kp.list_off[bin + 1] - a.kp.list_off[bin]) {
+            const int32_t u = a.list[a.kp.list_off[bin] + i];
+            const float acc = kt_gather<KT, W>(a, a.off[u], a.off[u + 1], 0, 1, lane);
+            res = kt_epilogue<KT>(a, u, lane, acc);
+        }
+    } else if (bin <= 4) {
+        const int32_t u = a.list[a.kp.list_off[bin] + lu];
+        float acc = kt_gather<KT, W>(a, a.off[u], a.off[u + 1], grp, G, lane);
+        acc = kt_block_sum<KT>(acc, red);
+        if (threadIdx.x < KT) res = kt_epilogue<KT>(a, u, lane, acc);
+    } else {
+        const int32_t b = a.tab[a.tab_cap + lu], e = a.tab[2 * a.tab_cap + lu];
+        float acc = kt_gather<KT, W>(a, b, e, grp, G, lane);
+        acc = kt_block_sum<KT>(acc, red);
+        if (threadIdx.x < KT) a.part[(size_t)lu * KT + lane] = acc;
+    }
+    if (a.resid_part) {
+        // per-workgroup residual (fixed order)
+        red[threadIdx.x] = res;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float t = 0.f;
+            for (int i = 0; i < kBlock; ++i) t += red[i];
+            a.resid_part[unit] = t;
+        }
+    }
+}
+
+// Finishes the chunked rows: partials in chunk order, then the epilogue.
+template <int KT>
+__global__ __launch_bounds__(kBlock) void k_kcol_fix(KArgs a, int32_t nsplit, float* resid_fix) {
+    const int lane = threadIdx.x % KT;
+    const int32_t i = blockIdx.x * (kBlock / KT) + threadIdx.x / KT;
+    float res = 0.f;
+    if (i < nsplit) {
+        const int32_t* first = a.tab + 3 * a.tab_cap;
+        float acc = 0.f;
+        for (int32_t e = first[i]; e < first[i + 1]; ++e) acc += a.part[(size_t)e * KT + lane];
+        res = kt_epilogue<KT>(a, a.tab[first[i]], lane, acc);
+    }
+    if (resid_fix) {
+        __shared__ float red[kBlock];
+        red[threadIdx.x] = res;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float t = 0.f;
+            for (int j = 0; j < kBlock; ++j) t += red[j];
+            resid_fix[blockIdx.x] = t;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ push
+struct KPushArgs {
+    KPlan kp;
+    const int32_t* off;
+    const int32_t* idx;
+    const float* wt;
+    const int32_t* list;
+    const int32_t* tab;
+    int32_t tab_cap;
+    const float* src;   // tile being scattered
+    double* acc;        // accumulator tile, FP64 so the unordered atomic sum keeps FP32 accuracy
+};
+
+template <int KT, bool W>
+__device__ __forceinline__ void kt_scatter(const KPushArgs& a, int32_t v, int32_t b, int32_t e, int32_t g,
+                                           int32_t stride, int lane) {
+    const float x = a.src[(size_t)v * KT + lane];
+    if (x == 0.f) return;  // per-lane: a zero contributes nothing
+    for (int32_t j = b + g; j < e; j += stride) {
+        const int32_t u = a.idx[j];
+        unsafeAtomicAdd(&a.acc[(size_t)u * KT + lane], (double)(W ? x * a.wt[j] : x));
+    }
+}
+
+template <int KT, bool W>
+__global__ __launch_bounds__(kBlock) void k_kcol_push(KPushArgs a) {
+    constexpr int G = kBlock / KT;
+    const int lane = threadIdx.x % KT;
+    const int grp = threadIdx.x / KT;
+    const int32_t unit = blockIdx.x;
+    const int bin = kunit_bin(a.kp, unit);
+    const int32_t lu = unit - a.kp.unit_off[bin];
+    if (bin <= 2) {
+        const int32_t i = lu * G + grp;
+        if (i < a.kp.list_off[bin + 1] - a.kp.list_off[bin]) {
+            const int32_t v = a.list[a.kp.list_off[bin] + i];
+            kt_scatter<KT, W>(a, v, a.off[v], a.off[v + 1], 0, 1, lane);
+        }
+    } else if (bin <= 4) {
+        const int32_t v = a.list[a.kp.list_off[bin] + lu];
+        kt_scatter<KT, W>(a, v, a.off[v], a.off[v + 1], grp, G, lane);
+    } else {
+        const int32_t v = a.tab[lu];
+        kt_scatter<KT, W>(a, v, a.tab[a.tab_cap + lu], a.tab[2 * a.tab_cap + lu], grp, G, lane);
+    }
+}
+
+// After a push sweep, per (row, column): the epilogue on the accumulated sum,
+// then the accumulator is reset for the next sweep (to zero plus, for the
+// forward, nothing: the teleport is added by the epilogue).
+template <int KT>
+__global__ __launch_bounds__(kBlock) void k_kcol_push_epi(KArgs a, int32_t n, double* accum) {
+    __shared__ float red[kBlock];
+    const int lane = threadIdx.x % KT;
+    const int32_t u = blockIdx.x * (kBlock / KT) + threadIdx.x / KT;
+    float res = 0.f;
+    if (u < n) {
+        const float acc = (float)accum[(size_t)u * KT + lane];
+        accum[(size_t)u * KT + lane] = 0.0;
+        res = kt_epilogue<KT>(a, u, lane, acc);
+    }
+    if (a.resid_part) {
+        red[threadIdx.x] = res;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float t = 0.f;
+            for (int i = 0; i < kBlock; ++i) t += red[i];
+            a.resid_part[blockIdx.x] = t;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ helpers
+// Start of a forward tile: x0 = e_s per column (prev), c0 = f x0 / s.
+template <int KT>
+__global__ void k_kcol_forward_init(int32_t n, const int32_t* __restrict__ src_int, int32_t col0, float f,
+                                    const float* __restrict__ inv_s, float* __restrict__ prev,
+                                    float* __restrict__ c, double* __restrict__ accum) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * KT) return;
+    const int32_t u = (int32_t)(t / KT);
+    const int lane = (int)(t % KT);
+    const float x0 = (src_int[col0 + lane] == u) ? 1.f : 0.f;
+    prev[t] = x0;
+    c[t] = f * x0 * inv_s[u];
+    if (accum) accum[t] = 0.0;
+}
+
+// Start of an adjoint tile: Lambda_0 = G (caller layout -> tile layout).
+template <int KT>
+__global__ void k_kcol_adjoint_init(int32_t n, int32_t k, int32_t col0, const int32_t* __restrict__ perm,
+                                    const float* __restrict__ g, float* __restrict__ lam, double* __restrict__ accum) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * KT) return;
+    const int32_t u = (int32_t)(t / KT);
+    const int lane = (int)(t % KT);
+    lam[t] = (col0 + lane < k) ? g[(size_t)user_id(perm, u) * k + col0 + lane] : 0.f;
+    if (accum) accum[t] = 0.0;
+}
+
+// Internal source ids, padded with -1 (no source) up to a whole tile.
+__global__ void k_sources_internal(int32_t k, int32_t k_pad, const int32_t* __restrict__ sources,
+                                   const int32_t* __restrict__ iperm, int32_t n, int32_t* __restrict__ out,
+                                   int32_t* __restrict__ bad) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= k_pad) return;
+    if (j >= k) {
+        out[j] = -1;
+        return;
+    }
+    const int32_t s = sources[j];
+    if (s < 0 || s >= n) {
+        atomicOr(bad, 1);
+        out[j] = -1;
+        return;
+    }
+    out[j] = iperm ? iperm[s] : s;
+}
+
+// Fixed-order sum of the residual partials (one workgroup).
+__global__ __launch_bounds__(1024) void k_sum_partials(int32_t m, const float* __restrict__ p, float* __restrict__ out) {
+    __shared__ float red[1024];
+    float t = 0.f;
+    for (int32_t i = threadIdx.x; i < m; i += 1024) t += p[i];
+    red[threadIdx.x] = t;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// Edge gradient of one tile, added into grad (caller CSR slot order):
+// slot (v -> u): f/s(v) * sum_j X[v,j] (Lambda[u,j] - ptl[v,j]).  One group
+// of KT lanes per slot of the row; slots of long rows spread over the groups
+// of a workgroup.  Each slot has one writer.
+struct GradArgs {
+    KPlan kp;  // over the CSR (out-degree) lists
+    const int32_t* off;
+    const int32_t* idx;
+    const int32_t* list;
+    const int32_t* tab;
+    int32_t tab_cap;
+    const float* lam;       // tile layout
+    const float* ptl;       // tile layout
+    const float* x_caller;  // caller layout n x k
+    const float* inv_s;
+    const int32_t* perm;
+    const int32_t* user_off;  // caller CSR offsets (slot mapping)
+    int32_t k, col0;
+    float f;
+    float* grad;
+};
+
+template <int KT>
+__device__ __forceinline__ void grad_row(const GradArgs& a, int32_t v, int32_t b, int32_t e, int32_t g,
+                                         int32_t stride, int lane) {
+    const int32_t vc = user_id(a.perm, v);
+    const float xv = (a.col0 + lane < a.k) ? a.x_caller[(size_t)vc * a.k + a.col0 + lane] : 0.f;
+    const float pv = a.ptl[(size_t)v * KT + lane];
+    const float scale = a.f * a.inv_s[v];
+    const int32_t row0 = a.off[v], crow0 = a.user_off[vc];
+    for (int32_t j = b + g; j < e; j += stride) {
+        const int32_t u = a.idx[j];
+        float t = xv * (a.lam[(size_t)u * KT + lane] - pv);
+#pragma unroll
+        for (int s = KT / 2; s > 0; s >>= 1) t += __shfl_xor(t, s);
+        if (lane == 0) a.grad[crow0 + (j - row0)] += scale * t;
+    }
+}
+
+template <int KT>
+__global__ __launch_bounds__(kBlock) void k_kcol_grad(GradArgs a) {
+    constexpr int G = kBlock / KT;
+    const int lane = threadIdx.x % KT;
+    const int grp = threadIdx.x / KT;
+    const int32_t unit = blockIdx.x;
+    const int bin = kunit_bin(a.kp, unit);
+    const int32_t lu = unit - a.kp.unit_off[bin];
+    if (bin <= 2) {
+        const int32_t i = lu * G + grp;
+        if (i < a.kp.list_off[bin + 1] - a.kp.list_off[bin]) {
+            const int32_t v = a.list[a.kp.list_off[bin] + i];
+            grad_row<KT>(a, v, a.off[v], a.off[v + 1], 0, 1, lane);
+        }
+    } else if (bin <= 4) {
+        const int32_t v = a.list[a.kp.list_off[bin] + lu];
+        grad_row<KT>(a, v, a.off[v], a.off[v + 1], grp, G, lane);
+    } else {
+        const int32_t v = a.tab[lu];
+        grad_row<KT>(a, v, a.tab[a.tab_cap + lu], a.tab[2 * a.tab_cap + lu], grp, G, lane);
+    }
+}
+
+__global__ void k_zero_f32(int64_t m, float* __restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) p[i] = 0.f;
+}
+
+// ------------------------------------------------------------------ host side
+struct PprLayout {
+    size_t t0, t1, t2, t3, t4, part, resid, scal, srcs, total;
+};
+
+static PprLayout ppr_layout(int32_t n, int32_t split_cap, int32_t k, int32_t kt, int32_t max_units) {
+    PprLayout L{};
+    size_t p = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = p;
+        p = align_up(p + bytes, 256);
+        return at;
+    };
+    const size_t tile = (size_t)n * kt * 4;
+    L.t0 = take(tile);
+    L.t1 = take(tile);
+    L.t2 = take(tile);
+    L.t3 = take(tile);
+    L.t4 = take(2 * tile);  // FP64 push accumulator
+    L.part = take((size_t)split_cap * kt * 4);
+    L.resid = take((size_t)(max_units + ceil_div(n, 4) + 64) * 4);
+    L.scal = take(64);
+    L.srcs = take((size_t)(ceil_div(std::max(k, 1), kt) * kt) * 4);
+    L.total = p;
+    return L;
+}
+
+static int32_t max_units(pp_graph g, int kt) {
+    const KPlan a = kplan(g->pull_plan, kt), b = kplan(g->push_plan, kt);
+    return std::max(a.units, b.units);
+}
+
+static bool valid_kt(int32_t kt) { return kt == 8 || kt == 16 || kt == 32 || kt == 64; }
+
+template <int KT>
+static void launch_kpull(const KArgs& a, int32_t nsplit, float* resid_fix, hipStream_t st, bool weighted) {
+    if (a.kp.units > 0) {
+        if (weighted) hipLaunchKernelGGL((k_kcol_pull<KT, true>), dim3(a.kp.units), dim3(kBlock), 0, st, a);
+        else hipLaunchKernelGGL((k_kcol_pull<KT, false>), dim3(a.kp.units), dim3(kBlock), 0, st, a);
+    }
+    if (nsplit > 0)
+        hipLaunchKernelGGL((k_kcol_fix<KT>), dim3(ceil_div(nsplit, kBlock / KT)), dim3(kBlock), 0, st, a, nsplit,
+                           resid_fix);
+}
+
+template <int KT>
+static void launch_kpush(const KPushArgs& a, hipStream_t st, bool weighted) {
+    if (a.kp.units == 0) return;
+    if (weighted) hipLaunchKernelGGL((k_kcol_push<KT, true>), dim3(a.kp.units), dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_kcol_push<KT, false>), dim3(a.kp.units), dim3(kBlock), 0, st, a);
+}
+
+// Pieces of the graph a k-column sweep walks: forward pull and adjoint push
+// walk the CSC (pull lists); forward push and adjoint pull walk the CSR.
+struct Walk {
+    KPlan kp;
+    const int32_t *off, *idx, *list, *tab;
+    const float* wt;
+    int32_t nsplit;
+};
+
+static Walk walk_csc(pp_graph g, int kt) {
+    Walk w;
+    w.kp = kplan(g->pull_plan, kt);
+    w.off = g->d.csc_off;
+    w.idx = g->d.csc_idx;
+    w.list = g->d.pull_list;
+    w.tab = g->d.split_tab;
+    w.wt = g->d.csc_w;
+    w.nsplit = g->pull_plan.count[5];
+    return w;
+}
+
+static Walk walk_csr(pp_graph g, int kt) {
+    Walk w;
+    w.kp = kplan(g->push_plan, kt);
+    w.off = g->d.csr_off;
+    w.idx = g->d.csr_idx;
+    w.list = g->d.push_list;
+    w.tab = g->d.split_tab + 4 * (size_t)g->split_cap + 1;
+    w.wt = g->d.csr_w;
+    w.nsplit = g->push_plan.count[5];
+    return w;
+}
+
+// Copies a tile (tile layout, internal ids) into caller layout columns.
+template <int KT>
+__global__ void k_tile_to_caller(int32_t n, int32_t k, int32_t col0, const int32_t* __restrict__ perm,
+                                 const float* __restrict__ tile, float* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * KT) return;
+    const int32_t u = (int32_t)(t / KT);
+    const int lane = (int)(t % KT);
+    if (col0 + lane < k) out[(size_t)user_id(perm, u) * k + col0 + lane] = tile[t];
+}
+
+// Runs one tile for `iters` sweeps, or until the L1 change of a sweep falls
+// below tol.  Forward state: t0/t1 iterates, t2/t3 scaled contributions;
+// adjoint state: t0/t1 Lambda; t4 is the push accumulator.  On return
+// *latest points at the newest iterate and *done holds the sweeps run.
+template <int KT>
+static pp_status run_tile(pp_graph g, bool adjoint, pp_dir dir, int32_t k, int32_t col0, int32_t iters, float tol,
+                          float f, const int32_t* src_int, const float* g_caller, char* base, const PprLayout& L,
+                          float** latest, int32_t* done, hipStream_t st) {
+    const int32_t n = g->d.n;
+    float* t0 = reinterpret_cast<float*>(base + L.t0);
+    float* t1 = reinterpret_cast<float*>(base + L.t1);
+    float* t2 = reinterpret_cast<float*>(base + L.t2);
+    float* t3 = reinterpret_cast<float*>(base + L.t3);
+    double* t4 = reinterpret_cast<double*>(base + L.t4);
+    float* part = reinterpret_cast<float*>(base + L.part);
+    float* resid = reinterpret_cast<float*>(base + L.resid);
+    float* scal = reinterpret_cast<float*>(base + L.scal);
+    const int64_t cells = (int64_t)n * KT;
+    const dim3 cb(ceil_div(cells, 256)), ct(256);
+    if (adjoint) hipLaunchKernelGGL(k_kcol_adjoint_init<KT>, cb, ct, 0, st, n, k, col0, g->d.perm, g_caller, t0, t4);
+    else hipLaunchKernelGGL(k_kcol_forward_init<KT>, cb, ct, 0, st, n, src_int, col0, f, g->d.inv_s, t0, t2, t4);
+    PP_LAUNCH_CHECK("ppr tile init");
+    const bool pull = (dir == PP_PULL);
+    float* prev = t0;   // current iterate
+    float* next = t1;
+    float* c_cur = t2;  // forward: scaled contributions of prev
+    float* c_nxt = t3;
+    *done = 0;
+    for (int32_t t = 0; t < iters; ++t) {
+        KArgs a{};
+        a.kind = adjoint ? kEpiAdjoint : kEpiForward;
+        a.inv_s = g->d.inv_s;
+        a.perm = g->d.perm;
+        a.f = f;
+        a.k = k;
+        a.col0 = col0;
+        a.src_int = src_int;
+        a.prev = prev;
+        a.out_tile = next;
+        a.out_scaled = adjoint ? nullptr : c_nxt;
+        a.g_caller = g_caller;
+        a.out_caller = nullptr;
+        a.resid_part = resid;
+        const float* moved = adjoint ? prev : c_cur;
+        int32_t nres = 0;
+        if (pull) {
+            // forward pull gathers along CSC; the adjoint pull gathers along CSR
+            const Walk w = adjoint ? walk_csr(g, KT) : walk_csc(g, KT);
+            a.kp = w.kp;
+            a.off = w.off;
+            a.idx = w.idx;
+            a.wt = w.wt;
+            a.list = w.list;
+            a.tab = w.tab;
+            a.tab_cap = g->split_cap;
+            a.part = part;
+            a.src = moved;
+            launch_kpull<KT>(a, w.nsplit, w.nsplit > 0 ? resid + w.kp.units : nullptr, st, g->weighted);
+            nres = w.kp.units + (w.nsplit > 0 ? ceil_div(w.nsplit, kBlock / KT) : 0);
+        } else {
+            // forward push scatters along CSR; the adjoint push scatters along CSC
+            const Walk w = adjoint ? walk_csc(g, KT) : walk_csr(g, KT);
+            KPushArgs p{};
+            p.kp = w.kp;
+            p.off = w.off;
+            p.idx = w.idx;
+            p.wt = w.wt;
+            p.list = w.list;
+            p.tab = w.tab;
+            p.tab_cap = g->split_cap;
+            p.src = moved;
+            p.acc = t4;
+            launch_kpush<KT>(p, st, g->weighted);
+            hipLaunchKernelGGL(k_kcol_push_epi<KT>, dim3(ceil_div(n, kBlock / KT)), dim3(kBlock), 0, st, a, n, t4);
+            nres = ceil_div(n, kBlock / KT);
+        }
+        PP_LAUNCH_CHECK("ppr sweep");
+        ++*done;
+        std::swap(prev, next);
+        std::swap(c_cur, c_nxt);
+        if (tol > 0.f && t + 1 < iters) {
+            float r = 0.f;
+            hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, nres, (const float*)resid, scal);
+            PP_HIP(hipMemcpyAsync(&r, scal, sizeof(float), hipMemcpyDeviceToHost, st));
+            PP_HIP(hipStreamSynchronize(st));
+            if (r < tol) break;
+        }
+    }
+    *latest = prev;
+    return PP_OK;
+}
+
+// (P^T Lambda) of one tile by a CSR gather, then the tile's edge gradient
+// added into grad (caller CSR slot order).
+template <int KT>
+static pp_status adjoint_grad(pp_graph g, int32_t k, int32_t col0, float f, const float* lam, float* ptl,
+                              float* part, const float* x_caller, float* grad, hipStream_t st) {
+    const Walk w = walk_csr(g, KT);
+    KArgs a{};
+    a.kind = kEpiPtl;
+    a.inv_s = g->d.inv_s;
+    a.perm = g->d.perm;
+    a.f = f;
+    a.k = k;
+    a.col0 = col0;
+    a.out_tile = ptl;
+    a.kp = w.kp;
+    a.off = w.off;
+    a.idx = w.idx;
+    a.wt = w.wt;
+    a.list = w.list;
+    a.tab = w.tab;
+    a.tab_cap = g->split_cap;
+    a.part = part;
+    a.src = lam;
+    launch_kpull<KT>(a, w.nsplit, nullptr, st, g->weighted);
+    GradArgs ga{};
+    ga.kp = w.kp;
+    ga.off = w.off;
+    ga.idx = w.idx;
+    ga.list = w.list;
+    ga.tab = w.tab;
+    ga.tab_cap = g->split_cap;
+    ga.lam = lam;
+    ga.ptl = ptl;
+    ga.x_caller = x_caller;
+    ga.inv_s = g->d.inv_s;
+    ga.perm = g->d.perm;
+    ga.user_off = g->d.user_csr_off;
+    ga.k = k;
+    ga.col0 = col0;
+    ga.f = f;
+    ga.grad = grad;
+    if (w.kp.units > 0) hipLaunchKernelGGL(k_kcol_grad<KT>, dim3(w.kp.units), dim3(kBlock), 0, st, ga);
+    PP_LAUNCH_CHECK("ppr adjoint gradient");
+    return PP_OK;
+}
+
+struct PprCall {
+    pp_graph g;
+    bool adjoint;
+    pp_dir dir;
+    int32_t k, iters, kt;
+    float tol, f;
+    const int32_t* sources;  // forward
+    const float* x_caller;   // adjoint: forward solution
+    const float* g_caller;   // adjoint: dL/dX
+    float* out;              // X (forward) or Lambda (adjoint), caller layout
+    float* grad;             // adjoint: per CSR slot
+    char* base;
+    PprLayout L;
+    hipStream_t st;
+};
+
+template <int KT>
+static pp_status ppr_call(const PprCall& c, int32_t* iters_done) {
+    const int32_t n = c.g->d.n;
+    int32_t* src_int = reinterpret_cast<int32_t*>(c.base + c.L.srcs);
+    int32_t* flag = reinterpret_cast<int32_t*>(c.base + c.L.scal) + 8;
+    if (!c.adjoint) {
+        int32_t bad = 0;
+        hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, c.st, (int64_t)1, reinterpret_cast<float*>(flag));
+        const int32_t k_pad = ceil_div(c.k, KT) * KT;
+        hipLaunchKernelGGL(k_sources_internal, dim3(ceil_div(k_pad, 256)), dim3(256), 0, c.st, c.k, k_pad, c.sources,
+                           c.g->d.iperm, n, src_int, flag);
+        PP_LAUNCH_CHECK("ppr sources");
+        PP_HIP(hipMemcpyAsync(&bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, c.st));
+        PP_HIP(hipStreamSynchronize(c.st));
+        if (bad) return set_error(PP_E_RANGE, "a source lies outside [0, n)");
+    } else if (c.g->d.nnz > 0) {
+        hipLaunchKernelGGL(k_zero_f32, dim3(ceil_div(c.g->d.nnz, 256)), dim3(256), 0, c.st, c.g->d.nnz, c.grad);
+    }
+    int32_t most = 0;
+    for (int32_t col0 = 0; col0 < c.k; col0 += KT) {
+        float* latest = nullptr;
+        int32_t done = 0;
+        pp_status s = run_tile<KT>(c.g, c.adjoint, c.dir, c.k, col0, c.iters, c.tol, c.f, src_int, c.g_caller, c.base,
+                                   c.L, &latest, &done, c.st);
+        if (s != PP_OK) return s;
+        most = std::max(most, done);
+        hipLaunchKernelGGL(k_tile_to_caller<KT>, dim3(ceil_div((int64_t)n * KT, 256)), dim3(256), 0, c.st, n, c.k,
+                           col0, c.g->d.perm, (const float*)latest, c.out);
+        PP_LAUNCH_CHECK("ppr tile copy-out");
+        if (c.adjoint) {
+            float* t0 = reinterpret_cast<float*>(c.base + c.L.t0);
+            float* ptl = (latest == t0) ? reinterpret_cast<float*>(c.base + c.L.t1) : t0;
+            s = adjoint_grad<KT>(c.g, c.k, col0, c.f, latest, ptl, reinterpret_cast<float*>(c.base + c.L.part),
+                                 c.x_caller, c.grad, c.st);
+            if (s != PP_OK) return s;
+        }
+    }
+    if (iters_done) *iters_done = most;
+    return PP_OK;
+}
+
+static pp_status ppr_dispatch(const PprCall& c, int32_t* iters_done) {
+    switch (c.kt) {
+        case 8: return ppr_call<8>(c, iters_done);
+        case 16: return ppr_call<16>(c, iters_done);
+        case 32: return ppr_call<32>(c, iters_done);
+        default: return ppr_call<64>(c, iters_done);
+    }
+}
+
+static pp_status check_ppr(pp_graph g, pp_dir dir, int32_t k, int32_t iters, float tol, float f, int32_t kt,
+                           void* scratch, size_t bytes, size_t need) {
+    if (!g) return set_error(PP_E_NULL, "graph handle is NULL");
+    if (dir != PP_PUSH && dir != PP_PULL) return set_error(PP_E_RANGE, "dir must be PP_PUSH or PP_PULL");
+    if (k < 0) return set_error(PP_E_SIZE, "k must be >= 0");
+    if (!valid_kt(kt)) return set_error(PP_E_RANGE, "k_tile must be 8, 16, 32 or 64");
+    if (iters < 0) return set_error(PP_E_RANGE, "iters must be >= 0");
+    if (!(tol >= 0.f)) return set_error(PP_E_RANGE, "tol must be >= 0");
+    if (!(f >= 0.f && f < 1.f)) return set_error(PP_E_RANGE, "f must lie in [0, 1)");
+    if (!scratch) return set_error(PP_E_NULL, "scratch is NULL");
+    if (bytes < need) return set_error(PP_E_WORKSPACE, "PPR scratch too small");
+    if (reinterpret_cast<uintptr_t>(scratch) % 256 != 0) return set_error(PP_E_RANGE, "scratch must be 256-byte aligned");
+    return PP_OK;
+}
+
+}  // namespace pp
+
+using namespace pp;
+
+PP_EXPORT size_t pp_ppr_scratch_bytes(pp_graph g, int32_t k, int32_t k_tile) {
+    if (!g || !valid_kt(k_tile) || k < 0) return 0;
+    return ppr_layout(g->d.n, g->split_cap, k, k_tile, max_units(g, k_tile)).total;
+}
+
+PP_EXPORT pp_status pp_ppr_run(pp_graph g, pp_dir dir, int32_t k, const int32_t* sources, int32_t iters, float tol,
+                               float f, int32_t k_tile, float* X, void* scratch, size_t scratch_bytes,
+                               int32_t* iters_done, void* stream) {
+    clear_error();
+    const size_t need = pp_ppr_scratch_bytes(g, k, k_tile);
+    pp_status s = check_ppr(g, dir, k, iters, tol, f, k_tile, scratch, scratch_bytes, need);
+    if (s != PP_OK) return s;
+    if (k > 0 && (!sources || !X)) return set_error(PP_E_NULL, "sources and X are required");
+    if (iters_done) *iters_done = 0;
+    if (k == 0) return PP_OK;
+    PprCall c{};
+    c.g = g;
+    c.adjoint = false;
+    c.dir = dir;
+    c.k = k;
+    c.iters = iters;
+    c.kt = k_tile;
+    c.tol = tol;
+    c.f = f;
+    c.sources = sources;
+    c.out = X;
+    c.base = static_cast<char*>(scratch);
+    c.L = ppr_layout(g->d.n, g->split_cap, k, k_tile, max_units(g, k_tile));
+    c.st = static_cast<hipStream_t>(stream);
+    return ppr_dispatch(c, iters_done);
+}
+
+PP_EXPORT pp_status pp_ppr_adjoint(pp_graph g, pp_dir dir, int32_t k, const float* X, const float* dLdX,
+                                   int32_t iters, float tol, float f, int32_t k_tile, float* Lambda, float* grad_w,
+                                   void* scratch, size_t scratch_bytes, int32_t* iters_done, void* stream) {
+    clear_error();
+    const size_t need = pp_ppr_scratch_bytes(g, k, k_tile);
+    pp_status s = check_ppr(g, dir, k, iters, tol, f, k_tile, scratch, scratch_bytes, need);
+    if (s != PP_OK) return s;
+    if (k > 0 && (!X || !dLdX || !Lambda)) return set_error(PP_E_NULL, "X, dLdX and Lambda are required");
+    if (g->d.nnz > 0 && !grad_w) return set_error(PP_E_NULL, "grad_w is required");
+    if (iters_done) *iters_done = 0;
+    if (k == 0) return PP_OK;
+    PprCall c{};
+    c.g = g;
+    c.adjoint = true;
+    c.dir = dir;
+    c.k = k;
+    c.iters = iters;
+    c.kt = k_tile;
+    c.tol = tol;
+    c.f = f;
+    c.x_caller = X;
+    c.g_caller = dLdX;
+    c.out = Lambda;
+    c.grad = grad_w;
+    c.base = static_cast<char*>(scratch);
+    c.L = ppr_layout(g->d.n, g->split_cap, k, k_tile, max_units(g, k_tile));
+    c.st = static_cast<hipStream_t>(stream);
+    return ppr_dispatch(c, iters_done);
+}

@@ -1,0 +1,178 @@
+"""Batched personalised PageRank and its adjoint on the GPU against the oracle.
+
+Bars: every column within 1e-6 L1 of the FP64 oracle column (FP32 sweeps);
+the adjoint gradient within 1e-5 relative (L2) of the FP64 oracle gradient
+at the fixed point, and of FP64 central differences of the dense solve.
+"""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+import paper_2010_16012_amd as pp
+from tests import helpers as H
+from tests.gpu_util import F, announce, default_bins, tiny_bins
+
+pytestmark = pytest.mark.gpu
+
+DIRS = [pp.PP_PULL, pp.PP_PUSH]
+
+
+@pytest.fixture(autouse=True)
+def _bins():
+    default_bins()
+    yield
+    default_bins()
+
+
+def _cols_close(got, want, tol=1e-6):
+    l1 = np.abs(got.astype(np.float64) - want).sum(axis=0)
+    assert l1.max() <= tol, f"worst column L1 {l1.max():.3e}"
+
+
+@pytest.mark.parametrize("kt,k", [(8, 64), (16, 64), (32, 64), (64, 64), (32, 45), (64, 3)])
+def test_batched_ppr_matches_oracle_columns(kt, k):
+    host = gg.workload("rmat14")
+    src = gg.pick_vertices(host, k, seed=5)
+    want, _ = oracle.ppr(host.off, host.idx, src, F, T=30)
+    for rl in (True, False):
+        g = pp.Graph(host, relabel=rl)
+        for d in DIRS:
+            announce(f"PPR kt={kt} relabel={rl} dir={d}")
+            X, done = pp.ppr(g, src, iters=30, f=F, k_tile=kt, direction=d)
+            assert done == 30
+            _cols_close(X.cpu().numpy(), want)
+
+
+def test_batched_ppr_directed_weighted_every_bin():
+    host = H.random_graph(4000, 30000, 3, symmetric=False, connected=True)
+    gg.with_weights(host, seed=8)
+    src = np.array([0, 5, 77, 1234, 3999, 2, 3, 4], dtype=np.int32)
+    want, _ = oracle.ppr(host.off, host.idx, src, F, T=25, weights=host.weights)
+    for bins in ("default", "tiny"):
+        (tiny_bins if bins == "tiny" else default_bins)()
+        for rl in (True, False):
+            g = pp.Graph(host, relabel=rl)
+            for d in DIRS:
+                X, _ = pp.ppr(g, src, iters=25, f=F, k_tile=8, direction=d)
+                _cols_close(X.cpu().numpy(), want)
+
+
+def test_pull_batched_is_deterministic_and_tile_independent():
+    host = gg.workload("rmat14")
+    src = gg.pick_vertices(host, 32, seed=6)
+    g = pp.Graph(host)
+    a, _ = pp.ppr(g, src, iters=20, f=F, k_tile=16)
+    b, _ = pp.ppr(g, src, iters=20, f=F, k_tile=16)
+    assert torch.equal(a, b)
+    c, _ = pp.ppr(g, src, iters=20, f=F, k_tile=32)
+    assert (a - c).abs().sum(dim=0).max().item() <= 1e-6
+    # a batch equals its columns run one tile at a time
+    d, _ = pp.ppr(g, src[:8], iters=20, f=F, k_tile=8)
+    assert (a[:, :8] - d).abs().sum(dim=0).max().item() <= 1e-6
+
+
+def test_converged_mode_matches_dense_solve():
+    host = H.random_graph(300, 1500, 9, symmetric=False, connected=True)
+    gg.with_weights(host, seed=1)
+    src = np.arange(8, dtype=np.int32) * 7
+    P = H.dense_transition(host, host.weights)
+    g = pp.Graph(host)
+    for d in DIRS:
+        X, done = pp.ppr(g, src, iters=5000, f=F, k_tile=8, direction=d, tol=1e-7)
+        assert done < 5000
+        for j, s in enumerate(src):
+            e = np.zeros(host.n)
+            e[s] = 1
+            want = np.linalg.solve(np.eye(host.n) - F * P, (1 - F) * e)
+            assert np.abs(X[:, j].cpu().numpy() - want).sum() <= 2e-6
+
+
+def test_ppr_edge_cases_and_errors():
+    host = gg.from_edges(10, [0, 1, 2], [1, 2, 3], True)  # vertices 4..9 isolated
+    g = pp.Graph(host)
+    X, _ = pp.ppr(g, [5, 0, 1, 2, 3, 4, 6, 7], iters=3, f=F, k_tile=8)
+    Xh = X.cpu().numpy()
+    assert Xh[5, 0] == pytest.approx(1 - F, abs=1e-7) and np.abs(Xh[:, 0]).sum() == pytest.approx(1 - F, abs=1e-7)
+    Z, done = pp.ppr(g, np.zeros(0, np.int32), iters=3, k_tile=8)
+    assert Z.shape == (10, 0) and done == 0
+    # a partial last tile: columns agree with a full-tile run
+    P3, _ = pp.ppr(g, [1, 2, 3], iters=3, f=F, k_tile=8)
+    assert torch.equal(P3, X[:, 2:5])
+    with pytest.raises(pp.PPError):
+        pp.ppr(g, [1] * 8, k_tile=12)
+    with pytest.raises(pp.PPError):
+        pp.ppr(g, [0, 1, 2, 3, 4, 5, 6, 10], k_tile=8)  # source out of range
+
+
+# ----------------------------------------------------------------------- adjoint
+def _forward_fixed_point(host, src):
+    X, _ = oracle.ppr(host.off, host.idx, src, F, T=20000, tol=1e-15, weights=host.weights)
+    return X
+
+
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_adjoint_matches_oracle_gradient(symmetric):
+    host = H.random_graph(600, 4000, 14, symmetric=symmetric, connected=True)
+    gg.with_weights(host, seed=3)
+    src = np.arange(16, dtype=np.int32) * 31
+    Xo = _forward_fixed_point(host, src)
+    c = gg.normal(host.n * len(src), seed=2).reshape(host.n, len(src)).astype(np.float64)
+    lam_o, grad_o, _ = oracle.ppr_adjoint(host.off, host.idx, Xo, c, F, T=20000, tol=1e-15, weights=host.weights)
+    for rl in (True, False):
+        g = pp.Graph(host, relabel=rl)
+        X, _ = pp.ppr(g, src, iters=3000, f=F, k_tile=16, tol=1e-9)
+        for fd in DIRS:
+            for ad in DIRS:
+                announce(f"adjoint sym={symmetric} relabel={rl} fwd={fd} adj={ad}")
+                Xf, _ = pp.ppr(g, src, iters=3000, f=F, k_tile=16, direction=fd, tol=1e-9)
+                lam, grad, done = pp.ppr_adjoint(g, Xf, torch.as_tensor(c, dtype=torch.float32, device="cuda"),
+                                                 iters=3000, f=F, k_tile=16, direction=ad, tol=1e-9)
+                assert done < 3000
+                gh = grad.cpu().numpy().astype(np.float64)
+                rel = np.linalg.norm(gh - grad_o) / np.linalg.norm(grad_o)
+                assert rel <= 1e-5, f"relative gradient error {rel:.2e}"
+                lh = lam.cpu().numpy().astype(np.float64)
+                assert np.abs(lh - lam_o).max() / np.abs(lam_o).max() <= 1e-5
+
+
+def test_adjoint_against_finite_differences_tiny():
+    host = H.random_graph(24, 80, 5, symmetric=True, connected=True)
+    gg.with_weights(host, seed=6)
+    src = np.arange(8, dtype=np.int32) * 3
+    c = gg.normal(host.n * 8, seed=9).reshape(host.n, 8).astype(np.float64)
+    w64 = host.weights.astype(np.float64)
+
+    def loss(w):
+        P = H.dense_transition(host, w)
+        M = np.linalg.inv(np.eye(host.n) - F * P)
+        L = 0.0
+        for j, s in enumerate(src):
+            L += c[:, j] @ ((1 - F) * M[:, s])
+        return L
+
+    h = 1e-6
+    fd = np.array([(loss(w64 + h * np.eye(host.nnz)[e]) - loss(w64 - h * np.eye(host.nnz)[e])) / (2 * h)
+                   for e in range(host.nnz)])
+    g = pp.Graph(host)
+    X, _ = pp.ppr(g, src, iters=3000, f=F, k_tile=8, tol=1e-10)
+    _, grad, _ = pp.ppr_adjoint(g, X, torch.as_tensor(c, dtype=torch.float32, device="cuda"), iters=3000, f=F,
+                                k_tile=8, tol=1e-10)
+    gh = grad.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(gh - fd) / np.linalg.norm(fd) <= 1e-5
+
+
+def test_autograd_function():
+    host = H.random_graph(200, 900, 21, symmetric=True, connected=True)
+    gg.with_weights(host, seed=4)
+    src = np.arange(8, dtype=np.int32) * 11
+    w = torch.tensor(host.weights, device="cuda", requires_grad=True)
+    X = pp.PPRFunction.apply(w, host, src)
+    c = torch.as_tensor(gg.normal(host.n * 8, seed=1).reshape(host.n, 8), device="cuda")
+    (X * c).sum().backward()
+    Xo = _forward_fixed_point(host, src)
+    _, grad_o, _ = oracle.ppr_adjoint(host.off, host.idx, Xo, c.cpu().numpy().astype(np.float64), F, T=20000,
+                                      tol=1e-15, weights=host.weights)
+    gh = w.grad.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(gh - grad_o) / np.linalg.norm(grad_o) <= 1e-5
