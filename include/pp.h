@@ -239,6 +239,32 @@ pp_status pp_ppr_adjoint(pp_graph g, pp_dir dir, int32_t k, const float* X, cons
                          float tol, float f, int32_t k_tile, float* Lambda, float* grad_w, void* scratch,
                          size_t scratch_bytes, int32_t* iters_done, void* stream);
 
+/* ------------------------------------------------------- many graphs */
+/* Device workspace bytes for pp_multi_run over num_graphs graphs holding
+ * total_vertices vertices together. */
+size_t pp_multi_workspace_bytes(int32_t num_graphs, int64_t total_vertices);
+
+/* PageRank and BFS for many small unweighted graphs in one launch (beyond
+ * the paper, which sweeps one graph at a time).  Graph i has graph_n[i]
+ * vertices (1..16384) and graph_nnz[i] stored edges (HOST arrays).  Arenas
+ * (device): off/in_off hold each graph's n+1 local offsets back to back (CSR
+ * = out-adjacency, CSC = in-adjacency; may alias for symmetric graphs);
+ * idx/in_idx each graph's local neighbour ids back to back; x (float),
+ * level and parent (int32) each graph's n entries back to back.  Runs
+ * pr_iters Jacobi steps of the PageRank equation (Sec. 3.1; x_0 = 1/n) in
+ * direction pr_dir, then, unless bfs_policy is -1, a BFS from local vertex
+ * bfs_root of every graph with policy PP_PUSH / PP_PULL / PP_SWITCH
+ * (alpha, beta as in pp_bfs_run).  One workgroup holds one graph's state in
+ * LDS: pull gathers and push updates are LDS operations and the barrier
+ * between sweeps is a workgroup barrier.  Pull sums with compensated FP32
+ * additions; push accumulates in FP64 LDS atomics.  Graphs are taken largest
+ * first.  SYNC. */
+pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, const int64_t* graph_nnz,
+                       const int32_t* off, const int32_t* idx, const int32_t* in_off, const int32_t* in_idx,
+                       pp_dir pr_dir, int32_t pr_iters, float f, float* x,
+                       int32_t bfs_policy, int32_t bfs_root, float alpha, float beta,
+                       int32_t* level, int32_t* parent, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

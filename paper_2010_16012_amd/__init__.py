@@ -15,7 +15,7 @@ from ._lib import (PP_PULL, PP_PUSH, PP_SWITCH, PPError, BfsStats)  # noqa: F401
 from ._lib import *  # noqa: F401,F403  (the C names)
 
 __all__ = ["Graph", "BfsRun", "PPError", "PP_PUSH", "PP_PULL", "PP_SWITCH", "pagerank", "pagerank_into", "bfs",
-           "ppr", "ppr_adjoint", "PPRFunction"]
+           "ppr", "ppr_adjoint", "PPRFunction", "MultiGraph"]
 
 
 class Graph:
@@ -188,3 +188,45 @@ class PPRFunction(torch.autograd.Function):
         f, iters, tol, k_tile, adir = ctx.cfg
         _, grad, _ = ppr_adjoint(ctx.g, X, dX.float(), iters=iters, f=f, k_tile=k_tile, direction=adir, tol=tol)
         return grad, None, None, None, None, None, None, None, None, None
+
+
+class MultiGraph:
+    """Many small symmetric (or directed, with in-adjacency) graphs in one
+    device arena, for pp_multi_run."""
+
+    def __init__(self, hosts, device="cuda"):
+        import numpy as np
+        self.hosts = hosts
+        self.n = np.array([h.n for h in hosts], dtype=np.int32)
+        self.nnz = np.array([int(h.off[-1]) for h in hosts], dtype=np.int64)
+        dev = torch.device(device)
+        cat = lambda arrs: torch.as_tensor(np.concatenate(arrs).astype(np.int32)).to(dev)  # noqa: E731
+        self.off = cat([h.off for h in hosts])
+        self.idx = cat([h.idx for h in hosts] + [np.zeros(1, np.int32)])
+        directed = [h for h in hosts if getattr(h, "in_off", None) is not None and h.in_off is not h.off]
+        if directed:
+            for h in hosts:
+                if getattr(h, "in_off", None) is None:
+                    h.ensure_transpose()
+            self.in_off = cat([h.in_off for h in hosts])
+            self.in_idx = cat([h.in_idx for h in hosts] + [np.zeros(1, np.int32)])
+        else:
+            self.in_off, self.in_idx = self.off, self.idx
+        self.total_n = int(self.n.sum())
+        self.ws = torch.empty(max(_lib.pp_multi_workspace_bytes(len(hosts), self.total_n), 1), dtype=torch.uint8,
+                              device=dev)
+        self.device = dev
+
+    def run(self, pr_iters=20, f=0.85, pr_dir=PP_PULL, bfs_policy=PP_SWITCH, bfs_root=0, alpha=14.0, beta=24.0,
+            stream=None):
+        x = torch.empty(max(self.total_n, 1), dtype=torch.float32, device=self.device)
+        level = torch.empty(max(self.total_n, 1), dtype=torch.int32, device=self.device)
+        parent = torch.empty_like(level)
+        _lib.pp_multi_run(self.n, self.nnz, self.off, self.idx, self.in_off, self.in_idx, pr_dir, pr_iters, f, x,
+                          bfs_policy, bfs_root, alpha, beta, level, parent, self.ws, stream)
+        return x, level, parent
+
+    def split(self, t):
+        import numpy as np
+        bounds = np.concatenate([[0], np.cumsum(self.n)])
+        return [t[bounds[i]:bounds[i + 1]] for i in range(len(self.n))]

@@ -78,6 +78,9 @@ _SIGS = {
     "pp_bfs_frontier": ([_P, _P, ctypes.POINTER(_I32), _P], ctypes.c_int),
     "pp_bfs_run": ([_P, _I32, ctypes.c_int, _F32, _F32, _P, _P, _P, _SZ, ctypes.POINTER(BfsStats), _P], ctypes.c_int),
     "pp_ppr_scratch_bytes": ([_P, _I32, _I32], _SZ),
+    "pp_multi_workspace_bytes": ([_I32, _I64], _SZ),
+    "pp_multi_run": ([_I32, _P, _P, _P, _P, _P, _P, ctypes.c_int, _I32, _F32, _P, _I32, _I32, _F32, _F32, _P, _P, _P,
+                      _SZ, _P], ctypes.c_int),
     "pp_ppr_run": ([_P, ctypes.c_int, _I32, _P, _I32, _F32, _F32, _I32, _P, _P, _SZ, ctypes.POINTER(_I32), _P],
                    ctypes.c_int),
     "pp_ppr_adjoint": ([_P, ctypes.c_int, _I32, _P, _P, _I32, _F32, _F32, _I32, _P, _P, _P, _SZ,
@@ -233,3 +236,18 @@ def pp_ppr_adjoint(h, direction, k, X, dLdX, iters, tol, f, k_tile, Lambda, grad
     _check(_lib.pp_ppr_adjoint(h, direction, k, _ptr(X), _ptr(dLdX), iters, tol, f, k_tile, _ptr(Lambda),
                                _ptr(grad_w), _ptr(scratch), scratch.numel(), ctypes.byref(done), _stream(stream)))
     return done.value
+
+
+def pp_multi_workspace_bytes(num_graphs: int, total_vertices: int) -> int:
+    return _lib.pp_multi_workspace_bytes(num_graphs, total_vertices)
+
+
+def pp_multi_run(graph_n, graph_nnz, off, idx, in_off, in_idx, pr_dir, pr_iters, f, x, bfs_policy, bfs_root,
+                 alpha, beta, level, parent, ws, stream=None) -> None:
+    """graph_n (int32) and graph_nnz (int64) are host numpy arrays; the rest device tensors."""
+    import numpy as np
+    gn = np.ascontiguousarray(graph_n, dtype=np.int32)
+    ge = np.ascontiguousarray(graph_nnz, dtype=np.int64)
+    _check(_lib.pp_multi_run(len(gn), ctypes.c_void_p(gn.ctypes.data), ctypes.c_void_p(ge.ctypes.data), _ptr(off),
+                             _ptr(idx), _ptr(in_off), _ptr(in_idx), pr_dir, pr_iters, f, _ptr(x), bfs_policy,
+                             bfs_root, alpha, beta, _ptr(level), _ptr(parent), _ptr(ws), ws.numel(), _stream(stream)))

@@ -1,0 +1,346 @@
+// Many small graphs in one launch: PageRank (push or pull) and BFS for every
+// graph of a concatenated arena, one workgroup per graph.
+//
+// Parallelism beyond one graph (the paper's sweeps are per graph; Sec. 4
+// assumes up to one processor per vertex): a graph of at most kMultiMaxN
+// vertices keeps its whole per-vertex state in the LDS of one compute unit,
+// so the pull gathers and the push updates are LDS operations (ds_read /
+// ds_add_f32) and the barrier between two sweeps is a workgroup barrier --
+// no grid-wide synchronisation, no spin waits.  Workgroups take graphs
+// largest first (longest-processing-time order) so the big graphs start
+// first and small ones fill in.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "pp_common.h"
+
+namespace pp {
+
+constexpr int kMultiBlock = 1024;
+constexpr int kMultiGroup = 8;  // lanes per row
+constexpr int32_t kMultiMaxN = 16384;
+
+struct MultiEntry {
+    int64_t vbase;  // first vertex of the graph in the vertex arenas (x, level, parent)
+    int64_t obase;  // first entry of the graph's n+1 offsets in the offset arenas
+    int64_t ebase;  // first slot of the graph in the index arenas
+    int32_t n;
+    int32_t nnz;
+};
+
+struct MultiArgs {
+    const MultiEntry* table;  // LPT order
+    int32_t count;
+    const int32_t* off;       // per graph: n+1 local offsets, graphs back to back
+    const int32_t* idx;       // local vertex ids
+    const int32_t* in_off;
+    const int32_t* in_idx;
+    int32_t pr_dir;
+    int32_t pr_iters;
+    float f;
+    float* x;                 // PageRank output, arena of vertices
+    float* c_scratch;         // push: contributions, arena of vertices
+    int32_t bfs_policy;       // -1: no BFS
+    int32_t root;             // local root of every graph
+    float alpha, beta;
+    int32_t* level;
+    int32_t* parent;
+};
+
+__device__ __forceinline__ uint32_t bit_of(const uint32_t* bm, int32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
+
+__global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
+    extern __shared__ float lds[];
+    __shared__ int32_t s_cnt[4];
+    __shared__ int64_t s_m[2];
+    const int32_t gi = blockIdx.x;
+    if (gi >= a.count) return;
+    const MultiEntry e = a.table[gi];
+    const int32_t n = e.n;
+    const int32_t* off = a.off + e.obase;
+    const int32_t* idx = a.idx + e.ebase;
+    const int32_t* in_off = a.in_off + e.obase;
+    const int32_t* in_idx = a.in_idx + e.ebase;
+    const int tid = threadIdx.x;
+    const int lane = tid % kMultiGroup;
+    const int grp = tid / kMultiGroup;
+    constexpr int groups = kMultiBlock / kMultiGroup;
+
+    // ---------------------------------------------------------------- PageRank
+    if (a.pr_iters > 0) {
+        const float base = (1.0f - a.f) / (float)n;
+        if (a.pr_dir == PP_PULL) {
+            float* s_c = lds;       // contributions of the current iterate
+            float* s_y = lds + n;   // contributions of the next one
+            for (int32_t u = tid; u < n; u += kMultiBlock) {
+                const int32_t d = off[u + 1] - off[u];
+                s_c[u] = d > 0 ? a.f * (1.0f / (float)n) / (float)d : 0.f;
+            }
+            __syncthreads();
+            for (int32_t t = 0; t < a.pr_iters; ++t) {
+                const bool last = (t == a.pr_iters - 1);
+                // owner of u gathers over its in-row (compensated sum per lane)
+                for (int32_t u = grp; u < n; u += groups) {
+                    float acc = 0.f, comp = 0.f;
+                    for (int32_t j = in_off[u] + lane; j < in_off[u + 1]; j += kMultiGroup) {
+                        const float yk = s_c[in_idx[j]] - comp;
+                        const float tk = acc + yk;
+                        comp = (tk - acc) - yk;
+                        acc = tk;
+                    }
+#pragma unroll
+                    for (int s = kMultiGroup / 2; s > 0; s >>= 1) acc += __shfl_xor(acc, s);
+                    if (lane == 0) {
+                        const float y = base + acc;
+                        const int32_t d = off[u + 1] - off[u];
+                        s_y[u] = d > 0 ? a.f * y / (float)d : 0.f;
+                        if (last) a.x[e.vbase + u] = y;
+                    }
+                }
+                __syncthreads();
+                float* tmp = s_c;
+                s_c = s_y;
+                s_y = tmp;
+            }
+        } else {
+            // every out-edge adds the source's contribution to an FP64 LDS
+            // accumulator (the order of the adds is arbitrary); contributions
+            // live in the global scratch arena
+            double* s_acc = reinterpret_cast<double*>(lds);
+            float* c = a.c_scratch + e.vbase;
+            for (int32_t u = tid; u < n; u += kMultiBlock) {
+                const int32_t d = off[u + 1] - off[u];
+                c[u] = d > 0 ? a.f * (1.0f / (float)n) / (float)d : 0.f;
+                s_acc[u] = 0.0;
+            }
+            __syncthreads();
+            for (int32_t t = 0; t < a.pr_iters; ++t) {
+                const bool last = (t == a.pr_iters - 1);
+                for (int32_t v = grp; v < n; v += groups) {
+                    const float cv = c[v];
+                    if (cv == 0.f) continue;
+                    for (int32_t j = off[v] + lane; j < off[v + 1]; j += kMultiGroup)
+                        atomicAdd(&s_acc[idx[j]], (double)cv);
+                }
+                __syncthreads();
+                for (int32_t u = tid; u < n; u += kMultiBlock) {
+                    const float y = base + (float)s_acc[u];
+                    const int32_t d = off[u + 1] - off[u];
+                    c[u] = d > 0 ? a.f * y / (float)d : 0.f;
+                    s_acc[u] = 0.0;
+                    if (last) a.x[e.vbase + u] = y;
+                }
+                __syncthreads();
+            }
+        }
+    }
+
+    // ---------------------------------------------------------------- BFS
+    if (a.bfs_policy < 0) return;
+    const int32_t words = (n + 31) / 32;
+    uint32_t* s_front = reinterpret_cast<uint32_t*>(lds);
+    uint32_t* s_next = s_front + words;
+    uint32_t* s_vis = s_next + words;
+    const int32_t root = a.root;
+    for (int32_t v = tid; v < n; v += kMultiBlock) {
+        a.level[e.vbase + v] = (v == root) ? 0 : -1;
+        a.parent[e.vbase + v] = (v == root) ? root : -1;
+    }
+    for (int32_t w = tid; w < words; w += kMultiBlock) {
+        const uint32_t m = (w == (root >> 5)) ? (1u << (root & 31)) : 0u;
+        s_front[w] = m;
+        s_vis[w] = m;
+        s_next[w] = 0u;
+    }
+    if (tid == 0) {
+        s_cnt[0] = 1;                          // |F|
+        s_m[0] = off[root + 1] - off[root];    // out-edges of F
+        s_m[1] = (int64_t)(off[n] - off[root + 1] + off[root]);  // out-edges of unvisited vertices
+        s_cnt[2] = PP_PUSH;                    // previous direction
+        s_cnt[3] = 0;                          // previous |F|
+    }
+    __syncthreads();
+    for (int32_t lvl = 0;; ++lvl) {
+        const int32_t nf = s_cnt[0];
+        if (nf == 0) break;
+        const int64_t mf = s_m[0], mu = s_m[1];
+        int32_t dir = a.bfs_policy;
+        if (dir == PP_SWITCH) {
+            if (lvl == 0 || s_cnt[2] == PP_PUSH) dir = ((double)mf > (double)mu / a.alpha) ? PP_PULL : PP_PUSH;
+            else dir = ((double)nf < (double)n / a.beta && nf < s_cnt[3]) ? PP_PUSH : PP_PULL;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            s_cnt[1] = 0;
+            s_cnt[2] = dir;
+            s_cnt[3] = nf;
+        }
+        if (tid < 2) s_m[tid] = 0;  // s_m[0] accumulates new out-edges; s_m[1] is recomputed below
+        __syncthreads();
+        int32_t my_new = 0;
+        int64_t my_deg = 0;
+        if (dir == PP_PUSH) {
+            // frontier vertices claim unvisited out-neighbours (LDS atomic OR)
+            for (int32_t v = grp; v < n; v += groups) {
+                if (!bit_of(s_front, v)) continue;
+                for (int32_t j = off[v] + lane; j < off[v + 1]; j += kMultiGroup) {
+                    const int32_t u = idx[j];
+                    const uint32_t b = 1u << (u & 31);
+                    if (s_vis[u >> 5] & b) continue;
+                    const uint32_t old = atomicOr(&s_vis[u >> 5], b);
+                    if (!(old & b)) {
+                        atomicOr(&s_next[u >> 5], b);
+                        a.level[e.vbase + u] = lvl + 1;
+                        a.parent[e.vbase + u] = v;
+                        my_new += 1;
+                        my_deg += off[u + 1] - off[u];
+                    }
+                }
+            }
+        } else {
+            // unvisited vertices look for a frontier in-neighbour, first in stored order
+            for (int32_t v = grp; v < n; v += groups) {
+                if (bit_of(s_vis, v)) continue;
+                const int32_t b0 = in_off[v], e0 = in_off[v + 1];
+                int32_t hit = INT32_MAX;
+                for (int32_t jb = b0; jb < e0 && hit == INT32_MAX; jb += kMultiGroup) {
+                    const int32_t j = jb + lane;
+                    const bool h = (j < e0) && bit_of(s_front, in_idx[j]);
+                    int32_t pos = h ? j : INT32_MAX;
+#pragma unroll
+                    for (int s = kMultiGroup / 2; s > 0; s >>= 1) pos = min(pos, __shfl_xor(pos, s));
+                    hit = pos;
+                }
+                if (hit != INT32_MAX && lane == 0) {
+                    atomicOr(&s_next[v >> 5], 1u << (v & 31));  // words are shared by groups
+                    a.level[e.vbase + v] = lvl + 1;
+                    a.parent[e.vbase + v] = in_idx[hit];
+                    my_new += 1;
+                    my_deg += off[v + 1] - off[v];
+                }
+            }
+        }
+        if (my_new) {
+            atomicAdd(&s_cnt[1], my_new);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&s_m[0]), (unsigned long long)my_deg);
+        }
+        __syncthreads();
+        // next frontier; bottom-up discoveries become visited now
+        for (int32_t w = tid; w < words; w += kMultiBlock) {
+            const uint32_t nw = s_next[w];
+            s_front[w] = nw;
+            s_vis[w] |= nw;
+            s_next[w] = 0u;
+        }
+        if (tid == 0) {
+            s_cnt[0] = s_cnt[1];
+            s_m[1] = mu - s_m[0];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ host side
+struct MultiLayout {
+    size_t table, cbuf, total;
+};
+
+static MultiLayout multi_layout(int32_t count, int64_t total_n) {
+    MultiLayout L{};
+    L.table = 0;
+    L.cbuf = align_up((size_t)std::max(count, 1) * sizeof(MultiEntry), 256);
+    L.total = L.cbuf + align_up((size_t)std::max<int64_t>(total_n, 1) * 4, 256);
+    return L;
+}
+
+}  // namespace pp
+
+using namespace pp;
+
+PP_EXPORT size_t pp_multi_workspace_bytes(int32_t num_graphs, int64_t total_vertices) {
+    if (num_graphs < 0 || total_vertices < 0) return 0;
+    return multi_layout(num_graphs, total_vertices).total;
+}
+
+PP_EXPORT pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, const int64_t* graph_nnz,
+                                 const int32_t* off, const int32_t* idx, const int32_t* in_off,
+                                 const int32_t* in_idx, pp_dir pr_dir, int32_t pr_iters, float f, float* x,
+                                 int32_t bfs_policy, int32_t bfs_root, float alpha, float beta, int32_t* level,
+                                 int32_t* parent, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (num_graphs < 0) return set_error(PP_E_SIZE, "num_graphs must be >= 0");
+    if (num_graphs == 0) return PP_OK;
+    if (!graph_n || !graph_nnz) return set_error(PP_E_NULL, "graph_n and graph_nnz (host arrays) are required");
+    if (!off || !in_off || !ws) return set_error(PP_E_NULL, "off, in_off and ws are required");
+    if (pr_dir != PP_PUSH && pr_dir != PP_PULL) return set_error(PP_E_RANGE, "pr_dir must be PP_PUSH or PP_PULL");
+    if (pr_iters < 0) return set_error(PP_E_RANGE, "pr_iters must be >= 0");
+    if (pr_iters > 0 && !x) return set_error(PP_E_NULL, "x is required when pr_iters > 0");
+    if (!(f >= 0.f && f < 1.f)) return set_error(PP_E_RANGE, "f must lie in [0, 1)");
+    if (bfs_policy != -1 && bfs_policy != PP_PUSH && bfs_policy != PP_PULL && bfs_policy != PP_SWITCH)
+        return set_error(PP_E_RANGE, "bfs_policy must be -1, PP_PUSH, PP_PULL or PP_SWITCH");
+    if (bfs_policy >= 0 && (!level || !parent)) return set_error(PP_E_NULL, "level and parent are required for BFS");
+    if (!(alpha > 0.f)) alpha = 14.f;
+    if (!(beta > 0.f)) beta = 24.f;
+    std::vector<MultiEntry> ent(num_graphs);
+    int64_t vb = 0, eb = 0, max_n = 1, total_nnz = 0;
+    for (int32_t i = 0; i < num_graphs; ++i) {
+        if (graph_n[i] < 1 || graph_n[i] > kMultiMaxN)
+            return set_error(PP_E_SIZE, "every graph needs 1 <= n <= 16384 vertices");
+        if (graph_nnz[i] < 0 || graph_nnz[i] > INT32_MAX) return set_error(PP_E_SIZE, "graph nnz out of range");
+        if (bfs_policy >= 0 && (bfs_root < 0 || bfs_root >= graph_n[i]))
+            return set_error(PP_E_RANGE, "bfs_root must be a vertex of every graph");
+        ent[i] = MultiEntry{vb, vb + i, eb, graph_n[i], (int32_t)graph_nnz[i]};
+        vb += graph_n[i];
+        eb += graph_nnz[i];
+        total_nnz += graph_nnz[i];
+        max_n = std::max<int64_t>(max_n, graph_n[i]);
+    }
+    if (total_nnz > 0 && (!idx || !in_idx)) return set_error(PP_E_NULL, "idx and in_idx are required");
+    const MultiLayout ML = multi_layout(num_graphs, vb);
+    if (ws_bytes < ML.total) return set_error(PP_E_WORKSPACE, "workspace too small");
+    // largest graphs first (workgroups are dispatched roughly in index order)
+    std::vector<int32_t> order(num_graphs);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t p, int32_t q) {
+        return (int64_t)ent[p].nnz + ent[p].n > (int64_t)ent[q].nnz + ent[q].n;
+    });
+    std::vector<MultiEntry> dev(num_graphs);
+    for (int32_t i = 0; i < num_graphs; ++i) dev[i] = ent[order[i]];
+    int dev_id = 0, lds_cu = 0;
+    PP_HIP(hipGetDevice(&dev_id));
+    PP_HIP(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerBlock, dev_id));
+    const size_t lds = std::max<size_t>((size_t)max_n * 8, (size_t)3 * ((max_n + 31) / 32) * 4);
+    if (lds > (size_t)lds_cu) return set_error(PP_E_UNSUPPORTED, "graphs too large for one workgroup's LDS");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    MultiEntry* table = static_cast<MultiEntry*>(ws);
+    PP_HIP(hipMemcpyAsync(table, dev.data(), sizeof(MultiEntry) * num_graphs, hipMemcpyHostToDevice, st));
+    MultiArgs a;
+    a.table = table;
+    a.count = num_graphs;
+    a.off = off;
+    a.idx = idx;
+    a.in_off = in_off;
+    a.in_idx = in_idx;
+    a.pr_dir = pr_dir;
+    a.pr_iters = pr_iters;
+    a.f = f;
+    a.x = x;
+    a.c_scratch = reinterpret_cast<float*>(static_cast<char*>(ws) + ML.cbuf);
+    a.bfs_policy = bfs_policy;
+    a.root = bfs_root;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.level = level;
+    a.parent = parent;
+    if (lds > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_multi), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+    hipLaunchKernelGGL(k_multi, dim3(num_graphs), dim3(kMultiBlock), lds, st, a);
+    PP_LAUNCH_CHECK("k_multi");
+    // the host table must outlive the asynchronous copy
+    PP_HIP(hipStreamSynchronize(st));
+    return PP_OK;
+}

@@ -1,0 +1,77 @@
+"""Many small graphs in one launch: PageRank and BFS per graph against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+import paper_2010_16012_amd as pp
+from tests import helpers as H
+from tests.gpu_util import F, PR_L1_TOL, announce
+
+pytestmark = pytest.mark.gpu
+
+
+def _mixed_graphs():
+    gs = gg.rmat_batch(24, 6, 12, seed=4)
+    gs += [gg.from_edges(1, [], [], True), gg.from_edges(50, [1, 2], [2, 3], True), H.path(300), H.star(1000),
+           H.full_grid(30, 40), H.complete(33)]
+    return gs
+
+
+def _check(gs, policies=(pp.PP_PUSH, pp.PP_PULL, pp.PP_SWITCH), dirs=(pp.PP_PULL, pp.PP_PUSH), iters=20):
+    mg = pp.MultiGraph(gs)
+    for d in dirs:
+        for pol in policies:
+            announce(f"multi graphs={len(gs)} pr_dir={d} bfs={pol}")
+            x, lv, par = mg.run(pr_iters=iters, f=F, pr_dir=d, bfs_policy=pol)
+            torch.cuda.synchronize()
+            xs, lvs, pars = mg.split(x.cpu().numpy()), mg.split(lv.cpu().numpy()), mg.split(par.cpu().numpy())
+            for h, xi, li, pi in zip(gs, xs, lvs, pars):
+                want = oracle.pagerank(h.off, h.idx, F, iters)
+                assert np.abs(xi.astype(np.float64) - want).sum() <= PR_L1_TOL, h.name
+                wl, _, _ = oracle.bfs(h.off, h.idx, 0)
+                assert np.array_equal(li, wl), h.name
+                assert H.bfs_violations(h, 0, li, pi) == [], h.name
+
+
+def test_mixed_batch_all_directions_and_policies():
+    _check(_mixed_graphs())
+
+
+def test_directed_batch():
+    gs = [H.random_graph(n, 4 * n, s, symmetric=False) for s, n in enumerate([10, 500, 3000, 7000])]
+    for h in gs:
+        h.ensure_transpose()
+    _check(gs, policies=(pp.PP_PULL, pp.PP_SWITCH, pp.PP_PUSH))
+
+
+def test_pr_only_and_bfs_only():
+    gs = gg.rmat_batch(6, 8, 10, seed=9)
+    mg = pp.MultiGraph(gs)
+    x, _, _ = mg.run(pr_iters=0, bfs_policy=pp.PP_SWITCH)
+    _, lv, _ = mg.run(pr_iters=5, f=F, bfs_policy=-1)
+
+
+def test_size_limit_and_errors():
+    with pytest.raises(pp.PPError):
+        pp.MultiGraph([gg.rmat(15, 2, seed=1)]).run()
+    mg = pp.MultiGraph([H.path(5)])
+    with pytest.raises(pp.PPError):
+        mg.run(bfs_root=7)
+
+
+@pytest.mark.slow
+def test_batch_of_512_rmat_graphs():
+    gs = gg.rmat_batch(512, 8, 14, seed=1)
+    mg = pp.MultiGraph(gs)
+    for d in (pp.PP_PULL, pp.PP_PUSH):
+        x, lv, par = mg.run(pr_iters=20, f=F, pr_dir=d, bfs_policy=pp.PP_SWITCH)
+        xs, lvs = mg.split(x.cpu().numpy()), mg.split(lv.cpu().numpy())
+        rng = np.random.default_rng(0)
+        for i in rng.choice(len(gs), 48, replace=False):
+            h = gs[i]
+            want = oracle.pagerank(h.off, h.idx, F, 20)
+            assert np.abs(xs[i].astype(np.float64) - want).sum() <= PR_L1_TOL
+            wl, _, _ = oracle.bfs(h.off, h.idx, 0)
+            assert np.array_equal(lvs[i], wl)
