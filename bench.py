@@ -45,6 +45,11 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
+    p.add_argument("--workload", default="rmat22",
+                   help="rmat22 (default: the headline step), or a supplementary measurement: "
+                        "ppr20, multi512, grid4096, er22, adjoint20")
+    p.add_argument("--tuned", default=os.path.join(ROOT, "paper_2010_16012_amd", "tuned.json"),
+                   help="autotuner cache to apply (ignored when missing)")
     return p.parse_args()
 
 
@@ -83,6 +88,10 @@ def main():
     import graphgen as gg
     import paper_2010_16012_amd as pp
 
+    if args.workload != "rmat22":
+        return supplementary(args)
+    from paper_2010_16012_amd import autotune
+
     parts = ["pr_pull", "pr_push", "bfs_push", "bfs_pull", "bfs_switch"]
     if args.only:
         parts = [p for p in parts if p in args.only.split(",")]
@@ -102,6 +111,9 @@ def main():
         root_edges = comp_edges[comp[roots]] / 2.0
         del A
 
+    tuned = autotune.load(args.tuned, n, nnz) if os.path.exists(args.tuned) else {}
+    autotune.apply(tuned)
+    alpha, beta = tuned.get("alpha", 14.0), tuned.get("beta", 24.0)
     t_up = time.time()
     g = pp.Graph(host, device=dev)
     torch.cuda.synchronize()
@@ -125,7 +137,7 @@ def main():
             else:
                 r = runs[p]
                 for root in roots:
-                    r.run(int(root), policy[p])
+                    r.run(int(root), policy[p], alpha, beta)
             e1 = ev()
             times.setdefault(p, []).append((e0, e1))
 
@@ -209,11 +221,113 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"rmat{args.scale}_ef16_seed1_sym: PageRank x{PR_ITERS} pull+push, "
                                f"BFS from {len(roots)} roots push/pull/switch",
-                   "n": n, "nnz": nnz, "parts": parts},
+                   "n": n, "nnz": nnz, "parts": parts, "tuning": tuned or "defaults"},
         "parts": out_parts,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(line), flush=True)
+
+
+def _events_ms(fn):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def supplementary(args):
+    """Measurements of the other configurations (one JSON line each)."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_2010_16012_amd as pp
+    from paper_2010_16012_amd import autotune
+
+    w = args.workload
+    line = {"workload": w, "n_gpus": 1, "data": "synthetic"}
+    if w == "ppr20":
+        # personalised PageRank, R-MAT 20, k = 256 seeded non-isolated sources, 30 sweeps
+        host = gg.rmat(20, 16, seed=1)
+        src = gg.pick_vertices(host, 256, seed=2)
+        tuned = autotune.load(args.tuned, host.n, host.nnz)
+        autotune.apply(tuned)
+        kt = tuned.get("k_tile", 32)
+        g = pp.Graph(host)
+        for d, name in ((pp.PP_PULL, "pull"), (pp.PP_PUSH, "push")):
+            pp.ppr(g, src, iters=2, k_tile=kt, direction=d)
+            ms = _events_ms(lambda: pp.ppr(g, src, iters=30, k_tile=kt, direction=d))
+            # sequential baseline: k single-vector sweeps of the same form (the
+            # PageRank sweep does the same per-edge work for one vector)
+            x = torch.full((host.n,), 1.0 / host.n, dtype=torch.float32, device="cuda")
+            ms_sweep = _events_ms(lambda: pp.pagerank_into(g, x, 20, 0.85, d)) / 20
+            ms_seq = ms_sweep * 30 * len(src)
+            work = host.nnz * len(src) * 30
+            line[name] = {"ms": round(ms, 2), "gteps": round(work / (ms * 1e-3) / 1e9, 2),
+                          "sequential_ms_est": round(ms_seq, 1),
+                          "sequential_gteps": round(work / (ms_seq * 1e-3) / 1e9, 2),
+                          "speedup_vs_sequential": round(ms_seq / ms, 2), "k_tile": kt}
+        line.update({"n": host.n, "nnz": host.nnz, "k": 256, "iters": 30})
+    elif w == "multi512":
+        gs = gg.rmat_batch(512, 8, 14, seed=1)
+        mg = pp.MultiGraph(gs)
+        nnz = int(sum(h.nnz for h in gs))
+        for d, name in ((pp.PP_PULL, "pull"), (pp.PP_PUSH, "push")):
+            mg.run(pr_iters=20, pr_dir=d, bfs_policy=pp.PP_SWITCH)
+            ms = _events_ms(lambda: mg.run(pr_iters=20, pr_dir=d, bfs_policy=pp.PP_SWITCH))
+            line[name] = {"ms_one_launch": round(ms, 3)}
+        # baseline: the same work graph by graph through the single-graph calls (first 64 graphs, scaled)
+        sub = gs[:64]
+        graphs = [pp.Graph(h) for h in sub]
+        runs = [pp.BfsRun(g) for g in graphs]
+
+        def seq():
+            for g, r in zip(graphs, runs):
+                pp.pagerank(g, 20, 0.85, pp.PP_PULL)
+                r.run(0, pp.PP_SWITCH)
+        seq()
+        ms_sub = _events_ms(seq)
+        share = sum(h.nnz for h in sub) / nnz
+        line["sequential_ms_est"] = round(ms_sub / share, 2)
+        line["speedup_vs_sequential_pull"] = round(ms_sub / share / line["pull"]["ms_one_launch"], 2)
+        line.update({"graphs": 512, "total_nnz": nnz, "pr_iters": 20})
+    elif w in ("grid4096", "er22"):
+        host = gg.workload(w)
+        g = pp.Graph(host)
+        x = torch.empty(host.n, dtype=torch.float32, device="cuda")
+        for d, name in ((pp.PP_PULL, "pr_pull"), (pp.PP_PUSH, "pr_push")):
+            x.fill_(1.0 / host.n)
+            pp.pagerank_into(g, x, 2, 0.85, d)
+            ms = _events_ms(lambda: pp.pagerank_into(g, x, 20, 0.85, d))
+            line[name] = {"us_per_iter": round(ms * 1e3 / 20, 1), "gteps": round(host.nnz * 20 / (ms * 1e-3) / 1e9, 2)}
+        r = pp.BfsRun(g)
+        for pol, name in ((pp.PP_PUSH, "bfs_push"), (pp.PP_PULL, "bfs_pull"), (pp.PP_SWITCH, "bfs_switch")):
+            st = r.run(0, pol)
+            ms = _events_ms(lambda: r.run(0, pol))
+            line[name] = {"ms": round(ms, 2), "levels": st.levels,
+                          "gteps": round(st.edges_reached / 2 / (ms * 1e-3) / 1e9, 3)}
+        line.update({"n": host.n, "nnz": host.nnz})
+    elif w == "adjoint20":
+        host = gg.rmat(20, 16, seed=1)
+        gg.with_weights(host, seed=5)
+        src = gg.pick_vertices(host, 32, seed=3)
+        g = pp.Graph(host)
+        c = torch.as_tensor(gg.normal(host.n * 32, seed=1).reshape(host.n, 32), device="cuda")
+        for fd, ad, name in ((pp.PP_PUSH, pp.PP_PULL, "push_then_pull"), (pp.PP_PULL, pp.PP_PUSH, "pull_then_push")):
+            X, it_f = pp.ppr(g, src, iters=300, k_tile=32, direction=fd, tol=1e-6)
+            ms_f = _events_ms(lambda: pp.ppr(g, src, iters=it_f, k_tile=32, direction=fd))
+            _, _, it_a = pp.ppr_adjoint(g, X, c, iters=300, k_tile=32, direction=ad, tol=1e-6)
+            ms_a = _events_ms(lambda: pp.ppr_adjoint(g, X, c, iters=it_a, k_tile=32, direction=ad))
+            line[name] = {"forward_sweeps": it_f, "forward_ms": round(ms_f, 2), "adjoint_sweeps": it_a,
+                          "adjoint_ms": round(ms_a, 2)}
+        line.update({"n": host.n, "nnz": host.nnz, "k": 32})
+    else:
+        raise SystemExit(f"unknown workload {w}")
     print(json.dumps(line), flush=True)
 
 

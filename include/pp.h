@@ -217,8 +217,8 @@ size_t pp_ppr_scratch_bytes(pp_graph g, int32_t k, int32_t k_tile);
  * moves one coalesced k_tile-float row.  dir PP_PULL gathers along CSC (no
  * atomics, deterministic), PP_PUSH scatters along CSR with FP32 atomics.
  * Runs `iters` sweeps per tile, or stops a tile early once the L1 change of
- * its iterate in one sweep falls below tol (tol = 0: exactly iters; each
- * check synchronises the stream).  iters_done (host, nullable): most sweeps
+ * its iterate in one sweep is at most tol times the iterate's L1 norm (tol =
+ * 0: exactly iters; each check synchronises the stream).  iters_done (host, nullable): most sweeps
  * any tile ran.  SYNC when tol > 0 (and once to validate the sources). */
 pp_status pp_ppr_run(pp_graph g, pp_dir dir, int32_t k, const int32_t* sources, int32_t iters, float tol,
                      float f, int32_t k_tile, float* X, void* scratch, size_t scratch_bytes,

@@ -1,0 +1,165 @@
+"""Autotuner for the sweep parameters, cached as JSON.
+
+Searches, per (GPU architecture, graph size class):
+  * pull sweep: LDS-staged contributions and workgroup size;
+  * push sweep: LDS-privatised targets and persistent workgroups;
+  * BFS direction switch: the alpha/beta constants of the switch rule;
+  * personalised PageRank: the column tile width for a given k.
+Every candidate is timed with HIP events on the device; the fastest wins.
+The cache maps "arch|size class" to the chosen values; ``apply`` installs a
+cached entry through the library's tuning entry points.
+
+CLI: python -m paper_2010_16012_amd.autotune --scale 22 --out tuned.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+
+import numpy as np
+import torch
+
+from . import PP_PULL, PP_PUSH, PP_SWITCH, BfsRun, Graph, _lib, pagerank_into, ppr
+
+DEFAULTS = {"upper": [4, 16, 64, 1024, 4096], "split_chunk": 4096, "hot": 8192, "push_blocks": 1024,
+            "pull_hot": 32768, "pull_block": 1024, "alpha": 14.0, "beta": 24.0, "k_tile": 32}
+
+
+def arch() -> str:
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def size_class(n: int, nnz: int) -> str:
+    return f"n2^{int(round(math.log2(max(n, 1))))}_m2^{int(round(math.log2(max(nnz, 1))))}"
+
+
+def key(n: int, nnz: int) -> str:
+    return f"{arch()}|{size_class(n, nnz)}"
+
+
+def apply(cfg: dict) -> None:
+    c = dict(DEFAULTS)
+    c.update(cfg or {})
+    _lib.pp_set_bin_thresholds(c["upper"], c["split_chunk"])
+    _lib.pp_set_push_tuning(c["hot"], c["push_blocks"])
+    _lib.pp_set_pull_tuning(c["pull_hot"], c["pull_block"])
+
+
+def load(path: str, n: int, nnz: int) -> dict:
+    """Cached entry for this GPU and size class (empty when absent)."""
+    if not path or not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        return json.load(fh).get(key(n, nnz), {})
+
+
+def _time(fn, reps=3) -> float:
+    fn()  # warm up
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def tune_pagerank(host, iters=5, log=print) -> dict:
+    """Best pull and push settings for this graph."""
+    out = {}
+    x = torch.empty(host.n, dtype=torch.float32, device="cuda")
+
+    def run(g, d):
+        def f():
+            x.fill_(1.0 / host.n)
+            pagerank_into(g, x, iters, 0.85, d)
+        return _time(f)
+
+    best = None
+    for pull_hot in (16384, 32768, 40960):
+        for block in (512, 1024):
+            apply({"pull_hot": pull_hot, "pull_block": block})
+            g = Graph(host)
+            t = run(g, PP_PULL)
+            g.close()
+            log(f"pull hot={pull_hot} block={block}: {t / iters * 1e3:.1f} us/iter")
+            if best is None or t < best[0]:
+                best = (t, pull_hot, block)
+    out["pull_hot"], out["pull_block"] = best[1], best[2]
+    best = None
+    for hot in (8192, 16384):
+        for blocks in (512, 1024, 2048):
+            apply({"hot": hot, "push_blocks": blocks, "pull_hot": out["pull_hot"], "pull_block": out["pull_block"]})
+            g = Graph(host)
+            t = run(g, PP_PUSH)
+            g.close()
+            log(f"push hot={hot} blocks={blocks}: {t / iters * 1e3:.1f} us/iter")
+            if best is None or t < best[0]:
+                best = (t, hot, blocks)
+    out["hot"], out["push_blocks"] = best[1], best[2]
+    apply(out)
+    return out
+
+
+def tune_bfs_switch(host, roots, log=print) -> dict:
+    """alpha/beta of the direction switch with the best harmonic-mean rate."""
+    g = Graph(host)
+    r = BfsRun(g)
+    best = None
+    for alpha in (2.0, 4.0, 8.0, 14.0, 24.0):
+        for beta in (8.0, 24.0, 64.0):
+            def f():
+                for root in roots:
+                    r.run(int(root), PP_SWITCH, alpha, beta)
+            t = _time(f, reps=2)
+            log(f"bfs alpha={alpha} beta={beta}: {t / len(roots):.3f} ms/root")
+            if best is None or t < best[0]:
+                best = (t, alpha, beta)
+    g.close()
+    return {"alpha": best[1], "beta": best[2]}
+
+
+def tune_ppr_tile(host, k, iters=3, log=print) -> dict:
+    g = Graph(host)
+    src = np.arange(k, dtype=np.int32) % host.n
+    best = None
+    for kt in (8, 16, 32, 64):
+        t = _time(lambda: ppr(g, src, iters=iters, k_tile=kt), reps=2)
+        log(f"ppr k={k} k_tile={kt}: {t:.2f} ms for {iters} sweeps")
+        if best is None or t < best[0]:
+            best = (t, kt)
+    g.close()
+    return {"k_tile": best[1]}
+
+
+def main():
+    import graphgen as gg
+
+    p = argparse.ArgumentParser()
+    p.add_argument("--scale", type=int, default=22)
+    p.add_argument("--roots", type=int, default=8)
+    p.add_argument("--ppr-k", type=int, default=0)
+    p.add_argument("--out", required=True)
+    a = p.parse_args()
+    host = gg.rmat(a.scale, 16, seed=1)
+    cfg = tune_pagerank(host)
+    cfg.update(tune_bfs_switch(host, gg.pick_vertices(host, a.roots, seed=1)))
+    if a.ppr_k:
+        cfg.update(tune_ppr_tile(host, a.ppr_k))
+    cache = {}
+    if os.path.exists(a.out):
+        with open(a.out) as fh:
+            cache = json.load(fh)
+    cache[key(host.n, host.nnz)] = cfg
+    with open(a.out, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    print(json.dumps({key(host.n, host.nnz): cfg}))
+
+
+if __name__ == "__main__":
+    main()

@@ -96,8 +96,9 @@ struct KArgs {
     float* resid_part;      // per-unit-group residual partials (nullable)
 };
 
+// Returns (|new - previous|, |new|) for the relative convergence test.
 template <int KT>
-__device__ __forceinline__ float kt_epilogue(const KArgs& a, int32_t u, int lane, float acc) {
+__device__ __forceinline__ float2 kt_epilogue(const KArgs& a, int32_t u, int lane, float acc) {
     float val;
     if (a.kind == kEpiForward) {
         val = acc + ((a.src_int[a.col0 + lane] == u) ? 1.0f - a.f : 0.f);
@@ -111,7 +112,23 @@ __device__ __forceinline__ float kt_epilogue(const KArgs& a, int32_t u, int lane
     }
     a.out_tile[(size_t)u * KT + lane] = val;
     if (a.out_caller && a.col0 + lane < a.k) a.out_caller[(size_t)user_id(a.perm, u) * a.k + a.col0 + lane] = val;
-    return a.prev ? fabsf(val - a.prev[(size_t)u * KT + lane]) : 0.f;
+    return a.prev ? make_float2(fabsf(val - a.prev[(size_t)u * KT + lane]), fabsf(val)) : make_float2(0.f, 0.f);
+}
+
+// Fixed-order workgroup sum of (difference, norm) pairs into out[2*slot].
+__device__ __forceinline__ void resid_flush(float2 r, float* red, float* out, int32_t slot) {
+    red[threadIdx.x] = r.x;
+    red[kBlock + threadIdx.x] = r.y;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float d = 0.f, m = 0.f;
+        for (int i = 0; i < kBlock; ++i) {
+            d += red[i];
+            m += red[kBlock + i];
+        }
+        out[2 * slot] = d;
+        out[2 * slot + 1] = m;
+    }
 }
 
 // One group of KT lanes sums src[idx[j]] (x wt[j]) over j = b + g, b + g + stride, ...
@@ -159,14 +176,14 @@ __device__ __forceinline__ float kt_block_sum(float v, float* red) {
 
 template <int KT, bool W>
 __global__ __launch_bounds__(kBlock) void k_kcol_pull(KArgs a) {
-    __shared__ float red[kBlock];
+    __shared__ float red[2 * kBlock];
     constexpr int G = kBlock / KT;
     const int lane = threadIdx.x % KT;
     const int grp = threadIdx.x / KT;
     const int32_t unit = blockIdx.x;
     const int bin = kunit_bin(a.kp, unit);
     const int32_t lu = unit - a.kp.unit_off[bin];
-    float res = 0.f;
+    float2 res = make_float2(0.f, 0.f);
     if (bin <= 2) {
         const int32_t i = lu * G + grp;
         if (i < a.kp.list_off[bin + 1] - a.kp.list_off[bin]) {
@@ -185,16 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_kcol_pull(KArgs a) {
         acc = kt_block_sum<KT>(acc, red);
         if (threadIdx.x < KT) a.part[(size_t)lu * KT + lane] = acc;
     }
-    if (a.resid_part) {
-        // per-workgroup residual (fixed order)
-        red[threadIdx.x] = res;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float t = 0.f;
-            for (int i = 0; i < kBlock; ++i) t += red[i];
-            a.resid_part[unit] = t;
-        }
-    }
+    if (a.resid_part) resid_flush(res, red, a.resid_part, unit);
 }
 
 // Finishes the chunked rows: partials in chunk order, then the epilogue.
@@ -202,7 +210,7 @@ template <int KT>
 __global__ __launch_bounds__(kBlock) void k_kcol_fix(KArgs a, int32_t nsplit, float* resid_fix) {
     const int lane = threadIdx.x % KT;
     const int32_t i = blockIdx.x * (kBlock / KT) + threadIdx.x / KT;
-    float res = 0.f;
+    float2 res = make_float2(0.f, 0.f);
     if (i < nsplit) {
         const int32_t* first = a.tab + 3 * a.tab_cap;
         float acc = 0.f;
@@ -210,14 +218,8 @@ __global__ __launch_bounds__(kBlock) void k_kcol_fix(KArgs a, int32_t nsplit, fl
         res = kt_epilogue<KT>(a, a.tab[first[i]], lane, acc);
     }
     if (resid_fix) {
-        __shared__ float red[kBlock];
-        red[threadIdx.x] = res;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float t = 0.f;
-            for (int j = 0; j < kBlock; ++j) t += red[j];
-            resid_fix[blockIdx.x] = t;
-        }
+        __shared__ float red[2 * kBlock];
+        resid_flush(res, red, resid_fix, blockIdx.x);
     }
 }
 
@@ -273,24 +275,16 @@ __global__ __launch_bounds__(kBlock) void k_kcol_push(KPushArgs a) {
 // forward, nothing: the teleport is added by the epilogue).
 template <int KT>
 __global__ __launch_bounds__(kBlock) void k_kcol_push_epi(KArgs a, int32_t n, double* accum) {
-    __shared__ float red[kBlock];
+    __shared__ float red[2 * kBlock];
     const int lane = threadIdx.x % KT;
     const int32_t u = blockIdx.x * (kBlock / KT) + threadIdx.x / KT;
-    float res = 0.f;
+    float2 res = make_float2(0.f, 0.f);
     if (u < n) {
         const float acc = (float)accum[(size_t)u * KT + lane];
         accum[(size_t)u * KT + lane] = 0.0;
         res = kt_epilogue<KT>(a, u, lane, acc);
     }
-    if (a.resid_part) {
-        red[threadIdx.x] = res;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float t = 0.f;
-            for (int i = 0; i < kBlock; ++i) t += red[i];
-            a.resid_part[blockIdx.x] = t;
-        }
-    }
+    if (a.resid_part) resid_flush(res, red, a.resid_part, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ helpers
@@ -340,18 +334,28 @@ __global__ void k_sources_internal(int32_t k, int32_t k_pad, const int32_t* __re
     out[j] = iperm ? iperm[s] : s;
 }
 
-// Fixed-order sum of the residual partials (one workgroup).
+// Fixed-order sum of m (difference, norm) partial pairs (one workgroup).
 __global__ __launch_bounds__(1024) void k_sum_partials(int32_t m, const float* __restrict__ p, float* __restrict__ out) {
-    __shared__ float red[1024];
-    float t = 0.f;
-    for (int32_t i = threadIdx.x; i < m; i += 1024) t += p[i];
-    red[threadIdx.x] = t;
+    __shared__ float red[2][1024];
+    float d = 0.f, q = 0.f;
+    for (int32_t i = threadIdx.x; i < m; i += 1024) {
+        d += p[2 * i];
+        q += p[2 * i + 1];
+    }
+    red[0][threadIdx.x] = d;
+    red[1][threadIdx.x] = q;
     __syncthreads();
     for (int s = 512; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        if (threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = red[0];
+    if (threadIdx.x == 0) {
+        out[0] = red[0][0];
+        out[1] = red[1][0];
+    }
 }
 
 // Edge gradient of one tile, added into grad (caller CSR slot order):
@@ -441,7 +445,7 @@ static PprLayout ppr_layout(int32_t n, int32_t split_cap, int32_t k, int32_t kt,
     L.t3 = take(tile);
     L.t4 = take(2 * tile);  // FP64 push accumulator
     L.part = take((size_t)split_cap * kt * 4);
-    L.resid = take((size_t)(max_units + ceil_div(n, 4) + 64) * 4);
+    L.resid = take((size_t)(max_units + ceil_div(n, 4) + 64) * 8);
     L.scal = take(64);
     L.srcs = take((size_t)(ceil_div(std::max(k, 1), kt) * kt) * 4);
     L.total = p;
@@ -574,7 +578,7 @@ static pp_status run_tile(pp_graph g, bool adjoint, pp_dir dir, int32_t k, int32
             a.tab_cap = g->split_cap;
             a.part = part;
             a.src = moved;
-            launch_kpull<KT>(a, w.nsplit, w.nsplit > 0 ? resid + w.kp.units : nullptr, st, g->weighted);
+            launch_kpull<KT>(a, w.nsplit, w.nsplit > 0 ? resid + 2 * (size_t)w.kp.units : nullptr, st, g->weighted);
             nres = w.kp.units + (w.nsplit > 0 ? ceil_div(w.nsplit, kBlock / KT) : 0);
         } else {
             // forward push scatters along CSR; the adjoint push scatters along CSC
@@ -598,11 +602,11 @@ static pp_status run_tile(pp_graph g, bool adjoint, pp_dir dir, int32_t k, int32
         std::swap(prev, next);
         std::swap(c_cur, c_nxt);
         if (tol > 0.f && t + 1 < iters) {
-            float r = 0.f;
+            float r[2] = {0.f, 0.f};
             hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, nres, (const float*)resid, scal);
-            PP_HIP(hipMemcpyAsync(&r, scal, sizeof(float), hipMemcpyDeviceToHost, st));
+            PP_HIP(hipMemcpyAsync(r, scal, sizeof(r), hipMemcpyDeviceToHost, st));
             PP_HIP(hipStreamSynchronize(st));
-            if (r < tol) break;
+            if (r[0] <= tol * r[1]) break;  // L1 change relative to the L1 norm of the tile
         }
     }
     *latest = prev;

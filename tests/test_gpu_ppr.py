@@ -80,7 +80,7 @@ def test_converged_mode_matches_dense_solve():
     P = H.dense_transition(host, host.weights)
     g = pp.Graph(host)
     for d in DIRS:
-        X, done = pp.ppr(g, src, iters=5000, f=F, k_tile=8, direction=d, tol=1e-7)
+        X, done = pp.ppr(g, src, iters=5000, f=F, k_tile=8, direction=d, tol=1e-8)
         assert done < 5000
         for j, s in enumerate(src):
             e = np.zeros(host.n)
