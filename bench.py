@@ -50,6 +50,11 @@ def parse():
                         "ppr20, multi512, grid4096, er22, adjoint20")
     p.add_argument("--tuned", default=os.path.join(ROOT, "paper_2010_16012_amd", "tuned.json"),
                    help="autotuner cache to apply (ignored when missing)")
+    p.add_argument("--counters-summary", nargs="+", metavar="CSV",
+                   help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, "
+                        "WRITE_SIZE) of 'bench.py --only pr_pull --copy-calibration' into the pull kernel's "
+                        "HBM traffic per launch, written to profiles/; an optional third file with "
+                        "TCC_EA0_RDREQ_{32B,64B,128B}_sum adds the read-request size breakdown")
     return p.parse_args()
 
 
@@ -74,8 +79,61 @@ def load_traffic(kernel_src_hash, launch_algo_bytes):
     return d.get("traffic_bytes_per_launch")
 
 
+PULL_KERNEL = "pp::k_pr_pull<"
+CALIB_BYTES = 1 << 30  # the calibration kernel reads 1 GiB and writes 1 GiB
+
+
+def counters_summary(fetch_csv, write_csv, sizes_csv=None):
+    """HBM bytes per pull launch from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), each divided by what the same counter reads for the plain
+    1 GiB-in / 1 GiB-out calibration kernel over 1 GiB."""
+    import csv
+
+    def per_kernel(path, counter, scale=1024.0):
+        pull, calib = [], []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"]) * scale
+                if PULL_KERNEL in r["Kernel_Name"]:
+                    pull.append(v)
+                elif "neg_kernel" in r["Kernel_Name"]:
+                    calib.append(v)
+        if not pull or len(calib) != 1:
+            raise SystemExit(f"{path}: expected pull dispatches and one calibration dispatch "
+                             f"(got {len(pull)} and {len(calib)})")
+        return sum(pull) / len(pull), calib[0]
+
+    f_pull, f_cal = per_kernel(fetch_csv, "FETCH_SIZE")
+    w_pull, w_cal = per_kernel(write_csv, "WRITE_SIZE")
+    k_f, k_w = f_cal / CALIB_BYTES, w_cal / CALIB_BYTES
+    traffic = f_pull / k_f + w_pull / k_w
+    out = {"kernel": "k_pr_pull", "workload": "rmat22_ef16_seed1_sym", "source_hash": source_hash("pr.hip"),
+           "fetch_bytes_per_launch_raw": round(f_pull), "write_bytes_per_launch_raw": round(w_pull),
+           "fetch_calibration_factor": round(k_f, 4), "write_calibration_factor": round(k_w, 4),
+           "traffic_bytes_per_launch": round(traffic)}
+    if sizes_csv:
+        # read requests from L2 to memory by size; bytes = sum(size * count)
+        by = {}
+        for sz in (32, 64, 128):
+            p_req, c_req = per_kernel(sizes_csv, f"TCC_EA0_RDREQ_{sz}B_sum", 1.0)
+            by[sz] = (p_req, c_req)
+        out["read_requests_per_launch"] = {f"{sz}B": round(by[sz][0]) for sz in by}
+        out["read_bytes_per_launch_by_size"] = round(sum(sz * by[sz][0] for sz in by))
+        out["calibration_read_bytes_by_size"] = round(sum(sz * by[sz][1] for sz in by))
+    path = os.path.join(ROOT, "profiles", "pr_pull_rmat22_counters.json")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
+    if args.counters_summary:
+        return counters_summary(*args.counters_summary)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sweep shards by vertex "
               "ranges across GPUs, see DESIGN.md, but this build runs on one GPU only)", file=sys.stderr)
