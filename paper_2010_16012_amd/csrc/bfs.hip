@@ -17,6 +17,13 @@
 // Per-level statistics (|F|, out-edges of F, out-edges of unvisited
 // vertices) live in three rotating slots so the direction is chosen on the
 // device and the host only polls for termination.
+//
+// Bit tests against the hot prefix of a bitmap go to LDS: after degree
+// relabelling the lowest vertex ids are the highest-degree vertices, which
+// most edges point to.  On large levels every workgroup first copies the
+// prefix of the bitmap it tests -- the frontier (bottom-up; read-only during
+// the level) or the visited set (top-down; a snapshot that can only miss
+// bits set later, so a clear bit still goes to global memory) -- into LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,9 +33,13 @@
 namespace pp {
 
 constexpr int32_t kPage = 256;      // queue entries per page
-constexpr int32_t kBigRow = 1024;   // top-down rows longer than this are chunked
-constexpr int32_t kBigInRow = 2048; // bottom-up in-rows longer than this are chunked
-constexpr int kBfsMaxBlocks = 1024;
+// Rows longer than one chunk are cut into chunk items that the whole grid
+// shares, so no wavefront walks a long row alone while the others idle.
+constexpr int32_t kBigRow = 256;    // top-down (out-rows)
+constexpr int32_t kBigInRow = 256;  // bottom-up (in-rows)
+constexpr int kBfsBlock = 1024;    // threads per workgroup of the level kernels
+constexpr int kBfsWaves = kBfsBlock / kWave;
+constexpr int32_t kStaticLds = 16384;  // LDS bytes kept for the kernels' own arrays
 
 struct BfsSlot {
     int32_t n;         // frontier size (accumulated by the level that builds it)
@@ -56,12 +67,16 @@ struct BfsHdr {
 
 struct BfsLayout {
     size_t hdr, queue0, queue1, fill0, fill1, fb0, fb1, fb2, visited, items, best, total;
-    int32_t words, blocks, page_cap, item_cap;
+    int32_t words, blocks, page_cap, item_cap, stage_words;
 };
 
-static int32_t bfs_blocks(int32_t n) { return std::min(std::max(ceil_div(n, 2048), 4), kBfsMaxBlocks); }
+// One workgroup per compute unit (the staged bitmap takes most of its LDS),
+// fewer on small graphs.
+static int32_t bfs_blocks(pp_graph g) { return std::max(1, std::min(ceil_div(g->d.n, 4096), g->num_cu)); }
 
-static BfsLayout bfs_layout(int32_t n, int64_t nnz) {
+static BfsLayout bfs_layout(pp_graph g) {
+    const int32_t n = g->d.n;
+    const int64_t nnz = g->d.nnz;
     BfsLayout L{};
     size_t p = 0;
     auto take = [&](size_t bytes) {
@@ -70,11 +85,12 @@ static BfsLayout bfs_layout(int32_t n, int64_t nnz) {
         return at;
     };
     L.words = ceil_div(n, 64);
-    L.blocks = bfs_blocks(n);
-    const int32_t waves = L.blocks * (kBlock / kWave);
-    // full pages hold at most n entries; each wavefront of each of the two
-    // kernels of a level leaves at most one partial page
-    L.page_cap = ceil_div(n, kPage) + 2 * waves + 2;
+    L.blocks = bfs_blocks(g);
+    L.stage_words = std::max(0, std::min(L.words, (g->max_lds - kStaticLds) / 8));
+    const int32_t waves = L.blocks * kBfsWaves;
+    // full pages hold at most n entries; each wavefront of each of the three
+    // appending kernels of a level leaves at most one partial page
+    L.page_cap = ceil_div(n, kPage) + 3 * waves + 2;
     L.item_cap = (int32_t)std::min<int64_t>(2 * nnz / std::min(kBigRow, kBigInRow) + 64, INT32_MAX / 4);
     L.hdr = take(sizeof(BfsHdr));
     L.queue0 = take((size_t)L.page_cap * kPage * 4);
@@ -96,6 +112,8 @@ struct BfsArgs {
     int32_t words;
     int32_t page_cap;
     int32_t item_cap;
+    int32_t stage_words;    // bitmap words a workgroup may stage in LDS
+    int64_t stage_min;      // stage only when the level examines at least this many edges
     const int32_t* csr_off;
     const int32_t* csr_idx;
     const int32_t* csc_off;
@@ -115,13 +133,17 @@ struct BfsArgs {
 };
 
 static BfsArgs bfs_args(pp_graph g, void* state, int32_t* level, int32_t* parent) {
-    const BfsLayout L = bfs_layout(g->d.n, g->d.nnz);
+    const BfsLayout L = bfs_layout(g);
     char* s = static_cast<char*>(state);
     BfsArgs a;
     a.n = g->d.n;
     a.words = L.words;
     a.page_cap = L.page_cap;
     a.item_cap = L.item_cap;
+    a.stage_words = L.stage_words;
+    // copying costs each workgroup stage_words loads; pay it only when the
+    // level has at least two edges per staged word per workgroup
+    a.stage_min = 2 * (int64_t)L.blocks * L.stage_words;
     a.csr_off = g->d.csr_off;
     a.csr_idx = g->d.csr_idx;
     a.csc_off = g->d.csc_off;
@@ -160,6 +182,19 @@ __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
     for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s);
     return v;
+}
+
+// Copies bitmap words [0, sw) into LDS.  Workgroup-collective.
+__device__ __forceinline__ void stage_bits(uint64_t* s_bits, const uint64_t* src, int32_t sw) {
+    for (int32_t i = threadIdx.x; i < sw; i += blockDim.x) s_bits[i] = src[i];
+    __syncthreads();
+}
+
+// Bit u of a bitmap whose words [0, sw) are also in LDS.
+__device__ __forceinline__ bool test_bit(const uint64_t* s_bits, int32_t sw, const uint64_t* g_bits, int32_t u) {
+    const int32_t w = u >> 6;
+    const uint64_t word = (w < sw) ? s_bits[w] : g_bits[w];
+    return (word >> (u & 63)) & 1ull;
 }
 
 // ------------------------------------------------------------------ output
@@ -206,8 +241,8 @@ __device__ __forceinline__ void page_close(const Pager& pg, int32_t* fill, int l
 
 // Per-workgroup sum of the new-frontier counters, then one atomic each.
 __device__ __forceinline__ void flush_stats(int32_t cnt, int64_t deg, BfsSlot* nxt) {
-    __shared__ int32_t s_cnt[kBlock / kWave];
-    __shared__ int64_t s_deg[kBlock / kWave];
+    __shared__ int32_t s_cnt[kBfsWaves];
+    __shared__ int64_t s_deg[kBfsWaves];
     cnt = wave_sum(cnt);
     deg = wave_sum(deg);
     const int w = threadIdx.x / kWave;
@@ -219,7 +254,7 @@ __device__ __forceinline__ void flush_stats(int32_t cnt, int64_t deg, BfsSlot* n
     if (threadIdx.x == 0) {
         int32_t c = 0;
         int64_t d = 0;
-        for (int i = 0; i < kBlock / kWave; ++i) {
+        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
             c += s_cnt[i];
             d += s_deg[i];
         }
@@ -268,7 +303,8 @@ __global__ void k_bfs_init(BfsArgs a, int32_t root_user, int64_t nnz) {
 }
 
 // Queues (v, begin, end) chunk items of `chunk` edges for the lanes with
-// `huge` set.  Wave-collective; one counter atomic per call.
+// `huge` set; the whole wave writes each row's items.  Wave-collective; one
+// counter atomic per call.
 __device__ __forceinline__ void queue_chunks(const BfsArgs& a, bool huge, int32_t v, int32_t rb, int32_t re,
                                              int32_t chunk, BfsSlot* nxt, int lane) {
     const int32_t nch = huge ? (re - rb + chunk - 1) / chunk : 0;
@@ -282,14 +318,21 @@ __device__ __forceinline__ void queue_chunks(const BfsArgs& a, bool huge, int32_
     int32_t base = 0;
     if (lane == 0) base = atomicAdd(&nxt->big, tot);
     base = __shfl(base, 0);
-    for (int32_t k = 0; k < nch; ++k) {
-        const int32_t it = base + incl - nch + k;
-        if (it < a.item_cap) {
-            a.items[3 * it] = v;
-            a.items[3 * it + 1] = rb + k * chunk;
-            a.items[3 * it + 2] = min(re, rb + (k + 1) * chunk);
-        } else {
-            atomicOr(&a.hdr->overflow, 2);
+    uint64_t rows = __ballot(huge);
+    while (rows) {
+        const int src = __ffsll((long long)rows) - 1;
+        rows &= rows - 1;
+        const int32_t hv = __shfl(v, src), hb = __shfl(rb, src), he = __shfl(re, src);
+        const int32_t first = base + __shfl(incl - nch, src), cnt = __shfl(nch, src);
+        for (int32_t k = lane; k < cnt; k += kWave) {
+            const int32_t it = first + k;
+            if (it < a.item_cap) {
+                a.items[3 * it] = hv;
+                a.items[3 * it + 1] = hb + k * chunk;
+                a.items[3 * it + 2] = min(he, hb + (k + 1) * chunk);
+            } else {
+                atomicOr(&a.hdr->overflow, 2);
+            }
         }
     }
 }
@@ -301,46 +344,89 @@ struct TdCtx {
     int32_t* fill_next;
     uint64_t* fb_next;
     BfsSlot* nxt;
+    const uint64_t* s_vis;  // LDS snapshot of visited words [0, sw)
+    int32_t sw;
 };
 
-// Claims u for parent v.  Wave-collective: every lane calls it.
-__device__ __forceinline__ void td_claim(const BfsArgs& a, const TdCtx& cx, Pager& pg, int32_t u, int32_t v,
-                                         int32_t& cnt, int64_t& deg, int lane) {
-    bool claimed = false;
-    if (u >= 0) {
-        const uint64_t bit = 1ull << (u & 63);
-        if (!(a.visited[u >> 6] & bit)) {
+// Claims the targets u[r] (parents pv[r]; -1 = no edge) of kTdU rounds of
+// 64 edges.  The rounds are independent, so their loads and atomics are
+// issued together and their latencies overlap.  Wave-collective.
+constexpr int kTdU = 4;
+
+__device__ __forceinline__ void td_batch(const BfsArgs& a, const TdCtx& cx, Pager& pg, const int32_t (&u)[kTdU],
+                                         const int32_t (&pv)[kTdU], int32_t& cnt, int64_t& deg, int lane) {
+    bool cand[kTdU];
+#pragma unroll
+    for (int r = 0; r < kTdU; ++r) {
+        // a set bit in the LDS snapshot is final; a clear one is checked in memory
+        const int32_t w = u[r] >> 6;
+        cand[r] = (u[r] >= 0) && (w >= cx.sw || !((cx.s_vis[w] >> (u[r] & 63)) & 1ull));
+    }
+    uint64_t word[kTdU];
+#pragma unroll
+    for (int r = 0; r < kTdU; ++r) word[r] = cand[r] ? a.visited[u[r] >> 6] : ~0ull;
+    bool claimed[kTdU];
+#pragma unroll
+    for (int r = 0; r < kTdU; ++r) {
+        claimed[r] = false;
+        const uint64_t bit = 1ull << (u[r] & 63);
+        if (cand[r] && !(word[r] & bit)) {
             const uint64_t old =
-                atomicOr(reinterpret_cast<unsigned long long*>(&a.visited[u >> 6]), (unsigned long long)bit);
-            claimed = !(old & bit);
-        }
-        if (claimed) {
-            const int32_t uu = user_id(a.perm, u);
-            a.level[uu] = cx.lvl + 1;
-            a.parent[uu] = user_id(a.perm, v);
-            atomicOr(reinterpret_cast<unsigned long long*>(&cx.fb_next[u >> 6]), (unsigned long long)bit);
-            cnt += 1;
-            deg += a.out_deg[u];
+                atomicOr(reinterpret_cast<unsigned long long*>(&a.visited[u[r] >> 6]), (unsigned long long)bit);
+            claimed[r] = !(old & bit);
         }
     }
-    const uint64_t mask = __ballot(claimed);
-    if (mask == 0) return;
-    page_append(a, pg, claimed, u, __popcll(mask & lanes_below(lane)), __popcll(mask), cx.q_next, cx.fill_next,
-                cx.nxt, lane);
+#pragma unroll
+    for (int r = 0; r < kTdU; ++r) {
+        if (claimed[r]) {
+            const int32_t uu = user_id(a.perm, u[r]);
+            a.level[uu] = cx.lvl + 1;
+            a.parent[uu] = user_id(a.perm, pv[r]);
+            atomicOr(reinterpret_cast<unsigned long long*>(&cx.fb_next[u[r] >> 6]),
+                     (unsigned long long)(1ull << (u[r] & 63)));
+            cnt += 1;
+            deg += a.out_deg[u[r]];
+        }
+        const uint64_t mask = __ballot(claimed[r]);
+        if (mask)
+            page_append(a, pg, claimed[r], u[r], __popcll(mask & lanes_below(lane)), __popcll(mask), cx.q_next,
+                        cx.fill_next, cx.nxt, lane);
+    }
+}
+
+// Edges [b, e) of the row of v, 64 x kTdU at a time.  Wave-collective
+// (b, e, v wave-uniform).
+__device__ __forceinline__ void td_row(const BfsArgs& a, const TdCtx& cx, Pager& pg, int32_t v, int32_t b,
+                                       int32_t e, int32_t& cnt, int64_t& deg, int lane) {
+    for (int32_t jb = b; jb < e; jb += kTdU * kWave) {
+        int32_t u[kTdU], pv[kTdU];
+#pragma unroll
+        for (int r = 0; r < kTdU; ++r) {
+            const int32_t j = jb + r * kWave + lane;
+            u[r] = (j < e) ? a.csr_idx[j] : -1;
+            pv[r] = v;
+        }
+        td_batch(a, cx, pg, u, pv, cnt, deg, lane);
+    }
 }
 
 __device__ void level_top_down(const BfsArgs& a, const TdCtx& cx, const int32_t* q_cur, const int32_t* fill_cur,
                                int32_t pages, int32_t& cnt, int64_t& deg, Pager& pg) {
-    __shared__ int32_t s_start[kBlock / kWave][kWave];
-    __shared__ int32_t s_rb[kBlock / kWave][kWave];
-    __shared__ int32_t s_v[kBlock / kWave][kWave];
+    __shared__ int32_t s_start[kBfsWaves][kWave];
+    __shared__ int32_t s_rb[kBfsWaves][kWave];
+    __shared__ int32_t s_v[kBfsWaves][kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
-    const int32_t gwave = blockIdx.x * (kBlock / kWave) + w;
-    const int32_t nwaves = gridDim.x * (kBlock / kWave);
-    for (int32_t p = gwave; p < pages; p += nwaves) {
+    const int32_t gwave = blockIdx.x * kBfsWaves + w;
+    const int32_t nwaves = gridDim.x * kBfsWaves;
+    // one unit = 64 queue slots (a quarter page)
+    constexpr int kUnitsPerPage = kPage / kWave;
+    for (int32_t unit = gwave; unit < pages * kUnitsPerPage; unit += nwaves) {
+        const int32_t p = unit / kUnitsPerPage;
         const int32_t pfill = fill_cur[p];
-        for (int32_t s = 0; s < pfill; s += kWave) {
+        {
+            const int32_t s = (unit % kUnitsPerPage) * kWave;
+            if (s >= pfill) continue;
             const int32_t i = s + lane;
             const int32_t v = (i < pfill) ? q_cur[p * kPage + i] : -1;
             const int32_t rb = (v >= 0) ? a.csr_off[v] : 0;
@@ -357,11 +443,7 @@ __device__ void level_top_down(const BfsArgs& a, const TdCtx& cx, const int32_t*
             while (big) {
                 const int src = __ffsll((long long)big) - 1;
                 big &= big - 1;
-                const int32_t bv = __shfl(v, src), bb = __shfl(rb, src), be = __shfl(re, src);
-                for (int32_t jb = bb; jb < be; jb += kWave) {
-                    const int32_t j = jb + lane;
-                    td_claim(a, cx, pg, (j < be) ? a.csr_idx[j] : -1, bv, cnt, deg, lane);
-                }
+                td_row(a, cx, pg, __shfl(v, src), __shfl(rb, src), __shfl(re, src), cnt, deg, lane);
             }
             // short rows: the wave's edges are enumerated densely through a scan
             const int32_t mine = (len < kWave) ? len : 0;
@@ -376,20 +458,25 @@ __device__ void level_top_down(const BfsArgs& a, const TdCtx& cx, const int32_t*
             s_rb[w][lane] = rb;
             s_v[w][lane] = v;
             wave_sync();
-            for (int32_t k = 0; k < total; k += kWave) {
-                const int32_t e = k + lane;
-                int32_t u = -1, pv = -1;
-                if (e < total) {
-                    int lo = 0, hi = kWave;  // last lane with start <= e
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_start[w][mid] <= e) lo = mid;
-                        else hi = mid;
+            for (int32_t k = 0; k < total; k += kTdU * kWave) {
+                int32_t u[kTdU], pv[kTdU];
+#pragma unroll
+                for (int r = 0; r < kTdU; ++r) {
+                    const int32_t e = k + r * kWave + lane;
+                    u[r] = -1;
+                    pv[r] = -1;
+                    if (e < total) {
+                        int lo = 0, hi = kWave;  // last lane with start <= e
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (s_start[w][mid] <= e) lo = mid;
+                            else hi = mid;
+                        }
+                        u[r] = a.csr_idx[s_rb[w][lo] + (e - s_start[w][lo])];
+                        pv[r] = s_v[w][lo];
                     }
-                    u = a.csr_idx[s_rb[w][lo] + (e - s_start[w][lo])];
-                    pv = s_v[w][lo];
                 }
-                td_claim(a, cx, pg, u, pv, cnt, deg, lane);
+                td_batch(a, cx, pg, u, pv, cnt, deg, lane);
             }
             wave_sync();
         }
@@ -397,12 +484,41 @@ __device__ void level_top_down(const BfsArgs& a, const TdCtx& cx, const int32_t*
 }
 
 // ------------------------------------------------------------------ bottom-up
-__device__ void level_bottom_up(const BfsArgs& a, int32_t lvl, const uint64_t* fb_cur, int32_t* q_next,
-                                int32_t* fill_next, uint64_t* fb_next, BfsSlot* nxt, int32_t& cnt, int64_t& deg,
-                                Pager& pg) {
+constexpr int kBuB = 4;  // in-edges one lane loads per step of a short row
+constexpr int kBuU = 4;  // rounds of 64 in-edges a wave loads per step of a long row
+
+// Position of the first frontier member among csc_idx[b, e) (-1 if none),
+// stopping at the first step that has one.  Wave-collective (b, e uniform).
+__device__ __forceinline__ void bu_scan_row(const BfsArgs& a, const uint64_t* fb_cur, const uint64_t* s_fb,
+                                            int32_t sw, int32_t b, int32_t e, int lane, int32_t& pos) {
+    pos = -1;
+    for (int32_t jb = b; jb < e; jb += kBuU * kWave) {
+        int32_t u[kBuU];
+#pragma unroll
+        for (int r = 0; r < kBuU; ++r) {
+            const int32_t j = jb + r * kWave + lane;
+            u[r] = (j < e) ? a.csc_idx[j] : -1;
+        }
+        bool hit[kBuU];
+#pragma unroll
+        for (int r = 0; r < kBuU; ++r) hit[r] = (u[r] >= 0) && test_bit(s_fb, sw, fb_cur, u[r]);
+#pragma unroll
+        for (int r = 0; r < kBuU; ++r) {
+            const uint64_t hm = __ballot(hit[r]);
+            if (hm) {
+                pos = jb + r * kWave + __ffsll((long long)hm) - 1;
+                return;
+            }
+        }
+    }
+}
+
+__device__ void level_bottom_up(const BfsArgs& a, int32_t lvl, const uint64_t* fb_cur, const uint64_t* s_fb,
+                                int32_t sw, int32_t* q_next, int32_t* fill_next, uint64_t* fb_next, BfsSlot* nxt,
+                                int32_t& cnt, int64_t& deg, Pager& pg) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int32_t gwave = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    const int32_t nwaves = gridDim.x * (kBlock / kWave);
+    const int32_t gwave = blockIdx.x * kBfsWaves + threadIdx.x / kWave;
+    const int32_t nwaves = gridDim.x * kBfsWaves;
     for (int32_t w = gwave; w < a.words; w += nwaves) {
         const uint64_t vis = a.visited[w];
         const int32_t v = w * kWave + lane;
@@ -425,30 +541,29 @@ __device__ void level_bottom_up(const BfsArgs& a, int32_t lvl, const uint64_t* f
             const int src = __ffsll((long long)big) - 1;
             big &= big - 1;
             const int32_t bb = __shfl(rb, src), be = __shfl(re, src);
-            for (int32_t jb = bb; jb < be; jb += kWave) {
-                const int32_t j = jb + lane;
-                const int32_t u = (j < be) ? a.csc_idx[j] : -1;
-                const bool hit = (u >= 0) && ((fb_cur[u >> 6] >> (u & 63)) & 1ull);
-                const uint64_t hm = __ballot(hit);
-                if (hm) {
-                    const int32_t p = __shfl(u, __ffsll((long long)hm) - 1);
-                    if (lane == src) {
-                        found = true;
-                        par = p;
-                    }
-                    break;
-                }
+            int32_t p = -1;
+            bu_scan_row(a, fb_cur, s_fb, sw, bb, be, lane, p);
+            if (lane == src && p >= 0) {
+                found = true;
+                par = a.csc_idx[p];
             }
         }
-        // short in-rows: each lane scans its own, in stored order
+        // short in-rows: each lane scans its own, in stored order, kBuB
+        // independent loads at a time
         if (unvisited && !coop) {
-            for (int32_t j = rb; j < re; ++j) {
-                const int32_t u = a.csc_idx[j];
-                if ((fb_cur[u >> 6] >> (u & 63)) & 1ull) {
-                    found = true;
-                    par = u;
-                    break;
-                }
+            for (int32_t j = rb; j < re && !found; j += kBuB) {
+                int32_t u[kBuB];
+#pragma unroll
+                for (int r = 0; r < kBuB; ++r) u[r] = (j + r < re) ? a.csc_idx[j + r] : -1;
+                bool hit[kBuB];
+#pragma unroll
+                for (int r = 0; r < kBuB; ++r) hit[r] = (u[r] >= 0) && test_bit(s_fb, sw, fb_cur, u[r]);
+#pragma unroll
+                for (int r = 0; r < kBuB; ++r)
+                    if (hit[r] && !found) {
+                        found = true;
+                        par = u[r];
+                    }
             }
         }
         const uint64_t fm = __ballot(found);
@@ -471,8 +586,9 @@ __device__ void level_bottom_up(const BfsArgs& a, int32_t lvl, const uint64_t* f
 // Expands frontier `lvl` (slot lvl % 3) into lvl+1.  policy: PP_PUSH,
 // PP_PULL or PP_SWITCH (decided here, identically in every workgroup, from
 // the slot statistics).
-__global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a, int32_t lvl, int32_t policy, float alpha,
-                                                       float beta) {
+__global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl, int32_t policy, float alpha,
+                                                          float beta) {
+    extern __shared__ uint64_t s_bits[];
     BfsHdr* h = a.hdr;
     const int sc = lvl % 3, sn = (lvl + 1) % 3, sz = (lvl + 2) % 3;
     const BfsSlot cur = h->slot[sc];
@@ -514,11 +630,16 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a, int32_t lvl, in
     Pager pg{-1, 0};
     int32_t* q_next = a.queue[(lvl + 1) & 1];
     int32_t* fill_next = a.fill[(lvl + 1) & 1];
+    // edges the level examines at most: the frontier's (top-down) or the
+    // unvisited vertices' (bottom-up)
+    const int32_t sw = ((dir == PP_PUSH ? cur.m : mu) >= a.stage_min) ? a.stage_words : 0;
     if (dir == PP_PUSH) {
-        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn]};
+        if (sw) stage_bits(s_bits, a.visited, sw);
+        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw};
         level_top_down(a, cx, a.queue[lvl & 1], a.fill[lvl & 1], min(cur.pages, a.page_cap), cnt, deg, pg);
     } else {
-        level_bottom_up(a, lvl, a.fb[sc], q_next, fill_next, a.fb[sn], &h->slot[sn], cnt, deg, pg);
+        if (sw) stage_bits(s_bits, a.fb[sc], sw);
+        level_bottom_up(a, lvl, a.fb[sc], s_bits, sw, q_next, fill_next, a.fb[sn], &h->slot[sn], cnt, deg, pg);
     }
     page_close(pg, fill_next, lane);
     flush_stats(cnt, deg, &h->slot[sn]);
@@ -526,26 +647,24 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a, int32_t lvl, in
 
 // Second top-down pass: the chunk items queued for rows longer than kBigRow,
 // one wavefront per chunk.
-__global__ __launch_bounds__(kBlock) void k_bfs_td_big(BfsArgs a, int32_t lvl) {
+__global__ __launch_bounds__(kBfsBlock) void k_bfs_td_big(BfsArgs a, int32_t lvl) {
+    extern __shared__ uint64_t s_bits[];
     BfsHdr* h = a.hdr;
     const int sn = (lvl + 1) % 3;
     if (h->slot[sn].dir_prev != PP_PUSH) return;
     const int32_t items = min(h->slot[sn].big, a.item_cap);
     if (items == 0) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int32_t gwave = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    const int32_t nwaves = gridDim.x * (kBlock / kWave);
+    const int32_t gwave = blockIdx.x * kBfsWaves + threadIdx.x / kWave;
+    const int32_t nwaves = gridDim.x * kBfsWaves;
     int32_t cnt = 0;
     int64_t deg = 0;
     Pager pg{-1, 0};
-    TdCtx cx{lvl, a.queue[(lvl + 1) & 1], a.fill[(lvl + 1) & 1], a.fb[sn], &h->slot[sn]};
-    for (int32_t it = gwave; it < items; it += nwaves) {
-        const int32_t v = a.items[3 * it], b = a.items[3 * it + 1], e = a.items[3 * it + 2];
-        for (int32_t jb = b; jb < e; jb += kWave) {
-            const int32_t j = jb + lane;
-            td_claim(a, cx, pg, (j < e) ? a.csr_idx[j] : -1, v, cnt, deg, lane);
-        }
-    }
+    const int32_t sw = ((int64_t)items * kBigRow >= a.stage_min) ? a.stage_words : 0;
+    if (sw) stage_bits(s_bits, a.visited, sw);
+    TdCtx cx{lvl, a.queue[(lvl + 1) & 1], a.fill[(lvl + 1) & 1], a.fb[sn], &h->slot[sn], s_bits, sw};
+    for (int32_t it = gwave; it < items; it += nwaves)
+        td_row(a, cx, pg, a.items[3 * it], a.items[3 * it + 1], a.items[3 * it + 2], cnt, deg, lane);
     page_close(pg, cx.fill_next, lane);
     flush_stats(cnt, deg, &h->slot[sn]);
 }
@@ -553,25 +672,27 @@ __global__ __launch_bounds__(kBlock) void k_bfs_td_big(BfsArgs a, int32_t lvl) {
 // Bottom-up pass over the chunks of very long in-rows, one wavefront per
 // chunk: the first frontier member in a chunk lowers best[v] to its slot.
 // A chunk stops early once an earlier slot of the same row has a hit.
-__global__ __launch_bounds__(kBlock) void k_bfs_bu_big(BfsArgs a, int32_t lvl) {
+__global__ __launch_bounds__(kBfsBlock) void k_bfs_bu_big(BfsArgs a, int32_t lvl) {
+    extern __shared__ uint64_t s_bits[];
     BfsHdr* h = a.hdr;
     const int sc = lvl % 3, sn = (lvl + 1) % 3;
     if (h->slot[sn].dir_prev != PP_PULL) return;
     const int32_t items = min(h->slot[sn].big, a.item_cap);
+    if (items == 0) return;
     const uint64_t* fb_cur = a.fb[sc];
+    const int32_t sw = ((int64_t)items * kBigInRow >= a.stage_min) ? a.stage_words : 0;
+    if (sw) stage_bits(s_bits, fb_cur, sw);
     const int lane = threadIdx.x & (kWave - 1);
-    const int32_t gwave = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    const int32_t nwaves = gridDim.x * (kBlock / kWave);
+    const int32_t gwave = blockIdx.x * kBfsWaves + threadIdx.x / kWave;
+    const int32_t nwaves = gridDim.x * kBfsWaves;
     for (int32_t it = gwave; it < items; it += nwaves) {
         const int32_t v = a.items[3 * it], b = a.items[3 * it + 1], e = a.items[3 * it + 2];
-        for (int32_t jb = b; jb < e; jb += kWave) {
+        for (int32_t jb = b; jb < e; jb += kBuU * kWave) {
             if (__shfl(lane == 0 ? a.best[v] : 0, 0) < jb) break;  // an earlier slot already hit
-            const int32_t j = jb + lane;
-            const int32_t u = (j < e) ? a.csc_idx[j] : -1;
-            const bool hit = (u >= 0) && ((fb_cur[u >> 6] >> (u & 63)) & 1ull);
-            const uint64_t hm = __ballot(hit);
-            if (hm) {
-                if (lane == 0) atomicMin(&a.best[v], jb + __ffsll((long long)hm) - 1);
+            int32_t pos = -1;
+            bu_scan_row(a, fb_cur, s_bits, sw, jb, min(e, jb + kBuU * kWave), lane, pos);
+            if (pos >= 0) {
+                if (lane == 0) atomicMin(&a.best[v], pos);
                 break;
             }
         }
@@ -580,7 +701,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_bu_big(BfsArgs a, int32_t lvl) {
 
 // Finishes the long in-row vertices: one item per vertex (its first chunk)
 // records the parent at best[v], sets the bitmaps and appends the vertex.
-__global__ __launch_bounds__(kBlock) void k_bfs_bu_fin(BfsArgs a, int32_t lvl) {
+__global__ __launch_bounds__(kBfsBlock) void k_bfs_bu_fin(BfsArgs a, int32_t lvl) {
     BfsHdr* h = a.hdr;
     const int sn = (lvl + 1) % 3;
     if (h->slot[sn].dir_prev != PP_PULL) return;
@@ -629,27 +750,40 @@ __global__ __launch_bounds__(kBlock) void k_bfs_bu_fin(BfsArgs a, int32_t lvl) {
 static pp_status check_state(pp_graph g, void* state, size_t bytes) {
     if (!g) return set_error(PP_E_NULL, "graph handle is NULL");
     if (!state) return set_error(PP_E_NULL, "state is NULL");
-    if (bytes < bfs_layout(g->d.n, g->d.nnz).total) return set_error(PP_E_WORKSPACE, "BFS state buffer too small");
+    if (bytes < bfs_layout(g).total) return set_error(PP_E_WORKSPACE, "BFS state buffer too small");
     if (reinterpret_cast<uintptr_t>(state) % 256 != 0) return set_error(PP_E_RANGE, "state must be 256-byte aligned");
     return PP_OK;
 }
 
+// Lets the staging kernels take LDS beyond the default 64 KiB.
+static void allow_stage_lds(const BfsArgs& a) {
+    const int bytes = a.stage_words * 8;
+    if (bytes <= 65536) return;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bfs_level), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              bytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bfs_td_big),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bfs_bu_big),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 static pp_status launch_level(pp_graph g, const BfsArgs& a, int32_t lvl, int32_t policy, float alpha, float beta,
                               hipStream_t st) {
-    const int32_t blocks = bfs_blocks(g->d.n);
-    hipLaunchKernelGGL(k_bfs_level, dim3(blocks), dim3(kBlock), 0, st, a, lvl, policy, alpha, beta);
+    const int32_t blocks = bfs_blocks(g);
+    const size_t lds = (size_t)a.stage_words * 8;
+    hipLaunchKernelGGL(k_bfs_level, dim3(blocks), dim3(kBfsBlock), lds, st, a, lvl, policy, alpha, beta);
     if (policy != PP_PULL && g->max_out_deg > kBigRow)
-        hipLaunchKernelGGL(k_bfs_td_big, dim3(blocks), dim3(kBlock), 0, st, a, lvl);
+        hipLaunchKernelGGL(k_bfs_td_big, dim3(blocks), dim3(kBfsBlock), lds, st, a, lvl);
     if (policy != PP_PUSH && g->max_in_deg > kBigInRow) {
-        hipLaunchKernelGGL(k_bfs_bu_big, dim3(blocks), dim3(kBlock), 0, st, a, lvl);
-        hipLaunchKernelGGL(k_bfs_bu_fin, dim3(blocks), dim3(kBlock), 0, st, a, lvl);
+        hipLaunchKernelGGL(k_bfs_bu_big, dim3(blocks), dim3(kBfsBlock), lds, st, a, lvl);
+        hipLaunchKernelGGL(k_bfs_bu_fin, dim3(blocks), dim3(kBfsBlock), 0, st, a, lvl);
     }
     PP_LAUNCH_CHECK("k_bfs_level");
     return PP_OK;
 }
 
 static pp_status read_hdr(pp_graph g, void* state, BfsHdr* h, hipStream_t st) {
-    const BfsLayout L = bfs_layout(g->d.n, g->d.nnz);
+    const BfsLayout L = bfs_layout(g);
     PP_HIP(hipMemcpyAsync(h, static_cast<char*>(state) + L.hdr, sizeof(BfsHdr), hipMemcpyDeviceToHost, st));
     PP_HIP(hipStreamSynchronize(st));
     if (h->overflow) return set_error(PP_E_WORKSPACE, "BFS queue capacity exceeded");
@@ -660,7 +794,7 @@ static pp_status read_hdr(pp_graph g, void* state, BfsHdr* h, hipStream_t st) {
 
 using namespace pp;
 
-PP_EXPORT size_t pp_bfs_state_bytes(pp_graph g) { return g ? bfs_layout(g->d.n, g->d.nnz).total : 0; }
+PP_EXPORT size_t pp_bfs_state_bytes(pp_graph g) { return g ? bfs_layout(g).total : 0; }
 
 PP_EXPORT pp_status pp_bfs_init(pp_graph g, int32_t root, int32_t* level, int32_t* parent, void* state,
                                 size_t state_bytes, void* stream) {
@@ -670,6 +804,7 @@ PP_EXPORT pp_status pp_bfs_init(pp_graph g, int32_t root, int32_t* level, int32_
     if (!level || !parent) return set_error(PP_E_NULL, "level and parent are required");
     if (root < 0 || root >= g->d.n) return set_error(PP_E_RANGE, "root out of range");
     BfsArgs a = bfs_args(g, state, level, parent);
+    allow_stage_lds(a);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int32_t blocks = std::min<int32_t>(ceil_div(g->d.n, 256), 4096);
     hipLaunchKernelGGL(k_bfs_init, dim3(blocks), dim3(256), 0, st, a, root, g->d.nnz);
@@ -683,6 +818,7 @@ static pp_status step(pp_graph g, void* state, int32_t* level, int32_t* parent, 
     if (!g || !state || !level || !parent) return set_error(PP_E_NULL, "graph, state, level and parent are required");
     if (cur_level < 0 || cur_level >= g->d.n) return set_error(PP_E_RANGE, "cur_level out of range");
     BfsArgs a = bfs_args(g, state, level, parent);
+    allow_stage_lds(a);
     return launch_level(g, a, cur_level, dir, 14.f, 24.f, static_cast<hipStream_t>(stream));
 }
 
@@ -716,7 +852,7 @@ PP_EXPORT pp_status pp_bfs_run(pp_graph g, int32_t root, pp_dir policy, float al
     pp_status s = pp_bfs_init(g, root, level, parent, state, state_bytes, stream);
     if (s != PP_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const BfsLayout L = bfs_layout(g->d.n, g->d.nnz);
+    const BfsLayout L = bfs_layout(g);
     const BfsHdr* dh = reinterpret_cast<const BfsHdr*>(static_cast<char*>(state) + L.hdr);
     BfsArgs a = bfs_args(g, state, level, parent);
     // Levels go out in growing batches; kernels past the last level find an
