@@ -179,8 +179,10 @@ pp_status pp_bfs_init(pp_graph g, int32_t root, int32_t* level, int32_t* parent,
  * bitmap per claim, wave-aggregated queue appends).  pull = bottom-up: every
  * unvisited vertex scans its in-neighbours in stored order and stops at the
  * first frontier member, which becomes its parent (no atomics on vertex
- * state; one counter update per wavefront).  Either step may follow the
- * other.  level/parent must be the arrays given to pp_bfs_init.  Enqueue
+ * state; one counter update per wavefront).  Rows longer than 256 edges are
+ * cut into 256-edge chunks that the whole grid shares; a bottom-up vertex
+ * whose in-row is chunked takes the first frontier member of whichever chunk
+ * claims it first (one atomic OR).  Either step may follow the other.  level/parent must be the arrays given to pp_bfs_init.  Enqueue
  * only; the frontier size is read with pp_bfs_frontier.  A step on an empty
  * frontier does nothing. */
 pp_status pp_bfs_step_push(pp_graph g, void* state, int32_t* level, int32_t* parent, int32_t cur_level,

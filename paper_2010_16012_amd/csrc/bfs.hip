@@ -59,6 +59,13 @@ struct BfsHdr {
     int32_t last;      // index of the newest frontier
     int32_t root;
     int32_t overflow;  // set if a capacity bound was ever hit (never expected)
+    // Level index on the device, so that a run's launches carry no level
+    // argument: a level kernel of parity p reads lv[p] and its lead thread
+    // writes lv[p ^ 1] for the next one (no kernel writes what it reads);
+    // c_lvl tells the chunk kernel which level it completes.
+    int32_t lv[2];
+    int32_t c_lvl;
+    int32_t finished;  // an empty frontier was reached
     int64_t reached;
     int64_t edges;
     int8_t log_dir[PP_BFS_MAX_LOG];
@@ -66,7 +73,7 @@ struct BfsHdr {
 };
 
 struct BfsLayout {
-    size_t hdr, queue0, queue1, fill0, fill1, fb0, fb1, fb2, visited, items, best, total;
+    size_t hdr, queue0, queue1, fill0, fill1, fb0, fb1, fb2, visited, items, total;
     int32_t words, blocks, page_cap, item_cap, stage_words;
 };
 
@@ -102,7 +109,6 @@ static BfsLayout bfs_layout(pp_graph g) {
     L.fb2 = take((size_t)L.words * 8);
     L.visited = take((size_t)L.words * 8);
     L.items = take((size_t)L.item_cap * 3 * 4);
-    L.best = take((size_t)n * 4);
     L.total = p;
     return L;
 }
@@ -129,7 +135,6 @@ struct BfsArgs {
     uint64_t* fb[3];
     uint64_t* visited;
     int32_t* items;         // (v, begin, end) chunk items of long rows
-    int32_t* best;          // bottom-up: first hit position in a long in-row (INT32_MAX: none)
 };
 
 static BfsArgs bfs_args(pp_graph g, void* state, int32_t* level, int32_t* parent) {
@@ -163,7 +168,6 @@ static BfsArgs bfs_args(pp_graph g, void* state, int32_t* level, int32_t* parent
     a.fb[2] = reinterpret_cast<uint64_t*>(s + L.fb2);
     a.visited = reinterpret_cast<uint64_t*>(s + L.visited);
     a.items = reinterpret_cast<int32_t*>(s + L.items);
-    a.best = reinterpret_cast<int32_t*>(s + L.best);
     return a;
 }
 
@@ -273,7 +277,6 @@ __global__ void k_bfs_init(BfsArgs a, int32_t root_user, int64_t nnz) {
     for (int32_t v = t; v < a.n; v += stride) {
         a.level[v] = (v == root_user) ? 0 : -1;
         a.parent[v] = (v == root_user) ? root_user : -1;
-        a.best[v] = INT32_MAX;
     }
     const uint64_t rbit = 1ull << (root & 63);
     for (int32_t w = t; w < a.words; w += stride) {
@@ -295,6 +298,10 @@ __global__ void k_bfs_init(BfsArgs a, int32_t root_user, int64_t nnz) {
         h->slot[0].mu_base = nnz;
         h->levels = 0;
         h->last = 0;
+        h->lv[0] = 0;
+        h->lv[1] = 0;
+        h->c_lvl = -1;
+        h->finished = 0;
         h->root = root;
         h->overflow = 0;
         h->reached = 0;
@@ -586,16 +593,22 @@ __device__ void level_bottom_up(const BfsArgs& a, int32_t lvl, const uint64_t* f
 // Expands frontier `lvl` (slot lvl % 3) into lvl+1.  policy: PP_PUSH,
 // PP_PULL or PP_SWITCH (decided here, identically in every workgroup, from
 // the slot statistics).
-__global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl, int32_t policy, float alpha,
-                                                          float beta) {
+// lvl_arg >= 0 names the level; -1 takes it from the header (lv[parity]).
+__global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_arg, int32_t parity, int32_t policy,
+                                                          float alpha, float beta) {
     extern __shared__ uint64_t s_bits[];
     BfsHdr* h = a.hdr;
+    const int32_t lvl = lvl_arg >= 0 ? lvl_arg : h->lv[parity];
     const int sc = lvl % 3, sn = (lvl + 1) % 3, sz = (lvl + 2) % 3;
     const BfsSlot cur = h->slot[sc];
     const int32_t nf = cur.n;
     const bool lead = (blockIdx.x == 0 && threadIdx.x == 0);
     if (nf == 0) {
-        if (lead) h->slot[sz] = BfsSlot{};
+        if (lead) {
+            h->lv[parity ^ 1] = lvl;  // stays at the empty level
+            h->c_lvl = -1;
+            h->finished = 1;
+        }
         return;
     }
     const int64_t mu = cur.mu_base - cur.m;  // out-edges of vertices not yet visited
@@ -619,6 +632,8 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl,
         h->last = lvl + 1;
         h->reached += nf;
         h->edges += cur.m;
+        h->lv[parity ^ 1] = lvl + 1;
+        h->c_lvl = lvl;
     }
     // the bitmap two levels ahead is rewritten next level: clear it now
     uint64_t* fb_clear = a.fb[sz];
@@ -645,103 +660,85 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl,
     flush_stats(cnt, deg, &h->slot[sn]);
 }
 
-// Second top-down pass: the chunk items queued for rows longer than kBigRow,
-// one wavefront per chunk.
-__global__ __launch_bounds__(kBfsBlock) void k_bfs_td_big(BfsArgs a, int32_t lvl) {
+// Second pass of a level: the chunk items of the long rows, one wavefront
+// per item.  Top-down chunks claim targets as the level kernel does.
+// Bottom-up chunks of one in-row run independently: each scans its slice in
+// stored order and the first chunk to find a frontier member claims the
+// vertex with an atomic OR on its visited bit (so the parent is a frontier
+// in-neighbour, not necessarily the first in stored order); a chunk whose
+// vertex is already claimed is skipped.
+__global__ __launch_bounds__(kBfsBlock) void k_bfs_chunks(BfsArgs a) {
     extern __shared__ uint64_t s_bits[];
     BfsHdr* h = a.hdr;
-    const int sn = (lvl + 1) % 3;
-    if (h->slot[sn].dir_prev != PP_PUSH) return;
-    const int32_t items = min(h->slot[sn].big, a.item_cap);
-    if (items == 0) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int32_t gwave = blockIdx.x * kBfsWaves + threadIdx.x / kWave;
-    const int32_t nwaves = gridDim.x * kBfsWaves;
-    int32_t cnt = 0;
-    int64_t deg = 0;
-    Pager pg{-1, 0};
-    const int32_t sw = ((int64_t)items * kBigRow >= a.stage_min) ? a.stage_words : 0;
-    if (sw) stage_bits(s_bits, a.visited, sw);
-    TdCtx cx{lvl, a.queue[(lvl + 1) & 1], a.fill[(lvl + 1) & 1], a.fb[sn], &h->slot[sn], s_bits, sw};
-    for (int32_t it = gwave; it < items; it += nwaves)
-        td_row(a, cx, pg, a.items[3 * it], a.items[3 * it + 1], a.items[3 * it + 2], cnt, deg, lane);
-    page_close(pg, cx.fill_next, lane);
-    flush_stats(cnt, deg, &h->slot[sn]);
-}
-
-// Bottom-up pass over the chunks of very long in-rows, one wavefront per
-// chunk: the first frontier member in a chunk lowers best[v] to its slot.
-// A chunk stops early once an earlier slot of the same row has a hit.
-__global__ __launch_bounds__(kBfsBlock) void k_bfs_bu_big(BfsArgs a, int32_t lvl) {
-    extern __shared__ uint64_t s_bits[];
-    BfsHdr* h = a.hdr;
+    const int32_t lvl = h->c_lvl;
+    if (lvl < 0) return;
     const int sc = lvl % 3, sn = (lvl + 1) % 3;
-    if (h->slot[sn].dir_prev != PP_PULL) return;
     const int32_t items = min(h->slot[sn].big, a.item_cap);
     if (items == 0) return;
-    const uint64_t* fb_cur = a.fb[sc];
-    const int32_t sw = ((int64_t)items * kBigInRow >= a.stage_min) ? a.stage_words : 0;
-    if (sw) stage_bits(s_bits, fb_cur, sw);
+    const int32_t dir = h->slot[sn].dir_prev;
     const int lane = threadIdx.x & (kWave - 1);
     const int32_t gwave = blockIdx.x * kBfsWaves + threadIdx.x / kWave;
     const int32_t nwaves = gridDim.x * kBfsWaves;
-    for (int32_t it = gwave; it < items; it += nwaves) {
-        const int32_t v = a.items[3 * it], b = a.items[3 * it + 1], e = a.items[3 * it + 2];
-        for (int32_t jb = b; jb < e; jb += kBuU * kWave) {
-            if (__shfl(lane == 0 ? a.best[v] : 0, 0) < jb) break;  // an earlier slot already hit
-            int32_t pos = -1;
-            bu_scan_row(a, fb_cur, s_bits, sw, jb, min(e, jb + kBuU * kWave), lane, pos);
-            if (pos >= 0) {
-                if (lane == 0) atomicMin(&a.best[v], pos);
-                break;
-            }
-        }
-    }
-}
-
-// Finishes the long in-row vertices: one item per vertex (its first chunk)
-// records the parent at best[v], sets the bitmaps and appends the vertex.
-__global__ __launch_bounds__(kBfsBlock) void k_bfs_bu_fin(BfsArgs a, int32_t lvl) {
-    BfsHdr* h = a.hdr;
-    const int sn = (lvl + 1) % 3;
-    if (h->slot[sn].dir_prev != PP_PULL) return;
-    const int32_t items = min(h->slot[sn].big, a.item_cap);
-    if (items == 0) return;
-    const int lane = threadIdx.x & (kWave - 1);
     int32_t cnt = 0;
     int64_t deg = 0;
     Pager pg{-1, 0};
     int32_t* q_next = a.queue[(lvl + 1) & 1];
     int32_t* fill_next = a.fill[(lvl + 1) & 1];
-    const int32_t nthreads = gridDim.x * blockDim.x;
-    const int32_t t0 = blockIdx.x * blockDim.x + threadIdx.x;
-    // wave-uniform trip count so page_append stays wave-collective
-    const int32_t trips = (items + nthreads - 1) / nthreads;
-    for (int32_t r = 0; r < trips; ++r) {
-        const int32_t it = t0 + r * nthreads;
-        bool found = false;
-        int32_t v = -1;
-        if (it < items) {
-            v = a.items[3 * it];
-            if (a.items[3 * it + 1] == a.csc_off[v]) {  // first chunk of v
-                const int32_t pos = a.best[v];
-                if (pos != INT32_MAX) {
-                    found = true;
+    const int32_t chunk = dir == PP_PUSH ? kBigRow : kBigInRow;
+    const int32_t sw = ((int64_t)items * chunk >= a.stage_min) ? a.stage_words : 0;
+    if (dir == PP_PUSH) {
+        if (sw) stage_bits(s_bits, a.visited, sw);
+        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw};
+        for (int32_t it = gwave; it < items; it += nwaves)
+            td_row(a, cx, pg, a.items[3 * it], a.items[3 * it + 1], a.items[3 * it + 2], cnt, deg, lane);
+    } else {
+        // Hits are collected per wavefront (vertex, slot) and claimed 64 at a
+        // time, one lane each, so a claim's round trip is shared.
+        __shared__ int32_t s_hv[kBfsWaves][kWave];
+        __shared__ int32_t s_hp[kBfsWaves][kWave];
+        const int w = threadIdx.x / kWave;
+        int32_t nh = 0;  // wave-uniform
+        auto claim_hits = [&]() {
+            wave_sync();
+            bool claimed = false;
+            int32_t v = -1;
+            if (lane < nh) {
+                v = s_hv[w][lane];
+                const uint64_t bit = 1ull << (v & 63);
+                const uint64_t old =
+                    atomicOr(reinterpret_cast<unsigned long long*>(&a.visited[v >> 6]), (unsigned long long)bit);
+                if (!(old & bit)) {
+                    claimed = true;
                     const int32_t vu = user_id(a.perm, v);
                     a.level[vu] = lvl + 1;
-                    a.parent[vu] = user_id(a.perm, a.csc_idx[pos]);
-                    const uint64_t bit = 1ull << (v & 63);
-                    atomicOr(reinterpret_cast<unsigned long long*>(&a.visited[v >> 6]), (unsigned long long)bit);
+                    a.parent[vu] = user_id(a.perm, a.csc_idx[s_hp[w][lane]]);
                     atomicOr(reinterpret_cast<unsigned long long*>(&a.fb[sn][v >> 6]), (unsigned long long)bit);
-                    a.best[v] = INT32_MAX;
                     cnt += 1;
                     deg += a.out_deg[v];
                 }
             }
-        }
-        const uint64_t fm = __ballot(found);
-        if (fm) page_append(a, pg, found, v, __popcll(fm & lanes_below(lane)), __popcll(fm), q_next, fill_next,
+            const uint64_t m = __ballot(claimed);
+            if (m)
+                page_append(a, pg, claimed, v, __popcll(m & lanes_below(lane)), __popcll(m), q_next, fill_next,
                             &h->slot[sn], lane);
+            wave_sync();
+            nh = 0;
+        };
+        const uint64_t* fb_cur = a.fb[sc];
+        if (sw) stage_bits(s_bits, fb_cur, sw);
+        for (int32_t it = gwave; it < items; it += nwaves) {
+            const int32_t v = a.items[3 * it], b = a.items[3 * it + 1], e = a.items[3 * it + 2];
+            int32_t pos = -1;
+            if (!((a.visited[v >> 6] >> (v & 63)) & 1ull)) bu_scan_row(a, fb_cur, s_bits, sw, b, e, lane, pos);
+            if (pos >= 0) {
+                if (lane == 0) {
+                    s_hv[w][nh] = v;
+                    s_hp[w][nh] = pos;
+                }
+                if (++nh == kWave) claim_hits();
+            }
+        }
+        if (nh) claim_hits();
     }
     page_close(pg, fill_next, lane);
     flush_stats(cnt, deg, &h->slot[sn]);
@@ -761,23 +758,24 @@ static void allow_stage_lds(const BfsArgs& a) {
     if (bytes <= 65536) return;
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bfs_level), hipFuncAttributeMaxDynamicSharedMemorySize,
                               bytes);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bfs_td_big),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bfs_bu_big),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bfs_chunks),
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-static pp_status launch_level(pp_graph g, const BfsArgs& a, int32_t lvl, int32_t policy, float alpha, float beta,
-                              hipStream_t st) {
+// Does a level of this policy on this graph ever queue chunk items?
+static bool needs_chunks(pp_graph g, int32_t policy) {
+    return (policy != PP_PULL && g->max_out_deg > kBigRow) || (policy != PP_PUSH && g->max_in_deg > kBigInRow);
+}
+
+// One level: the expansion kernel, then (when long rows can occur) the chunk
+// kernel.  lvl >= 0 names the level; lvl = -1 takes it from the header, the
+// level kernel reading lv[parity].
+static pp_status launch_level(pp_graph g, const BfsArgs& a, int32_t lvl, int32_t parity, int32_t policy, float alpha,
+                              float beta, hipStream_t st) {
     const int32_t blocks = bfs_blocks(g);
     const size_t lds = (size_t)a.stage_words * 8;
-    hipLaunchKernelGGL(k_bfs_level, dim3(blocks), dim3(kBfsBlock), lds, st, a, lvl, policy, alpha, beta);
-    if (policy != PP_PULL && g->max_out_deg > kBigRow)
-        hipLaunchKernelGGL(k_bfs_td_big, dim3(blocks), dim3(kBfsBlock), lds, st, a, lvl);
-    if (policy != PP_PUSH && g->max_in_deg > kBigInRow) {
-        hipLaunchKernelGGL(k_bfs_bu_big, dim3(blocks), dim3(kBfsBlock), lds, st, a, lvl);
-        hipLaunchKernelGGL(k_bfs_bu_fin, dim3(blocks), dim3(kBfsBlock), 0, st, a, lvl);
-    }
+    hipLaunchKernelGGL(k_bfs_level, dim3(blocks), dim3(kBfsBlock), lds, st, a, lvl, parity, policy, alpha, beta);
+    if (needs_chunks(g, policy)) hipLaunchKernelGGL(k_bfs_chunks, dim3(blocks), dim3(kBfsBlock), lds, st, a);
     PP_LAUNCH_CHECK("k_bfs_level");
     return PP_OK;
 }
@@ -819,7 +817,7 @@ static pp_status step(pp_graph g, void* state, int32_t* level, int32_t* parent, 
     if (cur_level < 0 || cur_level >= g->d.n) return set_error(PP_E_RANGE, "cur_level out of range");
     BfsArgs a = bfs_args(g, state, level, parent);
     allow_stage_lds(a);
-    return launch_level(g, a, cur_level, dir, 14.f, 24.f, static_cast<hipStream_t>(stream));
+    return launch_level(g, a, cur_level, 0, dir, 14.f, 24.f, static_cast<hipStream_t>(stream));
 }
 
 PP_EXPORT pp_status pp_bfs_step_push(pp_graph g, void* state, int32_t* level, int32_t* parent, int32_t cur_level,
@@ -855,19 +853,20 @@ PP_EXPORT pp_status pp_bfs_run(pp_graph g, int32_t root, pp_dir policy, float al
     const BfsLayout L = bfs_layout(g);
     const BfsHdr* dh = reinterpret_cast<const BfsHdr*>(static_cast<char*>(state) + L.hdr);
     BfsArgs a = bfs_args(g, state, level, parent);
-    // Levels go out in growing batches; kernels past the last level find an
-    // empty frontier and return at once, so only termination needs a read.
-    int32_t lvl = 0, batch = 2;
-    const int32_t max_levels = g->d.n;  // a BFS has at most n non-empty frontiers
+    // Levels go out in growing batches with the level index kept on the
+    // device; kernels past the last level find an empty frontier and return
+    // at once, so only termination needs a read.
+    int32_t launched = 0, batch = 2;
+    const int32_t max_levels = g->d.n + 1;  // at most n non-empty frontiers, then an empty one
     for (;;) {
-        for (int32_t i = 0; i < batch && lvl < max_levels; ++i, ++lvl) {
-            s = launch_level(g, a, lvl, policy, alpha, beta, st);
+        for (int32_t i = 0; i < batch && launched < max_levels; ++i, ++launched) {
+            s = launch_level(g, a, -1, launched & 1, policy, alpha, beta, st);
             if (s != PP_OK) return s;
         }
-        int32_t nf = 0;
-        PP_HIP(hipMemcpyAsync(&nf, &dh->slot[lvl % 3].n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        int32_t fin = 0;
+        PP_HIP(hipMemcpyAsync(&fin, &dh->finished, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         PP_HIP(hipStreamSynchronize(st));
-        if (nf == 0 || lvl >= max_levels) break;
+        if (fin || launched >= max_levels) break;
         batch = std::min<int32_t>(batch * 2, 64);
     }
     BfsHdr h;

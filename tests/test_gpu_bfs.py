@@ -116,15 +116,24 @@ def test_step_api_any_direction_sequence(relabel):
 
 @pytest.mark.parametrize("relabel", [True, False])
 def test_bottom_up_parents_are_first_in_stored_order(relabel):
-    # pull scans in-neighbours in stored order and stops at the first frontier member
+    # pull scans in-neighbours in stored order and stops at the first frontier
+    # member; in-rows of more than 256 edges are scanned in chunks, any of
+    # which may claim the vertex (still a frontier in-neighbour)
     host = gg.workload("rmat14")
     g = pp.Graph(host, relabel=relabel)
     want, _, _ = oracle.bfs(host.off, host.idx, 0)
     lv, par, _ = _run(g, 0, pp.PP_PULL)
-    for v in np.nonzero(want > 0)[0][:2000]:
+    deg = np.diff(host.off)
+    checked = 0
+    for v in np.nonzero(want > 0)[0]:
         row = host.idx[host.off[v]:host.off[v + 1]]
-        first = row[np.nonzero(want[row] == want[v] - 1)[0][0]]
-        assert par[v] == first
+        hits = row[want[row] == want[v] - 1]
+        if deg[v] <= 256:
+            assert par[v] == hits[0]
+            checked += 1
+        else:
+            assert par[v] in hits
+    assert checked > 1000
 
 
 def test_switch_policy_changes_direction_on_rmat():
