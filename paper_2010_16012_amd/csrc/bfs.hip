@@ -780,6 +780,64 @@ static pp_status launch_level(pp_graph g, const BfsArgs& a, int32_t lvl, int32_t
     return PP_OK;
 }
 
+// An instantiated HIP graph of `batch` levels (batch even; level kernels of
+// parity 0, 1, 0, ...), built once per argument set and kept in the handle.
+// Replaying it costs one launch instead of one or two per level.
+static pp_status bfs_graph(pp_graph g, BfsArgs a, int32_t policy, float alpha, float beta, int32_t batch,
+                           const void* state, hipGraphExec_t* out) {
+    for (auto& e : g->bfs_graphs)
+        if (e.state == state && e.level == a.level && e.parent == a.parent && e.policy == policy &&
+            e.alpha == alpha && e.beta == beta && e.batch == batch) {
+            *out = e.exec;
+            return PP_OK;
+        }
+    constexpr size_t kMaxCached = 24;
+    if (g->bfs_graphs.size() >= kMaxCached) {
+        (void)hipGraphExecDestroy(g->bfs_graphs.front().exec);
+        (void)hipGraphDestroy(g->bfs_graphs.front().graph);
+        g->bfs_graphs.erase(g->bfs_graphs.begin());
+    }
+    const int32_t blocks = bfs_blocks(g);
+    const unsigned lds = (unsigned)a.stage_words * 8;
+    const bool chunks = needs_chunks(g, policy);
+    hipGraph_t graph = nullptr;
+    PP_HIP(hipGraphCreate(&graph, 0));
+    hipGraphNode_t prev = nullptr;
+    auto add = [&](const void* fn, void** args) -> hipError_t {
+        hipKernelNodeParams p{};
+        p.func = const_cast<void*>(fn);
+        p.gridDim = dim3(blocks);
+        p.blockDim = dim3(kBfsBlock);
+        p.sharedMemBytes = lds;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        hipGraphNode_t node = nullptr;
+        const hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+        if (e == hipSuccess) prev = node;
+        return e;
+    };
+    hipError_t e = hipSuccess;
+    int32_t lvl = -1;
+    for (int32_t i = 0; i < batch && e == hipSuccess; ++i) {
+        int32_t parity = i & 1;
+        void* largs[] = {&a, &lvl, &parity, &policy, &alpha, &beta};
+        e = add(reinterpret_cast<const void*>(&k_bfs_level), largs);
+        if (e == hipSuccess && chunks) {
+            void* cargs[] = {&a};
+            e = add(reinterpret_cast<const void*>(&k_bfs_chunks), cargs);
+        }
+    }
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_error(e, "BFS level graph");
+    }
+    g->bfs_graphs.push_back({state, a.level, a.parent, policy, alpha, beta, batch, exec, graph});
+    *out = exec;
+    return PP_OK;
+}
+
 static pp_status read_hdr(pp_graph g, void* state, BfsHdr* h, hipStream_t st) {
     const BfsLayout L = bfs_layout(g);
     PP_HIP(hipMemcpyAsync(h, static_cast<char*>(state) + L.hdr, sizeof(BfsHdr), hipMemcpyDeviceToHost, st));
@@ -856,12 +914,20 @@ PP_EXPORT pp_status pp_bfs_run(pp_graph g, int32_t root, pp_dir policy, float al
     // Levels go out in growing batches with the level index kept on the
     // device; kernels past the last level find an empty frontier and return
     // at once, so only termination needs a read.
-    int32_t launched = 0, batch = 2;
+    int32_t launched = 0, batch = 4;
     const int32_t max_levels = g->d.n + 1;  // at most n non-empty frontiers, then an empty one
     for (;;) {
-        for (int32_t i = 0; i < batch && launched < max_levels; ++i, ++launched) {
-            s = launch_level(g, a, -1, launched & 1, policy, alpha, beta, st);
+        if (launched + batch <= max_levels) {  // a whole batch: replay its graph (launched stays even)
+            hipGraphExec_t exec = nullptr;
+            s = bfs_graph(g, a, policy, alpha, beta, batch, state, &exec);
             if (s != PP_OK) return s;
+            PP_HIP(hipGraphLaunch(exec, st));
+            launched += batch;
+        } else {
+            for (; launched < max_levels; ++launched) {
+                s = launch_level(g, a, -1, launched & 1, policy, alpha, beta, st);
+                if (s != PP_OK) return s;
+            }
         }
         int32_t fin = 0;
         PP_HIP(hipMemcpyAsync(&fin, &dh->finished, sizeof(int32_t), hipMemcpyDeviceToHost, st));

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string>
+#include <vector>
 
 #include "pp.h"
 
@@ -107,6 +108,25 @@ struct pp_graph_s {
     int32_t max_lds;             // LDS bytes one workgroup may allocate
     int32_t lds_per_cu;          // LDS bytes of one compute unit
     pp::Tuning tune;
+    // Instantiated HIP graphs of BFS level batches, keyed by their arguments
+    // (released by pp_graph_destroy).
+    struct BfsGraph {
+        const void* state;
+        const int32_t* level;
+        const int32_t* parent;
+        int32_t policy;
+        float alpha, beta;
+        int32_t batch;
+        hipGraphExec_t exec;
+        hipGraph_t graph;
+    };
+    std::vector<BfsGraph> bfs_graphs;
+    ~pp_graph_s() {
+        for (auto& e : bfs_graphs) {
+            (void)hipGraphExecDestroy(e.exec);
+            (void)hipGraphDestroy(e.graph);
+        }
+    }
 };
 
 namespace pp {
