@@ -121,8 +121,9 @@ pp_status pp_set_bin_thresholds(const int32_t* upper5, int32_t split_chunk);
 /* Push-sweep tuning: the first `hot` vertices (internal ids) are accumulated
  * per workgroup in LDS and merged once per sweep (the Partition-Awareness
  * strategy of Sec. 5 with a workgroup as the owner); the sweep runs on
- * `push_blocks` persistent workgroups.  Defaults 8192 and 1024; hot in
- * [0, 16384] (0 disables), push_blocks in [1, 65536].  Takes effect at the
+ * `push_blocks` persistent workgroups (of 256 threads, or of 1024 threads
+ * when more than 16384 targets are privatised).  Defaults 8192 and 1024; hot
+ * in [0, 40960] (0 disables), push_blocks in [1, 65536].  Takes effect at the
  * next pp_graph_create. */
 pp_status pp_set_push_tuning(int32_t hot, int32_t push_blocks);
 

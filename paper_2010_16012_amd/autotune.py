@@ -92,8 +92,8 @@ def tune_pagerank(host, iters=5, log=print) -> dict:
                 best = (t, pull_hot, block)
     out["pull_hot"], out["pull_block"] = best[1], best[2]
     best = None
-    for hot in (8192, 16384):
-        for blocks in (512, 1024, 2048):
+    for hot in (8192, 16384, 32768, 40960):
+        for blocks in ((512, 1024, 2048) if hot <= 16384 else (256, 512)):
             apply({"hot": hot, "push_blocks": blocks, "pull_hot": out["pull_hot"], "pull_block": out["pull_block"]})
             g = Graph(host)
             t = run(g, PP_PUSH)

@@ -526,7 +526,7 @@ PP_EXPORT pp_status pp_set_bin_thresholds(const int32_t* upper5, int32_t split_c
 
 PP_EXPORT pp_status pp_set_push_tuning(int32_t hot, int32_t push_blocks) {
     clear_error();
-    if (hot < 0 || hot > kHotMax) return set_error(PP_E_RANGE, "hot must lie in [0, 16384]");
+    if (hot < 0 || hot > kHotMax) return set_error(PP_E_RANGE, "hot must lie in [0, 40960]");
     if (push_blocks < 1 || push_blocks > 65536) return set_error(PP_E_RANGE, "push_blocks must lie in [1, 65536]");
     tuning().hot = hot;
     tuning().push_blocks = push_blocks;

@@ -28,8 +28,8 @@ constexpr int kPullLanes[PP_NUM_BINS] = {1, 1, 4, 16, 64, 64};
 constexpr int kPullLoads[PP_NUM_BINS] = {4, 16, 16, 16, 16, 16};
 
 // Push privatisation: the first kHotMax internal vertices can be accumulated
-// in LDS by each workgroup of the persistent push sweep.
-constexpr int kHotMax = 16384;
+// in LDS by each workgroup of the persistent push sweep (160 KB of LDS).
+constexpr int kHotMax = 40960;
 
 struct Tuning {
     int32_t upper[PP_NUM_BINS - 1] = {4, 16, 64, 1024, 4096};

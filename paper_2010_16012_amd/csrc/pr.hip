@@ -259,11 +259,12 @@ __device__ __forceinline__ void scatter_row(const PushArgs& a, float* s_hot, flo
     }
 }
 
+// Unit local_blk of bin `bin` for one kBlock-thread slice (thread tid).
 template <int G, bool W, bool HOT>
-__device__ __forceinline__ void push_group(const PushArgs& a, float* s_hot, int bin, int32_t local_blk) {
+__device__ __forceinline__ void push_group(const PushArgs& a, float* s_hot, int bin, int32_t local_blk, int tid) {
     constexpr int per_block = kBlock / G;
-    const int32_t i = local_blk * per_block + threadIdx.x / G;
-    const int lane = threadIdx.x & (G - 1);
+    const int32_t i = local_blk * per_block + tid / G;
+    const int lane = tid & (G - 1);
     const int32_t count = a.sp.list_off[bin + 1] - a.sp.list_off[bin];
     if (i < count) {
         const int32_t v = a.list[a.sp.list_off[bin] + i];
@@ -272,16 +273,20 @@ __device__ __forceinline__ void push_group(const PushArgs& a, float* s_hot, int 
     }
 }
 
-// Persistent: workgroup b takes units b, b + gridDim.x, ...  With HOT, LDS
-// holds this workgroup's sums for targets [0, hot), written out at the end.
-template <bool W, bool HOT>
-__global__ __launch_bounds__(kBlock) void k_pr_push(PushArgs a) {
+// Persistent: a workgroup is SUB slices of kBlock threads; slice q of
+// workgroup b takes units b*SUB + q, then strides by gridDim.x*SUB.  With HOT,
+// LDS holds the workgroup's sums for targets [0, hot) (SUB = 4 lets one
+// workgroup per CU privatise up to the whole LDS), written out at the end.
+template <int SUB, bool W, bool HOT>
+__global__ __launch_bounds__(SUB * kBlock) void k_pr_push(PushArgs a) {
     extern __shared__ float s_hot[];
     if (HOT) {
-        for (int32_t i = threadIdx.x; i < a.hot; i += kBlock) s_hot[i] = 0.f;
+        for (int32_t i = threadIdx.x; i < a.hot; i += SUB * kBlock) s_hot[i] = 0.f;
         __syncthreads();
     }
-    for (int32_t unit = blockIdx.x; unit < a.units; unit += gridDim.x) {
+    const int q = threadIdx.x / kBlock;
+    const int tid = threadIdx.x % kBlock;
+    for (int32_t unit = blockIdx.x * SUB + q; unit < a.units; unit += gridDim.x * SUB) {
         const int bin = unit_bin(a.sp, unit);
         const int32_t lb = unit - a.sp.block_off[bin];
         switch (bin) {
@@ -289,25 +294,25 @@ __global__ __launch_bounds__(kBlock) void k_pr_push(PushArgs a) {
                 const int32_t v = a.tab[lb];
                 const int32_t b = a.tab[a.tab_cap + lb], e = a.tab[2 * a.tab_cap + lb];
                 const float cv = a.c[v];
-                if (cv != 0.f) scatter_row<kBlock, W, HOT>(a, s_hot, cv, b, e, threadIdx.x);
+                if (cv != 0.f) scatter_row<kBlock, W, HOT>(a, s_hot, cv, b, e, tid);
                 break;
             }
             case 4: {
                 const int32_t v = a.list[a.sp.list_off[4] + lb];
                 const float cv = a.c[v];
-                if (cv != 0.f) scatter_row<kBlock, W, HOT>(a, s_hot, cv, a.off[v], a.off[v + 1], threadIdx.x);
+                if (cv != 0.f) scatter_row<kBlock, W, HOT>(a, s_hot, cv, a.off[v], a.off[v + 1], tid);
                 break;
             }
-            case 3: push_group<64, W, HOT>(a, s_hot, 3, lb); break;
-            case 2: push_group<16, W, HOT>(a, s_hot, 2, lb); break;
-            case 1: push_group<4, W, HOT>(a, s_hot, 1, lb); break;
-            default: push_group<1, W, HOT>(a, s_hot, 0, lb); break;
+            case 3: push_group<64, W, HOT>(a, s_hot, 3, lb, tid); break;
+            case 2: push_group<16, W, HOT>(a, s_hot, 2, lb, tid); break;
+            case 1: push_group<4, W, HOT>(a, s_hot, 1, lb, tid); break;
+            default: push_group<1, W, HOT>(a, s_hot, 0, lb, tid); break;
         }
     }
     if (HOT) {
         __syncthreads();
         float* dst = a.hot_part + (size_t)blockIdx.x * a.hot;
-        for (int32_t i = threadIdx.x; i < a.hot; i += kBlock) dst[i] = s_hot[i];
+        for (int32_t i = threadIdx.x; i < a.hot; i += SUB * kBlock) dst[i] = s_hot[i];
     }
 }
 
@@ -419,15 +424,30 @@ pp_status launch_push(pp_graph g, const float* c, float* y, hipStream_t st) {
     a.c = c;
     a.y = y;
     if (a.units == 0) return PP_OK;
-    const int32_t grid = std::min(a.units, g->tune.push_blocks);
     const bool hot = a.hot > 0;
     const size_t lds = hot ? (size_t)a.hot * sizeof(float) : 0;
-    if (g->weighted) {
-        if (hot) hipLaunchKernelGGL((k_pr_push<true, true>), dim3(grid), dim3(kBlock), lds, st, a);
-        else hipLaunchKernelGGL((k_pr_push<true, false>), dim3(grid), dim3(kBlock), 0, st, a);
+    // more than 64 KB of privatised targets: 1024-thread workgroups (one per
+    // CU holds the LDS), otherwise 256-thread workgroups
+    const bool wide = lds > 65536;
+    const int32_t sub = wide ? 4 : 1;
+    const int32_t grid = std::max(1, std::min(ceil_div(a.units, sub), g->tune.push_blocks));
+    if (wide) {
+        static bool attr_set = false;  // LDS beyond the default 64 KiB (same for every device)
+        if (!attr_set) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_push<4, true, true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, kHotMax * (int)sizeof(float));
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_push<4, false, true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, kHotMax * (int)sizeof(float));
+            attr_set = true;
+        }
+        if (g->weighted) hipLaunchKernelGGL((k_pr_push<4, true, true>), dim3(grid), dim3(4 * kBlock), lds, st, a);
+        else hipLaunchKernelGGL((k_pr_push<4, false, true>), dim3(grid), dim3(4 * kBlock), lds, st, a);
+    } else if (g->weighted) {
+        if (hot) hipLaunchKernelGGL((k_pr_push<1, true, true>), dim3(grid), dim3(kBlock), lds, st, a);
+        else hipLaunchKernelGGL((k_pr_push<1, true, false>), dim3(grid), dim3(kBlock), 0, st, a);
     } else {
-        if (hot) hipLaunchKernelGGL((k_pr_push<false, true>), dim3(grid), dim3(kBlock), lds, st, a);
-        else hipLaunchKernelGGL((k_pr_push<false, false>), dim3(grid), dim3(kBlock), 0, st, a);
+        if (hot) hipLaunchKernelGGL((k_pr_push<1, false, true>), dim3(grid), dim3(kBlock), lds, st, a);
+        else hipLaunchKernelGGL((k_pr_push<1, false, false>), dim3(grid), dim3(kBlock), 0, st, a);
     }
     if (hot) hipLaunchKernelGGL(k_pr_push_hot_reduce, dim3(ceil_div(a.hot, 64)), dim3(256), 0, st, a.hot, grid,
                                 (const float*)a.hot_part, y);

@@ -87,6 +87,21 @@ def test_push_privatisation_settings(hot, blocks):
         _lib.pp_set_push_tuning(8192, 1024)
 
 
+@pytest.mark.parametrize("hot,blocks", [(16385, 3), (40960, 256), (30000, 1000)])
+def test_push_wide_privatisation(hot, blocks):
+    # more than 16384 privatised targets: 1024-thread workgroups, up to 160 KB of LDS
+    host = gg.rmat(16, 16, seed=3)
+    want = oracle.pagerank(host.off, host.idx, F, 20)
+    _lib.pp_set_push_tuning(hot, blocks)
+    try:
+        for rl in (True, False):
+            g = pp.Graph(host, relabel=rl)
+            got = pr_gpu(g, pp.PP_PUSH, 20).astype(np.float64)
+            assert np.abs(got - want).sum() <= PR_L1_TOL, (hot, blocks, rl)
+    finally:
+        _lib.pp_set_push_tuning(8192, 1024)
+
+
 @pytest.mark.parametrize("hot,block", [(0, 1024), (1, 256), (300, 512), (1 << 20, 1024)])
 def test_pull_lds_staging_settings(hot, block):
     # no staging, a single staged entry, a partial prefix, everything that fits in LDS
