@@ -47,7 +47,7 @@ def parse():
                    help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     p.add_argument("--workload", default="rmat22",
                    help="rmat22 (default: the headline step), or a supplementary measurement: "
-                        "ppr20, multi512, grid4096, er22, adjoint20")
+                        "ppr20, multi512, grid4096, er22, adjoint20, tc16, tc18")
     p.add_argument("--tuned", default=os.path.join(ROOT, "paper_2010_16012_amd", "tuned.json"),
                    help="autotuner cache to apply (ignored when missing)")
     p.add_argument("--counters-summary", nargs="+", metavar="CSV",
@@ -384,6 +384,16 @@ def supplementary(args):
             line[name] = {"forward_sweeps": it_f, "forward_ms": round(ms_f, 2), "adjoint_sweeps": it_a,
                           "adjoint_ms": round(ms_a, 2)}
         line.update({"n": host.n, "nnz": host.nnz, "k": 32})
+    elif w in ("tc16", "tc18"):
+        # triangle counting, pulling (owner writes) vs pushing (64-bit fetch-and-add)
+        host = gg.rmat(int(w[2:]), 16, seed=1)
+        g = pp.Graph(host, relabel=False)
+        for d, name in ((pp.PP_PULL, "pull"), (pp.PP_PUSH, "push")):
+            pp.triangles(g, d)
+            ms = _events_ms(lambda: pp.triangles(g, d))
+            line[name] = {"ms": round(ms, 3), "gteps": round(host.nnz / (ms * 1e-3) / 1e9, 3)}
+        line["triangles"] = int(pp.triangles(g, pp.PP_PULL).sum().item() // 3)
+        line.update({"n": host.n, "nnz": host.nnz})
     else:
         raise SystemExit(f"unknown workload {w}")
     print(json.dumps(line), flush=True)

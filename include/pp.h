@@ -268,6 +268,22 @@ pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, const int64_t
                        int32_t bfs_policy, int32_t bfs_root, float alpha, float beta,
                        int32_t* level, int32_t* parent, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------- triangle counting */
+/* Workspace bytes of pp_tc_run for graph g (device, caller-owned, 256-byte
+ * aligned). */
+size_t pp_tc_workspace_bytes(pp_graph g);
+
+/* Triangles per vertex (Sec. 3.2; the NodeIterator listing of Sec. 4.2):
+ * tc[v] = 1/2 * #{(w1, w2) : w1, w2 in N(v), w2 in N(w1)}, N = the graph's
+ * CSR rows (out-neighbours), which must be in strictly ascending order (the
+ * call fails with PP_E_GRAPH otherwise; tc is then undefined).  The counts of
+ * one edge (v, w1) are found by intersecting the two rows.  dir = PP_PULL
+ * credits v (each counter written once, no atomics); PP_PUSH credits w1 with
+ * a 64-bit integer fetch-and-add.  On a symmetric graph both give the number
+ * of triangles containing each vertex.  tc: int64[n] device, caller ids.
+ * SYNC (reads the row-order check). */
+pp_status pp_tc_run(pp_graph g, pp_dir dir, int64_t* tc, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,7 @@ from ._lib import (PP_PULL, PP_PUSH, PP_SWITCH, PPError, BfsStats)  # noqa: F401
 from ._lib import *  # noqa: F401,F403  (the C names)
 
 __all__ = ["Graph", "BfsRun", "PPError", "PP_PUSH", "PP_PULL", "PP_SWITCH", "pagerank", "pagerank_into", "bfs",
-           "ppr", "ppr_adjoint", "PPRFunction", "MultiGraph"]
+           "ppr", "ppr_adjoint", "PPRFunction", "MultiGraph", "triangles"]
 
 
 class Graph:
@@ -188,6 +188,16 @@ class PPRFunction(torch.autograd.Function):
         f, iters, tol, k_tile, adir = ctx.cfg
         _, grad, _ = ppr_adjoint(ctx.g, X, dX.float(), iters=iters, f=f, k_tile=k_tile, direction=adir, tol=tol)
         return grad, None, None, None, None, None, None, None, None, None
+
+
+def triangles(g: Graph, direction=PP_PULL, stream=None):
+    """Triangles per vertex (int64[n], caller ids) by the pulling or pushing
+    form; the graph's rows must be in strictly ascending order."""
+    dev = g.device if hasattr(g, "device") else torch.device("cuda")
+    tc = torch.empty(g.n, dtype=torch.int64, device=dev)
+    ws = torch.empty(max(_lib.pp_tc_workspace_bytes(g.handle), 1), dtype=torch.uint8, device=dev)
+    _lib.pp_tc_run(g.handle, direction, tc, ws, stream)
+    return tc
 
 
 class MultiGraph:

@@ -85,6 +85,8 @@ _SIGS = {
                    ctypes.c_int),
     "pp_ppr_adjoint": ([_P, ctypes.c_int, _I32, _P, _P, _I32, _F32, _F32, _I32, _P, _P, _P, _SZ,
                         ctypes.POINTER(_I32), _P], ctypes.c_int),
+    "pp_tc_workspace_bytes": ([_P], _SZ),
+    "pp_tc_run": ([_P, ctypes.c_int, _P, _P, _SZ, _P], ctypes.c_int),
 }
 
 EXPORTS = tuple(_SIGS)
@@ -251,3 +253,11 @@ def pp_multi_run(graph_n, graph_nnz, off, idx, in_off, in_idx, pr_dir, pr_iters,
     _check(_lib.pp_multi_run(len(gn), ctypes.c_void_p(gn.ctypes.data), ctypes.c_void_p(ge.ctypes.data), _ptr(off),
                              _ptr(idx), _ptr(in_off), _ptr(in_idx), pr_dir, pr_iters, f, _ptr(x), bfs_policy,
                              bfs_root, alpha, beta, _ptr(level), _ptr(parent), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def pp_tc_workspace_bytes(h) -> int:
+    return _lib.pp_tc_workspace_bytes(h)
+
+
+def pp_tc_run(h, direction, tc, ws, stream=None) -> None:
+    _check(_lib.pp_tc_run(h, direction, _ptr(tc), _ptr(ws), ws.numel(), _stream(stream)))
