@@ -17,7 +17,8 @@ are stated at the top of ``oracle.c``:
   adjoint with respect to edge weights (not in the paper);
 * ``bfs`` -- FIFO-queue BFS (Sec. 3.3; Sec. 4.3 with ready counters of one);
 * ``bfs_replay`` -- what each top-down / bottom-up step examines (Sec. 4.3);
-* ``triangles`` -- per-vertex triangle counts (Sec. 3.2).
+* ``triangles`` -- per-vertex triangle counts (Sec. 3.2);
+* ``bc`` -- betweenness centrality over a set of sources (Sec. 3.5, Brandes).
 """
 from __future__ import annotations
 
@@ -59,6 +60,7 @@ def _load():
         "orc_bfs": [i64, P, P, i64, P, P],
         "orc_bfs_replay": [i64, P, P, i64, i32, P, P, P, P],
         "orc_triangles": [i64, P, P, P],
+        "orc_bc": [i64, P, P, P, i64, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -172,3 +174,12 @@ def triangles(off, idx) -> np.ndarray:
     tc = np.empty(n, dtype=np.int64)
     _check(_load().orc_triangles(n, _p(off), _p(idx), _p(tc)), "orc_triangles")
     return tc
+
+
+def bc(off, idx, sources) -> np.ndarray:
+    """Betweenness centrality summed over ``sources`` (ordered pairs)."""
+    n, off, idx = _graph(off, idx)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    out = np.empty(n, dtype=np.float64)
+    _check(_load().orc_bc(n, _p(off), _p(idx), _p(src), len(src), _p(out)), "orc_bc")
+    return out

@@ -386,3 +386,51 @@ int orc_triangles(int64_t n, const int64_t* off, const int32_t* idx, int64_t* tc
     }
     return 0;
 }
+
+/* Betweenness centrality restricted to a set of sources (Sec. 3.5; Brandes'
+ * scheme as in the Sec. 4.5 listing): for every source s, a FIFO BFS over
+ * out-edges counts shortest paths sigma(s, v); then, in reverse BFS order,
+ * delta(s, v) = sum over successors w (edge v->w, dist w = dist v + 1) of
+ * sigma(s,v)/sigma(s,w) * (1 + delta(s,w)).  bc[v] = sum over the sources
+ * s != v of delta(s, v): pairs (s, t) are ordered, so on an undirected graph
+ * every unordered pair counts twice, as in the paper's definition. */
+int orc_bc(int64_t n, const int64_t* off, const int32_t* idx, const int32_t* sources, int64_t ns, double* bc) {
+    int rc = check_graph(n, off, idx);
+    if (rc) return rc;
+    if (!bc || (ns > 0 && !sources)) return -1;
+    int32_t* dist = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    int32_t* order = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    double* sigma = (double*)malloc((size_t)n * sizeof(double));
+    double* delta = (double*)malloc((size_t)n * sizeof(double));
+    if (!dist || !order || !sigma || !delta) { free(dist); free(order); free(sigma); free(delta); return -3; }
+    for (int64_t v = 0; v < n; ++v) bc[v] = 0.0;
+    for (int64_t k = 0; k < ns; ++k) {
+        const int32_t s = sources[k];
+        if (s < 0 || s >= n) { free(dist); free(order); free(sigma); free(delta); return -1; }
+        for (int64_t v = 0; v < n; ++v) { dist[v] = -1; sigma[v] = 0.0; delta[v] = 0.0; }
+        int64_t head = 0, tail = 0;
+        dist[s] = 0;
+        sigma[s] = 1.0;
+        order[tail++] = s;
+        while (head < tail) {
+            const int32_t v = order[head++];
+            for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+                const int32_t w = idx[e];
+                if (dist[w] < 0) { dist[w] = dist[v] + 1; order[tail++] = w; }
+                if (dist[w] == dist[v] + 1) sigma[w] += sigma[v];
+            }
+        }
+        for (int64_t i = tail - 1; i >= 0; --i) {
+            const int32_t v = order[i];
+            double acc = 0.0;
+            for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+                const int32_t w = idx[e];
+                if (dist[w] == dist[v] + 1) acc += (1.0 + delta[w]) / sigma[w];
+            }
+            delta[v] = sigma[v] * acc;
+            if (v != s) bc[v] += delta[v];
+        }
+    }
+    free(dist); free(order); free(sigma); free(delta);
+    return 0;
+}

@@ -326,3 +326,78 @@ def test_triangles_closed_form_and_trace():
     A = H.dense_adjacency(g)
     tc = oracle.triangles(g.off, g.idx)
     np.testing.assert_array_equal(tc, np.diag(A @ A @ A).astype(np.int64) // 2)
+
+
+# --------------------------------------------------------------------------- betweenness
+def _bc_by_definition(g, sources=None):
+    """bc(v) = sum over ordered s != v != t of sigma_st(v) / sigma_st (s in
+    ``sources``, default all), with
+    sigma_st(v) = sigma_sv * sigma_vt when d(s,v) + d(v,t) = d(s,t): all-pairs
+    BFS path counts, no dependency recursion."""
+    n = g.n
+    A = H.dense_adjacency(g) > 0
+    dist = np.full((n, n), -1, dtype=np.int64)
+    sig = np.zeros((n, n))
+    for s in range(n):
+        dist[s, s], sig[s, s] = 0, 1.0
+        frontier = [s]
+        while frontier:
+            nxt = set()
+            for v in frontier:
+                for w in np.nonzero(A[v])[0]:
+                    if dist[s, w] < 0:
+                        dist[s, w] = dist[s, v] + 1
+                        nxt.add(int(w))
+                    if dist[s, w] == dist[s, v] + 1:
+                        sig[s, w] += sig[s, v]
+            frontier = sorted(nxt)
+    bc = np.zeros(n)
+    for s in (range(n) if sources is None else sources):
+        for t in range(n):
+            if s == t or dist[s, t] < 0:
+                continue
+            for v in range(n):
+                if v in (s, t) or dist[s, v] < 0 or dist[v, t] < 0:
+                    continue
+                if dist[s, v] + dist[v, t] == dist[s, t]:
+                    bc[v] += sig[s, v] * sig[v, t] / sig[s, t]
+    return bc
+
+
+@pytest.mark.parametrize("sym", [True, False])
+def test_bc_matches_definition_on_small_graphs(sym):
+    for seed, (n, m) in enumerate([(12, 20), (25, 60), (40, 90)]):
+        g = H.random_graph(n, m, 60 + seed, symmetric=sym)
+        np.testing.assert_allclose(oracle.bc(g.off, g.idx, np.arange(n)), _bc_by_definition(g), rtol=1e-12,
+                                   atol=1e-12)
+        # a subset of sources (on a directed graph this also fixes the edge direction)
+        sub = [0, n // 3, n - 1]
+        np.testing.assert_allclose(oracle.bc(g.off, g.idx, sub), _bc_by_definition(g, sub), rtol=1e-12,
+                                   atol=1e-12)
+
+
+def test_bc_closed_forms():
+    n = 9
+    # path: vertex i separates i vertices from n-1-i, both directions
+    i = np.arange(n)
+    np.testing.assert_allclose(oracle.bc(H.path(n).off, H.path(n).idx, i), 2.0 * i * (n - 1 - i))
+    st = H.star(n)
+    want = np.zeros(n)
+    want[0] = (n - 1) * (n - 2)
+    np.testing.assert_allclose(oracle.bc(st.off, st.idx, i), want)
+    k = H.complete(n)
+    np.testing.assert_allclose(oracle.bc(k.off, k.idx, i), np.zeros(n))
+    # even cycle C_2k: every vertex has the same score, and the scores sum to
+    # the total excess path length sum_{s != t} (d(s,t) - 1)
+    c = H.cycle(10)
+    b = oracle.bc(c.off, c.idx, np.arange(10))
+    d = np.minimum(np.arange(10), 10 - np.arange(10))
+    np.testing.assert_allclose(b, np.full(10, b[0]))
+    assert b.sum() == pytest.approx(10 * np.sum(np.maximum(d[1:] - 1, 0)))
+
+
+def test_bc_is_additive_over_sources():
+    g = H.random_graph(60, 200, 77)
+    a = oracle.bc(g.off, g.idx, [0, 5, 9])
+    b = oracle.bc(g.off, g.idx, [0]) + oracle.bc(g.off, g.idx, [5]) + oracle.bc(g.off, g.idx, [9])
+    np.testing.assert_allclose(a, b, rtol=1e-13)
