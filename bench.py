@@ -47,7 +47,7 @@ def parse():
                    help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     p.add_argument("--workload", default="rmat22",
                    help="rmat22 (default: the headline step), or a supplementary measurement: "
-                        "ppr20, multi512, grid4096, er22, adjoint20, tc16, tc18")
+                        "ppr20, multi512, grid4096, er22, adjoint20, tc16, tc18, bc16")
     p.add_argument("--tuned", default=os.path.join(ROOT, "paper_2010_16012_amd", "tuned.json"),
                    help="autotuner cache to apply (ignored when missing)")
     p.add_argument("--counters-summary", nargs="+", metavar="CSV",
@@ -394,6 +394,17 @@ def supplementary(args):
             line[name] = {"ms": round(ms, 3), "gteps": round(host.nnz / (ms * 1e-3) / 1e9, 3)}
         line["triangles"] = int(pp.triangles(g, pp.PP_PULL).sum().item() // 3)
         line.update({"n": host.n, "nnz": host.nnz})
+    elif w == "bc16":
+        # Brandes BC from 64 seeded sources on R-MAT 16, every phase combination
+        host = gg.rmat(16, 16, seed=1)
+        src = gg.pick_vertices(host, 64, seed=4)
+        g = pp.Graph(host)
+        for fd, bd, name in ((pp.PP_PUSH, pp.PP_PUSH, "push_push"), (pp.PP_PULL, pp.PP_PULL, "pull_pull"),
+                             (pp.PP_PUSH, pp.PP_PULL, "push_pull"), (pp.PP_PULL, pp.PP_PUSH, "pull_push")):
+            pp.betweenness(g, src[:2], fd, bd)
+            ms = _events_ms(lambda: pp.betweenness(g, src, fd, bd))
+            line[name] = {"ms": round(ms, 2), "ms_per_source": round(ms / len(src), 3)}
+        line.update({"n": host.n, "nnz": host.nnz, "sources": len(src)})
     else:
         raise SystemExit(f"unknown workload {w}")
     print(json.dumps(line), flush=True)

@@ -284,6 +284,28 @@ size_t pp_tc_workspace_bytes(pp_graph g);
  * SYNC (reads the row-order check). */
 pp_status pp_tc_run(pp_graph g, pp_dir dir, int64_t* tc, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------ betweenness centrality */
+/* Workspace bytes of pp_bc_run for graph g (device, caller-owned, 256-byte
+ * aligned): distances, path counts, dependencies and the BFS order. */
+size_t pp_bc_workspace_bytes(pp_graph g);
+
+/* Betweenness centrality over a set of sources (Sec. 3.5; Brandes' scheme as
+ * in the Sec. 4.5 listing): bc[v] = sum over sources s != v of
+ * delta_s(v) = sum over t of sigma_st(v) / sigma_st, with sigma the number of
+ * shortest paths along out-edges (ordered pairs: on an undirected graph each
+ * unordered pair counts twice).  Per source, a level-synchronous forward pass
+ * counts paths and a backward pass accumulates dependencies, deepest level
+ * first.  fwd_dir PP_PUSH: frontier vertices claim targets (CAS on the
+ * distance) and add their path counts with FP64 atomics; PP_PULL: unvisited
+ * vertices sum over their in-neighbours in the frontier (owner writes).
+ * bwd_dir PP_PUSH: vertices add to their predecessors' dependency with FP64
+ * atomics; PP_PULL: vertices sum over their successors (owner writes).
+ * sources: HOST int32[num_sources] (caller ids); bc: double[n] device,
+ * overwritten.  Reads one counter per forward level (synchronises the
+ * stream each level). */
+pp_status pp_bc_run(pp_graph g, pp_dir fwd_dir, pp_dir bwd_dir, int32_t num_sources, const int32_t* sources,
+                    double* bc, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

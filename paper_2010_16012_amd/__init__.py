@@ -15,7 +15,7 @@ from ._lib import (PP_PULL, PP_PUSH, PP_SWITCH, PPError, BfsStats)  # noqa: F401
 from ._lib import *  # noqa: F401,F403  (the C names)
 
 __all__ = ["Graph", "BfsRun", "PPError", "PP_PUSH", "PP_PULL", "PP_SWITCH", "pagerank", "pagerank_into", "bfs",
-           "ppr", "ppr_adjoint", "PPRFunction", "MultiGraph", "triangles"]
+           "ppr", "ppr_adjoint", "PPRFunction", "MultiGraph", "triangles", "betweenness"]
 
 
 class Graph:
@@ -198,6 +198,14 @@ def triangles(g: Graph, direction=PP_PULL, stream=None):
     ws = torch.empty(max(_lib.pp_tc_workspace_bytes(g.handle), 1), dtype=torch.uint8, device=dev)
     _lib.pp_tc_run(g.handle, direction, tc, ws, stream)
     return tc
+
+
+def betweenness(g: Graph, sources, fwd_dir=PP_PULL, bwd_dir=PP_PULL, stream=None):
+    """Betweenness centrality summed over ``sources`` (float64[n], caller ids)."""
+    bc = torch.empty(g.n, dtype=torch.float64, device=g.device)
+    ws = torch.empty(max(_lib.pp_bc_workspace_bytes(g.handle), 1), dtype=torch.uint8, device=g.device)
+    _lib.pp_bc_run(g.handle, fwd_dir, bwd_dir, sources, bc, ws, stream)
+    return bc
 
 
 class MultiGraph:

@@ -87,6 +87,8 @@ _SIGS = {
                         ctypes.POINTER(_I32), _P], ctypes.c_int),
     "pp_tc_workspace_bytes": ([_P], _SZ),
     "pp_tc_run": ([_P, ctypes.c_int, _P, _P, _SZ, _P], ctypes.c_int),
+    "pp_bc_workspace_bytes": ([_P], _SZ),
+    "pp_bc_run": ([_P, ctypes.c_int, ctypes.c_int, _I32, _P, _P, _P, _SZ, _P], ctypes.c_int),
 }
 
 EXPORTS = tuple(_SIGS)
@@ -261,3 +263,15 @@ def pp_tc_workspace_bytes(h) -> int:
 
 def pp_tc_run(h, direction, tc, ws, stream=None) -> None:
     _check(_lib.pp_tc_run(h, direction, _ptr(tc), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def pp_bc_workspace_bytes(h) -> int:
+    return _lib.pp_bc_workspace_bytes(h)
+
+
+def pp_bc_run(h, fwd_dir, bwd_dir, sources, bc, ws, stream=None) -> None:
+    """sources: host int32 array (caller ids); bc, ws: device tensors."""
+    import numpy as np
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    _check(_lib.pp_bc_run(h, fwd_dir, bwd_dir, len(src), ctypes.c_void_p(src.ctypes.data), _ptr(bc), _ptr(ws),
+                          ws.numel(), _stream(stream)))

@@ -1,0 +1,75 @@
+"""Betweenness centrality (Brandes on the BFS step), pushing and pulling
+phases in every combination, against the FP64 oracle."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+import paper_2010_16012_amd as pp
+from tests import helpers as H
+from tests.gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+COMBOS = list(itertools.product([pp.PP_PUSH, pp.PP_PULL], repeat=2))
+RTOL = 1e-9  # FP64 sums in another order (push: atomics)
+
+
+def _check(host, sources, combos=COMBOS):
+    want = oracle.bc(host.off, host.idx, sources)
+    g = pp.Graph(host)
+    for fd, bd in combos:
+        announce(f"bc {host.name} n={host.n} sources={len(sources)} fwd={fd} bwd={bd}")
+        got = pp.betweenness(g, sources, fd, bd)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(got.cpu().numpy(), want, rtol=RTOL, atol=1e-9 * max(1.0, np.abs(want).max()))
+    return want
+
+
+def test_closed_forms():
+    n = 33
+    i = np.arange(n)
+    np.testing.assert_allclose(_check(H.path(n), i), 2.0 * i * (n - 1 - i))
+    want = np.zeros(n)
+    want[0] = (n - 1) * (n - 2)
+    np.testing.assert_allclose(_check(H.star(n), i), want)
+    _check(H.complete(20), np.arange(20))
+    _check(H.full_grid(12, 17), np.arange(0, 204, 7))
+
+
+def test_random_undirected_and_directed():
+    for sym in (True, False):
+        for seed, (n, m) in enumerate([(50, 150), (700, 4000)]):
+            h = H.random_graph(n, m, 80 + seed, symmetric=sym)
+            if not sym:
+                h.ensure_transpose()
+            _check(h, np.arange(0, n, max(1, n // 40)))
+
+
+def test_rmat14_sources_with_hubs_and_isolated():
+    host = gg.workload("rmat14")
+    src = np.concatenate([[0], gg.pick_vertices(host, 15, seed=3)])
+    deg = np.diff(host.off)
+    isolated = np.nonzero(deg == 0)[0][:2]
+    _check(host, np.concatenate([src, isolated]))
+
+
+def test_long_rows_both_phases():
+    # hub rows (walked by a whole wave) and long in-rows summed by the wave
+    n = 3000
+    src = np.concatenate([np.zeros(n - 1, np.int64), np.arange(1, n - 1)])
+    dst = np.concatenate([np.arange(1, n), np.arange(2, n)])
+    _check(gg.from_edges(n, src, dst, True, "star+path"), [0, 1, 1500, 2999])
+
+
+def test_errors():
+    g = pp.Graph(H.path(5))
+    with pytest.raises(pp.PPError):
+        pp.betweenness(g, [5])
+    with pytest.raises(pp.PPError):
+        pp.betweenness(g, [0], pp.PP_SWITCH, pp.PP_PULL)
+    z = pp.betweenness(g, np.zeros(0, np.int32))
+    assert torch.count_nonzero(z).item() == 0
