@@ -47,7 +47,7 @@ def parse():
                    help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     p.add_argument("--workload", default="rmat22",
                    help="rmat22 (default: the headline step), or a supplementary measurement: "
-                        "ppr20, multi512, grid4096, er22, adjoint20, tc16, tc18, bc16")
+                        "ppr20, multi512, grid4096, er22, adjoint20, tc16, tc18, bc16, pprgrid")
     p.add_argument("--tuned", default=os.path.join(ROOT, "paper_2010_16012_amd", "tuned.json"),
                    help="autotuner cache to apply (ignored when missing)")
     p.add_argument("--counters-summary", nargs="+", metavar="CSV",
@@ -317,13 +317,14 @@ def supplementary(args):
         autotune.apply(tuned)
         kt = tuned.get("k_tile", 32)
         g = pp.Graph(host)
-        for d, name in ((pp.PP_PULL, "pull"), (pp.PP_PUSH, "push")):
+        for d, name in ((pp.PP_PULL, "pull"), (pp.PP_PUSH, "push"), (pp.PP_SWITCH, "switch")):
             pp.ppr(g, src, iters=2, k_tile=kt, direction=d)
             ms = _events_ms(lambda: pp.ppr(g, src, iters=30, k_tile=kt, direction=d))
             # sequential baseline: k single-vector sweeps of the same form (the
             # PageRank sweep does the same per-edge work for one vector)
             x = torch.full((host.n,), 1.0 / host.n, dtype=torch.float32, device="cuda")
-            ms_sweep = _events_ms(lambda: pp.pagerank_into(g, x, 20, 0.85, d)) / 20
+            seq_dir = pp.PP_PUSH if d == pp.PP_PUSH else pp.PP_PULL
+            ms_sweep = _events_ms(lambda: pp.pagerank_into(g, x, 20, 0.85, seq_dir)) / 20
             ms_seq = ms_sweep * 30 * len(src)
             work = host.nnz * len(src) * 30
             line[name] = {"ms": round(ms, 2), "gteps": round(work / (ms * 1e-3) / 1e9, 2),
@@ -394,6 +395,19 @@ def supplementary(args):
             line[name] = {"ms": round(ms, 3), "gteps": round(host.nnz / (ms * 1e-3) / 1e9, 3)}
         line["triangles"] = int(pp.triangles(g, pp.PP_PULL).sum().item() // 3)
         line.update({"n": host.n, "nnz": host.nnz})
+    elif w == "pprgrid":
+        # personalised PageRank on a 2048 x 2048 grid (5% of edges removed), k = 32
+        # sources, 30 sweeps: Generic-Switch (sparse push from the support, then
+        # dense pull) against dense pull sweeps from the start
+        host = gg.grid(2048, 2048, 0.05, seed=1)
+        src = gg.pick_vertices(host, 32, seed=5)
+        g = pp.Graph(host)
+        for d, name in ((pp.PP_PULL, "pull"), (pp.PP_SWITCH, "switch")):
+            pp.ppr(g, src, iters=2, k_tile=32, direction=d)
+            ms = _events_ms(lambda: pp.ppr(g, src, iters=30, k_tile=32, direction=d))
+            line[name] = {"ms": round(ms, 2)}
+        line["speedup_switch_vs_pull"] = round(line["pull"]["ms"] / line["switch"]["ms"], 2)
+        line.update({"n": host.n, "nnz": host.nnz, "k": 32, "iters": 30})
     elif w == "bc16":
         # Brandes BC from 64 seeded sources on R-MAT 16, every phase combination
         host = gg.rmat(16, 16, seed=1)

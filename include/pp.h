@@ -218,11 +218,17 @@ size_t pp_ppr_scratch_bytes(pp_graph g, int32_t k, int32_t k_tile);
  * caller ids (output).  Columns run in tiles of k_tile (8, 16, 32, 64; the
  * last tile may be partial); a tile's rows hold k_tile contiguous values so every edge
  * moves one coalesced k_tile-float row.  dir PP_PULL gathers along CSC (no
- * atomics, deterministic), PP_PUSH scatters along CSR with FP32 atomics.
- * Runs `iters` sweeps per tile, or stops a tile early once the L1 change of
- * its iterate in one sweep is at most tol times the iterate's L1 norm (tol =
- * 0: exactly iters; each check synchronises the stream).  iters_done (host, nullable): most sweeps
- * any tile ran.  SYNC when tol > 0 (and once to validate the sources). */
+ * atomics, deterministic), PP_PUSH scatters along CSR with FP64 atomics into
+ * an FP64 accumulator.  PP_SWITCH applies the Generic-Switch strategy of
+ * Sec. 5: while the tile's support (the vertices within t hops of its
+ * sources) has at most m/14 out-edges, a sweep pushes from the support only
+ * (sparse matrix times sparse vector along CSR, Sec. 7.1, FP64 atomics);
+ * afterwards the tile continues with pulling sweeps.  Runs `iters` sweeps per
+ * tile, or stops a tile early once the L1 change of its iterate in one sweep
+ * is at most tol times the iterate's L1 norm (tol = 0: exactly iters; each
+ * check synchronises the stream; PP_SWITCH also synchronises after each
+ * sparse sweep).  iters_done (host, nullable): most sweeps any tile ran.
+ * SYNC when tol > 0 or dir = PP_SWITCH (and once to validate the sources). */
 pp_status pp_ppr_run(pp_graph g, pp_dir dir, int32_t k, const int32_t* sources, int32_t iters, float tol,
                      float f, int32_t k_tile, float* X, void* scratch, size_t scratch_bytes,
                      int32_t* iters_done, void* stream);

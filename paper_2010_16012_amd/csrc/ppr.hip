@@ -421,16 +421,130 @@ __global__ __launch_bounds__(kBlock) void k_kcol_grad(GradArgs a) {
 }
 
 __global__ void k_zero_f32(int64_t m, float* __restrict__ p) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m) p[i] = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.f;
 }
 
 // ------------------------------------------------------------------ host side
-struct PprLayout {
-    size_t t0, t1, t2, t3, t4, part, resid, scal, srcs, total;
+// ------------------------------------------------- sparse phase (PP_SWITCH)
+// The Generic-Switch strategy (Sec. 5) for PPR: the iterate of a one-hot
+// start is supported on the ball of radius t around the sources, so the first
+// sweeps push from the support only (a sparse matrix - sparse vector product
+// along CSR, Sec. 7.1) and the run switches to the dense pull sweep once the
+// support's out-edges exceed m / kSwAlpha.  The support grows monotonically;
+// it is kept as a list of all its vertices (epilogue), a list of its vertices
+// with at most kSwChunk out-edges and (v, begin, end) chunk items of the longer
+// rows (scatter work units), all cumulative.
+constexpr int32_t kSwChunk = 64;
+constexpr int32_t kSwAlpha = 14;
+constexpr int32_t kSwEpiBlocks = 4096;  // workgroups of the sparse epilogue (upper bound)
+
+struct SwState {
+    uint64_t* bits;   // support membership
+    int32_t* all;     // support vertices
+    int32_t* small;   // support vertices with <= kSwChunk out-edges
+    int32_t* items;   // chunk items of the longer rows
+    int32_t* cnt;     // [0] |all|, [1] |small|, [2] items, [3] overflow; [4..5] out-edges (int64)
+    int32_t item_cap;
+    const int32_t* off;
 };
 
-static PprLayout ppr_layout(int32_t n, int32_t split_cap, int32_t k, int32_t kt, int32_t max_units) {
+// Adds u to the support (first caller only).
+__device__ __forceinline__ void sw_claim(const SwState& w, int32_t u) {
+    const uint64_t bit = 1ull << (u & 63);
+    if (w.bits[u >> 6] & bit) return;
+    const uint64_t old = atomicOr(reinterpret_cast<unsigned long long*>(&w.bits[u >> 6]), (unsigned long long)bit);
+    if (old & bit) return;
+    w.all[atomicAdd(&w.cnt[0], 1)] = u;
+    const int32_t b = w.off[u], e = w.off[u + 1];
+    atomicAdd(reinterpret_cast<unsigned long long*>(&w.cnt[4]), (unsigned long long)(e - b));
+    if (e - b <= kSwChunk) {
+        w.small[atomicAdd(&w.cnt[1], 1)] = u;
+    } else {
+        const int32_t nch = (e - b + kSwChunk - 1) / kSwChunk;
+        const int32_t first = atomicAdd(&w.cnt[2], nch);
+        for (int32_t c = 0; c < nch; ++c) {
+            const int32_t it = first + c;
+            if (it >= w.item_cap) {
+                atomicOr(&w.cnt[3], 1);
+                break;
+            }
+            w.items[3 * it] = u;
+            w.items[3 * it + 1] = b + c * kSwChunk;
+            w.items[3 * it + 2] = min(e, b + (c + 1) * kSwChunk);
+        }
+    }
+}
+
+__global__ void k_sw_seed(SwState w, const int32_t* __restrict__ src_int, int32_t col0, int32_t kt) {
+    const int32_t c = threadIdx.x;
+    if (c < kt && src_int[col0 + c] >= 0) sw_claim(w, src_int[col0 + c]);
+}
+
+// One sparse push sweep: a group of KT lanes (one per column) per work unit
+// scatters c[v] along the unit's edges into the FP64 accumulator and claims
+// the targets for the next support.  The unit counts are read at launch.
+template <int KT, bool W>
+__global__ __launch_bounds__(kBlock) void k_sw_scatter(SwState w, const int32_t* __restrict__ idx,
+                                                       const float* __restrict__ wt, const float* __restrict__ c,
+                                                       double* __restrict__ acc, int32_t n_small, int32_t n_items) {
+    constexpr int G = kBlock / KT;
+    const int lane = threadIdx.x % KT;
+    const int32_t grp = blockIdx.x * G + threadIdx.x / KT;
+    const int32_t ngrp = gridDim.x * G;
+    for (int32_t unit = grp; unit < n_small + n_items; unit += ngrp) {
+        int32_t v, b, e;
+        if (unit < n_small) {
+            v = w.small[unit];
+            b = w.off[v];
+            e = w.off[v + 1];
+        } else {
+            const int32_t it = unit - n_small;
+            v = w.items[3 * it];
+            b = w.items[3 * it + 1];
+            e = w.items[3 * it + 2];
+        }
+        const float x = c[(size_t)v * KT + lane];
+        for (int32_t j = b; j < e; ++j) {
+            const int32_t u = idx[j];
+            if (x != 0.f) unsafeAtomicAdd(&acc[(size_t)u * KT + lane], (double)(W ? x * wt[j] : x));
+            if (lane == 0) sw_claim(w, u);
+        }
+    }
+}
+
+// Epilogue of a sparse sweep over the support (count read on the device).
+template <int KT>
+__global__ __launch_bounds__(kBlock) void k_sw_epi(KArgs a, SwState w, double* accum) {
+    __shared__ float red[2 * kBlock];
+    constexpr int G = kBlock / KT;
+    const int lane = threadIdx.x % KT;
+    const int32_t count = w.cnt[0];
+    float2 res = make_float2(0.f, 0.f);
+    for (int32_t i = blockIdx.x * G + threadIdx.x / KT; i < count; i += gridDim.x * G) {
+        const int32_t u = w.all[i];
+        const float acc = (float)accum[(size_t)u * KT + lane];
+        accum[(size_t)u * KT + lane] = 0.0;
+        const float2 r = kt_epilogue<KT>(a, u, lane, acc);
+        res.x += r.x;
+        res.y += r.y;
+    }
+    if (a.resid_part) resid_flush(res, red, a.resid_part, blockIdx.x);
+}
+
+__global__ void k_sw_clear(int32_t words, uint64_t* bits, int32_t* cnt) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x) bits[i] = 0ull;
+    if (blockIdx.x == 0 && threadIdx.x < 16) cnt[threadIdx.x] = 0;
+}
+
+struct PprLayout {
+    size_t t0, t1, t2, t3, t4, part, resid, scal, srcs;
+    size_t sw_bits, sw_all, sw_small, sw_items, sw_cnt;  // sparse-phase support (PP_SWITCH)
+    int32_t sw_item_cap;
+    size_t total;
+};
+
+static PprLayout ppr_layout(int32_t n, int64_t nnz, int32_t split_cap, int32_t k, int32_t kt, int32_t max_units) {
     PprLayout L{};
     size_t p = 0;
     auto take = [&](size_t bytes) {
@@ -445,9 +559,17 @@ static PprLayout ppr_layout(int32_t n, int32_t split_cap, int32_t k, int32_t kt,
     L.t3 = take(tile);
     L.t4 = take(2 * tile);  // FP64 push accumulator
     L.part = take((size_t)split_cap * kt * 4);
-    L.resid = take((size_t)(max_units + ceil_div(n, 4) + 64) * 8);
+    // residual pairs: one per work unit of a dense sweep, or one per
+    // workgroup of the sparse epilogue (at most kSwEpiBlocks)
+    L.resid = take((size_t)(std::max<int64_t>((int64_t)max_units + ceil_div(n, 4), kSwEpiBlocks) + 64) * 8);
     L.scal = take(64);
     L.srcs = take((size_t)(ceil_div(std::max(k, 1), kt) * kt) * 4);
+    L.sw_bits = take((size_t)ceil_div(n, 64) * 8);
+    L.sw_all = take((size_t)n * 4);
+    L.sw_small = take((size_t)n * 4);
+    L.sw_item_cap = (int32_t)std::min<int64_t>((int64_t)nnz / kSwChunk + n + 64, INT32_MAX / 4);
+    L.sw_items = take((size_t)L.sw_item_cap * 3 * 4);
+    L.sw_cnt = take(64);
     L.total = p;
     return L;
 }
@@ -525,6 +647,84 @@ __global__ void k_tile_to_caller(int32_t n, int32_t k, int32_t col0, const int32
 // below tol.  Forward state: t0/t1 iterates, t2/t3 scaled contributions;
 // adjoint state: t0/t1 Lambda; t4 is the push accumulator.  On return
 // *latest points at the newest iterate and *done holds the sweeps run.
+// Sparse sweeps of a forward tile while the support is small (PP_SWITCH).
+// On return *done = sweeps taken (negative if the tolerance was met, then no
+// dense sweep follows).  Buffers rotate as in the dense loop.
+template <int KT>
+static pp_status sparse_phase(pp_graph g, int32_t k, int32_t col0, int32_t iters, float tol, float f,
+                              const int32_t* src_int, char* base, const PprLayout& L, float* prev, float* next,
+                              float* c_cur, float* c_nxt, double* t4, float* resid, float* scal, int32_t* done,
+                              hipStream_t st) {
+    const int32_t n = g->d.n;
+    SwState w;
+    w.bits = reinterpret_cast<uint64_t*>(base + L.sw_bits);
+    w.all = reinterpret_cast<int32_t*>(base + L.sw_all);
+    w.small = reinterpret_cast<int32_t*>(base + L.sw_small);
+    w.items = reinterpret_cast<int32_t*>(base + L.sw_items);
+    w.cnt = reinterpret_cast<int32_t*>(base + L.sw_cnt);
+    w.item_cap = L.sw_item_cap;
+    const Walk csr = walk_csr(g, KT);
+    w.off = csr.off;
+    // the other two tiles start at zero: cells outside the support stay zero
+    const int64_t cells = (int64_t)n * KT;
+    hipLaunchKernelGGL(k_zero_f32, dim3(std::min<int64_t>(ceil_div(cells, 256), 65536)), dim3(256), 0, st, cells, next);
+    hipLaunchKernelGGL(k_zero_f32, dim3(std::min<int64_t>(ceil_div(cells, 256), 65536)), dim3(256), 0, st, cells,
+                       c_nxt);
+    hipLaunchKernelGGL(k_sw_clear, dim3(std::max(1, std::min(ceil_div(ceil_div(n, 64), 256), 4096))), dim3(256), 0,
+                       st, ceil_div(n, 64), w.bits, w.cnt);
+    hipLaunchKernelGGL(k_sw_seed, dim3(1), dim3(64), 0, st, w, src_int, col0, KT);
+    PP_LAUNCH_CHECK("ppr sparse seed");
+    int32_t h[8] = {};
+    PP_HIP(hipMemcpyAsync(h, w.cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+    PP_HIP(hipStreamSynchronize(st));
+    const int64_t m_switch = g->d.nnz / kSwAlpha;
+    const int32_t eb = std::min(g->num_cu * 4, kSwEpiBlocks);
+    *done = 0;
+    for (int32_t t = 0; t < iters; ++t) {
+        const int64_t m_s = (int64_t)((uint64_t)(uint32_t)h[4] | ((uint64_t)(uint32_t)h[5] << 32));
+        if (m_s > m_switch) break;  // dense from here on
+        const int32_t units = h[1] + std::min(h[2], w.item_cap);
+        if (units > 0) {
+            const int32_t blocks = std::max(1, std::min(eb, ceil_div(units, kBlock / KT)));
+            if (g->weighted)
+                hipLaunchKernelGGL((k_sw_scatter<KT, true>), dim3(blocks), dim3(kBlock), 0, st, w, csr.idx, csr.wt,
+                                   (const float*)c_cur, t4, h[1], std::min(h[2], w.item_cap));
+            else
+                hipLaunchKernelGGL((k_sw_scatter<KT, false>), dim3(blocks), dim3(kBlock), 0, st, w, csr.idx, csr.wt,
+                                   (const float*)c_cur, t4, h[1], std::min(h[2], w.item_cap));
+        }
+        KArgs a{};
+        a.kind = kEpiForward;
+        a.inv_s = g->d.inv_s;
+        a.perm = g->d.perm;
+        a.f = f;
+        a.k = k;
+        a.col0 = col0;
+        a.src_int = src_int;
+        a.prev = prev;
+        a.out_tile = next;
+        a.out_scaled = c_nxt;
+        a.resid_part = resid;
+        hipLaunchKernelGGL(k_sw_epi<KT>, dim3(eb), dim3(kBlock), 0, st, a, w, t4);
+        PP_LAUNCH_CHECK("ppr sparse sweep");
+        ++*done;
+        std::swap(prev, next);
+        std::swap(c_cur, c_nxt);
+        if (tol > 0.f && t + 1 < iters)
+            hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, eb, (const float*)resid, scal);
+        PP_HIP(hipMemcpyAsync(h, w.cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+        float r[2] = {0.f, 0.f};
+        if (tol > 0.f && t + 1 < iters) PP_HIP(hipMemcpyAsync(r, scal, sizeof(r), hipMemcpyDeviceToHost, st));
+        PP_HIP(hipStreamSynchronize(st));
+        if (h[3]) return set_error(PP_E_WORKSPACE, "sparse PPR item capacity exceeded");
+        if (tol > 0.f && t + 1 < iters && r[0] <= tol * r[1]) {
+            *done = -*done;
+            return PP_OK;
+        }
+    }
+    return PP_OK;
+}
+
 template <int KT>
 static pp_status run_tile(pp_graph g, bool adjoint, pp_dir dir, int32_t k, int32_t col0, int32_t iters, float tol,
                           float f, const int32_t* src_int, const float* g_caller, char* base, const PprLayout& L,
@@ -543,13 +743,29 @@ static pp_status run_tile(pp_graph g, bool adjoint, pp_dir dir, int32_t k, int32
     if (adjoint) hipLaunchKernelGGL(k_kcol_adjoint_init<KT>, cb, ct, 0, st, n, k, col0, g->d.perm, g_caller, t0, t4);
     else hipLaunchKernelGGL(k_kcol_forward_init<KT>, cb, ct, 0, st, n, src_int, col0, f, g->d.inv_s, t0, t2, t4);
     PP_LAUNCH_CHECK("ppr tile init");
-    const bool pull = (dir == PP_PULL);
     float* prev = t0;   // current iterate
     float* next = t1;
     float* c_cur = t2;  // forward: scaled contributions of prev
     float* c_nxt = t3;
     *done = 0;
-    for (int32_t t = 0; t < iters; ++t) {
+    int32_t t0_dense = 0;  // first dense sweep
+    if (dir == PP_SWITCH) {
+        pp_status s = sparse_phase<KT>(g, k, col0, iters, tol, f, src_int, base, L, prev, next, c_cur, c_nxt, t4,
+                                       resid, scal, done, st);
+        if (s != PP_OK) return s;
+        t0_dense = *done;
+        if (*done & 1) {  // the sparse sweeps swapped the buffers an odd number of times
+            std::swap(prev, next);
+            std::swap(c_cur, c_nxt);
+        }
+        if (*done < 0) {  // converged during the sparse phase
+            *done = -*done;
+            *latest = ((*done) & 1) ? t1 : t0;
+            return PP_OK;
+        }
+    }
+    const bool pull = (dir != PP_PUSH);
+    for (int32_t t = t0_dense; t < iters; ++t) {
         KArgs a{};
         a.kind = adjoint ? kEpiAdjoint : kEpiForward;
         a.inv_s = g->d.inv_s;
@@ -728,7 +944,8 @@ static pp_status ppr_dispatch(const PprCall& c, int32_t* iters_done) {
 static pp_status check_ppr(pp_graph g, pp_dir dir, int32_t k, int32_t iters, float tol, float f, int32_t kt,
                            void* scratch, size_t bytes, size_t need) {
     if (!g) return set_error(PP_E_NULL, "graph handle is NULL");
-    if (dir != PP_PUSH && dir != PP_PULL) return set_error(PP_E_RANGE, "dir must be PP_PUSH or PP_PULL");
+    if (dir != PP_PUSH && dir != PP_PULL && dir != PP_SWITCH)
+        return set_error(PP_E_RANGE, "dir must be PP_PUSH, PP_PULL or PP_SWITCH");
     if (k < 0) return set_error(PP_E_SIZE, "k must be >= 0");
     if (!valid_kt(kt)) return set_error(PP_E_RANGE, "k_tile must be 8, 16, 32 or 64");
     if (iters < 0) return set_error(PP_E_RANGE, "iters must be >= 0");
@@ -746,7 +963,7 @@ using namespace pp;
 
 PP_EXPORT size_t pp_ppr_scratch_bytes(pp_graph g, int32_t k, int32_t k_tile) {
     if (!g || !valid_kt(k_tile) || k < 0) return 0;
-    return ppr_layout(g->d.n, g->split_cap, k, k_tile, max_units(g, k_tile)).total;
+    return ppr_layout(g->d.n, g->d.nnz, g->split_cap, k, k_tile, max_units(g, k_tile)).total;
 }
 
 PP_EXPORT pp_status pp_ppr_run(pp_graph g, pp_dir dir, int32_t k, const int32_t* sources, int32_t iters, float tol,
@@ -771,7 +988,7 @@ PP_EXPORT pp_status pp_ppr_run(pp_graph g, pp_dir dir, int32_t k, const int32_t*
     c.sources = sources;
     c.out = X;
     c.base = static_cast<char*>(scratch);
-    c.L = ppr_layout(g->d.n, g->split_cap, k, k_tile, max_units(g, k_tile));
+    c.L = ppr_layout(g->d.n, g->d.nnz, g->split_cap, k, k_tile, max_units(g, k_tile));
     c.st = static_cast<hipStream_t>(stream);
     return ppr_dispatch(c, iters_done);
 }
@@ -783,6 +1000,7 @@ PP_EXPORT pp_status pp_ppr_adjoint(pp_graph g, pp_dir dir, int32_t k, const floa
     const size_t need = pp_ppr_scratch_bytes(g, k, k_tile);
     pp_status s = check_ppr(g, dir, k, iters, tol, f, k_tile, scratch, scratch_bytes, need);
     if (s != PP_OK) return s;
+    if (dir == PP_SWITCH) return set_error(PP_E_RANGE, "the adjoint runs PP_PUSH or PP_PULL sweeps");
     if (k > 0 && (!X || !dLdX || !Lambda)) return set_error(PP_E_NULL, "X, dLdX and Lambda are required");
     if (g->d.nnz > 0 && !grad_w) return set_error(PP_E_NULL, "grad_w is required");
     if (iters_done) *iters_done = 0;
@@ -801,7 +1019,7 @@ PP_EXPORT pp_status pp_ppr_adjoint(pp_graph g, pp_dir dir, int32_t k, const floa
     c.out = Lambda;
     c.grad = grad_w;
     c.base = static_cast<char*>(scratch);
-    c.L = ppr_layout(g->d.n, g->split_cap, k, k_tile, max_units(g, k_tile));
+    c.L = ppr_layout(g->d.n, g->d.nnz, g->split_cap, k, k_tile, max_units(g, k_tile));
     c.st = static_cast<hipStream_t>(stream);
     return ppr_dispatch(c, iters_done);
 }

@@ -45,6 +45,41 @@ def test_batched_ppr_matches_oracle_columns(kt, k):
             _cols_close(X.cpu().numpy(), want)
 
 
+@pytest.mark.parametrize("name,kt,k", [("rmat14", 32, 64), ("grid64", 16, 20), ("grid200", 8, 8),
+                                        ("star5000", 8, 3)])
+def test_switch_sparse_push_then_dense_pull(name, kt, k):
+    # rmat14 switches to dense after a sweep or two; the 64x64 grid part-way
+    # through; on the 200x200 grid the 30-hop support stays sparse throughout
+    host = {"rmat14": lambda: gg.workload("rmat14"), "grid64": lambda: H.full_grid(64, 64),
+            "grid200": lambda: H.full_grid(200, 200), "star5000": lambda: H.star(5000)}[name]()
+    src = gg.pick_vertices(host, k, seed=11)
+    want, _ = oracle.ppr(host.off, host.idx, src, F, T=30)
+    for rl in (True, False):
+        g = pp.Graph(host, relabel=rl)
+        announce(f"PPR switch {name} kt={kt} relabel={rl}")
+        X, done = pp.ppr(g, src, iters=30, f=F, k_tile=kt, direction=pp.PP_SWITCH)
+        assert done == 30
+        _cols_close(X.cpu().numpy(), want)
+
+
+def test_switch_weighted_directed_and_converged():
+    host = H.random_graph(3000, 9000, 12, symmetric=False, connected=True)
+    gg.with_weights(host, seed=2)
+    src = np.array([3, 700, 2999], dtype=np.int32)
+    want, _ = oracle.ppr(host.off, host.idx, src, F, T=25, weights=host.weights)
+    g = pp.Graph(host)
+    X, _ = pp.ppr(g, src, iters=25, f=F, k_tile=8, direction=pp.PP_SWITCH)
+    _cols_close(X.cpu().numpy(), want)
+    P = H.dense_transition(host, host.weights) if host.n <= 3000 else None
+    Xc, done = pp.ppr(g, src, iters=5000, f=F, k_tile=8, direction=pp.PP_SWITCH, tol=1e-8)
+    assert done < 5000
+    for j, s in enumerate(src):
+        e = np.zeros(host.n)
+        e[s] = 1
+        exact = np.linalg.solve(np.eye(host.n) - F * P, (1 - F) * e)
+        assert np.abs(Xc[:, j].cpu().numpy() - exact).sum() <= 2e-6
+
+
 def test_batched_ppr_directed_weighted_every_bin():
     host = H.random_graph(4000, 30000, 3, symmetric=False, connected=True)
     gg.with_weights(host, seed=8)
@@ -104,6 +139,8 @@ def test_ppr_edge_cases_and_errors():
         pp.ppr(g, [1] * 8, k_tile=12)
     with pytest.raises(pp.PPError):
         pp.ppr(g, [0, 1, 2, 3, 4, 5, 6, 10], k_tile=8)  # source out of range
+    with pytest.raises(pp.PPError):  # the adjoint has no sparse phase
+        pp.ppr_adjoint(g, X, torch.ones_like(X), iters=2, k_tile=8, direction=pp.PP_SWITCH)
 
 
 # ----------------------------------------------------------------------- adjoint
