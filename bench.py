@@ -239,7 +239,7 @@ def main():
         src_hash = source_hash("pr.hip")
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(src_hash, algo),
-                    "kernel": "k_pr_pull<false>", "algorithmic_bytes_per_launch": algo,
+                    "kernel": "k_pr_pull", "algorithmic_bytes_per_launch": algo,
                     "launch_us": round(t_launch * 1e6, 2)}
 
     if args.copy_calibration:

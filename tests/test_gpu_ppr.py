@@ -213,3 +213,62 @@ def test_autograd_function():
                                       tol=1e-15, weights=host.weights)
     gh = w.grad.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(gh - grad_o) / np.linalg.norm(grad_o) <= 1e-5
+
+
+def test_adjoint_finite_differences_rmat10_sampled_edges_and_directions():
+    # R-MAT scale 10 (n = 1024), weighted, 8 sources: the GPU gradient against
+    # FP64 central differences of the dense solve on 256 sampled edges and on
+    # 8 random directions (g . delta vs [L(w + h delta) - L(w - h delta)] / 2h)
+    import scipy.linalg as sla
+
+    host = gg.rmat(10, 16, seed=1)
+    gg.with_weights(host, seed=5)
+    n = host.n
+    src = gg.pick_vertices(host, 8, seed=3)
+    c = gg.normal(n * 8, seed=7).reshape(n, 8).astype(np.float64)
+    w64 = host.weights.astype(np.float64)
+    rows = np.repeat(np.arange(n), np.diff(host.off))
+    E = np.zeros((n, 8))
+    E[src, np.arange(8)] = 1.0 - F
+
+    def transition(w):
+        s = np.bincount(rows, weights=w, minlength=n)
+        P = np.zeros((n, n))
+        np.add.at(P, (host.idx, rows), w / s[rows])
+        return P
+
+    def loss(w):
+        return float((c * np.linalg.solve(np.eye(n) - F * transition(w), E)).sum())
+
+    P0 = transition(w64)
+    lu = sla.lu_factor(np.eye(n) - F * P0)
+    X0 = sla.lu_solve(lu, E)
+    L0 = float((c * X0).sum())
+
+    def loss_edge(e, dh):
+        # one weight changes column v of P only: I - fP changes by a rank-one
+        # term, so the solve is updated by Sherman-Morrison
+        v = rows[e]
+        w = w64.copy()
+        w[e] += dh
+        b, t = host.off[v], host.off[v + 1]
+        col = np.zeros(n)
+        np.add.at(col, host.idx[b:t], w[b:t] / w[b:t].sum())
+        y = sla.lu_solve(lu, F * (col - P0[:, v]))
+        return L0 + float((c.T @ y) @ X0[v]) / (1.0 - y[v])
+
+    g = pp.Graph(host)
+    X, _ = pp.ppr(g, src, iters=3000, f=F, k_tile=8, tol=1e-10)
+    _, grad, _ = pp.ppr_adjoint(g, X, torch.as_tensor(c, dtype=torch.float32, device="cuda"), iters=3000, f=F,
+                                k_tile=8, tol=1e-10)
+    gh = grad.cpu().numpy().astype(np.float64)
+    h = 1e-6
+    edges = np.unique(gg.uniform_int(256, 0, host.nnz - 1, seed=9))
+    fd = np.array([(loss_edge(e, h) - loss_edge(e, -h)) / (2 * h) for e in edges])
+    assert abs(loss_edge(int(edges[0]), h) - loss(w64 + h * np.eye(1, host.nnz, int(edges[0]))[0])) <= 1e-10
+    assert np.linalg.norm(gh[edges] - fd) / np.linalg.norm(fd) <= 1e-5
+    for r in range(8):
+        d = gg.normal(host.nnz, seed=100 + r).astype(np.float64)
+        d /= np.linalg.norm(d)
+        fdd = (loss(w64 + h * d) - loss(w64 - h * d)) / (2 * h)
+        assert abs(gh @ d - fdd) <= 1e-5 * np.linalg.norm(gh), (r, gh @ d, fdd)
