@@ -417,8 +417,12 @@ __device__ __forceinline__ void td_row(const BfsArgs& a, const TdCtx& cx, Pager&
     }
 }
 
+// by_bitmap: the frontier is large, so it is read from its bitmap word by
+// word (ascending ids: coalesced offsets, rows in memory order) instead of
+// from the queue (claim order).
 __device__ void level_top_down(const BfsArgs& a, const TdCtx& cx, const int32_t* q_cur, const int32_t* fill_cur,
-                               int32_t pages, int32_t& cnt, int64_t& deg, Pager& pg) {
+                               int32_t pages, const uint64_t* fb_cur, bool by_bitmap, int32_t& cnt, int64_t& deg,
+                               Pager& pg) {
     __shared__ int32_t s_start[kBfsWaves][kWave];
     __shared__ int32_t s_rb[kBfsWaves][kWave];
     __shared__ int32_t s_v[kBfsWaves][kWave];
@@ -428,14 +432,22 @@ __device__ void level_top_down(const BfsArgs& a, const TdCtx& cx, const int32_t*
     const int32_t nwaves = gridDim.x * kBfsWaves;
     // one unit = 64 queue slots (a quarter page)
     constexpr int kUnitsPerPage = kPage / kWave;
-    for (int32_t unit = gwave; unit < pages * kUnitsPerPage; unit += nwaves) {
-        const int32_t p = unit / kUnitsPerPage;
-        const int32_t pfill = fill_cur[p];
-        {
+    const int32_t nunits = by_bitmap ? a.words : pages * kUnitsPerPage;
+    for (int32_t unit = gwave; unit < nunits; unit += nwaves) {
+        int32_t v = -1;
+        if (by_bitmap) {
+            const uint64_t word = fb_cur[unit];
+            if (word == 0) continue;
+            if ((word >> lane) & 1ull) v = unit * kWave + lane;
+        } else {
+            const int32_t p = unit / kUnitsPerPage;
+            const int32_t pfill = fill_cur[p];
             const int32_t s = (unit % kUnitsPerPage) * kWave;
             if (s >= pfill) continue;
             const int32_t i = s + lane;
-            const int32_t v = (i < pfill) ? q_cur[p * kPage + i] : -1;
+            if (i < pfill) v = q_cur[p * kPage + i];
+        }
+        {
             const int32_t rb = (v >= 0) ? a.csr_off[v] : 0;
             const int32_t re = (v >= 0) ? a.csr_off[v + 1] : 0;
             int32_t len = re - rb;
@@ -535,13 +547,13 @@ __device__ void level_bottom_up(const BfsArgs& a, int32_t lvl, const uint64_t* f
         int32_t re = unvisited ? a.csc_off[v + 1] : 0;
         bool found = false;
         int32_t par = -1;
-        // very long in-rows: chunks scanned grid-wide by k_bfs_bu_big
+        // long in-rows: the wave scans 64 x kBuU in-neighbours at a time and
+        // stops at the first hit; of an in-row longer than kBigInRow only the
+        // first kBigInRow entries are scanned here (most hits come early) and,
+        // without a hit there, the rest becomes chunk items for the grid
         const bool huge = (re - rb) > kBigInRow;
-        if (__ballot(huge)) {
-            queue_chunks(a, huge, v, rb, re, kBigInRow, nxt, lane);
-            if (huge) re = rb;
-        }
-        // long in-rows: the wave scans 64 in-neighbours at a time, stops at the first hit
+        const int32_t rest_b = rb + kBigInRow, rest_e = re;
+        if (huge) re = rest_b;
         const bool coop = (re - rb) >= 32;
         uint64_t big = __ballot(coop);
         while (big) {
@@ -555,6 +567,8 @@ __device__ void level_bottom_up(const BfsArgs& a, int32_t lvl, const uint64_t* f
                 par = a.csc_idx[p];
             }
         }
+        const bool rest = huge && !found;
+        if (__ballot(rest)) queue_chunks(a, rest, v, rest_b, rest_e, kBigInRow, nxt, lane);
         // short in-rows: each lane scans its own, in stored order, kBuB
         // independent loads at a time
         if (unvisited && !coop) {
@@ -651,7 +665,8 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
     if (dir == PP_PUSH) {
         if (sw) stage_bits(s_bits, a.visited, sw);
         TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw};
-        level_top_down(a, cx, a.queue[lvl & 1], a.fill[lvl & 1], min(cur.pages, a.page_cap), cnt, deg, pg);
+        level_top_down(a, cx, a.queue[lvl & 1], a.fill[lvl & 1], min(cur.pages, a.page_cap), a.fb[sc], nf > a.words,
+                       cnt, deg, pg);
     } else {
         if (sw) stage_bits(s_bits, a.fb[sc], sw);
         level_bottom_up(a, lvl, a.fb[sc], s_bits, sw, q_next, fill_next, a.fb[sn], &h->slot[sn], cnt, deg, pg);
