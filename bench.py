@@ -152,7 +152,7 @@ def main():
 
     parts = ["pr_pull", "pr_push", "bfs_push", "bfs_pull", "bfs_switch"]
     if args.only:
-        parts = [p for p in parts if p in args.only.split(",")]
+        parts = [p for p in parts + ["pr_hybrid"] if p in args.only.split(",")]
     dev = torch.device("cuda:0")
     t_gen = time.time()
     host = gg.rmat(args.scale, 16, seed=1)
@@ -191,7 +191,8 @@ def main():
             if p.startswith("pr_"):
                 x.fill_(1.0 / n)
                 e0 = ev()  # the fill is not part of the sweep
-                pp.pagerank_into(g, x, PR_ITERS, F, pp.PP_PULL if p == "pr_pull" else pp.PP_PUSH)
+                d = {"pr_pull": pp.PP_PULL, "pr_push": pp.PP_PUSH, "pr_hybrid": pp.PP_SWITCH}[p]
+                pp.pagerank_into(g, x, PR_ITERS, F, d)
             else:
                 r = runs[p]
                 for root in roots:
@@ -211,7 +212,7 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
 
     part_ms = {p: float(np.mean([a.elapsed_time(b) for a, b in times[p]])) for p in parts}
-    part_edges = {"pr_pull": PR_ITERS * nnz, "pr_push": PR_ITERS * nnz}
+    part_edges = {"pr_pull": PR_ITERS * nnz, "pr_push": PR_ITERS * nnz, "pr_hybrid": PR_ITERS * nnz}
     for p in ("bfs_push", "bfs_pull", "bfs_switch"):
         part_edges[p] = float(root_edges.sum())
     step_edges = sum(part_edges[p] for p in parts)

@@ -147,10 +147,15 @@ pp_status pp_set_pull_tuning(int32_t pull_hot, int32_t pull_block);
 pp_status pp_pr_push(pp_graph g, const float* x, float* y, float f, void* stream);
 pp_status pp_pr_pull(pp_graph g, const float* x, float* y, float f, void* stream);
 
-/* iters Jacobi steps in direction dir (PP_PUSH or PP_PULL) starting from
- * x_inout (float[n], x_0 in, x_iters out), with the contribution
- * c[v] = f * x[v] * P-normaliser computed once per step in the fused
- * epilogue of the previous step.  iters >= 0. */
+/* iters Jacobi steps in direction dir starting from x_inout (float[n], x_0
+ * in, x_iters out), with the contribution c[v] = f * x[v] * P-normaliser
+ * computed once per step in the fused epilogue of the previous step.
+ * PP_PUSH and PP_PULL as above.  PP_SWITCH chooses the direction per edge
+ * class (the Partition-Awareness and switching ideas of Sec. 5 combined):
+ * edges into the first `hot` vertices (internal ids, pp_set_push_tuning) are
+ * pushed into per-workgroup LDS accumulators, which are summed in a fixed
+ * order (no global atomics), and the rows of all other vertices pull.
+ * iters >= 0. */
 pp_status pp_pr_run(pp_graph g, pp_dir dir, int32_t iters, float f, float* x_inout, void* stream);
 
 /* -------------------------------------------------------------------- BFS */

@@ -139,6 +139,7 @@ struct PullArgs {
     float* y;              // new iterate, caller ids (nullable)
     float base;            // (1-f)/n
     float f;
+    int32_t skip_below;    // rows u < skip_below are left to the hybrid's push part (0: none)
 };
 
 // Owner of u writes y = base + acc and the next contribution.
@@ -166,6 +167,7 @@ __device__ __forceinline__ void pull_unit(const PullArgs& a, int32_t lu, int lan
     const int32_t count = a.sp.list_off[BIN + 1] - a.sp.list_off[BIN];
     if (i >= count) return;  // whole groups leave together
     const int32_t u = a.list[a.sp.list_off[BIN] + i];
+    if (u < a.skip_below) return;  // likewise
     const int gl = lane & (G - 1);
     float acc = gather_row<G, U, W, HOT>(a.idx, a.wt, a.c, a.off[u], a.off[u + 1], gl, s_c, a.hot);
     acc = group_reduce<G>(acc);
@@ -190,6 +192,7 @@ __global__ __launch_bounds__(1024) void k_pr_pull(PullArgs a) {
         const int32_t lu = unit - a.wave_off[bin];
         switch (bin) {
             case 5: {  // one chunk of a very long row -> partial sum, finished by k_pr_pull_fix
+                if (a.tab[lu] < a.skip_below) break;
                 const int32_t b = a.tab[a.tab_cap + lu], e = a.tab[2 * a.tab_cap + lu];
                 float acc = gather_row<kPullLanes[5], kPullLoads[5], W, HOT>(a.idx, a.wt, a.c, b, e, lane, s_c, a.hot);
                 acc = group_reduce<kWave>(acc);
@@ -210,6 +213,7 @@ __global__ void k_pr_pull_fix(PullArgs a, int32_t nsplit) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nsplit) return;
     const int32_t* first = a.tab + 3 * a.tab_cap;
+    if (a.tab[first[i]] < a.skip_below) return;
     float acc = 0.f;
     for (int32_t e = first[i]; e < first[i + 1]; ++e) acc += a.part[e];
     pull_finish(a, a.tab[first[i]], acc);
@@ -332,6 +336,28 @@ __global__ __launch_bounds__(256) void k_pr_push_hot_reduce(int32_t hot, int32_t
     if (r == 0 && u < hot) y[u] += (s[0][threadIdx.x] + s[1][threadIdx.x]) + (s[2][threadIdx.x] + s[3][threadIdx.x]);
 }
 
+// Hybrid sweep, rows of the hot targets (u < hot): y = base + the sum of the
+// workgroups' LDS partials in fixed order, then the next contribution (or,
+// after the last step, x in caller ids).  Block: 64 targets x 4 row groups.
+__global__ __launch_bounds__(256) void k_pr_hyb_hot(int32_t hot, int32_t parts, const float* __restrict__ hot_part,
+                                                    float base, const float* __restrict__ inv_s, float f,
+                                                    float* __restrict__ c_next, float* __restrict__ x_out,
+                                                    const int32_t* __restrict__ perm) {
+    __shared__ float s[4][64];
+    const int32_t u = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int r = threadIdx.x >> 6;
+    float acc = 0.f;
+    if (u < hot)
+        for (int32_t b = r; b < parts; b += 4) acc += hot_part[(size_t)b * hot + u];
+    s[r][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (r == 0 && u < hot) {
+        const float yv = base + ((s[0][threadIdx.x] + s[1][threadIdx.x]) + (s[2][threadIdx.x] + s[3][threadIdx.x]));
+        if (c_next) c_next[u] = f * yv * inv_s[u];
+        if (x_out) x_out[user_id(perm, u)] = yv;
+    }
+}
+
 // c[u] = f * x[caller id of u] / s(u); optionally y[u] = base (push accumulator).
 __global__ void k_pr_prologue(int32_t n, const float* __restrict__ x, const int32_t* __restrict__ perm,
                               const float* __restrict__ inv_s, float f, float* __restrict__ c,
@@ -358,8 +384,111 @@ __global__ void k_pr_push_epilogue(int32_t n, const float* __restrict__ y, const
 // ------------------------------------------------------------------ launchers
 static float teleport(int32_t n, float f) { return (float)((1.0 - (double)f) / (double)n); }
 
-pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float f, hipStream_t st) {
+// ------------------------------------------------------------------ hybrid
+// The hybrid sweep's push part, laid out like the pull sweep (persistent
+// wavefront units over the out-degree bins, G lanes per row, U loads in
+// flight per lane): every row u adds c[u] to its targets below `hot` in this
+// workgroup's LDS accumulator; other targets are skipped (the pull part
+// computes their rows).  The accumulators are written to part[blockIdx][hot].
+template <int G, int U, bool W>
+__device__ __forceinline__ void scatter_hot(const int32_t* __restrict__ idx, const float* __restrict__ wt, float cv,
+                                            int32_t b, int32_t e, int lane, float* s_y, int32_t hot) {
+    for (int32_t j0 = b + lane; j0 < e; j0 += U * G) {
+        int32_t jj[U], ii[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) jj[k] = min(j0 + k * G, e - 1);
+#pragma unroll
+        for (int k = 0; k < U; ++k) ii[k] = idx[jj[k]];
+        float wv[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) wv[k] = W ? wt[jj[k]] : 1.f;
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (j0 + k * G < e && ii[k] < hot) atomicAdd(&s_y[ii[k]], W ? cv * wv[k] : cv);
+    }
+}
+
+template <int BIN, bool W>
+__device__ __forceinline__ void hyb_push_unit(const PullArgs& a, int32_t lu, int lane, float* s_y) {
+    constexpr int G = kPullLanes[BIN];
+    constexpr int U = kPullLoads[BIN];
+    const int32_t i = lu * (kWave / G) + lane / G;
+    const int32_t count = a.sp.list_off[BIN + 1] - a.sp.list_off[BIN];
+    if (i >= count) return;  // whole groups leave together
+    const int32_t u = a.list[a.sp.list_off[BIN] + i];
+    const float cv = a.c[u];
+    if (cv == 0.f) return;
+    scatter_hot<G, U, W>(a.idx, a.wt, cv, a.off[u], a.off[u + 1], lane & (G - 1), s_y, a.hot);
+}
+
+template <bool W>
+__global__ __launch_bounds__(1024) void k_pr_hyb_push(PullArgs a) {
+    extern __shared__ float s_y[];
+    for (int32_t i = threadIdx.x; i < a.hot; i += blockDim.x) s_y[i] = 0.f;
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t nw = gridDim.x * (blockDim.x / kWave);
+    for (int32_t unit = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; unit < a.units; unit += nw) {
+        const int bin = wave_unit_bin(a.wave_off, unit);
+        const int32_t lu = unit - a.wave_off[bin];
+        switch (bin) {
+            case 5: {  // one chunk of a very long row
+                const int32_t v = a.tab[lu];
+                const float cv = a.c[v];
+                if (cv != 0.f)
+                    scatter_hot<kPullLanes[5], kPullLoads[5], W>(a.idx, a.wt, cv, a.tab[a.tab_cap + lu],
+                                                                a.tab[2 * a.tab_cap + lu], lane, s_y, a.hot);
+                break;
+            }
+            case 4: hyb_push_unit<4, W>(a, lu, lane, s_y); break;
+            case 3: hyb_push_unit<3, W>(a, lu, lane, s_y); break;
+            case 2: hyb_push_unit<2, W>(a, lu, lane, s_y); break;
+            case 1: hyb_push_unit<1, W>(a, lu, lane, s_y); break;
+            default: hyb_push_unit<0, W>(a, lu, lane, s_y); break;
+        }
+    }
+    __syncthreads();
+    float* dst = a.part + (size_t)blockIdx.x * a.hot;
+    for (int32_t i = threadIdx.x; i < a.hot; i += blockDim.x) dst[i] = s_y[i];
+}
+
+// Launches the hybrid push part; *parts = its workgroups (rows of hot_part).
+pp_status launch_hyb_push(pp_graph g, const float* c, int32_t hot, hipStream_t st, int32_t* parts) {
+    PullArgs a{};
+    a.sp = sweep_plan(g->push_plan);
+    a.off = g->d.csr_off;
+    a.idx = g->d.csr_idx;
+    a.wt = g->d.csr_w;
+    a.list = g->d.push_list;
+    a.tab_cap = g->split_cap;
+    a.tab = g->d.split_tab + 4 * (size_t)a.tab_cap + 1;
+    a.part = g->d.hot_part;
+    a.c = c;
+    a.hot = hot;
+    for (int b = 0; b <= PP_NUM_BINS; ++b) a.wave_off[b] = g->push_plan.wave_off[b];
+    a.units = g->push_plan.total_wave_units;
+    const int32_t tpb = 1024;
+    const size_t lds = (size_t)hot * sizeof(float);
+    int32_t per_cu = std::max(1, std::min<int32_t>(2, (int32_t)(g->lds_per_cu / std::max<size_t>(lds, 1))));
+    const int32_t grid =
+        std::max(1, std::min(std::min(g->num_cu * per_cu, ceil_div(a.units, tpb / kWave)), g->tune.push_blocks));
+    *parts = grid;
+    if (lds > 65536) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_hyb_push<true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_hyb_push<false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    }
+    if (g->weighted) hipLaunchKernelGGL((k_pr_hyb_push<true>), dim3(grid), dim3(tpb), lds, st, a);
+    else hipLaunchKernelGGL((k_pr_hyb_push<false>), dim3(grid), dim3(tpb), lds, st, a);
+    PP_LAUNCH_CHECK("k_pr_hyb_push");
+    return PP_OK;
+}
+
+pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float f, hipStream_t st,
+                      int32_t skip_below = 0) {
     PullArgs a;
+    a.skip_below = skip_below;
     a.sp = sweep_plan(g->pull_plan);
     a.off = g->d.csc_off;
     a.idx = g->d.csc_idx;
@@ -434,10 +563,11 @@ pp_status launch_push(pp_graph g, const float* c, float* y, hipStream_t st) {
     if (wide) {
         static bool attr_set = false;  // LDS beyond the default 64 KiB (same for every device)
         if (!attr_set) {
+            const int mx = kHotMax * (int)sizeof(float);
             (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_push<4, true, true>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, kHotMax * (int)sizeof(float));
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, mx);
             (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_push<4, false, true>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, kHotMax * (int)sizeof(float));
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, mx);
             attr_set = true;
         }
         if (g->weighted) hipLaunchKernelGGL((k_pr_push<4, true, true>), dim3(grid), dim3(4 * kBlock), lds, st, a);
@@ -503,12 +633,45 @@ PP_EXPORT pp_status pp_pr_run(pp_graph g, pp_dir dir, int32_t iters, float f, fl
     if (!x_inout) return set_error(PP_E_NULL, "x_inout is required");
     if (!(f >= 0.f && f < 1.f)) return set_error(PP_E_RANGE, "f must lie in [0, 1)");
     if (iters < 0) return set_error(PP_E_RANGE, "iters must be >= 0");
-    if (dir != PP_PUSH && dir != PP_PULL) return set_error(PP_E_RANGE, "dir must be PP_PUSH or PP_PULL");
+    if (dir != PP_PUSH && dir != PP_PULL && dir != PP_SWITCH)
+        return set_error(PP_E_RANGE, "dir must be PP_PUSH, PP_PULL or PP_SWITCH");
     if (iters == 0) return PP_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int32_t n = g->d.n;
     const float base = teleport(n, f);
     const dim3 vb(ceil_div(n, 256)), vt(256);
+    if (dir == PP_SWITCH) {
+        // hybrid: edges into the first `hot` vertices are pushed into LDS
+        // accumulators (no global atomics), all other rows pull
+        const int32_t hot = std::min(g->tune.hot, n);
+        float* c = g->d.buf0;
+        float* cn = g->d.buf1;
+        hipLaunchKernelGGL(k_pr_prologue, vb, vt, 0, st, n, (const float*)x_inout, g->d.perm, g->d.inv_s, f, c,
+                           (float*)nullptr, 0.f);
+        PP_LAUNCH_CHECK("k_pr_prologue");
+        for (int32_t t = 0; t < iters; ++t) {
+            const bool last = (t == iters - 1);
+            if (hot > 0 && g->push_plan.total_wave_units > 0) {
+                int32_t parts = 0;  // workgroups of the push part = rows of hot_part
+                pp_status s = launch_hyb_push(g, c, hot, st, &parts);
+                if (s != PP_OK) return s;
+                hipLaunchKernelGGL(k_pr_hyb_hot, dim3(ceil_div(hot, 64)), dim3(256), 0, st, hot, parts,
+                                   (const float*)g->d.hot_part, base, g->d.inv_s, f, last ? nullptr : cn,
+                                   last ? x_inout : nullptr, g->d.perm);
+            } else if (hot > 0) {  // no edges at all: the hot rows are the teleport alone
+                hipLaunchKernelGGL(k_pr_hyb_hot, dim3(ceil_div(hot, 64)), dim3(256), 0, st, hot, 0,
+                                   (const float*)g->d.hot_part, base, g->d.inv_s, f, last ? nullptr : cn,
+                                   last ? x_inout : nullptr, g->d.perm);
+            }
+            pp_status s = launch_pull(g, c, last ? nullptr : cn, last ? x_inout : nullptr, f, st, hot);
+            if (s != PP_OK) return s;
+            PP_LAUNCH_CHECK("k_pr_hyb_hot");
+            float* tmp = c;
+            c = cn;
+            cn = tmp;
+        }
+        return PP_OK;
+    }
     if (dir == PP_PULL) {
         float* c = g->d.buf0;
         float* cn = g->d.buf1;

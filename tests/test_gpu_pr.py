@@ -87,6 +87,50 @@ def test_push_privatisation_settings(hot, blocks):
         _lib.pp_set_push_tuning(8192, 1024)
 
 
+@pytest.mark.parametrize("hot,blocks", [(8192, 1024), (0, 64), (1, 7), (16384, 100), (100000, 512)])
+def test_hybrid_push_hot_pull_cold(hot, blocks):
+    # edges into the first `hot` vertices pushed into LDS, the other rows pulled;
+    # hot = 0 is a pure pull, hot >= n a pure (LDS-only) push
+    host = gg.workload("rmat14")
+    want = oracle.pagerank(host.off, host.idx, F, 20)
+    _lib.pp_set_push_tuning(min(hot, 40960), blocks)
+    try:
+        for rl in (True, False):
+            g = pp.Graph(host, relabel=rl)
+            got = pr_gpu(g, pp.PP_SWITCH, 20).astype(np.float64)
+            assert np.abs(got - want).sum() <= PR_L1_TOL, (hot, blocks, rl)
+    finally:
+        _lib.pp_set_push_tuning(8192, 1024)
+
+
+def test_hybrid_wide_privatisation():
+    # 40960 hot targets: 1024-thread workgroups holding 160 KB of LDS
+    host = gg.rmat(16, 16, seed=3)
+    want = oracle.pagerank(host.off, host.idx, F, 20)
+    _lib.pp_set_push_tuning(40960, 256)
+    try:
+        g = pp.Graph(host)
+        assert np.abs(pr_gpu(g, pp.PP_SWITCH, 20).astype(np.float64) - want).sum() <= PR_L1_TOL
+    finally:
+        _lib.pp_set_push_tuning(8192, 1024)
+
+
+def test_hybrid_directed_weighted():
+    # weighted uniform PageRank = mean over all sources of weighted PPR
+    host = H.random_graph(2000, 12000, 6, symmetric=False, connected=True)
+    gg.with_weights(host, seed=3)
+    X, _ = oracle.ppr(host.off, host.idx, np.arange(host.n), F, T=15, weights=host.weights)
+    want = X.mean(axis=1)
+    _lib.pp_set_push_tuning(500, 37)
+    try:
+        for rl in (True, False):
+            g = pp.Graph(host, relabel=rl)
+            got = pr_gpu(g, pp.PP_SWITCH, 15).astype(np.float64)
+            assert np.abs(got - want).sum() <= PR_L1_TOL, rl
+    finally:
+        _lib.pp_set_push_tuning(8192, 1024)
+
+
 @pytest.mark.parametrize("hot,blocks", [(16385, 3), (40960, 256), (30000, 1000)])
 def test_push_wide_privatisation(hot, blocks):
     # more than 16384 privatised targets: 1024-thread workgroups, up to 160 KB of LDS
@@ -221,7 +265,7 @@ def test_argument_errors_raise():
     with pytest.raises(pp.PPError):
         _lib.pp_pr_push(g.handle, x, torch.zeros(8, device="cuda"), 1.5)  # f out of range
     with pytest.raises(pp.PPError):
-        _lib.pp_pr_run(g.handle, pp.PP_SWITCH, 3, F, x)
+        _lib.pp_pr_run(g.handle, 7, 3, F, x)  # not a direction
     bad = gg.from_edges(4, [0, 1], [1, 2], True)
     bad.idx = bad.idx.copy()
     bad.idx[0] = 7  # out of range index
