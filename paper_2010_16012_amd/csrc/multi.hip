@@ -21,6 +21,7 @@ namespace pp {
 
 constexpr int kMultiBlock = 1024;
 constexpr int kMultiGroup = 8;  // lanes per row
+constexpr int kMultiU = 8;      // index loads in flight per lane
 constexpr int32_t kMultiMaxN = 16384;
 
 struct MultiEntry {
@@ -85,11 +86,22 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                 // owner of u gathers over its in-row (compensated sum per lane)
                 for (int32_t u = grp; u < n; u += groups) {
                     float acc = 0.f, comp = 0.f;
-                    for (int32_t j = in_off[u] + lane; j < in_off[u + 1]; j += kMultiGroup) {
-                        const float yk = s_c[in_idx[j]] - comp;
-                        const float tk = acc + yk;
-                        comp = (tk - acc) - yk;
-                        acc = tk;
+                    const int32_t rb = in_off[u], re = in_off[u + 1];
+                    for (int32_t j0 = rb + lane; j0 < re; j0 += kMultiU * kMultiGroup) {
+                        int32_t ii[kMultiU];  // independent loads first, then the adds in order
+#pragma unroll
+                        for (int k = 0; k < kMultiU; ++k) {
+                            const int32_t j = j0 + k * kMultiGroup;
+                            ii[k] = j < re ? in_idx[j] : -1;
+                        }
+#pragma unroll
+                        for (int k = 0; k < kMultiU; ++k) {
+                            if (ii[k] < 0) break;
+                            const float yk = s_c[ii[k]] - comp;
+                            const float tk = acc + yk;
+                            comp = (tk - acc) - yk;
+                            acc = tk;
+                        }
                     }
 #pragma unroll
                     for (int s = kMultiGroup / 2; s > 0; s >>= 1) acc += __shfl_xor(acc, s);
@@ -122,8 +134,18 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                 for (int32_t v = grp; v < n; v += groups) {
                     const float cv = c[v];
                     if (cv == 0.f) continue;
-                    for (int32_t j = off[v] + lane; j < off[v + 1]; j += kMultiGroup)
-                        atomicAdd(&s_acc[idx[j]], (double)cv);
+                    const int32_t rb = off[v], re = off[v + 1];
+                    for (int32_t j0 = rb + lane; j0 < re; j0 += kMultiU * kMultiGroup) {
+                        int32_t ii[kMultiU];
+#pragma unroll
+                        for (int k = 0; k < kMultiU; ++k) {
+                            const int32_t j = j0 + k * kMultiGroup;
+                            ii[k] = j < re ? idx[j] : -1;
+                        }
+#pragma unroll
+                        for (int k = 0; k < kMultiU; ++k)
+                            if (ii[k] >= 0) atomicAdd(&s_acc[ii[k]], (double)cv);
+                    }
                 }
                 __syncthreads();
                 for (int32_t u = tid; u < n; u += kMultiBlock) {
@@ -186,17 +208,28 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
             // frontier vertices claim unvisited out-neighbours (LDS atomic OR)
             for (int32_t v = grp; v < n; v += groups) {
                 if (!bit_of(s_front, v)) continue;
-                for (int32_t j = off[v] + lane; j < off[v + 1]; j += kMultiGroup) {
-                    const int32_t u = idx[j];
-                    const uint32_t b = 1u << (u & 31);
-                    if (s_vis[u >> 5] & b) continue;
-                    const uint32_t old = atomicOr(&s_vis[u >> 5], b);
-                    if (!(old & b)) {
-                        atomicOr(&s_next[u >> 5], b);
-                        a.level[e.vbase + u] = lvl + 1;
-                        a.parent[e.vbase + u] = v;
-                        my_new += 1;
-                        my_deg += off[u + 1] - off[u];
+                const int32_t rb = off[v], re = off[v + 1];
+                for (int32_t j0 = rb + lane; j0 < re; j0 += kMultiU * kMultiGroup) {
+                    int32_t ii[kMultiU];
+#pragma unroll
+                    for (int k = 0; k < kMultiU; ++k) {
+                        const int32_t j = j0 + k * kMultiGroup;
+                        ii[k] = j < re ? idx[j] : -1;
+                    }
+#pragma unroll
+                    for (int k = 0; k < kMultiU; ++k) {
+                        const int32_t u = ii[k];
+                        if (u < 0) continue;
+                        const uint32_t b = 1u << (u & 31);
+                        if (s_vis[u >> 5] & b) continue;
+                        const uint32_t old = atomicOr(&s_vis[u >> 5], b);
+                        if (!(old & b)) {
+                            atomicOr(&s_next[u >> 5], b);
+                            a.level[e.vbase + u] = lvl + 1;
+                            a.parent[e.vbase + u] = v;
+                            my_new += 1;
+                            my_deg += off[u + 1] - off[u];
+                        }
                     }
                 }
             }
@@ -206,10 +239,19 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                 if (bit_of(s_vis, v)) continue;
                 const int32_t b0 = in_off[v], e0 = in_off[v + 1];
                 int32_t hit = INT32_MAX;
-                for (int32_t jb = b0; jb < e0 && hit == INT32_MAX; jb += kMultiGroup) {
-                    const int32_t j = jb + lane;
-                    const bool h = (j < e0) && bit_of(s_front, in_idx[j]);
-                    int32_t pos = h ? j : INT32_MAX;
+                // kMultiU steps of kMultiGroup in-neighbours per round; the
+                // first frontier member in stored order wins
+                for (int32_t jb = b0; jb < e0 && hit == INT32_MAX; jb += kMultiU * kMultiGroup) {
+                    int32_t ii[kMultiU];
+#pragma unroll
+                    for (int k = 0; k < kMultiU; ++k) {
+                        const int32_t j = jb + k * kMultiGroup + lane;
+                        ii[k] = j < e0 ? in_idx[j] : -1;
+                    }
+                    int32_t pos = INT32_MAX;
+#pragma unroll
+                    for (int k = kMultiU - 1; k >= 0; --k)
+                        if (ii[k] >= 0 && bit_of(s_front, ii[k])) pos = jb + k * kMultiGroup + lane;
 #pragma unroll
                     for (int s = kMultiGroup / 2; s > 0; s >>= 1) pos = min(pos, __shfl_xor(pos, s));
                     hit = pos;
