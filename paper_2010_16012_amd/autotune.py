@@ -1,6 +1,8 @@
 """Autotuner for the sweep parameters, cached as JSON.
 
 Searches, per (GPU architecture, graph size class):
+  * degree-bin thresholds and the split chunk of the longest rows (both
+    sweeps);
   * pull sweep: LDS-staged contributions and workgroup size;
   * push sweep: LDS-privatised targets and persistent workgroups;
   * BFS direction switch: the alpha/beta constants of the switch rule;
@@ -35,8 +37,8 @@ def size_class(n: int, nnz: int) -> str:
     return f"n2^{int(round(math.log2(max(n, 1))))}_m2^{int(round(math.log2(max(nnz, 1))))}"
 
 
-def key(n: int, nnz: int) -> str:
-    return f"{arch()}|{size_class(n, nnz)}"
+def key(n: int, nnz: int, gpu_arch: str | None = None) -> str:
+    return f"{gpu_arch or arch()}|{size_class(n, nnz)}"
 
 
 def apply(cfg: dict) -> None:
@@ -47,12 +49,12 @@ def apply(cfg: dict) -> None:
     _lib.pp_set_pull_tuning(c["pull_hot"], c["pull_block"])
 
 
-def load(path: str, n: int, nnz: int) -> dict:
-    """Cached entry for this GPU and size class (empty when absent)."""
+def load(path: str, n: int, nnz: int, gpu_arch: str | None = None) -> dict:
+    """Cached entry for this GPU (or ``gpu_arch``) and size class (empty when absent)."""
     if not path or not os.path.exists(path):
         return {}
     with open(path) as fh:
-        return json.load(fh).get(key(n, nnz), {})
+        return json.load(fh).get(key(n, nnz, gpu_arch), {})
 
 
 def _time(fn, reps=3) -> float:
@@ -69,9 +71,37 @@ def _time(fn, reps=3) -> float:
     return best
 
 
-def tune_pagerank(host, iters=5, log=print) -> dict:
+BIN_CANDIDATES = (
+    ([4, 16, 64, 1024, 4096], 4096),
+    ([8, 32, 128, 1024, 4096], 4096),
+    ([2, 8, 32, 256, 2048], 2048),
+    ([4, 16, 64, 512, 8192], 8192),
+)
+
+
+def tune_bins(host, iters=5, log=print) -> dict:
+    """Degree-bin thresholds with the lowest pull + push sweep time."""
+    x = torch.empty(host.n, dtype=torch.float32, device="cuda")
+    best = None
+    for upper, chunk in BIN_CANDIDATES:
+        apply({"upper": upper, "split_chunk": chunk})
+        g = Graph(host)
+        t = 0.0
+        for d in (PP_PULL, PP_PUSH):
+            def f():
+                x.fill_(1.0 / host.n)
+                pagerank_into(g, x, iters, 0.85, d)
+            t += _time(f)
+        g.close()
+        log(f"bins upper={upper} chunk={chunk}: {t / iters * 1e3:.1f} us per pull+push step")
+        if best is None or t < best[0]:
+            best = (t, upper, chunk)
+    return {"upper": best[1], "split_chunk": best[2]}
+
+
+def tune_pagerank(host, iters=5, log=print, base=None) -> dict:
     """Best pull and push settings for this graph."""
-    out = {}
+    out = dict(base or {})
     x = torch.empty(host.n, dtype=torch.float32, device="cuda")
 
     def run(g, d):
@@ -83,7 +113,7 @@ def tune_pagerank(host, iters=5, log=print) -> dict:
     best = None
     for pull_hot in (16384, 32768, 40960):
         for block in (512, 1024):
-            apply({"pull_hot": pull_hot, "pull_block": block})
+            apply({**out, "pull_hot": pull_hot, "pull_block": block})
             g = Graph(host)
             t = run(g, PP_PULL)
             g.close()
@@ -94,7 +124,7 @@ def tune_pagerank(host, iters=5, log=print) -> dict:
     best = None
     for hot in (8192, 16384, 32768, 40960):
         for blocks in ((512, 1024, 2048) if hot <= 16384 else (256, 512)):
-            apply({"hot": hot, "push_blocks": blocks, "pull_hot": out["pull_hot"], "pull_block": out["pull_block"]})
+            apply({**out, "hot": hot, "push_blocks": blocks})
             g = Graph(host)
             t = run(g, PP_PUSH)
             g.close()
@@ -147,7 +177,7 @@ def main():
     p.add_argument("--out", required=True)
     a = p.parse_args()
     host = gg.rmat(a.scale, 16, seed=1)
-    cfg = tune_pagerank(host)
+    cfg = tune_pagerank(host, base=tune_bins(host))
     cfg.update(tune_bfs_switch(host, gg.pick_vertices(host, a.roots, seed=1)))
     if a.ppr_k:
         cfg.update(tune_ppr_tile(host, a.ppr_k))
