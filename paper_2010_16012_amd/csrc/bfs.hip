@@ -699,8 +699,9 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_chunks(BfsArgs a) {
     Pager pg{-1, 0};
     int32_t* q_next = a.queue[(lvl + 1) & 1];
     int32_t* fill_next = a.fill[(lvl + 1) & 1];
-    const int32_t chunk = dir == PP_PUSH ? kBigRow : kBigInRow;
-    const int32_t sw = ((int64_t)items * chunk >= a.stage_min) ? a.stage_words : 0;
+    // no LDS stage here: the kernel runs without dynamic LDS, so several
+    // workgroups share a compute unit (more chunk chains in flight)
+    const int32_t sw = 0;
     if (dir == PP_PUSH) {
         if (sw) stage_bits(s_bits, a.visited, sw);
         TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw};
@@ -777,6 +778,9 @@ static void allow_stage_lds(const BfsArgs& a) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+// Workgroups of the chunk kernel: two per compute unit (it stages no LDS).
+static int32_t chunk_blocks(pp_graph g) { return std::max(1, std::min(ceil_div(g->d.n, 4096), 2 * g->num_cu)); }
+
 // Does a level of this policy on this graph ever queue chunk items?
 static bool needs_chunks(pp_graph g, int32_t policy) {
     return (policy != PP_PULL && g->max_out_deg > kBigRow) || (policy != PP_PUSH && g->max_in_deg > kBigInRow);
@@ -790,7 +794,7 @@ static pp_status launch_level(pp_graph g, const BfsArgs& a, int32_t lvl, int32_t
     const int32_t blocks = bfs_blocks(g);
     const size_t lds = (size_t)a.stage_words * 8;
     hipLaunchKernelGGL(k_bfs_level, dim3(blocks), dim3(kBfsBlock), lds, st, a, lvl, parity, policy, alpha, beta);
-    if (needs_chunks(g, policy)) hipLaunchKernelGGL(k_bfs_chunks, dim3(blocks), dim3(kBfsBlock), lds, st, a);
+    if (needs_chunks(g, policy)) hipLaunchKernelGGL(k_bfs_chunks, dim3(chunk_blocks(g)), dim3(kBfsBlock), 0, st, a);
     PP_LAUNCH_CHECK("k_bfs_level");
     return PP_OK;
 }
@@ -818,12 +822,12 @@ static pp_status bfs_graph(pp_graph g, BfsArgs a, int32_t policy, float alpha, f
     hipGraph_t graph = nullptr;
     PP_HIP(hipGraphCreate(&graph, 0));
     hipGraphNode_t prev = nullptr;
-    auto add = [&](const void* fn, void** args) -> hipError_t {
+    auto add = [&](const void* fn, void** args, int32_t grid, unsigned shared) -> hipError_t {
         hipKernelNodeParams p{};
         p.func = const_cast<void*>(fn);
-        p.gridDim = dim3(blocks);
+        p.gridDim = dim3(grid);
         p.blockDim = dim3(kBfsBlock);
-        p.sharedMemBytes = lds;
+        p.sharedMemBytes = shared;
         p.kernelParams = args;
         p.extra = nullptr;
         hipGraphNode_t node = nullptr;
@@ -836,10 +840,10 @@ static pp_status bfs_graph(pp_graph g, BfsArgs a, int32_t policy, float alpha, f
     for (int32_t i = 0; i < batch && e == hipSuccess; ++i) {
         int32_t parity = i & 1;
         void* largs[] = {&a, &lvl, &parity, &policy, &alpha, &beta};
-        e = add(reinterpret_cast<const void*>(&k_bfs_level), largs);
+        e = add(reinterpret_cast<const void*>(&k_bfs_level), largs, blocks, lds);
         if (e == hipSuccess && chunks) {
             void* cargs[] = {&a};
-            e = add(reinterpret_cast<const void*>(&k_bfs_chunks), cargs);
+            e = add(reinterpret_cast<const void*>(&k_bfs_chunks), cargs, chunk_blocks(g), 0);
         }
     }
     hipGraphExec_t exec = nullptr;
