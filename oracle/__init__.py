@@ -13,8 +13,9 @@ are stated at the top of ``oracle.c``:
 * ``pagerank`` / ``pagerank_push`` -- the PageRank equation of Sec. 3.1 as a
   Jacobi iteration in its pulling and pushing forms (Sec. 4.1);
 * ``pagerank_step_at`` -- one update at chosen vertices from a given iterate;
-* ``ppr`` / ``ppr_adjoint`` -- personalised (and weighted) PageRank and its
-  adjoint with respect to edge weights (not in the paper);
+* ``ppr`` / ``ppr_adjoint`` / ``ppr_adjoint_unrolled`` -- personalised (and
+  weighted) PageRank and its adjoint with respect to edge weights, at the
+  fixed point or exactly for T steps (not in the paper);
 * ``bfs`` -- FIFO-queue BFS (Sec. 3.3; Sec. 4.3 with ready counters of one);
 * ``bfs_replay`` -- what each top-down / bottom-up step examines (Sec. 4.3);
 * ``triangles`` -- per-vertex triangle counts (Sec. 3.2);
@@ -61,6 +62,7 @@ def _load():
         "orc_bfs_replay": [i64, P, P, i64, i32, P, P, P, P],
         "orc_triangles": [i64, P, P, P],
         "orc_bc": [i64, P, P, P, i64, P],
+        "orc_ppr_adjoint_unrolled": [i64, P, P, P, i64, P, f64, i32, P, P, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -144,6 +146,22 @@ def ppr_adjoint(off, idx, X, G, f=0.85, T=2000, tol=0.0, weights=None):
     _check(_load().orc_ppr_adjoint(n, _p(off), _p(idx), _p(w), k, _p(X), _p(G), f, T, tol, _p(lam), _p(grad), _p(it)),
            "orc_ppr_adjoint")
     return lam, grad[:nnz], int(it[0])
+
+
+def ppr_adjoint_unrolled(off, idx, sources, G, f=0.85, T=30, weights=None):
+    """Exact gradient of L(X_T) for T PPR steps from X_0 = e_s: returns
+    (dL/dX_0 n*k, grad[nnz] in CSR slot order)."""
+    n, off, idx = _graph(off, idx)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    G = _arr(G, np.float64)
+    k = G.shape[1]
+    lam = np.empty_like(G)
+    nnz = int(off[-1])
+    grad = np.empty(max(nnz, 1), dtype=np.float64)
+    w = None if weights is None else _arr(weights, np.float32)
+    _check(_load().orc_ppr_adjoint_unrolled(n, _p(off), _p(idx), _p(w), k, _p(src), f, T, _p(G), _p(lam), _p(grad)),
+           "orc_ppr_adjoint_unrolled")
+    return lam, grad[:nnz]
 
 
 def bfs(off, idx, root):

@@ -276,6 +276,67 @@ int orc_ppr_adjoint(int64_t n, const int64_t* off, const int32_t* idx, const flo
     return 0;
 }
 
+/* Unrolled adjoint: the exact gradient of L(X_T) for the T-step map
+ * X_0 = e_s (per column), X_{t+1} = (1-f) E + f P X_t.  G = dL/dX_T (n*k).
+ * The iterates X_0..X_{T-1} are recomputed and kept; then, for t = T-1 down
+ * to 0 with Lambda = dL/dX_{t+1}:
+ *   grad[v->u] += (f/s(v)) sum_j X_t[v,j] (Lambda[u,j] - (P^T Lambda)[v,j]),
+ *   Lambda <- f P^T Lambda  (= dL/dX_t).
+ * Lambda0 (n*k out) receives dL/dX_0; grad (nnz out, CSR slot order). */
+int orc_ppr_adjoint_unrolled(int64_t n, const int64_t* off, const int32_t* idx, const float* w, int64_t k,
+                             const int32_t* sources, double f, int T, const double* G, double* Lambda0,
+                             double* grad) {
+    int rc = check_graph(n, off, idx);
+    if (rc) return rc;
+    if (k < 1 || T < 0 || !sources || !G || !Lambda0 || !grad) return -1;
+    for (int64_t j = 0; j < k; ++j)
+        if (sources[j] < 0 || sources[j] >= n) return -2;
+    const size_t cells = (size_t)(n * k);
+    double* s = (double*)malloc((size_t)n * sizeof(double));
+    double* hist = (double*)malloc(cells * (size_t)(T > 0 ? T : 1) * sizeof(double));
+    double* lam = (double*)malloc(cells * sizeof(double));
+    double* ptl = (double*)malloc(cells * sizeof(double));
+    if (!s || !hist || !lam || !ptl) { free(s); free(hist); free(lam); free(ptl); return -3; }
+    out_strength(n, off, w, s);
+    /* forward, scattering along out-edges: X_{t+1}(u) += f w(v->u)/s(v) X_t(v) */
+    if (T > 0) {
+        for (size_t i = 0; i < cells; ++i) hist[i] = 0.0;
+        for (int64_t j = 0; j < k; ++j) hist[(size_t)sources[j] * k + j] = 1.0;
+    }
+    for (int t = 0; t + 1 < T; ++t) {
+        const double* x = hist + (size_t)t * cells;
+        double* y = hist + (size_t)(t + 1) * cells;
+        for (size_t i = 0; i < cells; ++i) y[i] = 0.0;
+        for (int64_t j = 0; j < k; ++j) y[(size_t)sources[j] * k + j] = 1.0 - f;
+        for (int64_t v = 0; v < n; ++v) {
+            if (s[v] == 0.0) continue;
+            for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+                const double p = f * (w ? (double)w[e] : 1.0) / s[v];
+                for (int64_t j = 0; j < k; ++j) y[(int64_t)idx[e] * k + j] += p * x[v * k + j];
+            }
+        }
+    }
+    for (int64_t e = 0; e < off[n]; ++e) grad[e] = 0.0;
+    memcpy(lam, G, cells * sizeof(double));
+    for (int t = T - 1; t >= 0; --t) {
+        const double* x = hist + (size_t)t * cells;
+        for (int64_t v = 0; v < n; ++v)
+            for (int64_t j = 0; j < k; ++j) ptl[v * k + j] = pt_apply(off, idx, w, s, v, lam, k, j);
+        for (int64_t v = 0; v < n; ++v) {
+            if (s[v] == 0.0) continue;
+            for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+                double acc = 0.0;
+                for (int64_t j = 0; j < k; ++j) acc += x[v * k + j] * (lam[(int64_t)idx[e] * k + j] - ptl[v * k + j]);
+                grad[e] += f / s[v] * acc;
+            }
+        }
+        for (size_t i = 0; i < cells; ++i) lam[i] = f * ptl[i];
+    }
+    memcpy(Lambda0, lam, cells * sizeof(double));
+    free(s); free(hist); free(lam); free(ptl);
+    return 0;
+}
+
 /* ---------------------------------------------------------------------- */
 /* BFS from `root` with a FIFO queue over out-edges (Sec. 3.3; the
  * generalised BFS of Sec. 4.3 with all ready counters equal to one and the

@@ -401,3 +401,46 @@ def test_bc_is_additive_over_sources():
     a = oracle.bc(g.off, g.idx, [0, 5, 9])
     b = oracle.bc(g.off, g.idx, [0]) + oracle.bc(g.off, g.idx, [5]) + oracle.bc(g.off, g.idx, [9])
     np.testing.assert_allclose(a, b, rtol=1e-13)
+
+
+# --------------------------------------------------------------------------- unrolled adjoint
+@pytest.mark.parametrize("sym,weighted,T", [(True, False, 5), (False, True, 12), (True, True, 1), (False, False, 0)])
+def test_unrolled_adjoint_matches_finite_differences_of_the_T_step_map(sym, weighted, T):
+    g = H.random_graph(30, 90, 90 + T, symmetric=sym, connected=True)
+    if weighted:
+        gg.with_weights(g, seed=3)
+    w0 = g.weights.astype(np.float64) if weighted else np.ones(g.nnz)
+    src = np.array([0, 7, 29], dtype=np.int32)
+    c = gg.normal(g.n * 3, seed=5).reshape(g.n, 3).astype(np.float64)
+
+    def xT(w):
+        P = H.dense_transition(g, w)
+        X = np.zeros((g.n, 3))
+        X[src, np.arange(3)] = 1.0
+        E = (1 - F) * X.copy()
+        for _ in range(T):
+            X = E + F * P @ X
+        return X
+
+    lam0, grad = oracle.ppr_adjoint_unrolled(g.off, g.idx, src, c, F, T, weights=w0.astype(np.float32))
+    h = 1e-6
+    fd = np.array([((c * xT(w0 + h * np.eye(1, g.nnz, e)[0])).sum() - (c * xT(w0 - h * np.eye(1, g.nnz, e)[0])).sum())
+                   / (2 * h) for e in range(g.nnz)])
+    scale = max(1.0, np.abs(fd).max())
+    np.testing.assert_allclose(grad, fd, atol=1e-8 * scale, rtol=1e-6)
+    # dL/dX_0 = (f P^T)^T ... = (f P)^T applied T times to c
+    P = H.dense_transition(g, w0)
+    want0 = c.copy()
+    for _ in range(T):
+        want0 = F * P.T @ want0
+    np.testing.assert_allclose(lam0, want0, rtol=1e-12, atol=1e-14)
+
+
+def test_unrolled_adjoint_approaches_the_implicit_one():
+    g = H.random_graph(40, 160, 3, symmetric=True, connected=True)
+    src = np.array([1, 2], dtype=np.int32)
+    c = gg.normal(g.n * 2, seed=8).reshape(g.n, 2).astype(np.float64)
+    X, _ = oracle.ppr(g.off, g.idx, src, F, T=3000, tol=1e-15)
+    _, g_imp, _ = oracle.ppr_adjoint(g.off, g.idx, X, c, F, T=3000, tol=1e-15)
+    _, g_unr = oracle.ppr_adjoint_unrolled(g.off, g.idx, src, c, F, 400)
+    assert np.abs(g_unr - g_imp).max() <= 1e-9 * np.abs(g_imp).max()
