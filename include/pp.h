@@ -279,6 +279,25 @@ pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, const int64_t
                        int32_t bfs_policy, int32_t bfs_root, float alpha, float beta,
                        int32_t* level, int32_t* parent, void* ws, size_t ws_bytes, void* stream);
 
+/* Scratch bytes for pp_ppr_adjoint_unrolled (k columns, tiles of k_tile, T
+ * steps: it keeps T iterates of one tile). */
+size_t pp_ppr_unrolled_scratch_bytes(pp_graph g, int32_t k, int32_t k_tile, int32_t T);
+
+/* Unrolled adjoint: the exact gradient of a loss on X_T, the iterate after T
+ * steps of the personalised PageRank update from X_0 = e_s (the map
+ * pp_ppr_run computes with iters = T and tol = 0).  Given G = dL/dX_T
+ * (device float[n*k], caller layout), the call recomputes X_0..X_{T-1} with
+ * pulling sweeps, then runs T reverse steps: with Lambda = dL/dX_{t+1},
+ *   dL/dw(v->u) += f/s(v) * sum_j X_t[v,j] (Lambda[u,j] - (P^T Lambda)[v,j]),
+ *   Lambda <- f P^T Lambda.
+ * Lambda0: device float[n*k], receives dL/dX_0.  grad_w: device float[nnz],
+ * caller CSR slot order, overwritten.  sources: device int32[k].  Not in the
+ * paper; the derivative of the Sec. 3.1 update with per-slot weights.  SYNC
+ * (once, to validate the sources). */
+pp_status pp_ppr_adjoint_unrolled(pp_graph g, int32_t k, const int32_t* sources, int32_t T, float f,
+                                  int32_t k_tile, const float* dLdXT, float* Lambda0, float* grad_w,
+                                  void* scratch, size_t scratch_bytes, void* stream);
+
 /* ------------------------------------------------------- triangle counting */
 /* Workspace bytes of pp_tc_run for graph g (device, caller-owned, 256-byte
  * aligned). */

@@ -15,7 +15,7 @@ from ._lib import (PP_PULL, PP_PUSH, PP_SWITCH, PPError, BfsStats)  # noqa: F401
 from ._lib import *  # noqa: F401,F403  (the C names)
 
 __all__ = ["Graph", "BfsRun", "PPError", "PP_PUSH", "PP_PULL", "PP_SWITCH", "pagerank", "pagerank_into", "bfs",
-           "ppr", "ppr_adjoint", "PPRFunction", "MultiGraph", "triangles", "betweenness"]
+           "ppr", "ppr_adjoint", "ppr_adjoint_unrolled", "PPRFunction", "MultiGraph", "triangles", "betweenness"]
 
 
 class Graph:
@@ -156,6 +156,19 @@ def ppr_adjoint(g: Graph, X, dLdX, iters=2000, f=0.85, k_tile=32, direction=PP_P
     done = _lib.pp_ppr_adjoint(g.handle, direction, k, X, dLdX, iters, tol, f, k_tile, lam, grad,
                                _scratch(g, k, k_tile), stream)
     return lam, grad[: g.nnz], done
+
+
+def ppr_adjoint_unrolled(g: Graph, sources, dLdXT, T=30, f=0.85, k_tile=32, stream=None):
+    """Exact gradient of a loss on the T-step PPR iterate: (dL/dX_0, dL/dw)."""
+    src = torch.as_tensor(sources, dtype=torch.int32, device=g.device).contiguous()
+    k = int(src.numel())
+    G = dLdXT.to(device=g.device, dtype=torch.float32).contiguous()
+    lam = torch.empty((g.n, k), dtype=torch.float32, device=g.device)
+    grad = torch.empty(max(g.nnz, 1), dtype=torch.float32, device=g.device)
+    nbytes = _lib.pp_ppr_unrolled_scratch_bytes(g.handle, k, k_tile, T)
+    scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=g.device)
+    _lib.pp_ppr_adjoint_unrolled(g.handle, k, src, T, f, k_tile, G, lam, grad, scratch, stream)
+    return lam, grad[:g.nnz]
 
 
 class PPRFunction(torch.autograd.Function):

@@ -85,6 +85,8 @@ _SIGS = {
                    ctypes.c_int),
     "pp_ppr_adjoint": ([_P, ctypes.c_int, _I32, _P, _P, _I32, _F32, _F32, _I32, _P, _P, _P, _SZ,
                         ctypes.POINTER(_I32), _P], ctypes.c_int),
+    "pp_ppr_unrolled_scratch_bytes": ([_P, _I32, _I32, _I32], _SZ),
+    "pp_ppr_adjoint_unrolled": ([_P, _I32, _P, _I32, _F32, _I32, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "pp_tc_workspace_bytes": ([_P], _SZ),
     "pp_tc_run": ([_P, ctypes.c_int, _P, _P, _SZ, _P], ctypes.c_int),
     "pp_bc_workspace_bytes": ([_P], _SZ),
@@ -275,3 +277,12 @@ def pp_bc_run(h, fwd_dir, bwd_dir, sources, bc, ws, stream=None) -> None:
     src = np.ascontiguousarray(sources, dtype=np.int32)
     _check(_lib.pp_bc_run(h, fwd_dir, bwd_dir, len(src), ctypes.c_void_p(src.ctypes.data), _ptr(bc), _ptr(ws),
                           ws.numel(), _stream(stream)))
+
+
+def pp_ppr_adjoint_unrolled(h, k, sources, T, f, k_tile, dLdXT, Lambda0, grad_w, scratch, stream=None) -> None:
+    _check(_lib.pp_ppr_adjoint_unrolled(h, k, _ptr(sources), T, f, k_tile, _ptr(dLdXT), _ptr(Lambda0), _ptr(grad_w),
+                                        _ptr(scratch), scratch.numel(), _stream(stream)))
+
+
+def pp_ppr_unrolled_scratch_bytes(h, k, k_tile, T) -> int:
+    return _lib.pp_ppr_unrolled_scratch_bytes(h, k, k_tile, T)

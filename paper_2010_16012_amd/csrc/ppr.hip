@@ -371,7 +371,8 @@ struct GradArgs {
     int32_t tab_cap;
     const float* lam;       // tile layout
     const float* ptl;       // tile layout
-    const float* x_caller;  // caller layout n x k
+    const float* x_caller;  // caller layout n x k (used when x_tile is NULL)
+    const float* x_tile;    // tile layout n x KT, internal ids (nullable)
     const float* inv_s;
     const int32_t* perm;
     const int32_t* user_off;  // caller CSR offsets (slot mapping)
@@ -384,7 +385,8 @@ template <int KT>
 __device__ __forceinline__ void grad_row(const GradArgs& a, int32_t v, int32_t b, int32_t e, int32_t g,
                                          int32_t stride, int lane) {
     const int32_t vc = user_id(a.perm, v);
-    const float xv = (a.col0 + lane < a.k) ? a.x_caller[(size_t)vc * a.k + a.col0 + lane] : 0.f;
+    const float xv = a.x_tile ? a.x_tile[(size_t)v * KT + lane]
+                              : ((a.col0 + lane < a.k) ? a.x_caller[(size_t)vc * a.k + a.col0 + lane] : 0.f);
     const float pv = a.ptl[(size_t)v * KT + lane];
     const float scale = a.f * a.inv_s[v];
     const int32_t row0 = a.off[v], crow0 = a.user_off[vc];
@@ -418,6 +420,11 @@ __global__ __launch_bounds__(kBlock) void k_kcol_grad(GradArgs a) {
         const int32_t v = a.tab[lu];
         grad_row<KT>(a, v, a.tab[a.tab_cap + lu], a.tab[2 * a.tab_cap + lu], grp, G, lane);
     }
+}
+
+__global__ void k_scale_f32(int64_t m, float s, float* __restrict__ p) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] *= s;
 }
 
 __global__ void k_zero_f32(int64_t m, float* __restrict__ p) {
@@ -538,13 +545,14 @@ __global__ void k_sw_clear(int32_t words, uint64_t* bits, int32_t* cnt) {
 }
 
 struct PprLayout {
-    size_t t0, t1, t2, t3, t4, part, resid, scal, srcs;
+    size_t t0, t1, t2, t3, t4, part, resid, scal, srcs, hist;  // hist: T iterates (unrolled adjoint)
     size_t sw_bits, sw_all, sw_small, sw_items, sw_cnt;  // sparse-phase support (PP_SWITCH)
     int32_t sw_item_cap;
     size_t total;
 };
 
-static PprLayout ppr_layout(int32_t n, int64_t nnz, int32_t split_cap, int32_t k, int32_t kt, int32_t max_units) {
+static PprLayout ppr_layout(int32_t n, int64_t nnz, int32_t split_cap, int32_t k, int32_t kt, int32_t max_units,
+                            int32_t hist_tiles = 0) {
     PprLayout L{};
     size_t p = 0;
     auto take = [&](size_t bytes) {
@@ -570,6 +578,7 @@ static PprLayout ppr_layout(int32_t n, int64_t nnz, int32_t split_cap, int32_t k
     L.sw_item_cap = (int32_t)std::min<int64_t>((int64_t)nnz / kSwChunk + n + 64, INT32_MAX / 4);
     L.sw_items = take((size_t)L.sw_item_cap * 3 * 4);
     L.sw_cnt = take(64);
+    L.hist = take(tile * (size_t)std::max(hist_tiles, 0));
     L.total = p;
     return L;
 }
@@ -833,7 +842,8 @@ static pp_status run_tile(pp_graph g, bool adjoint, pp_dir dir, int32_t k, int32
 // added into grad (caller CSR slot order).
 template <int KT>
 static pp_status adjoint_grad(pp_graph g, int32_t k, int32_t col0, float f, const float* lam, float* ptl,
-                              float* part, const float* x_caller, float* grad, hipStream_t st) {
+                              float* part, const float* x_caller, float* grad, hipStream_t st,
+                              const float* x_tile = nullptr) {
     const Walk w = walk_csr(g, KT);
     KArgs a{};
     a.kind = kEpiPtl;
@@ -863,6 +873,7 @@ static pp_status adjoint_grad(pp_graph g, int32_t k, int32_t col0, float f, cons
     ga.lam = lam;
     ga.ptl = ptl;
     ga.x_caller = x_caller;
+    ga.x_tile = x_tile;
     ga.inv_s = g->d.inv_s;
     ga.perm = g->d.perm;
     ga.user_off = g->d.user_csr_off;
@@ -872,6 +883,94 @@ static pp_status adjoint_grad(pp_graph g, int32_t k, int32_t col0, float f, cons
     ga.grad = grad;
     if (w.kp.units > 0) hipLaunchKernelGGL(k_kcol_grad<KT>, dim3(w.kp.units), dim3(kBlock), 0, st, ga);
     PP_LAUNCH_CHECK("ppr adjoint gradient");
+    return PP_OK;
+}
+
+// Unrolled adjoint of one tile: the T-step forward iterates X_0..X_{T-1}
+// (pull sweeps, kept in `hist`), then T reverse steps.  With Lambda =
+// dL/dX_{t+1}: the edge gradient of step t from X_t (CSR gather of
+// P^T Lambda, then k_kcol_grad), and Lambda <- f P^T Lambda.
+template <int KT>
+static pp_status unrolled_tile(pp_graph g, int32_t k, int32_t col0, int32_t T, float f, const int32_t* src_int,
+                               const float* g_caller, char* base, const PprLayout& L, float* lambda0, float* grad,
+                               hipStream_t st) {
+    const int32_t n = g->d.n;
+    const int64_t cells = (int64_t)n * KT;
+    const size_t tile = (size_t)cells;
+    float* t0 = reinterpret_cast<float*>(base + L.t0);
+    float* t1 = reinterpret_cast<float*>(base + L.t1);
+    float* c_cur = reinterpret_cast<float*>(base + L.t2);
+    float* c_nxt = reinterpret_cast<float*>(base + L.t3);
+    float* part = reinterpret_cast<float*>(base + L.part);
+    float* hist = reinterpret_cast<float*>(base + L.hist);
+    const dim3 cb(ceil_div(cells, 256)), ct(256);
+    if (T > 0) {
+        hipLaunchKernelGGL(k_kcol_forward_init<KT>, cb, ct, 0, st, n, src_int, col0, f, g->d.inv_s, hist, c_cur,
+                           (double*)nullptr);
+        const Walk w = walk_csc(g, KT);
+        for (int32_t t = 0; t + 1 < T; ++t) {
+            KArgs a{};
+            a.kind = kEpiForward;
+            a.inv_s = g->d.inv_s;
+            a.perm = g->d.perm;
+            a.f = f;
+            a.k = k;
+            a.col0 = col0;
+            a.src_int = src_int;
+            a.out_tile = hist + (size_t)(t + 1) * tile;
+            a.out_scaled = c_nxt;
+            a.kp = w.kp;
+            a.off = w.off;
+            a.idx = w.idx;
+            a.wt = w.wt;
+            a.list = w.list;
+            a.tab = w.tab;
+            a.tab_cap = g->split_cap;
+            a.part = part;
+            a.src = c_cur;
+            launch_kpull<KT>(a, w.nsplit, nullptr, st, g->weighted);
+            std::swap(c_cur, c_nxt);
+        }
+        PP_LAUNCH_CHECK("ppr unrolled forward");
+    }
+    float* lam = t0;
+    float* ptl = t1;
+    hipLaunchKernelGGL(k_kcol_adjoint_init<KT>, cb, ct, 0, st, n, k, col0, g->d.perm, g_caller, lam, (double*)nullptr);
+    for (int32_t t = T - 1; t >= 0; --t) {
+        pp_status s = adjoint_grad<KT>(g, k, col0, f, lam, ptl, part, nullptr, grad, st, hist + (size_t)t * tile);
+        if (s != PP_OK) return s;
+        hipLaunchKernelGGL(k_scale_f32, dim3(std::min<int64_t>(ceil_div(cells, 256), 65536)), dim3(256), 0, st, cells,
+                           f, ptl);
+        std::swap(lam, ptl);
+    }
+    hipLaunchKernelGGL(k_tile_to_caller<KT>, cb, ct, 0, st, n, k, col0, g->d.perm, (const float*)lam, lambda0);
+    PP_LAUNCH_CHECK("ppr unrolled adjoint");
+    return PP_OK;
+}
+
+template <int KT>
+static pp_status unrolled_call(pp_graph g, int32_t k, const int32_t* sources, int32_t T, float f,
+                               const float* dLdXT, float* lambda0, float* grad, char* base, const PprLayout& L,
+                               hipStream_t st) {
+    const int32_t n = g->d.n;
+    int32_t* src_int = reinterpret_cast<int32_t*>(base + L.srcs);
+    int32_t* flag = reinterpret_cast<int32_t*>(base + L.scal) + 8;
+    int32_t bad = 0;
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, st, (int64_t)1, reinterpret_cast<float*>(flag));
+    const int32_t k_pad = ceil_div(k, KT) * KT;
+    hipLaunchKernelGGL(k_sources_internal, dim3(ceil_div(k_pad, 256)), dim3(256), 0, st, k, k_pad, sources,
+                       g->d.iperm, n, src_int, flag);
+    PP_LAUNCH_CHECK("ppr sources");
+    PP_HIP(hipMemcpyAsync(&bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    PP_HIP(hipStreamSynchronize(st));
+    if (bad) return set_error(PP_E_RANGE, "a source lies outside [0, n)");
+    if (g->d.nnz > 0)
+        hipLaunchKernelGGL(k_zero_f32, dim3(std::min<int64_t>(ceil_div(g->d.nnz, 256), 65536)), dim3(256), 0, st,
+                           g->d.nnz, grad);
+    for (int32_t col0 = 0; col0 < k; col0 += KT) {
+        pp_status s = unrolled_tile<KT>(g, k, col0, T, f, src_int, dLdXT, base, L, lambda0, grad, st);
+        if (s != PP_OK) return s;
+    }
     return PP_OK;
 }
 
@@ -1022,4 +1121,31 @@ PP_EXPORT pp_status pp_ppr_adjoint(pp_graph g, pp_dir dir, int32_t k, const floa
     c.L = ppr_layout(g->d.n, g->d.nnz, g->split_cap, k, k_tile, max_units(g, k_tile));
     c.st = static_cast<hipStream_t>(stream);
     return ppr_dispatch(c, iters_done);
+}
+
+PP_EXPORT size_t pp_ppr_unrolled_scratch_bytes(pp_graph g, int32_t k, int32_t k_tile, int32_t T) {
+    if (!g || !valid_kt(k_tile) || k < 0 || T < 0) return 0;
+    return ppr_layout(g->d.n, g->d.nnz, g->split_cap, k, k_tile, max_units(g, k_tile), T).total;
+}
+
+PP_EXPORT pp_status pp_ppr_adjoint_unrolled(pp_graph g, int32_t k, const int32_t* sources, int32_t T, float f,
+                                            int32_t k_tile, const float* dLdXT, float* Lambda0, float* grad_w,
+                                            void* scratch, size_t scratch_bytes, void* stream) {
+    clear_error();
+    if (T < 0) return set_error(PP_E_RANGE, "T must be >= 0");
+    const size_t need = pp_ppr_unrolled_scratch_bytes(g, k, k_tile, T);
+    pp_status s = check_ppr(g, PP_PULL, k, T, 0.f, f, k_tile, scratch, scratch_bytes, need);
+    if (s != PP_OK) return s;
+    if (k > 0 && (!sources || !dLdXT || !Lambda0)) return set_error(PP_E_NULL, "sources, dLdXT and Lambda0 are required");
+    if (g->d.nnz > 0 && !grad_w) return set_error(PP_E_NULL, "grad_w is required");
+    if (k == 0) return PP_OK;
+    char* base = static_cast<char*>(scratch);
+    const PprLayout L = ppr_layout(g->d.n, g->d.nnz, g->split_cap, k, k_tile, max_units(g, k_tile), T);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    switch (k_tile) {
+        case 8: return unrolled_call<8>(g, k, sources, T, f, dLdXT, Lambda0, grad_w, base, L, st);
+        case 16: return unrolled_call<16>(g, k, sources, T, f, dLdXT, Lambda0, grad_w, base, L, st);
+        case 32: return unrolled_call<32>(g, k, sources, T, f, dLdXT, Lambda0, grad_w, base, L, st);
+        default: return unrolled_call<64>(g, k, sources, T, f, dLdXT, Lambda0, grad_w, base, L, st);
+    }
 }

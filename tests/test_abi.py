@@ -52,3 +52,8 @@ def test_host_side_queries_and_validation():
         _lib.pp_set_bin_thresholds([5, 4, 3, 2, 1], 1024)
     with pytest.raises(_lib.PPError):
         _lib.pp_set_bin_thresholds([1, 2, 3, 4, 5], 10)
+
+
+def test_binding_has_a_function_for_every_export():
+    from paper_2010_16012_amd import _lib
+    assert [n for n in _lib.EXPORTS if not callable(getattr(_lib, n, None))] == []

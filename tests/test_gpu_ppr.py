@@ -272,3 +272,54 @@ def test_adjoint_finite_differences_rmat10_sampled_edges_and_directions():
         d /= np.linalg.norm(d)
         fdd = (loss(w64 + h * d) - loss(w64 - h * d)) / (2 * h)
         assert abs(gh @ d - fdd) <= 1e-5 * np.linalg.norm(gh), (r, gh @ d, fdd)
+
+
+@pytest.mark.parametrize("sym,kt,k,T", [(True, 8, 8, 30), (False, 16, 20, 12), (True, 32, 3, 1), (False, 8, 5, 0)])
+def test_unrolled_adjoint_matches_oracle(sym, kt, k, T):
+    host = H.random_graph(3000, 15000, 30 + T, symmetric=sym, connected=True)
+    gg.with_weights(host, seed=9)
+    src = gg.pick_vertices(host, k, seed=4)
+    c = gg.normal(host.n * k, seed=6).reshape(host.n, k).astype(np.float64)
+    lam_o, grad_o = oracle.ppr_adjoint_unrolled(host.off, host.idx, src, c, F, T, weights=host.weights)
+    for rl in (True, False):
+        g = pp.Graph(host, relabel=rl)
+        announce(f"unrolled adjoint sym={sym} kt={kt} k={k} T={T} relabel={rl}")
+        lam, grad = pp.ppr_adjoint_unrolled(g, src, torch.as_tensor(c, dtype=torch.float32), T=T, f=F, k_tile=kt)
+        gh = grad.cpu().numpy().astype(np.float64)
+        lh = lam.cpu().numpy().astype(np.float64)
+        if T == 0:
+            assert np.abs(gh).max() == 0.0
+        else:
+            assert np.linalg.norm(gh - grad_o) / np.linalg.norm(grad_o) <= 1e-5
+        assert np.abs(lh - lam_o).max() <= 1e-5 * max(np.abs(lam_o).max(), 1e-30)
+
+
+def test_unrolled_adjoint_finite_differences_rmat10():
+    # the T-step map itself: central differences of c . X_T(w) in FP64
+    host = gg.rmat(10, 16, seed=2)
+    gg.with_weights(host, seed=1)
+    n, T = host.n, 20
+    src = gg.pick_vertices(host, 4, seed=2)
+    c = gg.normal(n * 4, seed=3).reshape(n, 4).astype(np.float64)
+    w64 = host.weights.astype(np.float64)
+    rows = np.repeat(np.arange(n), np.diff(host.off))
+
+    def loss(w):
+        s = np.bincount(rows, weights=w, minlength=n)
+        P = np.zeros((n, n))
+        np.add.at(P, (host.idx, rows), w / s[rows])
+        X = np.zeros((n, 4))
+        X[src, np.arange(4)] = 1.0
+        E = (1 - F) * X.copy()
+        for _ in range(T):
+            X = E + F * (P @ X)
+        return float((c * X).sum())
+
+    g = pp.Graph(host)
+    _, grad = pp.ppr_adjoint_unrolled(g, src, torch.as_tensor(c, dtype=torch.float32), T=T, f=F, k_tile=8)
+    gh = grad.cpu().numpy().astype(np.float64)
+    h = 1e-6
+    edges = np.unique(gg.uniform_int(64, 0, host.nnz - 1, seed=11))
+    fd = np.array([(loss(w64 + h * np.eye(1, host.nnz, e)[0]) - loss(w64 - h * np.eye(1, host.nnz, e)[0])) / (2 * h)
+                   for e in edges])
+    assert np.linalg.norm(gh[edges] - fd) / np.linalg.norm(fd) <= 1e-5
