@@ -115,6 +115,8 @@ __device__ __forceinline__ void for_each_edge(const int32_t* verts, int32_t coun
 // Sum of val(u) over the row [rb, re) of each lane's vertex (lanes with
 // `own`), in stored order per lane; rows of 32 or more entries are summed by
 // the wave (lane-strided, then a fixed shuffle tree).  Wave-collective.
+constexpr int kBcU = 8;  // independent index loads in flight per lane
+
 template <typename Val>
 __device__ __forceinline__ double row_sum(bool own, int32_t rb, int32_t re, const int32_t* idx, int lane,
                                           Val&& val) {
@@ -126,13 +128,28 @@ __device__ __forceinline__ double row_sum(bool own, int32_t rb, int32_t re, cons
         big &= big - 1;
         const int32_t bb = __shfl(rb, src), be = __shfl(re, src);
         double t = 0.0;
-        for (int32_t j = bb + lane; j < be; j += kWave) t += val(idx[j]);
+        for (int32_t j0 = bb + lane; j0 < be; j0 += kBcU * kWave) {
+            int32_t ii[kBcU];
+#pragma unroll
+            for (int k = 0; k < kBcU; ++k) ii[k] = (j0 + k * kWave < be) ? idx[j0 + k * kWave] : -1;
+#pragma unroll
+            for (int k = 0; k < kBcU; ++k)
+                if (ii[k] >= 0) t += val(ii[k]);
+        }
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) t += __shfl_xor(t, d);
         if (lane == src) acc = t;
     }
-    if (own && !coop)
-        for (int32_t j = rb; j < re; ++j) acc += val(idx[j]);
+    if (own && !coop) {
+        for (int32_t j0 = rb; j0 < re; j0 += kBcU) {
+            int32_t ii[kBcU];
+#pragma unroll
+            for (int k = 0; k < kBcU; ++k) ii[k] = (j0 + k < re) ? idx[j0 + k] : -1;
+#pragma unroll
+            for (int k = 0; k < kBcU; ++k)
+                if (ii[k] >= 0) acc += val(ii[k]);
+        }
+    }
     return acc;
 }
 
