@@ -33,6 +33,10 @@
 namespace pp {
 
 constexpr int32_t kPage = 256;      // queue entries per page
+// true: each level-kernel wavefront starts on the page numbered by its global
+// index (no page atomic until it is full); false: all pages come from the
+// slot's page counter
+constexpr bool kStaticPages = false;
 // Rows longer than one chunk are cut into chunk items that the whole grid
 // shares, so no wavefront walks a long row alone while the others idle.
 constexpr int32_t kBigRow = 256;    // top-down (out-rows)
@@ -95,8 +99,9 @@ static BfsLayout bfs_layout(pp_graph g) {
     L.blocks = bfs_blocks(g);
     L.stage_words = std::max(0, std::min(L.words, (g->max_lds - kStaticLds) / 8));
     const int32_t waves = L.blocks * kBfsWaves;
-    // full pages hold at most n entries; each wavefront of each of the three
-    // appending kernels of a level leaves at most one partial page
+    // full pages hold at most n entries; each wavefront of the level kernel
+    // (its own page, possibly empty) and of the chunk kernel (twice as many
+    // wavefronts) leaves at most one partial page
     L.page_cap = ceil_div(n, kPage) + 3 * waves + 2;
     L.item_cap = (int32_t)std::min<int64_t>(2 * nnz / std::min(kBigRow, kBigInRow) + 64, INT32_MAX / 4);
     L.hdr = take(sizeof(BfsHdr));
@@ -119,6 +124,7 @@ struct BfsArgs {
     int32_t page_cap;
     int32_t item_cap;
     int32_t stage_words;    // bitmap words a workgroup may stage in LDS
+    int32_t static_pages;   // queue pages owned one per wavefront of the level kernel
     int64_t stage_min;      // stage only when the level examines at least this many edges
     const int32_t* csr_off;
     const int32_t* csr_idx;
@@ -146,6 +152,7 @@ static BfsArgs bfs_args(pp_graph g, void* state, int32_t* level, int32_t* parent
     a.page_cap = L.page_cap;
     a.item_cap = L.item_cap;
     a.stage_words = L.stage_words;
+    a.static_pages = L.blocks * kBfsWaves;
     // copying costs each workgroup stage_words loads; pay it only when the
     // level has at least two edges per staged word per workgroup
     a.stage_min = 2 * (int64_t)L.blocks * L.stage_words;
@@ -269,6 +276,16 @@ __device__ __forceinline__ void flush_stats(int32_t cnt, int64_t deg, BfsSlot* n
     }
 }
 
+// The fields of a slot a level kernel reads at its start.
+struct SlotView {
+    int32_t n, dir_prev, n_prev, pages;
+    int64_t m, mu_base;
+};
+
+__device__ __forceinline__ SlotView view(const BfsSlot& s) {
+    return SlotView{s.n, s.dir_prev, s.n_prev, s.pages, s.m, s.mu_base};
+}
+
 // ------------------------------------------------------------------ init
 __global__ void k_bfs_init(BfsArgs a, int32_t root_user, int64_t nnz) {
     const int32_t root = a.iperm ? a.iperm[root_user] : root_user;
@@ -291,6 +308,7 @@ __global__ void k_bfs_init(BfsArgs a, int32_t root_user, int64_t nnz) {
         a.fill[0][0] = 1;
         BfsHdr* h = a.hdr;
         for (int i = 0; i < 3; ++i) h->slot[i] = BfsSlot{};
+        h->slot[1].pages = kStaticPages ? a.static_pages : 0;  // pages level 0 starts with
         h->slot[0].n = 1;
         h->slot[0].dir_prev = PP_PUSH;
         h->slot[0].pages = 1;
@@ -353,7 +371,14 @@ struct TdCtx {
     BfsSlot* nxt;
     const uint64_t* s_vis;  // LDS snapshot of visited words [0, sw)
     int32_t sw;
+    // read the visited word before claiming: filters targets visited earlier,
+    // which pays on large levels; small levels go straight to the atomic and
+    // save a round trip
+    bool probe;
 };
+
+// Below this many frontier out-edges a level claims without probing first.
+constexpr int64_t kProbeMin = 1 << 16;
 
 // Claims the targets u[r] (parents pv[r]; -1 = no edge) of kTdU rounds of
 // 64 edges.  The rounds are independent, so their loads and atomics are
@@ -371,13 +396,24 @@ __device__ __forceinline__ void td_batch(const BfsArgs& a, const TdCtx& cx, Page
     }
     uint64_t word[kTdU];
 #pragma unroll
-    for (int r = 0; r < kTdU; ++r) word[r] = cand[r] ? a.visited[u[r] >> 6] : ~0ull;
+    for (int r = 0; r < kTdU; ++r) word[r] = (cand[r] && cx.probe) ? a.visited[u[r] >> 6] : (cand[r] ? 0ull : ~0ull);
+    // the out-degree and the caller ids a claim needs are loaded in flight
+    // with the claim itself
+    bool need[kTdU];
+    int32_t od[kTdU], uid[kTdU], pid[kTdU];
+#pragma unroll
+    for (int r = 0; r < kTdU; ++r) {
+        need[r] = cand[r] && !((word[r] >> (u[r] & 63)) & 1ull);
+        od[r] = need[r] ? a.out_deg[u[r]] : 0;
+        uid[r] = (need[r] && a.perm) ? a.perm[u[r]] : u[r];
+        pid[r] = (need[r] && a.perm) ? a.perm[pv[r]] : pv[r];
+    }
     bool claimed[kTdU];
 #pragma unroll
     for (int r = 0; r < kTdU; ++r) {
         claimed[r] = false;
         const uint64_t bit = 1ull << (u[r] & 63);
-        if (cand[r] && !(word[r] & bit)) {
+        if (need[r]) {
             const uint64_t old =
                 atomicOr(reinterpret_cast<unsigned long long*>(&a.visited[u[r] >> 6]), (unsigned long long)bit);
             claimed[r] = !(old & bit);
@@ -386,13 +422,12 @@ __device__ __forceinline__ void td_batch(const BfsArgs& a, const TdCtx& cx, Page
 #pragma unroll
     for (int r = 0; r < kTdU; ++r) {
         if (claimed[r]) {
-            const int32_t uu = user_id(a.perm, u[r]);
-            a.level[uu] = cx.lvl + 1;
-            a.parent[uu] = user_id(a.perm, pv[r]);
+            a.level[uid[r]] = cx.lvl + 1;
+            a.parent[uid[r]] = pid[r];
             atomicOr(reinterpret_cast<unsigned long long*>(&cx.fb_next[u[r] >> 6]),
                      (unsigned long long)(1ull << (u[r] & 63)));
             cnt += 1;
-            deg += a.out_deg[u[r]];
+            deg += od[r];
         }
         const uint64_t mask = __ballot(claimed[r]);
         if (mask)
@@ -417,87 +452,117 @@ __device__ __forceinline__ void td_row(const BfsArgs& a, const TdCtx& cx, Pager&
     }
 }
 
-// by_bitmap: the frontier is large, so it is read from its bitmap word by
-// word (ascending ids: coalesced offsets, rows in memory order) instead of
-// from the queue (claim order).
-__device__ void level_top_down(const BfsArgs& a, const TdCtx& cx, const int32_t* q_cur, const int32_t* fill_cur,
-                               int32_t pages, const uint64_t* fb_cur, bool by_bitmap, int32_t& cnt, int64_t& deg,
-                               Pager& pg) {
+// The 64 frontier vertices v of one unit (-1 = none) expand their out-rows.
+// Wave-collective.
+__device__ __forceinline__ void td_unit(const BfsArgs& a, const TdCtx& cx, Pager& pg, int32_t v, int32_t& cnt, int64_t& deg) {
     __shared__ int32_t s_start[kBfsWaves][kWave];
     __shared__ int32_t s_rb[kBfsWaves][kWave];
     __shared__ int32_t s_v[kBfsWaves][kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
-    const int32_t gwave = blockIdx.x * kBfsWaves + w;
+    const int32_t rb = (v >= 0) ? a.csr_off[v] : 0;
+    const int32_t re = (v >= 0) ? a.csr_off[v + 1] : 0;
+    int32_t len = re - rb;
+    // very long rows: queue chunks for the second kernel
+    const bool huge = len > kBigRow;
+    if (__ballot(huge)) {
+        queue_chunks(a, huge, v, rb, re, kBigRow, cx.nxt, lane);
+        if (huge) len = 0;
+    }
+    // medium rows: the whole wave walks one row at a time
+    uint64_t big = __ballot(len >= kWave);
+    while (big) {
+        const int src = __ffsll((long long)big) - 1;
+        big &= big - 1;
+        td_row(a, cx, pg, __shfl(v, src), __shfl(rb, src), __shfl(re, src), cnt, deg, lane);
+    }
+    // short rows: the wave's edges are enumerated densely through a scan
+    const int32_t mine = (len < kWave) ? len : 0;
+    int32_t incl = mine;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
+    }
+    const int32_t total = __shfl(incl, kWave - 1);
+    if (total == 0) return;
+    s_start[w][lane] = incl - mine;
+    s_rb[w][lane] = rb;
+    s_v[w][lane] = v;
+    wave_sync();
+    for (int32_t k = 0; k < total; k += kTdU * kWave) {
+        int32_t u[kTdU], pv[kTdU];
+#pragma unroll
+        for (int r = 0; r < kTdU; ++r) {
+            const int32_t e = k + r * kWave + lane;
+            u[r] = -1;
+            pv[r] = -1;
+            if (e < total) {
+                int lo = 0, hi = kWave;  // last lane with start <= e
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_start[w][mid] <= e) lo = mid;
+                    else hi = mid;
+                }
+                u[r] = a.csr_idx[s_rb[w][lo] + (e - s_start[w][lo])];
+                pv[r] = s_v[w][lo];
+            }
+        }
+        td_batch(a, cx, pg, u, pv, cnt, deg, lane);
+    }
+    wave_sync();
+}
+
+// by_bitmap: the frontier is large, so it is read from its bitmap word by
+// word (ascending ids: coalesced offsets, rows in memory order).  Otherwise
+// it is read from the queue in units of 64 slots (a quarter page), one unit
+// per wavefront at a time; a wavefront loads the page fills and entries of up
+// to four of its units in one round trip (entries past a fill are stale but
+// inside the queue).  A queue-driven level never reads the frontier bitmap,
+// so its vertices clear their words there: the bitmap is clean when it is
+// reused two levels on, without a full clear.
+__device__ void level_top_down(const BfsArgs& a, const TdCtx& cx, const int32_t* q_cur, const int32_t* fill_cur,
+                               int32_t pages, uint64_t* fb_cur, bool by_bitmap, int32_t& cnt, int64_t& deg,
+                               Pager& pg) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t gwave = blockIdx.x * kBfsWaves + threadIdx.x / kWave;
     const int32_t nwaves = gridDim.x * kBfsWaves;
-    // one unit = 64 queue slots (a quarter page)
-    constexpr int kUnitsPerPage = kPage / kWave;
-    const int32_t nunits = by_bitmap ? a.words : pages * kUnitsPerPage;
-    for (int32_t unit = gwave; unit < nunits; unit += nwaves) {
-        int32_t v = -1;
-        if (by_bitmap) {
+    if (by_bitmap) {
+        for (int32_t unit = gwave; unit < a.words; unit += nwaves) {
             const uint64_t word = fb_cur[unit];
             if (word == 0) continue;
-            if ((word >> lane) & 1ull) v = unit * kWave + lane;
-        } else {
-            const int32_t p = unit / kUnitsPerPage;
-            const int32_t pfill = fill_cur[p];
-            const int32_t s = (unit % kUnitsPerPage) * kWave;
-            if (s >= pfill) continue;
-            const int32_t i = s + lane;
-            if (i < pfill) v = q_cur[p * kPage + i];
+            td_unit(a, cx, pg, ((word >> lane) & 1ull) ? unit * kWave + lane : -1, cnt, deg);
         }
-        {
-            const int32_t rb = (v >= 0) ? a.csr_off[v] : 0;
-            const int32_t re = (v >= 0) ? a.csr_off[v + 1] : 0;
-            int32_t len = re - rb;
-            // very long rows: queue chunks for the second kernel
-            const bool huge = len > kBigRow;
-            if (__ballot(huge)) {
-                queue_chunks(a, huge, v, rb, re, kBigRow, cx.nxt, lane);
-                if (huge) len = 0;
-            }
-            // medium rows: the whole wave walks one row at a time
-            uint64_t big = __ballot(len >= kWave);
-            while (big) {
-                const int src = __ffsll((long long)big) - 1;
-                big &= big - 1;
-                td_row(a, cx, pg, __shfl(v, src), __shfl(rb, src), __shfl(re, src), cnt, deg, lane);
-            }
-            // short rows: the wave's edges are enumerated densely through a scan
-            const int32_t mine = (len < kWave) ? len : 0;
-            int32_t incl = mine;
+        return;
+    }
+    constexpr int kUnitsPerPage = kPage / kWave;
+    constexpr int kAhead = 4;
+    const int32_t nunits = pages * kUnitsPerPage;
+    for (int32_t u0 = gwave; u0 < nunits; u0 += kAhead * nwaves) {
+        int32_t left[kAhead], qv[kAhead];  // entries of each unit (<= 0: none), lane's entry
 #pragma unroll
-            for (int d = 1; d < kWave; d <<= 1) {
-                const int32_t y = __shfl_up(incl, d);
-                if (lane >= d) incl += y;
+        for (int j = 0; j < kAhead; ++j) {
+            const int32_t unit = u0 + j * nwaves;
+            left[j] = 0;
+            qv[j] = -1;
+            if (unit < nunits) {
+                const int32_t p = unit / kUnitsPerPage, s = (unit % kUnitsPerPage) * kWave;
+                left[j] = min(fill_cur[p], kPage) - s;
+                qv[j] = q_cur[(size_t)p * kPage + s + lane];
             }
-            const int32_t total = __shfl(incl, kWave - 1);
-            s_start[w][lane] = incl - mine;
-            s_rb[w][lane] = rb;
-            s_v[w][lane] = v;
-            wave_sync();
-            for (int32_t k = 0; k < total; k += kTdU * kWave) {
-                int32_t u[kTdU], pv[kTdU];
+        }
+#pragma unroll 1
+        for (int j = 0; j < kAhead; ++j) {
+            const int32_t n_here = left[0], q_here = qv[0];
 #pragma unroll
-                for (int r = 0; r < kTdU; ++r) {
-                    const int32_t e = k + r * kWave + lane;
-                    u[r] = -1;
-                    pv[r] = -1;
-                    if (e < total) {
-                        int lo = 0, hi = kWave;  // last lane with start <= e
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (s_start[w][mid] <= e) lo = mid;
-                            else hi = mid;
-                        }
-                        u[r] = a.csr_idx[s_rb[w][lo] + (e - s_start[w][lo])];
-                        pv[r] = s_v[w][lo];
-                    }
-                }
-                td_batch(a, cx, pg, u, pv, cnt, deg, lane);
+            for (int t = 0; t + 1 < kAhead; ++t) {  // shift, so every index stays constant
+                left[t] = left[t + 1];
+                qv[t] = qv[t + 1];
             }
-            wave_sync();
+            if (n_here <= 0) continue;
+            const int32_t v = (lane < n_here) ? q_here : -1;
+            if (v >= 0) fb_cur[v >> 6] = 0ull;
+            td_unit(a, cx, pg, v, cnt, deg);
         }
     }
 }
@@ -612,9 +677,11 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
                                                           float alpha, float beta) {
     extern __shared__ uint64_t s_bits[];
     BfsHdr* h = a.hdr;
+    // the three slots are read in the same round trip as the level index
+    const SlotView v0 = view(h->slot[0]), v1 = view(h->slot[1]), v2 = view(h->slot[2]);
     const int32_t lvl = lvl_arg >= 0 ? lvl_arg : h->lv[parity];
     const int sc = lvl % 3, sn = (lvl + 1) % 3, sz = (lvl + 2) % 3;
-    const BfsSlot cur = h->slot[sc];
+    const SlotView cur = (sc == 0) ? v0 : ((sc == 1) ? v1 : v2);
     const int32_t nf = cur.n;
     const bool lead = (blockIdx.x == 0 && threadIdx.x == 0);
     if (nf == 0) {
@@ -634,7 +701,9 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
             dir = ((double)nf < (double)a.n / (double)beta && nf < cur.n_prev) ? PP_PUSH : PP_PULL;
     }
     if (lead) {
-        h->slot[sz] = BfsSlot{};
+        BfsSlot fresh{};
+        fresh.pages = kStaticPages ? a.static_pages : 0;  // pages level lvl + 1 starts with
+        h->slot[sz] = fresh;
         h->slot[sn].dir_prev = dir;
         h->slot[sn].n_prev = nf;
         h->slot[sn].mu_base = mu;
@@ -649,14 +718,18 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
         h->lv[parity ^ 1] = lvl + 1;
         h->c_lvl = lvl;
     }
-    // the bitmap two levels ahead is rewritten next level: clear it now
-    uint64_t* fb_clear = a.fb[sz];
-    for (int32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < a.words; w += gridDim.x * blockDim.x)
-        fb_clear[w] = 0ull;
+    // the bitmap two levels ahead (frontier lvl - 1) is rewritten next level:
+    // clear it now, unless level lvl - 1 was a queue-driven top-down level,
+    // which cleared its words itself
+    if (!(cur.dir_prev == PP_PUSH && cur.n_prev <= a.words)) {
+        uint64_t* fb_clear = a.fb[sz];
+        for (int32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < a.words; w += gridDim.x * blockDim.x)
+            fb_clear[w] = 0ull;
+    }
     const int lane = threadIdx.x & (kWave - 1);
     int32_t cnt = 0;
     int64_t deg = 0;
-    Pager pg{-1, 0};
+    Pager pg{kStaticPages ? (int32_t)(blockIdx.x * kBfsWaves + threadIdx.x / kWave) : -1, 0};
     int32_t* q_next = a.queue[(lvl + 1) & 1];
     int32_t* fill_next = a.fill[(lvl + 1) & 1];
     // edges the level examines at most: the frontier's (top-down) or the
@@ -664,7 +737,7 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
     const int32_t sw = ((dir == PP_PUSH ? cur.m : mu) >= a.stage_min) ? a.stage_words : 0;
     if (dir == PP_PUSH) {
         if (sw) stage_bits(s_bits, a.visited, sw);
-        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw};
+        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw, cur.m >= kProbeMin};
         level_top_down(a, cx, a.queue[lvl & 1], a.fill[lvl & 1], min(cur.pages, a.page_cap), a.fb[sc], nf > a.words,
                        cnt, deg, pg);
     } else {
@@ -685,12 +758,19 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
 __global__ __launch_bounds__(kBfsBlock) void k_bfs_chunks(BfsArgs a) {
     extern __shared__ uint64_t s_bits[];
     BfsHdr* h = a.hdr;
+    // slot fields read in the same round trip as the level index
+    int32_t bigs[3], dirs[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        bigs[i] = h->slot[i].big;
+        dirs[i] = h->slot[i].dir_prev;
+    }
     const int32_t lvl = h->c_lvl;
     if (lvl < 0) return;
     const int sc = lvl % 3, sn = (lvl + 1) % 3;
-    const int32_t items = min(h->slot[sn].big, a.item_cap);
+    const int32_t items = min((sn == 0) ? bigs[0] : ((sn == 1) ? bigs[1] : bigs[2]), a.item_cap);
     if (items == 0) return;
-    const int32_t dir = h->slot[sn].dir_prev;
+    const int32_t dir = (sn == 0) ? dirs[0] : ((sn == 1) ? dirs[1] : dirs[2]);
     const int lane = threadIdx.x & (kWave - 1);
     const int32_t gwave = blockIdx.x * kBfsWaves + threadIdx.x / kWave;
     const int32_t nwaves = gridDim.x * kBfsWaves;
@@ -704,7 +784,7 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_chunks(BfsArgs a) {
     const int32_t sw = 0;
     if (dir == PP_PUSH) {
         if (sw) stage_bits(s_bits, a.visited, sw);
-        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw};
+        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw, true};
         for (int32_t it = gwave; it < items; it += nwaves)
             td_row(a, cx, pg, a.items[3 * it], a.items[3 * it + 1], a.items[3 * it + 2], cnt, deg, lane);
     } else {
