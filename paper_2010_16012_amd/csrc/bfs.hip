@@ -10,7 +10,11 @@
 // Contention design: a device-scope atomic on one address serialises across
 // the whole GPU, so no address is hit per edge or per wavefront step:
 //  - the frontier queue is paged: each wavefront fills its own page of
-//    kPage entries and takes a new page with one atomic when it is full;
+//    kPage entries and takes a new page with one atomic when it is full.
+//    The first `static_pages` pages (one per level-kernel wavefront) are
+//    reserved: in a bottom-up level, which appends a lot, every wavefront
+//    starts on its own reserved page and takes no atomic until it is full;
+//    a top-down level leaves them unused, and its readers skip them;
 //  - frontier statistics are summed per workgroup, one atomic each;
 //  - top-down claims use one atomic OR on a 64-vertex visited word, tried
 //    only after a plain read shows the vertex unvisited.
@@ -33,10 +37,6 @@
 namespace pp {
 
 constexpr int32_t kPage = 256;      // queue entries per page
-// true: each level-kernel wavefront starts on the page numbered by its global
-// index (no page atomic until it is full); false: all pages come from the
-// slot's page counter
-constexpr bool kStaticPages = false;
 // Rows longer than one chunk are cut into chunk items that the whole grid
 // shares, so no wavefront walks a long row alone while the others idle.
 constexpr int32_t kBigRow = 256;    // top-down (out-rows)
@@ -99,10 +99,10 @@ static BfsLayout bfs_layout(pp_graph g) {
     L.blocks = bfs_blocks(g);
     L.stage_words = std::max(0, std::min(L.words, (g->max_lds - kStaticLds) / 8));
     const int32_t waves = L.blocks * kBfsWaves;
-    // full pages hold at most n entries; each wavefront of the level kernel
-    // (its own page, possibly empty) and of the chunk kernel (twice as many
-    // wavefronts) leaves at most one partial page
-    L.page_cap = ceil_div(n, kPage) + 3 * waves + 2;
+    // the reserved pages (one per level-kernel wavefront); full pages hold at
+    // most n entries; each wavefront of the level kernel and of the chunk
+    // kernel (twice as many wavefronts) leaves at most one partial page
+    L.page_cap = waves + ceil_div(n, kPage) + 3 * waves + 2;
     L.item_cap = (int32_t)std::min<int64_t>(2 * nnz / std::min(kBigRow, kBigInRow) + 64, INT32_MAX / 4);
     L.hdr = take(sizeof(BfsHdr));
     L.queue0 = take((size_t)L.page_cap * kPage * 4);
@@ -304,14 +304,18 @@ __global__ void k_bfs_init(BfsArgs a, int32_t root_user, int64_t nnz) {
         a.fb[2][w] = 0ull;
     }
     if (t == 0) {
-        a.queue[0][0] = root;
-        a.fill[0][0] = 1;
+        // the root frontier looks built by a top-down level: first page after
+        // the reserved ones
+        a.queue[0][(size_t)a.static_pages * kPage] = root;
+        a.fill[0][a.static_pages] = 1;
         BfsHdr* h = a.hdr;
-        for (int i = 0; i < 3; ++i) h->slot[i] = BfsSlot{};
-        h->slot[1].pages = kStaticPages ? a.static_pages : 0;  // pages level 0 starts with
+        for (int i = 0; i < 3; ++i) {
+            h->slot[i] = BfsSlot{};
+            h->slot[i].pages = a.static_pages;
+        }
         h->slot[0].n = 1;
         h->slot[0].dir_prev = PP_PUSH;
-        h->slot[0].pages = 1;
+        h->slot[0].pages = a.static_pages + 1;
         h->slot[0].m = a.out_deg[root];
         h->slot[0].mu_base = nnz;
         h->levels = 0;
@@ -521,9 +525,10 @@ __device__ __forceinline__ void td_unit(const BfsArgs& a, const TdCtx& cx, Pager
 // inside the queue).  A queue-driven level never reads the frontier bitmap,
 // so its vertices clear their words there: the bitmap is clean when it is
 // reused two levels on, without a full clear.
+// Queue pages [first, pages) hold the frontier.
 __device__ void level_top_down(const BfsArgs& a, const TdCtx& cx, const int32_t* q_cur, const int32_t* fill_cur,
-                               int32_t pages, uint64_t* fb_cur, bool by_bitmap, int32_t& cnt, int64_t& deg,
-                               Pager& pg) {
+                               int32_t first, int32_t pages, uint64_t* fb_cur, bool by_bitmap, int32_t& cnt,
+                               int64_t& deg, Pager& pg) {
     const int lane = threadIdx.x & (kWave - 1);
     const int32_t gwave = blockIdx.x * kBfsWaves + threadIdx.x / kWave;
     const int32_t nwaves = gridDim.x * kBfsWaves;
@@ -538,7 +543,7 @@ __device__ void level_top_down(const BfsArgs& a, const TdCtx& cx, const int32_t*
     constexpr int kUnitsPerPage = kPage / kWave;
     constexpr int kAhead = 4;
     const int32_t nunits = pages * kUnitsPerPage;
-    for (int32_t u0 = gwave; u0 < nunits; u0 += kAhead * nwaves) {
+    for (int32_t u0 = first * kUnitsPerPage + gwave; u0 < nunits; u0 += kAhead * nwaves) {
         int32_t left[kAhead], qv[kAhead];  // entries of each unit (<= 0: none), lane's entry
 #pragma unroll
         for (int j = 0; j < kAhead; ++j) {
@@ -702,7 +707,7 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
     }
     if (lead) {
         BfsSlot fresh{};
-        fresh.pages = kStaticPages ? a.static_pages : 0;  // pages level lvl + 1 starts with
+        fresh.pages = a.static_pages;  // counting starts after the reserved pages
         h->slot[sz] = fresh;
         h->slot[sn].dir_prev = dir;
         h->slot[sn].n_prev = nf;
@@ -729,7 +734,8 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
     const int lane = threadIdx.x & (kWave - 1);
     int32_t cnt = 0;
     int64_t deg = 0;
-    Pager pg{kStaticPages ? (int32_t)(blockIdx.x * kBfsWaves + threadIdx.x / kWave) : -1, 0};
+    // bottom-up: each wavefront starts on its reserved page
+    Pager pg{(dir == PP_PULL) ? (int32_t)(blockIdx.x * kBfsWaves + threadIdx.x / kWave) : -1, 0};
     int32_t* q_next = a.queue[(lvl + 1) & 1];
     int32_t* fill_next = a.fill[(lvl + 1) & 1];
     // edges the level examines at most: the frontier's (top-down) or the
@@ -738,8 +744,9 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
     if (dir == PP_PUSH) {
         if (sw) stage_bits(s_bits, a.visited, sw);
         TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw, cur.m >= kProbeMin};
-        level_top_down(a, cx, a.queue[lvl & 1], a.fill[lvl & 1], min(cur.pages, a.page_cap), a.fb[sc], nf > a.words,
-                       cnt, deg, pg);
+        // a frontier built top-down left the reserved pages unused
+        level_top_down(a, cx, a.queue[lvl & 1], a.fill[lvl & 1], (cur.dir_prev == PP_PULL) ? 0 : a.static_pages,
+                       min(cur.pages, a.page_cap), a.fb[sc], nf > a.words, cnt, deg, pg);
     } else {
         if (sw) stage_bits(s_bits, a.fb[sc], sw);
         level_bottom_up(a, lvl, a.fb[sc], s_bits, sw, q_next, fill_next, a.fb[sn], &h->slot[sn], cnt, deg, pg);
