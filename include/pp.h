@@ -331,8 +331,10 @@ size_t pp_bc_workspace_bytes(pp_graph g);
  * bwd_dir PP_PUSH: vertices add to their predecessors' dependency with FP64
  * atomics; PP_PULL: vertices sum over their successors (owner writes).
  * sources: HOST int32[num_sources] (caller ids); bc: double[n] device,
- * overwritten.  Reads one counter per forward level (synchronises the
- * stream each level). */
+ * caller ids, overwritten.  The forward levels run in batches with their
+ * bookkeeping on the device; the call synchronises the stream once per batch
+ * (usually once per source) to read the depth, then queues the backward
+ * levels. */
 pp_status pp_bc_run(pp_graph g, pp_dir fwd_dir, pp_dir bwd_dir, int32_t num_sources, const int32_t* sources,
                     double* bc, void* ws, size_t ws_bytes, void* stream);
 
