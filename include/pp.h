@@ -84,7 +84,9 @@ size_t pp_graph_workspace_bytes(int32_t n, int64_t nnz, uint32_t flags);
  * (PP_GRAPH_WEIGHTED) pass csr_w (float[nnz], one weight per CSR slot, > 0)
  * and csc_to_csr (int32[nnz], the CSR slot of each CSC slot).  ws: device
  * workspace of at least pp_graph_workspace_bytes(n, nnz, flags) bytes, kept
- * by the handle until pp_graph_destroy.  SYNC (reads back bin sizes). */
+ * by the handle until pp_graph_destroy; it also holds the owner (row) of
+ * every in-adjacency slot, which streamed bottom-up BFS levels use.  SYNC
+ * (reads back bin sizes). */
 pp_status pp_graph_create(int32_t n, int64_t nnz,
                           const int32_t* csr_off, const int32_t* csr_idx,
                           const int32_t* csc_off, const int32_t* csc_idx,
@@ -188,7 +190,10 @@ pp_status pp_bfs_init(pp_graph g, int32_t root, int32_t* level, int32_t* parent,
  * state; one counter update per wavefront).  Rows longer than 256 edges are
  * cut into 256-edge chunks that the whole grid shares; a bottom-up vertex
  * whose in-row is chunked takes the first frontier member of whichever chunk
- * claims it first (one atomic OR).  Either step may follow the other.  level/parent must be the arrays given to pp_bfs_init.  Enqueue
+ * claims it first (one atomic OR).  A bottom-up level with a sparse frontier
+ * (8 |F| < ceil(n/64), its out-edges at most nnz/256) while at least half the
+ * edges leave unvisited vertices streams the whole in-edge array instead, and
+ * a vertex takes whichever frontier in-neighbour claims it first.  Either step may follow the other.  level/parent must be the arrays given to pp_bfs_init.  Enqueue
  * only; the frontier size is read with pp_bfs_frontier.  A step on an empty
  * frontier does nothing. */
 pp_status pp_bfs_step_push(pp_graph g, void* state, int32_t* level, int32_t* parent, int32_t cur_level,

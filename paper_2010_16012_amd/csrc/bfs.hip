@@ -44,6 +44,10 @@ constexpr int32_t kBigInRow = 256;  // bottom-up (in-rows)
 constexpr int kBfsBlock = 1024;    // threads per workgroup of the level kernels
 constexpr int kBfsWaves = kBfsBlock / kWave;
 constexpr int32_t kStaticLds = 16384;  // LDS bytes kept for the kernels' own arrays
+// Bottom-up levels with a sparse frontier keep, in LDS, one bit per frontier
+// bitmap word (set if the word is nonzero): a test of a vertex whose word is
+// empty then needs no global load.  At most kSumMax summary words (8 KB).
+constexpr int32_t kSumMax = 1024;
 
 struct BfsSlot {
     int32_t n;         // frontier size (accumulated by the level that builds it)
@@ -78,7 +82,7 @@ struct BfsHdr {
 
 struct BfsLayout {
     size_t hdr, queue0, queue1, fill0, fill1, fb0, fb1, fb2, visited, items, total;
-    int32_t words, blocks, page_cap, item_cap, stage_words;
+    int32_t words, blocks, page_cap, item_cap, stage_words, sum_words;
 };
 
 // One workgroup per compute unit (the staged bitmap takes most of its LDS),
@@ -97,7 +101,9 @@ static BfsLayout bfs_layout(pp_graph g) {
     };
     L.words = ceil_div(n, 64);
     L.blocks = bfs_blocks(g);
-    L.stage_words = std::max(0, std::min(L.words, (g->max_lds - kStaticLds) / 8));
+    const int32_t lds_words = std::max(0, (g->max_lds - kStaticLds) / 8);
+    L.sum_words = (L.words > lds_words) ? std::min(ceil_div(L.words, 64), kSumMax) : 0;
+    L.stage_words = std::max(0, std::min(L.words, lds_words - L.sum_words));
     const int32_t waves = L.blocks * kBfsWaves;
     // the reserved pages (one per level-kernel wavefront); full pages hold at
     // most n entries; each wavefront of the level kernel and of the chunk
@@ -120,16 +126,19 @@ static BfsLayout bfs_layout(pp_graph g) {
 
 struct BfsArgs {
     int32_t n;
+    int64_t nnz;
     int32_t words;
     int32_t page_cap;
     int32_t item_cap;
     int32_t stage_words;    // bitmap words a workgroup may stage in LDS
+    int32_t sum_words;      // LDS summary words (after the staged words; 0 = none)
     int32_t static_pages;   // queue pages owned one per wavefront of the level kernel
     int64_t stage_min;      // stage only when the level examines at least this many edges
     const int32_t* csr_off;
     const int32_t* csr_idx;
     const int32_t* csc_off;
     const int32_t* csc_idx;
+    const int32_t* csc_row;  // owner (row) of every CSC slot
     const int32_t* out_deg;
     const int32_t* perm;    // internal -> caller id (nullable)
     const int32_t* iperm;   // caller -> internal id (nullable)
@@ -148,10 +157,12 @@ static BfsArgs bfs_args(pp_graph g, void* state, int32_t* level, int32_t* parent
     char* s = static_cast<char*>(state);
     BfsArgs a;
     a.n = g->d.n;
+    a.nnz = g->d.nnz;
     a.words = L.words;
     a.page_cap = L.page_cap;
     a.item_cap = L.item_cap;
     a.stage_words = L.stage_words;
+    a.sum_words = L.sum_words;
     a.static_pages = L.blocks * kBfsWaves;
     // copying costs each workgroup stage_words loads; pay it only when the
     // level has at least two edges per staged word per workgroup
@@ -160,6 +171,7 @@ static BfsArgs bfs_args(pp_graph g, void* state, int32_t* level, int32_t* parent
     a.csr_idx = g->d.csr_idx;
     a.csc_off = g->d.csc_off;
     a.csc_idx = g->d.csc_idx;
+    a.csc_row = g->d.csc_row;
     a.out_deg = g->d.out_deg;
     a.perm = g->d.perm;
     a.iperm = g->d.iperm;
@@ -201,11 +213,40 @@ __device__ __forceinline__ void stage_bits(uint64_t* s_bits, const uint64_t* src
     __syncthreads();
 }
 
-// Bit u of a bitmap whose words [0, sw) are also in LDS.
-__device__ __forceinline__ bool test_bit(const uint64_t* s_bits, int32_t sw, const uint64_t* g_bits, int32_t u) {
+// A frontier bitmap as a bottom-up level tests it: words [0, sw) staged in
+// LDS, and for words below lim an LDS summary (bit w clear: word w is zero).
+struct FbView {
+    const uint64_t* s_bits;
+    int32_t sw;
+    const uint64_t* s_sum;
+    int32_t lim;  // 0: no summary
+    const uint64_t* g_bits;
+};
+
+__device__ __forceinline__ bool fb_test(const FbView& f, int32_t u) {
     const int32_t w = u >> 6;
-    const uint64_t word = (w < sw) ? s_bits[w] : g_bits[w];
-    return (word >> (u & 63)) & 1ull;
+    if (w < f.sw) return (f.s_bits[w] >> (u & 63)) & 1ull;
+    if (w < f.lim && !((f.s_sum[w >> 6] >> (w & 63)) & 1ull)) return false;
+    return (f.g_bits[w] >> (u & 63)) & 1ull;
+}
+
+// Summary bits of bitmap words [from rounded down to 64, 64 * sum_words)
+// (words past the bitmap read as zero).  Workgroup-collective; the caller
+// ends it with a barrier.
+__device__ __forceinline__ void build_summary(uint64_t* s_sum, const uint64_t* g_bits, int32_t words, int32_t from,
+                                              int32_t sum_words) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t nw = blockDim.x / kWave;
+    for (int32_t c = (from >> 6) + (int32_t)(threadIdx.x / kWave); c < sum_words; c += nw) {
+        const int32_t i = c * kWave + lane;
+        const uint64_t m = __ballot(i < words && g_bits[i] != 0ull);
+        if (lane == 0) s_sum[c] = m;
+    }
+}
+
+// Summary only when the frontier is sparse enough for most words to be zero.
+__device__ __forceinline__ bool use_summary(const BfsArgs& a, int32_t nf) {
+    return a.sum_words > 0 && (int64_t)nf * 8 < a.words;
 }
 
 // ------------------------------------------------------------------ output
@@ -456,12 +497,22 @@ __device__ __forceinline__ void td_row(const BfsArgs& a, const TdCtx& cx, Pager&
     }
 }
 
+// Per-wavefront LDS arrays of the level kernel, shared by its paths: the
+// top-down dense enumeration (each lane's first edge, row start and vertex)
+// and the streamed bottom-up hit list (slot, source).
+struct WaveLds {
+    int32_t a[kBfsWaves][kWave];
+    int32_t b[kBfsWaves][kWave];
+    int32_t c[kBfsWaves][kWave];
+};
+
 // The 64 frontier vertices v of one unit (-1 = none) expand their out-rows.
 // Wave-collective.
-__device__ __forceinline__ void td_unit(const BfsArgs& a, const TdCtx& cx, Pager& pg, int32_t v, int32_t& cnt, int64_t& deg) {
-    __shared__ int32_t s_start[kBfsWaves][kWave];
-    __shared__ int32_t s_rb[kBfsWaves][kWave];
-    __shared__ int32_t s_v[kBfsWaves][kWave];
+__device__ __forceinline__ void td_unit(const BfsArgs& a, const TdCtx& cx, WaveLds& sl, Pager& pg, int32_t v,
+                                        int32_t& cnt, int64_t& deg) {
+    auto& s_start = sl.a;
+    auto& s_rb = sl.b;
+    auto& s_v = sl.c;
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
     const int32_t rb = (v >= 0) ? a.csr_off[v] : 0;
@@ -526,9 +577,10 @@ __device__ __forceinline__ void td_unit(const BfsArgs& a, const TdCtx& cx, Pager
 // so its vertices clear their words there: the bitmap is clean when it is
 // reused two levels on, without a full clear.
 // Queue pages [first, pages) hold the frontier.
-__device__ void level_top_down(const BfsArgs& a, const TdCtx& cx, const int32_t* q_cur, const int32_t* fill_cur,
-                               int32_t first, int32_t pages, uint64_t* fb_cur, bool by_bitmap, int32_t& cnt,
-                               int64_t& deg, Pager& pg) {
+__device__ __forceinline__ void level_top_down(const BfsArgs& a, const TdCtx& cx, WaveLds& sl, const int32_t* q_cur,
+                                               const int32_t* fill_cur, int32_t first, int32_t pages,
+                                               uint64_t* fb_cur, bool by_bitmap, int32_t& cnt, int64_t& deg,
+                                               Pager& pg) {
     const int lane = threadIdx.x & (kWave - 1);
     const int32_t gwave = blockIdx.x * kBfsWaves + threadIdx.x / kWave;
     const int32_t nwaves = gridDim.x * kBfsWaves;
@@ -536,7 +588,7 @@ __device__ void level_top_down(const BfsArgs& a, const TdCtx& cx, const int32_t*
         for (int32_t unit = gwave; unit < a.words; unit += nwaves) {
             const uint64_t word = fb_cur[unit];
             if (word == 0) continue;
-            td_unit(a, cx, pg, ((word >> lane) & 1ull) ? unit * kWave + lane : -1, cnt, deg);
+            td_unit(a, cx, sl, pg, ((word >> lane) & 1ull) ? unit * kWave + lane : -1, cnt, deg);
         }
         return;
     }
@@ -567,7 +619,7 @@ __device__ void level_top_down(const BfsArgs& a, const TdCtx& cx, const int32_t*
             if (n_here <= 0) continue;
             const int32_t v = (lane < n_here) ? q_here : -1;
             if (v >= 0) fb_cur[v >> 6] = 0ull;
-            td_unit(a, cx, pg, v, cnt, deg);
+            td_unit(a, cx, sl, pg, v, cnt, deg);
         }
     }
 }
@@ -578,8 +630,8 @@ constexpr int kBuU = 4;  // rounds of 64 in-edges a wave loads per step of a lon
 
 // Position of the first frontier member among csc_idx[b, e) (-1 if none),
 // stopping at the first step that has one.  Wave-collective (b, e uniform).
-__device__ __forceinline__ void bu_scan_row(const BfsArgs& a, const uint64_t* fb_cur, const uint64_t* s_fb,
-                                            int32_t sw, int32_t b, int32_t e, int lane, int32_t& pos) {
+__device__ __forceinline__ void bu_scan_row(const BfsArgs& a, const FbView& fv, int32_t b, int32_t e, int lane,
+                                            int32_t& pos) {
     pos = -1;
     for (int32_t jb = b; jb < e; jb += kBuU * kWave) {
         int32_t u[kBuU];
@@ -590,7 +642,7 @@ __device__ __forceinline__ void bu_scan_row(const BfsArgs& a, const uint64_t* fb
         }
         bool hit[kBuU];
 #pragma unroll
-        for (int r = 0; r < kBuU; ++r) hit[r] = (u[r] >= 0) && test_bit(s_fb, sw, fb_cur, u[r]);
+        for (int r = 0; r < kBuU; ++r) hit[r] = (u[r] >= 0) && fb_test(fv, u[r]);
 #pragma unroll
         for (int r = 0; r < kBuU; ++r) {
             const uint64_t hm = __ballot(hit[r]);
@@ -602,9 +654,8 @@ __device__ __forceinline__ void bu_scan_row(const BfsArgs& a, const uint64_t* fb
     }
 }
 
-__device__ void level_bottom_up(const BfsArgs& a, int32_t lvl, const uint64_t* fb_cur, const uint64_t* s_fb,
-                                int32_t sw, int32_t* q_next, int32_t* fill_next, uint64_t* fb_next, BfsSlot* nxt,
-                                int32_t& cnt, int64_t& deg, Pager& pg) {
+__device__ __forceinline__ void level_bottom_up(const BfsArgs& a, int32_t lvl, const FbView& fv, int32_t* q_next, int32_t* fill_next,
+                                uint64_t* fb_next, BfsSlot* nxt, int32_t& cnt, int64_t& deg, Pager& pg) {
     const int lane = threadIdx.x & (kWave - 1);
     const int32_t gwave = blockIdx.x * kBfsWaves + threadIdx.x / kWave;
     const int32_t nwaves = gridDim.x * kBfsWaves;
@@ -631,7 +682,7 @@ __device__ void level_bottom_up(const BfsArgs& a, int32_t lvl, const uint64_t* f
             big &= big - 1;
             const int32_t bb = __shfl(rb, src), be = __shfl(re, src);
             int32_t p = -1;
-            bu_scan_row(a, fb_cur, s_fb, sw, bb, be, lane, p);
+            bu_scan_row(a, fv, bb, be, lane, p);
             if (lane == src && p >= 0) {
                 found = true;
                 par = a.csc_idx[p];
@@ -648,7 +699,7 @@ __device__ void level_bottom_up(const BfsArgs& a, int32_t lvl, const uint64_t* f
                 for (int r = 0; r < kBuB; ++r) u[r] = (j + r < re) ? a.csc_idx[j + r] : -1;
                 bool hit[kBuB];
 #pragma unroll
-                for (int r = 0; r < kBuB; ++r) hit[r] = (u[r] >= 0) && test_bit(s_fb, sw, fb_cur, u[r]);
+                for (int r = 0; r < kBuB; ++r) hit[r] = (u[r] >= 0) && fb_test(fv, u[r]);
 #pragma unroll
                 for (int r = 0; r < kBuB; ++r)
                     if (hit[r] && !found) {
@@ -674,6 +725,84 @@ __device__ void level_bottom_up(const BfsArgs& a, int32_t lvl, const uint64_t* f
     }
 }
 
+// Bottom-up level over the whole in-edge array, for a sparse frontier while
+// most edges still belong to unvisited vertices.  Row by row, a wavefront
+// walks its bitmap words one after another, and the hub words (64 rows of
+// hundreds of edges each) serialise whole levels; streamed, every slot is
+// read once in memory order with kStreamU loads in flight per lane.  The
+// slots whose source is in the frontier are collected per wavefront in LDS
+// and resolved 64 at a time, one lane each: the vertex comes from csc_row and
+// is claimed with an atomic OR, so its parent is some frontier in-neighbour
+// (not necessarily the first in stored order).
+constexpr int kStreamU = 8;
+
+__device__ __forceinline__ void level_bottom_up_stream(const BfsArgs& a, int32_t lvl, const FbView& fv, WaveLds& sl,
+                                                       int32_t* q_next, int32_t* fill_next, uint64_t* fb_next,
+                                                       BfsSlot* nxt, int32_t& cnt, int64_t& deg, Pager& pg) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const int64_t gwave = blockIdx.x * kBfsWaves + w;
+    const int64_t nwaves = (int64_t)gridDim.x * kBfsWaves;
+    constexpr int64_t kStep = kStreamU * kWave;
+    int32_t nh = 0;  // hits held in sl.a / sl.b (wave-uniform)
+    auto resolve = [&]() {
+        wave_sync();
+        bool claimed = false;
+        int32_t v = -1;
+        if (lane < nh) {
+            const int32_t u = sl.b[w][lane];
+            v = a.csc_row[sl.a[w][lane]];
+            const uint64_t bit = 1ull << (v & 63);
+            const uint64_t old =
+                atomicOr(reinterpret_cast<unsigned long long*>(&a.visited[v >> 6]), (unsigned long long)bit);
+            if (!(old & bit)) {
+                claimed = true;
+                const int32_t vu = user_id(a.perm, v);
+                a.level[vu] = lvl + 1;
+                a.parent[vu] = user_id(a.perm, u);
+                atomicOr(reinterpret_cast<unsigned long long*>(&fb_next[v >> 6]), (unsigned long long)bit);
+                cnt += 1;
+                deg += a.out_deg[v];
+            }
+        }
+        const uint64_t m = __ballot(claimed);
+        if (m)
+            page_append(a, pg, claimed, v, __popcll(m & lanes_below(lane)), __popcll(m), q_next, fill_next, nxt, lane);
+        wave_sync();
+        nh = 0;
+    };
+    for (int64_t e0 = gwave * kStep; e0 < a.nnz; e0 += nwaves * kStep) {
+        int32_t u[kStreamU];
+#pragma unroll
+        for (int r = 0; r < kStreamU; ++r) {
+            const int64_t e = e0 + r * kWave + lane;
+            u[r] = (e < a.nnz) ? a.csc_idx[e] : -1;
+        }
+        bool hit[kStreamU];
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < kStreamU; ++r) {
+            hit[r] = (u[r] >= 0) && fb_test(fv, u[r]);
+            any = any || hit[r];
+        }
+        if (__ballot(any) == 0) continue;
+#pragma unroll
+        for (int r = 0; r < kStreamU; ++r) {
+            const uint64_t m = __ballot(hit[r]);
+            if (!m) continue;
+            const int32_t k = __popcll(m);
+            if (nh + k > kWave) resolve();
+            if (hit[r]) {
+                const int32_t at = nh + __popcll(m & lanes_below(lane));
+                sl.a[w][at] = (int32_t)(e0 + r * kWave + lane);
+                sl.b[w][at] = u[r];
+            }
+            nh += k;
+        }
+    }
+    if (nh) resolve();
+}
+
 // Expands frontier `lvl` (slot lvl % 3) into lvl+1.  policy: PP_PUSH,
 // PP_PULL or PP_SWITCH (decided here, identically in every workgroup, from
 // the slot statistics).
@@ -681,6 +810,7 @@ __device__ void level_bottom_up(const BfsArgs& a, int32_t lvl, const uint64_t* f
 __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_arg, int32_t parity, int32_t policy,
                                                           float alpha, float beta) {
     extern __shared__ uint64_t s_bits[];
+    __shared__ WaveLds s_wave;
     BfsHdr* h = a.hdr;
     // the three slots are read in the same round trip as the level index
     const SlotView v0 = view(h->slot[0]), v1 = view(h->slot[1]), v2 = view(h->slot[2]);
@@ -745,11 +875,22 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
         if (sw) stage_bits(s_bits, a.visited, sw);
         TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw, cur.m >= kProbeMin};
         // a frontier built top-down left the reserved pages unused
-        level_top_down(a, cx, a.queue[lvl & 1], a.fill[lvl & 1], (cur.dir_prev == PP_PULL) ? 0 : a.static_pages,
+        level_top_down(a, cx, s_wave, a.queue[lvl & 1], a.fill[lvl & 1], (cur.dir_prev == PP_PULL) ? 0 : a.static_pages,
                        min(cur.pages, a.page_cap), a.fb[sc], nf > a.words, cnt, deg, pg);
     } else {
+        // the summary pays on large levels only (each workgroup builds it)
+        const bool sum = sw && use_summary(a, nf);
+        uint64_t* s_sum = s_bits + a.stage_words;
+        if (sum) build_summary(s_sum, a.fb[sc], a.words, sw, a.sum_words);
         if (sw) stage_bits(s_bits, a.fb[sc], sw);
-        level_bottom_up(a, lvl, a.fb[sc], s_bits, sw, q_next, fill_next, a.fb[sn], &h->slot[sn], cnt, deg, pg);
+        const FbView fv{s_bits, sw, s_sum, sum ? min(a.words, a.sum_words * kWave) : 0, a.fb[sc]};
+        // a sparse frontier while most in-edges still belong to unvisited
+        // vertices: stream the in-edge array instead of scanning row by row
+        // (its hits, the frontier's out-edges, must stay few)
+        if ((int64_t)nf * 8 < a.words && 2 * mu >= a.nnz && 256 * cur.m <= a.nnz)
+            level_bottom_up_stream(a, lvl, fv, s_wave, q_next, fill_next, a.fb[sn], &h->slot[sn], cnt, deg, pg);
+        else
+            level_bottom_up(a, lvl, fv, q_next, fill_next, a.fb[sn], &h->slot[sn], cnt, deg, pg);
     }
     page_close(pg, fill_next, lane);
     flush_stats(cnt, deg, &h->slot[sn]);
@@ -766,11 +907,12 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_chunks(BfsArgs a) {
     extern __shared__ uint64_t s_bits[];
     BfsHdr* h = a.hdr;
     // slot fields read in the same round trip as the level index
-    int32_t bigs[3], dirs[3];
+    int32_t bigs[3], dirs[3], ns[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         bigs[i] = h->slot[i].big;
         dirs[i] = h->slot[i].dir_prev;
+        ns[i] = h->slot[i].n;
     }
     const int32_t lvl = h->c_lvl;
     if (lvl < 0) return;
@@ -786,12 +928,10 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_chunks(BfsArgs a) {
     Pager pg{-1, 0};
     int32_t* q_next = a.queue[(lvl + 1) & 1];
     int32_t* fill_next = a.fill[(lvl + 1) & 1];
-    // no LDS stage here: the kernel runs without dynamic LDS, so several
-    // workgroups share a compute unit (more chunk chains in flight)
-    const int32_t sw = 0;
+    // no bitmap prefix is staged here: the kernel keeps its LDS small, so
+    // two workgroups share a compute unit (more chunk chains in flight)
     if (dir == PP_PUSH) {
-        if (sw) stage_bits(s_bits, a.visited, sw);
-        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw, true};
+        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, 0, true};
         for (int32_t it = gwave; it < items; it += nwaves)
             td_row(a, cx, pg, a.items[3 * it], a.items[3 * it + 1], a.items[3 * it + 2], cnt, deg, lane);
     } else {
@@ -828,11 +968,19 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_chunks(BfsArgs a) {
             nh = 0;
         };
         const uint64_t* fb_cur = a.fb[sc];
-        if (sw) stage_bits(s_bits, fb_cur, sw);
+        // the summary (built by every workgroup) pays when the items bring at
+        // least two edges per summarised word
+        const bool sum = use_summary(a, (sc == 0) ? ns[0] : ((sc == 1) ? ns[1] : ns[2])) &&
+                         (int64_t)items * kBigInRow >= 2 * (int64_t)gridDim.x * a.sum_words * kWave;
+        if (sum) {
+            build_summary(s_bits, fb_cur, a.words, 0, a.sum_words);
+            __syncthreads();
+        }
+        const FbView fv{s_bits, 0, s_bits, sum ? min(a.words, a.sum_words * kWave) : 0, fb_cur};
         for (int32_t it = gwave; it < items; it += nwaves) {
             const int32_t v = a.items[3 * it], b = a.items[3 * it + 1], e = a.items[3 * it + 2];
             int32_t pos = -1;
-            if (!((a.visited[v >> 6] >> (v & 63)) & 1ull)) bu_scan_row(a, fb_cur, s_bits, sw, b, e, lane, pos);
+            if (!((a.visited[v >> 6] >> (v & 63)) & 1ull)) bu_scan_row(a, fv, b, e, lane, pos);
             if (pos >= 0) {
                 if (lane == 0) {
                     s_hv[w][nh] = v;
@@ -857,7 +1005,7 @@ static pp_status check_state(pp_graph g, void* state, size_t bytes) {
 
 // Lets the staging kernels take LDS beyond the default 64 KiB.
 static void allow_stage_lds(const BfsArgs& a) {
-    const int bytes = a.stage_words * 8;
+    const int bytes = (a.stage_words + a.sum_words) * 8;
     if (bytes <= 65536) return;
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bfs_level), hipFuncAttributeMaxDynamicSharedMemorySize,
                               bytes);
@@ -865,7 +1013,7 @@ static void allow_stage_lds(const BfsArgs& a) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-// Workgroups of the chunk kernel: two per compute unit (it stages no LDS).
+// Workgroups of the chunk kernel: two per compute unit (its LDS is small).
 static int32_t chunk_blocks(pp_graph g) { return std::max(1, std::min(ceil_div(g->d.n, 4096), 2 * g->num_cu)); }
 
 // Does a level of this policy on this graph ever queue chunk items?
@@ -879,9 +1027,10 @@ static bool needs_chunks(pp_graph g, int32_t policy) {
 static pp_status launch_level(pp_graph g, const BfsArgs& a, int32_t lvl, int32_t parity, int32_t policy, float alpha,
                               float beta, hipStream_t st) {
     const int32_t blocks = bfs_blocks(g);
-    const size_t lds = (size_t)a.stage_words * 8;
+    const size_t lds = (size_t)(a.stage_words + a.sum_words) * 8;
     hipLaunchKernelGGL(k_bfs_level, dim3(blocks), dim3(kBfsBlock), lds, st, a, lvl, parity, policy, alpha, beta);
-    if (needs_chunks(g, policy)) hipLaunchKernelGGL(k_bfs_chunks, dim3(chunk_blocks(g)), dim3(kBfsBlock), 0, st, a);
+    if (needs_chunks(g, policy))
+        hipLaunchKernelGGL(k_bfs_chunks, dim3(chunk_blocks(g)), dim3(kBfsBlock), (size_t)a.sum_words * 8, st, a);
     PP_LAUNCH_CHECK("k_bfs_level");
     return PP_OK;
 }
@@ -904,7 +1053,7 @@ static pp_status bfs_graph(pp_graph g, BfsArgs a, int32_t policy, float alpha, f
         g->bfs_graphs.erase(g->bfs_graphs.begin());
     }
     const int32_t blocks = bfs_blocks(g);
-    const unsigned lds = (unsigned)a.stage_words * 8;
+    const unsigned lds = (unsigned)(a.stage_words + a.sum_words) * 8;
     const bool chunks = needs_chunks(g, policy);
     hipGraph_t graph = nullptr;
     PP_HIP(hipGraphCreate(&graph, 0));
@@ -930,7 +1079,7 @@ static pp_status bfs_graph(pp_graph g, BfsArgs a, int32_t policy, float alpha, f
         e = add(reinterpret_cast<const void*>(&k_bfs_level), largs, blocks, lds);
         if (e == hipSuccess && chunks) {
             void* cargs[] = {&a};
-            e = add(reinterpret_cast<const void*>(&k_bfs_chunks), cargs, chunk_blocks(g), 0);
+            e = add(reinterpret_cast<const void*>(&k_bfs_chunks), cargs, chunk_blocks(g), (unsigned)a.sum_words * 8);
         }
     }
     hipGraphExec_t exec = nullptr;

@@ -298,6 +298,28 @@ __global__ void k_check_indices(int32_t n, int64_t nnz, const int32_t* __restric
     if (u < 0 || u >= n) atomicAdd(&err[1], 1);
 }
 
+// row[j] = v for every slot j of the row of v (rows of more than 64 slots
+// are written by the whole wavefront).
+__global__ void k_row_owner(int32_t n, const int32_t* off, int32_t* row) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t gw = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+    const int32_t nw = (int32_t)(gridDim.x * blockDim.x / kWave);
+    for (int32_t base = gw * kWave; base < n; base += nw * kWave) {
+        const int32_t v = base + lane;
+        const int32_t b = v < n ? off[v] : 0, e = v < n ? off[v + 1] : 0;
+        const bool longrow = e - b > kWave;
+        if (!longrow)
+            for (int32_t j = b; j < e; ++j) row[j] = v;
+        uint64_t m = __ballot(longrow);
+        while (m) {
+            const int src = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int32_t lb = __shfl(b, src), le = __shfl(e, src);
+            for (int32_t j = lb + lane; j < le; j += kWave) row[j] = base + src;
+        }
+    }
+}
+
 __global__ void k_zero_i32(int32_t n, int32_t* p) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -305,7 +327,7 @@ __global__ void k_zero_i32(int32_t n, int32_t* p) {
 
 // ------------------------------------------------------------------ host side
 struct WsLayout {
-    size_t inv_s, out_deg, pull_list, push_list, buf0, buf1, buf2, csc_w, split_tab, split_part, hot_part, err,
+    size_t inv_s, out_deg, pull_list, push_list, buf0, buf1, buf2, csc_w, csc_row, split_tab, split_part, hot_part, err,
         tiles, keys, perm, iperm, r_csr_off, r_csr_idx, r_csc_off, r_csc_idx, r_csr_w, total;
     int32_t split_cap;
 };
@@ -337,6 +359,7 @@ static WsLayout layout(int32_t n, int64_t nnz, uint32_t flags, const Tuning& t, 
     L.buf1 = take(nn * 4);
     L.buf2 = take(nn * 4);
     L.csc_w = weighted ? take(nz * 4) : 0;
+    L.csc_row = take(nz * 4);
     // split tables: per entry (vertex, begin, end) + per split vertex first entry, for pull and push
     L.split_tab = take((size_t)2 * (4 * (size_t)L.split_cap + 1) * 4);
     L.split_part = take((size_t)L.split_cap * 4);
@@ -594,6 +617,7 @@ PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_o
     d.buf1 = static_cast<float*>(at(L.buf1));
     d.buf2 = static_cast<float*>(at(L.buf2));
     d.csc_w = weighted ? static_cast<float*>(at(L.csc_w)) : nullptr;
+    d.csc_row = static_cast<int32_t*>(at(L.csc_row));
     d.split_tab = static_cast<int32_t*>(at(L.split_tab));
     d.split_part = static_cast<float*>(at(L.split_part));
     d.hot_part = static_cast<float*>(at(L.hot_part));
@@ -655,6 +679,8 @@ PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_o
         hipLaunchKernelGGL(k_gather_weights, dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz, csr_w, csc_to_csr,
                            d.csc_w);
     }
+    hipLaunchKernelGGL(k_row_owner, dim3(std::max(std::min<int32_t>(ceil_div(n, 256), 4096), 1)), dim3(256), 0, st, n,
+                       d.csc_off, d.csc_row);
     hipLaunchKernelGGL(k_degrees, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, d.csr_off, d.csr_w, d.out_deg,
                        d.inv_s);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, 2, d.err + 48);

@@ -74,6 +74,7 @@ struct GraphDev {
     const int32_t* user_csr_idx;
     const int32_t* user_csc_off;
     const int32_t* user_csc_idx;
+    int32_t* csc_row;         // the row (in-row owner) of every CSC slot
     float* inv_s;             // 1/d(v) or 1/s(v); 0 when nothing leaves v
     int32_t* out_deg;         // d(v)
     int32_t* pull_list;       // vertices grouped by in-degree bin
