@@ -48,6 +48,9 @@ constexpr int32_t kStaticLds = 16384;  // LDS bytes kept for the kernels' own ar
 // bitmap word (set if the word is nonzero): a test of a vertex whose word is
 // empty then needs no global load.  At most kSumMax summary words (8 KB).
 constexpr int32_t kSumMax = 1024;
+// Visited words the chunk kernel's top-down items test in LDS (60 KB: two
+// workgroups of it still share a compute unit).
+constexpr int32_t kChunkStage = 7680;
 
 struct BfsSlot {
     int32_t n;         // frontier size (accumulated by the level that builds it)
@@ -132,6 +135,7 @@ struct BfsArgs {
     int32_t item_cap;
     int32_t stage_words;    // bitmap words a workgroup may stage in LDS
     int32_t sum_words;      // LDS summary words (after the staged words; 0 = none)
+    int32_t chunk_stage;    // visited words the chunk kernel may stage
     int32_t static_pages;   // queue pages owned one per wavefront of the level kernel
     int64_t stage_min;      // stage only when the level examines at least this many edges
     const int32_t* csr_off;
@@ -163,6 +167,7 @@ static BfsArgs bfs_args(pp_graph g, void* state, int32_t* level, int32_t* parent
     a.item_cap = L.item_cap;
     a.stage_words = L.stage_words;
     a.sum_words = L.sum_words;
+    a.chunk_stage = std::min(L.words, kChunkStage);
     a.static_pages = L.blocks * kBfsWaves;
     // copying costs each workgroup stage_words loads; pay it only when the
     // level has at least two edges per staged word per workgroup
@@ -928,10 +933,14 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_chunks(BfsArgs a) {
     Pager pg{-1, 0};
     int32_t* q_next = a.queue[(lvl + 1) & 1];
     int32_t* fill_next = a.fill[(lvl + 1) & 1];
-    // no bitmap prefix is staged here: the kernel keeps its LDS small, so
-    // two workgroups share a compute unit (more chunk chains in flight)
+    // LDS stays at most 60 KB, so two workgroups share a compute unit (more
+    // chunk chains in flight)
     if (dir == PP_PUSH) {
-        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, 0, true};
+        // top-down items test the hottest visited words in LDS when the items
+        // bring at least two edges per staged word
+        const int32_t sw = ((int64_t)items * kBigRow >= 2 * (int64_t)gridDim.x * a.chunk_stage) ? a.chunk_stage : 0;
+        if (sw) stage_bits(s_bits, a.visited, sw);
+        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw, true};
         for (int32_t it = gwave; it < items; it += nwaves)
             td_row(a, cx, pg, a.items[3 * it], a.items[3 * it + 1], a.items[3 * it + 2], cnt, deg, lane);
     } else {
@@ -1013,6 +1022,10 @@ static void allow_stage_lds(const BfsArgs& a) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+// Dynamic LDS of the chunk kernel: the bottom-up summary or the top-down
+// visited stage.
+static size_t chunk_lds(const BfsArgs& a) { return (size_t)std::max(a.sum_words, a.chunk_stage) * 8; }
+
 // Workgroups of the chunk kernel: two per compute unit (its LDS is small).
 static int32_t chunk_blocks(pp_graph g) { return std::max(1, std::min(ceil_div(g->d.n, 4096), 2 * g->num_cu)); }
 
@@ -1030,7 +1043,7 @@ static pp_status launch_level(pp_graph g, const BfsArgs& a, int32_t lvl, int32_t
     const size_t lds = (size_t)(a.stage_words + a.sum_words) * 8;
     hipLaunchKernelGGL(k_bfs_level, dim3(blocks), dim3(kBfsBlock), lds, st, a, lvl, parity, policy, alpha, beta);
     if (needs_chunks(g, policy))
-        hipLaunchKernelGGL(k_bfs_chunks, dim3(chunk_blocks(g)), dim3(kBfsBlock), (size_t)a.sum_words * 8, st, a);
+        hipLaunchKernelGGL(k_bfs_chunks, dim3(chunk_blocks(g)), dim3(kBfsBlock), chunk_lds(a), st, a);
     PP_LAUNCH_CHECK("k_bfs_level");
     return PP_OK;
 }
@@ -1079,7 +1092,7 @@ static pp_status bfs_graph(pp_graph g, BfsArgs a, int32_t policy, float alpha, f
         e = add(reinterpret_cast<const void*>(&k_bfs_level), largs, blocks, lds);
         if (e == hipSuccess && chunks) {
             void* cargs[] = {&a};
-            e = add(reinterpret_cast<const void*>(&k_bfs_chunks), cargs, chunk_blocks(g), (unsigned)a.sum_words * 8);
+            e = add(reinterpret_cast<const void*>(&k_bfs_chunks), cargs, chunk_blocks(g), (unsigned)chunk_lds(a));
         }
     }
     hipGraphExec_t exec = nullptr;
