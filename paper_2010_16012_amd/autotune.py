@@ -141,8 +141,8 @@ def tune_bfs_switch(host, roots, log=print) -> dict:
     g = Graph(host)
     r = BfsRun(g)
     best = None
-    for alpha in (2.0, 4.0, 8.0, 14.0, 24.0):
-        for beta in (8.0, 24.0, 64.0):
+    for alpha in (8.0, 14.0, 24.0, 48.0, 96.0, 192.0, 384.0):
+        for beta in (24.0, 64.0, 128.0, 256.0):
             def f():
                 for root in roots:
                     r.run(int(root), PP_SWITCH, alpha, beta)
@@ -175,17 +175,26 @@ def main():
     p.add_argument("--roots", type=int, default=8)
     p.add_argument("--ppr-k", type=int, default=0)
     p.add_argument("--out", required=True)
+    p.add_argument("--only", default="", help="comma list of searches to rerun (pagerank, bfs, ppr); the cached "
+                   "entry keeps the other settings, which also apply while searching")
     a = p.parse_args()
     host = gg.rmat(a.scale, 16, seed=1)
-    cfg = tune_pagerank(host, base=tune_bins(host))
-    cfg.update(tune_bfs_switch(host, gg.pick_vertices(host, a.roots, seed=1)))
-    if a.ppr_k:
-        cfg.update(tune_ppr_tile(host, a.ppr_k))
     cache = {}
     if os.path.exists(a.out):
         with open(a.out) as fh:
             cache = json.load(fh)
-    cache[key(host.n, host.nnz)] = cfg
+    k = key(host.n, host.nnz)
+    only = set(filter(None, a.only.split(",")))
+    if only:
+        cfg = dict(cache.get(k, {}))
+        apply(cfg)
+    if not only or "pagerank" in only:
+        cfg = tune_pagerank(host, base=tune_bins(host))
+    if not only or "bfs" in only:
+        cfg.update(tune_bfs_switch(host, gg.pick_vertices(host, a.roots, seed=1)))
+    if a.ppr_k and (not only or "ppr" in only):
+        cfg.update(tune_ppr_tile(host, a.ppr_k))
+    cache[k] = cfg
     with open(a.out, "w") as fh:
         json.dump(cache, fh, indent=1, sort_keys=True)
     print(json.dumps({key(host.n, host.nnz): cfg}))

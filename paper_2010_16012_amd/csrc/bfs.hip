@@ -632,6 +632,7 @@ __device__ __forceinline__ void level_top_down(const BfsArgs& a, const TdCtx& cx
 // ------------------------------------------------------------------ bottom-up
 constexpr int kBuB = 4;  // in-edges one lane loads per step of a short row
 constexpr int kBuU = 4;  // rounds of 64 in-edges a wave loads per step of a long row
+constexpr int32_t kCoopRow = 128;  // in-rows at least this long are scanned by the whole wave
 
 // Position of the first frontier member among csc_idx[b, e) (-1 if none),
 // stopping at the first step that has one.  Wave-collective (b, e uniform).
@@ -673,14 +674,16 @@ __device__ __forceinline__ void level_bottom_up(const BfsArgs& a, int32_t lvl, c
         int32_t re = unvisited ? a.csc_off[v + 1] : 0;
         bool found = false;
         int32_t par = -1;
-        // long in-rows: the wave scans 64 x kBuU in-neighbours at a time and
-        // stops at the first hit; of an in-row longer than kBigInRow only the
-        // first kBigInRow entries are scanned here (most hits come early) and,
-        // without a hit there, the rest becomes chunk items for the grid
+        // in-rows of kCoopRow or more: the wave scans 64 x kBuU in-neighbours
+        // at a time and stops at the first hit (one row after another, so the
+        // threshold is high: shorter rows go per lane, all in parallel); of an
+        // in-row longer than kBigInRow only the first kBigInRow entries are
+        // scanned here (most hits come early) and, without a hit there, the
+        // rest becomes chunk items for the grid
         const bool huge = (re - rb) > kBigInRow;
         const int32_t rest_b = rb + kBigInRow, rest_e = re;
         if (huge) re = rest_b;
-        const bool coop = (re - rb) >= 32;
+        const bool coop = (re - rb) >= kCoopRow;
         uint64_t big = __ballot(coop);
         while (big) {
             const int src = __ffsll((long long)big) - 1;
@@ -1176,14 +1179,23 @@ PP_EXPORT pp_status pp_bfs_run(pp_graph g, int32_t root, pp_dir policy, float al
     pp_status s = pp_bfs_init(g, root, level, parent, state, state_bytes, stream);
     if (s != PP_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const BfsLayout L = bfs_layout(g);
-    const BfsHdr* dh = reinterpret_cast<const BfsHdr*>(static_cast<char*>(state) + L.hdr);
     BfsArgs a = bfs_args(g, state, level, parent);
-    // Levels go out in growing batches with the level index kept on the
-    // device; kernels past the last level find an empty frontier and return
-    // at once, so only termination needs a read.
-    int32_t launched = 0, batch = 4;
+    // Levels go out in batches with the level index kept on the device;
+    // kernels past the last level find an empty frontier and return at once,
+    // so only termination needs a read, which takes the whole header (the
+    // statistics come with it).  The first batch covers the previous run's
+    // depth on this graph plus the empty level, so a run of similar depth
+    // needs one host read.
+    constexpr int32_t kBatches[] = {4, 8, 12, 16, 24, 32, 48, 64};
+    int32_t batch = 64;
+    for (int32_t b : kBatches)
+        if (b >= g->bfs_last_levels + 2) {
+            batch = b;
+            break;
+        }
+    int32_t launched = 0;
     const int32_t max_levels = g->d.n + 1;  // at most n non-empty frontiers, then an empty one
+    BfsHdr h;
     for (;;) {
         if (launched + batch <= max_levels) {  // a whole batch: replay its graph (launched stays even)
             hipGraphExec_t exec = nullptr;
@@ -1197,15 +1209,12 @@ PP_EXPORT pp_status pp_bfs_run(pp_graph g, int32_t root, pp_dir policy, float al
                 if (s != PP_OK) return s;
             }
         }
-        int32_t fin = 0;
-        PP_HIP(hipMemcpyAsync(&fin, &dh->finished, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        PP_HIP(hipStreamSynchronize(st));
-        if (fin || launched >= max_levels) break;
+        s = read_hdr(g, state, &h, st);
+        if (s != PP_OK) return s;
+        if (h.finished || launched >= max_levels) break;
         batch = std::min<int32_t>(batch * 2, 64);
     }
-    BfsHdr h;
-    s = read_hdr(g, state, &h, st);
-    if (s != PP_OK) return s;
+    g->bfs_last_levels = h.levels;
     if (stats) {
         stats->levels = h.levels;
         stats->reached = (int32_t)h.reached;

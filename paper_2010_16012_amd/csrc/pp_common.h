@@ -122,6 +122,7 @@ struct pp_graph_s {
         hipGraph_t graph;
     };
     std::vector<BfsGraph> bfs_graphs;
+    int32_t bfs_last_levels = 0;  // levels of the last BFS run on this graph (sizes the first batch)
     ~pp_graph_s() {
         for (auto& e : bfs_graphs) {
             (void)hipGraphExecDestroy(e.exec);
