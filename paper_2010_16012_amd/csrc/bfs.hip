@@ -911,7 +911,9 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
 // vertex with an atomic OR on its visited bit (so the parent is a frontier
 // in-neighbour, not necessarily the first in stored order); a chunk whose
 // vertex is already claimed is skipped.
-__global__ __launch_bounds__(kBfsBlock) void k_bfs_chunks(BfsArgs a) {
+// Two workgroups per compute unit: 32 wavefronts, 8 per SIMD, which caps the
+// kernel at 64 VGPRs (the second bound is the minimum wavefronts per SIMD).
+__global__ __launch_bounds__(kBfsBlock, 8) void k_bfs_chunks(BfsArgs a) {
     extern __shared__ uint64_t s_bits[];
     BfsHdr* h = a.hdr;
     // slot fields read in the same round trip as the level index
