@@ -321,7 +321,9 @@ pp_status pp_tc_run(pp_graph g, pp_dir dir, int64_t* tc, void* ws, size_t ws_byt
 
 /* ------------------------------------------------ betweenness centrality */
 /* Workspace bytes of pp_bc_run for graph g (device, caller-owned, 256-byte
- * aligned): distances, path counts, dependencies and the BFS order. */
+ * aligned): per source of a batch of up to 32, its distances, path counts,
+ * dependencies, BFS order and level offsets (about 28 n bytes each).  A
+ * smaller workspace (at least one source's share) runs smaller batches. */
 size_t pp_bc_workspace_bytes(pp_graph g);
 
 /* Betweenness centrality over a set of sources (Sec. 3.5; Brandes' scheme as
@@ -336,10 +338,11 @@ size_t pp_bc_workspace_bytes(pp_graph g);
  * bwd_dir PP_PUSH: vertices add to their predecessors' dependency with FP64
  * atomics; PP_PULL: vertices sum over their successors (owner writes).
  * sources: HOST int32[num_sources] (caller ids); bc: double[n] device,
- * caller ids, overwritten.  The forward levels run in batches with their
- * bookkeeping on the device; the call synchronises the stream once per batch
- * (usually once per source) to read the depth, then queues the backward
- * levels. */
+ * caller ids, overwritten.  Sources run up to 32 at a time (they are
+ * independent), each level kernel covering all sources of the batch; the
+ * level bookkeeping is on the device.  The call synchronises the stream once
+ * per batch of forward levels (usually once per batch of sources) to read
+ * the depths, then queues the backward levels. */
 pp_status pp_bc_run(pp_graph g, pp_dir fwd_dir, pp_dir bwd_dir, int32_t num_sources, const int32_t* sources,
                     double* bc, void* ws, size_t ws_bytes, void* stream);
 

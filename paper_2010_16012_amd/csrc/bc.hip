@@ -24,11 +24,17 @@
 // this, a hub's claim and its FP64 additions arrive from every one of its
 // frontier neighbours and serialise on one address.
 //
-// The forward pass keeps its level bookkeeping on the device: the last
-// workgroup of a level kernel to finish records where the next level ends in
-// `order` and whether it is empty.  The host launches forward kernels in
-// batches (kernels past the last level return at once) and reads the state
-// once per batch.
+// Sources run in batches of up to kBcBatch at once (the sources are
+// independent, Sec. 4.5): every kernel has a grid row (blockIdx.y) per source
+// of the batch, and each source owns a slab of the workspace (distances, path
+// counts, dependencies, BFS order, level offsets).  The level bookkeeping of
+// both passes is on the device: the last workgroup of a source's row to
+// finish a level kernel records where its next level ends, whether it is
+// empty, and (backward) which level comes next.  The host launches level
+// kernels in batches (a source past its last level returns at once) and
+// reads the states once per batch of forward levels; the backward levels
+// follow without a read, and the dependencies are summed into bc in source
+// order, without atomics.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -41,15 +47,21 @@ namespace pp {
 constexpr int kBcWaves = kBlock / kWave;
 constexpr int32_t kBcHot = 4096;  // LDS-accumulated targets of the pushing kernels (32 KB of FP64)
 
-// Forward-pass state, then the level offsets: level l is
-// order[lvl_off[l], lvl_off[l + 1]).
+constexpr int32_t kBcBatch = 32;  // sources processed together
+
+// Level state of one source (level l is order[lvl_off[l], lvl_off[l + 1])).
 struct BcState {
     int32_t l;         // level the next forward kernel expands
     int32_t done;      // set once a forward kernel found its next level empty
     int32_t depth;     // non-empty levels (valid once done)
     int32_t finished;  // workgroups of the running forward kernel that have finished
+    int32_t bl;        // level the next backward kernel completes (-1: none left)
+    int32_t bfinished; // workgroups of the running backward kernel that have finished
+    int32_t pad[2];
 };
 
+// Pointers of source 0 of a batch; source s is `stride` bytes further on
+// (see slab()).  st is an array over the batch.
 struct BcArgs {
     int32_t n;
     int32_t hot;             // min(n, kBcHot)
@@ -64,10 +76,35 @@ struct BcArgs {
     double* delta;
     int32_t* order;    // vertices in BFS order
     int32_t* cnt;      // vertices in order so far
+    int32_t* lvl_off;  // n + 2 entries
     BcState* st;
-    int32_t* lvl_off;  // n + 2 entries, right after st
+    size_t stride;     // bytes between the slabs of consecutive sources
     double* bc;        // caller ids
 };
+
+// The sources of a batch (caller ids), passed by value.
+struct BcSources {
+    int32_t s[kBcBatch];
+};
+
+template <typename T>
+__device__ __forceinline__ T* shift(T* p, size_t bytes) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(p) + bytes);
+}
+
+// The arguments of source `s` of the batch.
+__device__ __forceinline__ BcArgs slab(const BcArgs& a0, int32_t s) {
+    BcArgs a = a0;
+    const size_t b = (size_t)s * a0.stride;
+    a.dist = shift(a0.dist, b);
+    a.sigma = shift(a0.sigma, b);
+    a.delta = shift(a0.delta, b);
+    a.order = shift(a0.order, b);
+    a.cnt = shift(a0.cnt, b);
+    a.lvl_off = shift(a0.lvl_off, b);
+    a.st = a0.st + s;
+    return a;
+}
 
 __device__ __forceinline__ uint64_t bc_lanes_below(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
 
@@ -191,7 +228,9 @@ __device__ __forceinline__ double row_sum(bool own, int32_t rb, int32_t re, cons
     return acc;
 }
 
-__global__ void k_bc_init(BcArgs a, int32_t s_user) {
+__global__ void k_bc_init(BcArgs a0, BcSources src) {
+    const BcArgs a = slab(a0, blockIdx.y);
+    const int32_t s_user = src.s[blockIdx.y];
     const int32_t s = a.iperm ? a.iperm[s_user] : s_user;
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
         a.dist[v] = v == s ? 0 : -1;
@@ -201,7 +240,7 @@ __global__ void k_bc_init(BcArgs a, int32_t s_user) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.order[0] = s;
         *a.cnt = 1;
-        *a.st = BcState{0, 0, 0, 0};
+        *a.st = BcState{0, 0, 0, 0, -1, 0, {0, 0}};
         a.lvl_off[0] = 0;
         a.lvl_off[1] = 1;
     }
@@ -211,27 +250,42 @@ __global__ void k_bc_zero(int32_t n, double* bc) {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) bc[v] = 0.0;
 }
 
-// End of a forward level kernel: the last workgroup to finish (every other
-// one has then read the state) records the end of level l + 1 and whether it
-// is empty, and advances the level.  Workgroup-collective.
+// Is this workgroup the last of its source's row to finish the kernel?
+// (Every other one has then read the state.)  Workgroup-collective.
 // No device-wide fence is needed (one would write back the whole L2 per
 // workgroup): the appends are returning atomics on the counter, complete
 // before the barrier, so the last workgroup's atomic read of the counter sees
-// them all; what it writes is read by the next kernel only.
-__device__ __forceinline__ void bc_level_end(const BcArgs& a, int32_t l) {
+// them all; what it writes is read by later kernels only.
+__device__ __forceinline__ bool bc_last_group(int32_t* finished) {
     __shared__ int32_t s_last;
     __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(&a.st->finished, 1) == (int32_t)gridDim.x - 1;
+    if (threadIdx.x == 0) s_last = atomicAdd(finished, 1) == (int32_t)gridDim.x - 1;
     __syncthreads();
-    if (s_last && threadIdx.x == 0) {
+    return s_last != 0;
+}
+
+// End of a forward level kernel: the last workgroup records the end of level
+// l + 1 and whether it is empty (then the backward pass starts at the second
+// deepest level), and advances the level.  Workgroup-collective.
+__device__ __forceinline__ void bc_level_end(const BcArgs& a, int32_t l) {
+    if (bc_last_group(&a.st->finished) && threadIdx.x == 0) {
         const int32_t c = atomicAdd(a.cnt, 0);
         a.lvl_off[l + 2] = c;
         if (c == a.lvl_off[l + 1]) {
             a.st->done = 1;
             a.st->depth = l + 1;
+            a.st->bl = l - 1;
         }
         a.st->l = l + 1;
         a.st->finished = 0;
+    }
+}
+
+// End of a backward level kernel: the last workgroup moves to the level above.
+__device__ __forceinline__ void bc_back_end(const BcArgs& a, int32_t l) {
+    if (bc_last_group(&a.st->bfinished) && threadIdx.x == 0) {
+        a.st->bl = l - 1;
+        a.st->bfinished = 0;
     }
 }
 
@@ -242,8 +296,9 @@ __device__ __forceinline__ void hot_zero(double* s_acc, int32_t hot) {
 }
 
 // Forward, pushing: the frontier (level l) expands along out-edges.
-__global__ __launch_bounds__(kBlock) void k_bc_fwd_push(BcArgs a) {
+__global__ __launch_bounds__(kBlock) void k_bc_fwd_push(BcArgs a0) {
     __shared__ double s_acc[kBcHot];
+    const BcArgs a = slab(a0, blockIdx.y);
     const BcState st = *a.st;
     if (st.done) return;
     const int32_t l = st.l, lo = a.lvl_off[l], hi = a.lvl_off[l + 1];
@@ -289,7 +344,8 @@ __global__ __launch_bounds__(kBlock) void k_bc_fwd_push(BcArgs a) {
 
 // Forward, pulling: every unvisited vertex sums sigma over its in-neighbours
 // of level l; found vertices take level l+1.
-__global__ __launch_bounds__(kBlock) void k_bc_fwd_pull(BcArgs a) {
+__global__ __launch_bounds__(kBlock) void k_bc_fwd_pull(BcArgs a0) {
+    const BcArgs a = slab(a0, blockIdx.y);
     const BcState st = *a.st;
     if (st.done) return;
     const int32_t l = st.l;
@@ -311,11 +367,15 @@ __global__ __launch_bounds__(kBlock) void k_bc_fwd_pull(BcArgs a) {
     bc_level_end(a, l);
 }
 
-// Backward, pushing: every vertex w of order[lo, hi) (level l+1) adds
-// sigma(v) (1 + delta(w)) / sigma(w) to each predecessor v (level l); hot
-// predecessors collect the sum of (1 + delta(w)) / sigma(w) in LDS first.
-__global__ __launch_bounds__(kBlock) void k_bc_bwd_push(BcArgs a, int32_t l, int32_t lo, int32_t hi) {
+// Backward, pushing: every vertex w of level l+1 adds sigma(v) (1 + delta(w))
+// / sigma(w) to each predecessor v (level l); hot predecessors collect the sum
+// of (1 + delta(w)) / sigma(w) in LDS first.
+__global__ __launch_bounds__(kBlock) void k_bc_bwd_push(BcArgs a0) {
     __shared__ double s_acc[kBcHot];
+    const BcArgs a = slab(a0, blockIdx.y);
+    const int32_t l = a.st->bl;
+    if (l < 0) return;
+    const int32_t lo = a.lvl_off[l + 1], hi = a.lvl_off[l + 2];
     const int lane = threadIdx.x & (kWave - 1);
     hot_zero(s_acc, a.hot);
     for_each_edge(a.order + lo, hi - lo, a.in_off, a.in_idx, [&](bool valid, int32_t w, int32_t v) {
@@ -331,11 +391,16 @@ __global__ __launch_bounds__(kBlock) void k_bc_bwd_push(BcArgs a, int32_t l, int
         const double sum = v < a.hot ? s_acc[v] : 0.0;
         if (sum != 0.0) unsafeAtomicAdd(&a.delta[v], a.sigma[v] * sum);
     }
+    bc_back_end(a, l);
 }
 
-// Backward, pulling: every vertex v of order[lo, hi) (level l) sums over its
-// successors (level l+1) and writes delta(v).
-__global__ __launch_bounds__(kBlock) void k_bc_bwd_pull(BcArgs a, int32_t l, int32_t lo, int32_t hi) {
+// Backward, pulling: every vertex v of level l sums over its successors
+// (level l+1) and writes delta(v).
+__global__ __launch_bounds__(kBlock) void k_bc_bwd_pull(BcArgs a0) {
+    const BcArgs a = slab(a0, blockIdx.y);
+    const int32_t l = a.st->bl;
+    if (l < 0) return;
+    const int32_t lo = a.lvl_off[l], hi = a.lvl_off[l + 1];
     const int lane = threadIdx.x & (kWave - 1);
     const int32_t gwave = blockIdx.x * kBcWaves + threadIdx.x / kWave, nwaves = gridDim.x * kBcWaves;
     for (int32_t base = lo; base < hi; base += nwaves * kWave) {
@@ -348,18 +413,24 @@ __global__ __launch_bounds__(kBlock) void k_bc_bwd_pull(BcArgs a, int32_t l, int
         });
         if (own) a.delta[v] = a.sigma[v] * acc;
     }
+    bc_back_end(a, l);
 }
 
-// bc(v) += delta(v) for every vertex reached but the source (order[0]).
-__global__ void k_bc_acc(BcArgs a, int32_t count) {
-    for (int32_t i = 1 + blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
-        const int32_t v = a.order[i];
-        a.bc[a.perm ? a.perm[v] : v] += a.delta[v];
+// bc(v) += delta_s(v) over the batch's sources s != v, in source order.
+__global__ void k_bc_acc(BcArgs a0, BcSources src, int32_t count) {
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < a0.n; v += gridDim.x * blockDim.x) {
+        const int32_t vu = a0.perm ? a0.perm[v] : v;
+        double acc = 0.0;
+        for (int32_t s = 0; s < count; ++s)
+            if (src.s[s] != vu) acc += shift(a0.delta, (size_t)s * a0.stride)[v];
+        a0.bc[vu] += acc;
     }
 }
 
+// One source's slab; the workspace holds the batch's states, then up to
+// kBcBatch slabs.
 struct BcLayout {
-    size_t dist, sigma, delta, order, cnt, meta, total;
+    size_t dist, sigma, delta, order, cnt, lvl_off, slab;
 };
 
 static BcLayout bc_layout(int32_t n) {
@@ -375,16 +446,18 @@ static BcLayout bc_layout(int32_t n) {
     L.delta = take((size_t)n * 8);
     L.order = take((size_t)n * 4);
     L.cnt = take(4);
-    L.meta = take(sizeof(BcState) + ((size_t)n + 2) * 4);  // state, then the level offsets
-    L.total = p;
+    L.lvl_off = take(((size_t)n + 2) * 4);
+    L.slab = p;
     return L;
 }
+
+constexpr size_t kBcStates = (sizeof(BcState) * kBcBatch + 255) / 256 * 256;
 
 }  // namespace pp
 
 using namespace pp;
 
-PP_EXPORT size_t pp_bc_workspace_bytes(pp_graph g) { return g ? bc_layout(g->d.n).total : 0; }
+PP_EXPORT size_t pp_bc_workspace_bytes(pp_graph g) { return g ? kBcStates + kBcBatch * bc_layout(g->d.n).slab : 0; }
 
 PP_EXPORT pp_status pp_bc_run(pp_graph g, pp_dir fwd_dir, pp_dir bwd_dir, int32_t num_sources,
                               const int32_t* sources, double* bc, void* ws, size_t ws_bytes, void* stream) {
@@ -398,9 +471,12 @@ PP_EXPORT pp_status pp_bc_run(pp_graph g, pp_dir fwd_dir, pp_dir bwd_dir, int32_
     for (int32_t k = 0; k < num_sources; ++k)
         if (sources[k] < 0 || sources[k] >= n) return set_error(PP_E_RANGE, "source out of range");
     const BcLayout L = bc_layout(n);
-    if (ws_bytes < L.total) return set_error(PP_E_WORKSPACE, "BC workspace too small");
+    if (ws_bytes < kBcStates + L.slab) return set_error(PP_E_WORKSPACE, "BC workspace too small");
     if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return set_error(PP_E_RANGE, "ws must be 256-byte aligned");
+    // as many sources at once as the workspace holds, at most kBcBatch
+    const int32_t per_batch = (int32_t)std::min<size_t>(kBcBatch, (ws_bytes - kBcStates) / L.slab);
     char* w = static_cast<char*>(ws);
+    char* slab0 = w + kBcStates;
     BcArgs a;
     a.n = n;
     a.hot = std::min(n, kBcHot);
@@ -410,61 +486,59 @@ PP_EXPORT pp_status pp_bc_run(pp_graph g, pp_dir fwd_dir, pp_dir bwd_dir, int32_
     a.in_idx = g->d.csc_idx;
     a.perm = g->d.perm;
     a.iperm = g->d.iperm;
-    a.dist = reinterpret_cast<int32_t*>(w + L.dist);
-    a.sigma = reinterpret_cast<double*>(w + L.sigma);
-    a.delta = reinterpret_cast<double*>(w + L.delta);
-    a.order = reinterpret_cast<int32_t*>(w + L.order);
-    a.cnt = reinterpret_cast<int32_t*>(w + L.cnt);
-    a.st = reinterpret_cast<BcState*>(w + L.meta);
-    a.lvl_off = reinterpret_cast<int32_t*>(w + L.meta + sizeof(BcState));
+    a.dist = reinterpret_cast<int32_t*>(slab0 + L.dist);
+    a.sigma = reinterpret_cast<double*>(slab0 + L.sigma);
+    a.delta = reinterpret_cast<double*>(slab0 + L.delta);
+    a.order = reinterpret_cast<int32_t*>(slab0 + L.order);
+    a.cnt = reinterpret_cast<int32_t*>(slab0 + L.cnt);
+    a.lvl_off = reinterpret_cast<int32_t*>(slab0 + L.lvl_off);
+    a.st = reinterpret_cast<BcState*>(w);
+    a.stride = L.slab;
     a.bc = bc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int32_t vb = std::max(1, std::min(ceil_div(n, kBlock), 4096));
-    const int32_t eb = g->num_cu * 8;  // blocks of the backward frontier kernels (grid-stride)
-    // the pushing forward kernel: every workgroup zeroes and flushes its hot
-    // accumulators, so a few per compute unit
+    // per source: every pushing workgroup zeroes and flushes its hot
+    // accumulators, so a few per compute unit; the pulling kernels sweep
+    // vertex or level lists grid-stride
     const int32_t pb = std::max(1, std::min(ceil_div(n, kBlock), 2 * g->num_cu));
+    const int32_t fx = (fwd_dir == PP_PUSH) ? pb : vb;
+    const int32_t bx = (bwd_dir == PP_PUSH) ? pb : std::min(vb, 2 * g->num_cu);
     hipLaunchKernelGGL(k_bc_zero, dim3(vb), dim3(kBlock), 0, st, n, bc);
     PP_LAUNCH_CHECK("k_bc_zero");
-    // host copy of the state and level offsets
-    std::vector<int32_t> meta(sizeof(BcState) / 4 + (size_t)n + 2);
-    int32_t batch = 4;
-    for (int32_t k = 0; k < num_sources; ++k) {
-        hipLaunchKernelGGL(k_bc_init, dim3(vb), dim3(kBlock), 0, st, a, sources[k]);
-        // forward levels in batches; kernels past the last level return at once
-        int32_t launched = 0;
-        BcState hs{};
+    std::vector<BcState> hs(per_batch);
+    int32_t batch = 4;  // forward kernels per launch batch: one more than the last depth seen
+    for (int32_t k0 = 0; k0 < num_sources; k0 += per_batch) {
+        const int32_t cnt = std::min(per_batch, num_sources - k0);
+        BcSources src{};
+        for (int32_t i = 0; i < cnt; ++i) src.s[i] = sources[k0 + i];
+        hipLaunchKernelGGL(k_bc_init, dim3(vb, cnt), dim3(kBlock), 0, st, a, src);
+        // forward levels in batches; a source past its last level returns at once
+        int32_t launched = 0, depth = 0;
         for (;;) {
             for (int32_t i = 0; i < batch; ++i) {
-                if (fwd_dir == PP_PUSH) hipLaunchKernelGGL(k_bc_fwd_push, dim3(pb), dim3(kBlock), 0, st, a);
-                else hipLaunchKernelGGL(k_bc_fwd_pull, dim3(vb), dim3(kBlock), 0, st, a);
+                if (fwd_dir == PP_PUSH) hipLaunchKernelGGL(k_bc_fwd_push, dim3(fx, cnt), dim3(kBlock), 0, st, a);
+                else hipLaunchKernelGGL(k_bc_fwd_pull, dim3(fx, cnt), dim3(kBlock), 0, st, a);
             }
             PP_LAUNCH_CHECK("k_bc_fwd");
             launched += batch;
-            const size_t words = sizeof(BcState) / 4 + (size_t)std::min<int64_t>((int64_t)launched + 2, (int64_t)n + 2);
-            PP_HIP(hipMemcpyAsync(meta.data(), a.st, words * 4, hipMemcpyDeviceToHost, st));
+            PP_HIP(hipMemcpyAsync(hs.data(), a.st, sizeof(BcState) * cnt, hipMemcpyDeviceToHost, st));
             PP_HIP(hipStreamSynchronize(st));
-            std::memcpy(&hs, meta.data(), sizeof(BcState));
-            if (hs.done) break;
+            bool all = true;
+            depth = 0;
+            for (int32_t i = 0; i < cnt; ++i) {
+                all = all && hs[i].done;
+                depth = std::max(depth, hs[i].depth);
+            }
+            if (all || launched > n) break;
             batch = std::min(batch * 2, 64);
         }
-        // levels 0..D-1 are order[lvl_off[l], lvl_off[l+1]); the next source
-        // starts with a batch one longer than this one's depth
-        const int32_t D = hs.depth;
-        const int32_t* off = meta.data() + sizeof(BcState) / 4;
-        batch = std::max(2, D + 1);
-        for (int32_t l = D - 2; l >= 0; --l) {
-            if (bwd_dir == PP_PUSH) {
-                const int32_t lo = off[l + 1], hi = off[l + 2];
-                hipLaunchKernelGGL(k_bc_bwd_push, dim3(std::min(pb, ceil_div(hi - lo, kBlock) + 1)), dim3(kBlock), 0,
-                                   st, a, l, lo, hi);
-            } else {
-                const int32_t lo = off[l], hi = off[l + 1];
-                hipLaunchKernelGGL(k_bc_bwd_pull, dim3(std::min(eb, ceil_div(hi - lo, kBlock) + 1)), dim3(kBlock), 0,
-                                   st, a, l, lo, hi);
-            }
+        batch = std::max(2, depth + 1);
+        // backward levels D-2 .. 0 of each source, its state counting down
+        for (int32_t l = depth - 2; l >= 0; --l) {
+            if (bwd_dir == PP_PUSH) hipLaunchKernelGGL(k_bc_bwd_push, dim3(bx, cnt), dim3(kBlock), 0, st, a);
+            else hipLaunchKernelGGL(k_bc_bwd_pull, dim3(bx, cnt), dim3(kBlock), 0, st, a);
         }
-        hipLaunchKernelGGL(k_bc_acc, dim3(std::min(vb, ceil_div(off[D], kBlock) + 1)), dim3(kBlock), 0, st, a, off[D]);
+        hipLaunchKernelGGL(k_bc_acc, dim3(vb), dim3(kBlock), 0, st, a, src, cnt);
         PP_LAUNCH_CHECK("k_bc_bwd");
     }
     return PP_OK;

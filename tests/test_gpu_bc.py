@@ -73,3 +73,31 @@ def test_errors():
         pp.betweenness(g, [0], pp.PP_SWITCH, pp.PP_PULL)
     z = pp.betweenness(g, np.zeros(0, np.int32))
     assert torch.count_nonzero(z).item() == 0
+
+
+def test_source_batches_and_small_workspace():
+    # 70 sources run as batches of 32, 32 and 6; a workspace for a few
+    # sources at a time gives smaller batches and the same scores
+    from paper_2010_16012_amd import _lib
+
+    host = gg.workload("rmat14")
+    src = gg.pick_vertices(host, 70, seed=5)
+    want = oracle.bc(host.off, host.idx, src)
+    g = pp.Graph(host)
+    tol = dict(rtol=RTOL, atol=1e-9 * max(1.0, np.abs(want).max()))
+    for fd, bd in [(pp.PP_PULL, pp.PP_PULL), (pp.PP_PUSH, pp.PP_PUSH)]:
+        announce(f"bc rmat14 70 sources fwd={fd} bwd={bd}")
+        got = pp.betweenness(g, src, fd, bd)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(got.cpu().numpy(), want, **tol)
+    full = _lib.pp_bc_workspace_bytes(g.handle)
+    ws = torch.empty(full // 8, dtype=torch.uint8, device=g.device)
+    bc = torch.empty(g.n, dtype=torch.float64, device=g.device)
+    announce("bc rmat14 9 sources, workspace for four at a time")
+    _lib.pp_bc_run(g.handle, pp.PP_PULL, pp.PP_PUSH, src[:9], bc, ws)
+    torch.cuda.synchronize()
+    want9 = oracle.bc(host.off, host.idx, src[:9])
+    np.testing.assert_allclose(bc.cpu().numpy(), want9, rtol=RTOL, atol=1e-9 * max(1.0, np.abs(want9).max()))
+    with pytest.raises(pp.PPError):
+        _lib.pp_bc_run(g.handle, pp.PP_PULL, pp.PP_PULL, src[:2], bc, torch.empty(1024, dtype=torch.uint8,
+                                                                                   device=g.device))
