@@ -12,9 +12,11 @@ traverses nnz edges; a BFS traverses the undirected edges of the root's
 component (sum of reached degrees / 2).  Per-part rates are in "parts".
 
 The roofline object covers the pull sweep kernel: algorithmic bytes per launch
-(4*nnz + 16*n) over the average launch time measured with HIP
-events around the 20-step pull run.  The CPU baseline is the FP64 C oracle on
-a bounded sample (one PageRank step and two BFS roots).
+(4*nnz + 16*n: offsets, indices, gathered contributions, 1/d, next
+contributions) over the average launch time measured with HIP events around
+the 20-step pull run.  roofline_bfs_push does the same per top-down BFS run
+for the BFS level kernels (4*E + 8*R + 12*(R-1) bytes).  The CPU baseline is
+the FP64 C oracle on a bounded sample (one PageRank step and two BFS roots).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -135,8 +137,8 @@ def main():
     if args.counters_summary:
         return counters_summary(*args.counters_summary)
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sweep shards by vertex "
-              "ranges across GPUs, see DESIGN.md, but this build runs on one GPU only)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sweep would shard by "
+              "vertex ranges across GPUs; the library runs on one GPU)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import scipy.sparse as sp
@@ -243,6 +245,24 @@ def main():
                     "kernel": "k_pr_pull", "algorithmic_bytes_per_launch": algo,
                     "launch_us": round(t_launch * 1e6, 2)}
 
+    # The BFS level kernels take most of the step, but their work changes from
+    # level to level, so their roofline is stated per run: a top-down BFS
+    # examines every out-edge of every frontier vertex once, i.e. per run
+    # 4*E (indices) + 8*R (frontier offsets) + 12*(R-1) (level, parent, queue
+    # of every new vertex), with E the out-edges of the R reached vertices.
+    roofline_bfs = None
+    if "bfs_push" in parts:
+        tot = 0
+        for root in roots:  # outside the timed region: statistics only
+            st = runs["bfs_push"].run(int(root), pp.PP_PUSH, alpha, beta)
+            tot += 4 * st.edges_reached + 8 * st.reached + 12 * (st.reached - 1)
+        achieved = tot / (part_ms["bfs_push"] * 1e-3) / 1e9
+        roofline_bfs = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "k_bfs_level+k_bfs_chunks, top-down runs",
+                        "algorithmic_bytes_per_run": round(tot / len(roots)),
+                        "run_ms": round(part_ms["bfs_push"] / len(roots), 4)}
+
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
@@ -283,6 +303,7 @@ def main():
                    "n": n, "nnz": nnz, "parts": parts, "tuning": tuned or "defaults"},
         "parts": out_parts,
         "roofline": roofline,
+        "roofline_bfs_push": roofline_bfs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
