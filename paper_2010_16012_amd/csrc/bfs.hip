@@ -3,9 +3,11 @@
 // the per-level direction switch (Sec. 5 Generic-Switch, applied to BFS as in
 // the direction-optimising BFS the paper cites in Sec. 1).
 //
-// One kernel expands one level; top-down levels add a second kernel for the
-// chunks of very long rows.  Both forms leave the new frontier as a queue AND
-// a bitmap, so any sequence of directions works without conversions.
+// One kernel expands one level; a second kernel takes the chunks of very long
+// rows.  Both forms leave the new frontier as a queue AND a bitmap, so any
+// sequence of directions works without conversions.  A bottom-up level with
+// a sparse frontier streams the whole in-edge array instead of scanning row
+// by row (see level_bottom_up_stream).
 //
 // Contention design: a device-scope atomic on one address serialises across
 // the whole GPU, so no address is hit per edge or per wavefront step:
@@ -16,8 +18,8 @@
 //    starts on its own reserved page and takes no atomic until it is full;
 //    a top-down level leaves them unused, and its readers skip them;
 //  - frontier statistics are summed per workgroup, one atomic each;
-//  - top-down claims use one atomic OR on a 64-vertex visited word, tried
-//    only after a plain read shows the vertex unvisited.
+//  - top-down claims use one atomic OR on a 64-vertex visited word, tried,
+//    on large levels, only after a plain read shows the vertex unvisited.
 // Per-level statistics (|F|, out-edges of F, out-edges of unvisited
 // vertices) live in three rotating slots so the direction is chosen on the
 // device and the host only polls for termination.
@@ -28,6 +30,8 @@
 // prefix of the bitmap it tests -- the frontier (bottom-up; read-only during
 // the level) or the visited set (top-down; a snapshot that can only miss
 // bits set later, so a clear bit still goes to global memory) -- into LDS.
+// A sparse bottom-up frontier also gets an LDS summary with one bit per
+// bitmap word, so tests against empty words need no global load.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
