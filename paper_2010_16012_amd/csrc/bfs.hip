@@ -788,7 +788,7 @@ __device__ __forceinline__ void level_bottom_up_stream(const BfsArgs& a, int32_t
 #pragma unroll
         for (int r = 0; r < kStreamU; ++r) {
             const int64_t e = e0 + r * kWave + lane;
-            u[r] = (e < a.nnz) ? a.csc_idx[e] : -1;
+            u[r] = (e < a.nnz) ? __builtin_nontemporal_load(a.csc_idx + e) : -1;
         }
         bool hit[kStreamU];
         bool any = false;
@@ -1192,8 +1192,9 @@ PP_EXPORT pp_status pp_bfs_run(pp_graph g, int32_t root, pp_dir policy, float al
     // statistics come with it).  The first batch covers the previous run's
     // depth on this graph plus the empty level, so a run of similar depth
     // needs one host read.
-    constexpr int32_t kBatches[] = {4, 8, 12, 16, 24, 32, 48, 64};
-    int32_t batch = 64;
+    constexpr int32_t kBatches[] = {4, 8, 12, 16, 24, 32, 48, 64, 128, 256};
+    constexpr int32_t kMaxBatch = 256;  // deep graphs (grids) take long batches
+    int32_t batch = kMaxBatch;
     for (int32_t b : kBatches)
         if (b >= g->bfs_last_levels + 2) {
             batch = b;
@@ -1218,7 +1219,7 @@ PP_EXPORT pp_status pp_bfs_run(pp_graph g, int32_t root, pp_dir policy, float al
         s = read_hdr(g, state, &h, st);
         if (s != PP_OK) return s;
         if (h.finished || launched >= max_levels) break;
-        batch = std::min<int32_t>(batch * 2, 64);
+        batch = std::min<int32_t>(batch * 2, kMaxBatch);
     }
     g->bfs_last_levels = h.levels;
     if (stats) {
