@@ -23,6 +23,11 @@ constexpr int kMultiBlock = 1024;
 constexpr int kMultiGroup = 8;  // lanes per row
 constexpr int kMultiU = 8;      // index loads in flight per lane
 constexpr int32_t kMultiMaxN = 16384;
+// PageRank rows at least kMultiBig long get a whole wavefront each (up to
+// kMultiBigCap of them per graph); eight lanes per row would leave the
+// wavefront holding the hubs running long after the others.
+constexpr int32_t kMultiBig = 512;
+constexpr int32_t kMultiBigCap = 512;
 
 struct MultiEntry {
     int64_t vbase;  // first vertex of the graph in the vertex arenas (x, level, parent)
@@ -69,10 +74,30 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
     const int lane = tid % kMultiGroup;
     const int grp = tid / kMultiGroup;
     constexpr int groups = kMultiBlock / kMultiGroup;
+    constexpr int kWaves = kMultiBlock / kWave;
+    const int wl = tid & (kWave - 1), wv = tid / kWave;
+    // PageRank rows of 8-lane groups: consecutive rows go to different
+    // wavefronts (row 16 q' + w for wavefront w, group q of it, q' = q + 8 k),
+    // so neighbouring ids -- the hubs of an R-MAT graph -- are spread out
+    const int32_t row0 = kWaves * ((tid % kWave) / kMultiGroup) + wv;
 
     // ---------------------------------------------------------------- PageRank
+    __shared__ int32_t s_big[kMultiBigCap];
+    __shared__ int32_t s_nbig;
     if (a.pr_iters > 0) {
         const float base = (1.0f - a.f) / (float)n;
+        // the long rows of the sweep's direction (in-rows pull, out-rows push)
+        const int32_t* roff = (a.pr_dir == PP_PULL) ? in_off : off;
+        if (tid == 0) s_nbig = 0;
+        __syncthreads();
+        for (int32_t u = tid; u < n; u += kMultiBlock)
+            if (roff[u + 1] - roff[u] >= kMultiBig) {
+                const int32_t at = atomicAdd(&s_nbig, 1);
+                if (at < kMultiBigCap) s_big[at] = u;
+            }
+        __syncthreads();
+        // more long rows than the list holds: all rows stay with the groups
+        const int32_t nbig = (s_nbig <= kMultiBigCap) ? s_nbig : 0;
         if (a.pr_dir == PP_PULL) {
             float* s_c = lds;       // contributions of the current iterate
             float* s_y = lds + n;   // contributions of the next one
@@ -83,10 +108,42 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
             __syncthreads();
             for (int32_t t = 0; t < a.pr_iters; ++t) {
                 const bool last = (t == a.pr_iters - 1);
-                // owner of u gathers over its in-row (compensated sum per lane)
-                for (int32_t u = grp; u < n; u += groups) {
+                // long in-rows: a whole wavefront each (compensated sum per lane)
+                for (int32_t i = wv; i < nbig; i += kWaves) {
+                    const int32_t u = s_big[i];
                     float acc = 0.f, comp = 0.f;
                     const int32_t rb = in_off[u], re = in_off[u + 1];
+                    for (int32_t j0 = rb + wl; j0 < re; j0 += kMultiU * kWave) {
+                        int32_t ii[kMultiU];
+#pragma unroll
+                        for (int k = 0; k < kMultiU; ++k) {
+                            const int32_t j = j0 + k * kWave;
+                            ii[k] = j < re ? in_idx[j] : -1;
+                        }
+#pragma unroll
+                        for (int k = 0; k < kMultiU; ++k) {
+                            if (ii[k] < 0) break;
+                            const float yk = s_c[ii[k]] - comp;
+                            const float tk = acc + yk;
+                            comp = (tk - acc) - yk;
+                            acc = tk;
+                        }
+                    }
+#pragma unroll
+                    for (int s = kWave / 2; s > 0; s >>= 1) acc += __shfl_xor(acc, s);
+                    if (wl == 0) {
+                        const float y = base + acc;
+                        const int32_t d = off[u + 1] - off[u];
+                        s_y[u] = d > 0 ? a.f * y / (float)d : 0.f;
+                        if (last) a.x[e.vbase + u] = y;
+                    }
+                }
+                // other rows: owner of u gathers over its in-row (compensated
+                // sum per lane), 8 lanes per row
+                for (int32_t u = row0; u < n; u += groups) {
+                    float acc = 0.f, comp = 0.f;
+                    const int32_t rb = in_off[u], re = in_off[u + 1];
+                    if (nbig > 0 && re - rb >= kMultiBig) continue;  // group-uniform
                     for (int32_t j0 = rb + lane; j0 < re; j0 += kMultiU * kMultiGroup) {
                         int32_t ii[kMultiU];  // independent loads first, then the adds in order
 #pragma unroll
@@ -131,10 +188,29 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
             __syncthreads();
             for (int32_t t = 0; t < a.pr_iters; ++t) {
                 const bool last = (t == a.pr_iters - 1);
-                for (int32_t v = grp; v < n; v += groups) {
+                // long out-rows: a whole wavefront each
+                for (int32_t i = wv; i < nbig; i += kWaves) {
+                    const int32_t v = s_big[i];
                     const float cv = c[v];
                     if (cv == 0.f) continue;
                     const int32_t rb = off[v], re = off[v + 1];
+                    for (int32_t j0 = rb + wl; j0 < re; j0 += kMultiU * kWave) {
+                        int32_t ii[kMultiU];
+#pragma unroll
+                        for (int k = 0; k < kMultiU; ++k) {
+                            const int32_t j = j0 + k * kWave;
+                            ii[k] = j < re ? idx[j] : -1;
+                        }
+#pragma unroll
+                        for (int k = 0; k < kMultiU; ++k)
+                            if (ii[k] >= 0) atomicAdd(&s_acc[ii[k]], (double)cv);
+                    }
+                }
+                for (int32_t v = row0; v < n; v += groups) {
+                    const float cv = c[v];
+                    if (cv == 0.f) continue;
+                    const int32_t rb = off[v], re = off[v + 1];
+                    if (nbig > 0 && re - rb >= kMultiBig) continue;
                     for (int32_t j0 = rb + lane; j0 < re; j0 += kMultiU * kMultiGroup) {
                         int32_t ii[kMultiU];
 #pragma unroll
