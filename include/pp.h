@@ -268,18 +268,23 @@ size_t pp_multi_workspace_bytes(int32_t num_graphs, int64_t total_vertices);
  * vertices (1..16384) and graph_nnz[i] stored edges (HOST arrays).  Arenas
  * (device): off/in_off hold each graph's n+1 local offsets back to back (CSR
  * = out-adjacency, CSC = in-adjacency; may alias for symmetric graphs);
- * idx/in_idx each graph's local neighbour ids back to back; x (float),
+ * idx/in_idx each graph's local neighbour ids back to back as uint16 (a
+ * graph has at most 16384 vertices, so 16 bits hold every id; half the
+ * bytes of int32 ids per sweep); every id must lie below its graph's n
+ * (not checked: the BFS skips larger ids, PageRank results are then
+ * undefined); x (float),
  * level and parent (int32) each graph's n entries back to back.  Runs
  * pr_iters Jacobi steps of the PageRank equation (Sec. 3.1; x_0 = 1/n) in
  * direction pr_dir, then, unless bfs_policy is -1, a BFS from local vertex
  * bfs_root of every graph with policy PP_PUSH / PP_PULL / PP_SWITCH
  * (alpha, beta as in pp_bfs_run).  One workgroup holds one graph's state in
  * LDS: pull gathers and push updates are LDS operations and the barrier
- * between sweeps is a workgroup barrier.  Pull sums with compensated FP32
- * additions; push accumulates in FP64 LDS atomics.  Graphs are taken largest
- * first.  SYNC. */
+ * between sweeps is a workgroup barrier.  Pull sums every row in FP64 (per
+ * lane in slot order, then a fixed lane reduction), so results are
+ * bit-reproducible; push accumulates in FP64 LDS atomics.  Graphs are taken
+ * largest first.  SYNC. */
 pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, const int64_t* graph_nnz,
-                       const int32_t* off, const int32_t* idx, const int32_t* in_off, const int32_t* in_idx,
+                       const int32_t* off, const uint16_t* idx, const int32_t* in_off, const uint16_t* in_idx,
                        pp_dir pr_dir, int32_t pr_iters, float f, float* x,
                        int32_t bfs_policy, int32_t bfs_root, float alpha, float beta,
                        int32_t* level, int32_t* parent, void* ws, size_t ws_bytes, void* stream);

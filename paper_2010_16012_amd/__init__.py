@@ -231,16 +231,22 @@ class MultiGraph:
         self.n = np.array([h.n for h in hosts], dtype=np.int32)
         self.nnz = np.array([int(h.off[-1]) for h in hosts], dtype=np.int64)
         dev = torch.device(device)
+        for h in hosts:
+            for ids in (h.idx, getattr(h, "in_idx", None)):
+                if ids is not None and len(ids) and (int(ids.min()) < 0 or int(ids.max()) >= h.n):
+                    raise PPError(PP_E_GRAPH, f"{getattr(h, 'name', 'graph')}: neighbour id outside 0..n-1")
         cat = lambda arrs: torch.as_tensor(np.concatenate(arrs).astype(np.int32)).to(dev)  # noqa: E731
+        # local ids as 16 bits (graphs hold at most 16384 vertices); int16 storage, read as uint16
+        cat16 = lambda arrs: torch.as_tensor(np.concatenate(arrs).astype(np.int16)).to(dev)  # noqa: E731
         self.off = cat([h.off for h in hosts])
-        self.idx = cat([h.idx for h in hosts] + [np.zeros(1, np.int32)])
+        self.idx = cat16([h.idx for h in hosts] + [np.zeros(1, np.int16)])
         directed = [h for h in hosts if getattr(h, "in_off", None) is not None and h.in_off is not h.off]
         if directed:
             for h in hosts:
                 if getattr(h, "in_off", None) is None:
                     h.ensure_transpose()
             self.in_off = cat([h.in_off for h in hosts])
-            self.in_idx = cat([h.in_idx for h in hosts] + [np.zeros(1, np.int32)])
+            self.in_idx = cat16([h.in_idx for h in hosts] + [np.zeros(1, np.int16)])
         else:
             self.in_off, self.in_idx = self.off, self.idx
         self.total_n = int(self.n.sum())

@@ -22,6 +22,7 @@ namespace pp {
 constexpr int kMultiBlock = 1024;
 constexpr int kMultiGroup = 8;  // lanes per row
 constexpr int kMultiU = 8;      // index loads in flight per lane
+constexpr int kMultiPullU = 8;  // slots per lane and round of a pull row
 constexpr int32_t kMultiMaxN = 16384;
 // PageRank rows at least kMultiBig long get a whole wavefront each (up to
 // kMultiBigCap of them per graph); eight lanes per row would leave the
@@ -41,9 +42,9 @@ struct MultiArgs {
     const MultiEntry* table;  // LPT order
     int32_t count;
     const int32_t* off;       // per graph: n+1 local offsets, graphs back to back
-    const int32_t* idx;       // local vertex ids
+    const uint16_t* idx;      // local vertex ids (below 16384, so 16 bits hold them)
     const int32_t* in_off;
-    const int32_t* in_idx;
+    const uint16_t* in_idx;
     int32_t pr_dir;
     int32_t pr_iters;
     float f;
@@ -58,6 +59,29 @@ struct MultiArgs {
 
 __device__ __forceinline__ uint32_t bit_of(const uint32_t* bm, int32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
 
+// U slots j0, j0 + STRIDE, ... of a row ending at re (j0 < re) added to an
+// FP64 sum in slot order.  The index loads are clamped to the row's last
+// slot and the LDS gathers issued together, so neither waits on the one
+// before; slots past the row's end read the zero word s_zero.
+template <int STRIDE, int U, typename I>
+__device__ __forceinline__ void gather_row_slots(const I* __restrict__ ids, const float* s_c, const float* s_zero,
+                                                 int32_t j0, int32_t re, double& acc) {
+    const char* base = reinterpret_cast<const char*>(ids);
+    const float* src[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const int32_t j = j0 + k * STRIDE;
+        const uint32_t boff = (uint32_t)min(j, re - 1) * (uint32_t)sizeof(I);
+        const uint32_t id = *reinterpret_cast<const I*>(base + boff);
+        src[k] = j < re ? s_c + id : s_zero;
+    }
+    float cv[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) cv[k] = *src[k];
+#pragma unroll
+    for (int k = 0; k < U; ++k) acc += (double)cv[k];
+}
+
 __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
     extern __shared__ float lds[];
     __shared__ int32_t s_cnt[4];
@@ -67,9 +91,9 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
     const MultiEntry e = a.table[gi];
     const int32_t n = e.n;
     const int32_t* off = a.off + e.obase;
-    const int32_t* idx = a.idx + e.ebase;
+    const uint16_t* idx = a.idx + e.ebase;
     const int32_t* in_off = a.in_off + e.obase;
-    const int32_t* in_idx = a.in_idx + e.ebase;
+    const uint16_t* in_idx = a.in_idx + e.ebase;
     const int tid = threadIdx.x;
     const int lane = tid % kMultiGroup;
     const int grp = tid / kMultiGroup;
@@ -84,11 +108,15 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
     // ---------------------------------------------------------------- PageRank
     __shared__ int32_t s_big[kMultiBigCap];
     __shared__ int32_t s_nbig;
+    __shared__ float s_zero;
     if (a.pr_iters > 0) {
         const float base = (1.0f - a.f) / (float)n;
         // the long rows of the sweep's direction (in-rows pull, out-rows push)
         const int32_t* roff = (a.pr_dir == PP_PULL) ? in_off : off;
-        if (tid == 0) s_nbig = 0;
+        if (tid == 0) {
+            s_nbig = 0;
+            s_zero = 0.f;
+        }
         __syncthreads();
         for (int32_t u = tid; u < n; u += kMultiBlock)
             if (roff[u + 1] - roff[u] >= kMultiBig) {
@@ -108,63 +136,49 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
             __syncthreads();
             for (int32_t t = 0; t < a.pr_iters; ++t) {
                 const bool last = (t == a.pr_iters - 1);
-                // long in-rows: a whole wavefront each (compensated sum per lane)
+                // long in-rows: a whole wavefront each (FP64 sum per lane)
                 for (int32_t i = wv; i < nbig; i += kWaves) {
                     const int32_t u = s_big[i];
-                    float acc = 0.f, comp = 0.f;
+                    double acc = 0.0;
                     const int32_t rb = in_off[u], re = in_off[u + 1];
-                    for (int32_t j0 = rb + wl; j0 < re; j0 += kMultiU * kWave) {
-                        int32_t ii[kMultiU];
-#pragma unroll
-                        for (int k = 0; k < kMultiU; ++k) {
-                            const int32_t j = j0 + k * kWave;
-                            ii[k] = j < re ? in_idx[j] : -1;
-                        }
-#pragma unroll
-                        for (int k = 0; k < kMultiU; ++k) {
-                            if (ii[k] < 0) break;
-                            const float yk = s_c[ii[k]] - comp;
-                            const float tk = acc + yk;
-                            comp = (tk - acc) - yk;
-                            acc = tk;
-                        }
-                    }
+                    for (int32_t j0 = rb + wl; j0 < re; j0 += kMultiU * kWave)
+                        gather_row_slots<kWave, kMultiU>(in_idx, s_c, &s_zero, j0, re, acc);
 #pragma unroll
                     for (int s = kWave / 2; s > 0; s >>= 1) acc += __shfl_xor(acc, s);
                     if (wl == 0) {
-                        const float y = base + acc;
+                        const float y = (float)((double)base + acc);
                         const int32_t d = off[u + 1] - off[u];
                         s_y[u] = d > 0 ? a.f * y / (float)d : 0.f;
                         if (last) a.x[e.vbase + u] = y;
                     }
                 }
-                // other rows: owner of u gathers over its in-row (compensated
-                // sum per lane), 8 lanes per row
+                // other rows: the group owning u gathers over its in-row (FP64
+                // sum per lane, 8 lanes per row); the offsets and out-degree of
+                // the group's next row load while this row is summed
+                int32_t nrb = 0, nre = 0, nob = 0, noe = 0;
+                if (row0 < n) {
+                    nrb = in_off[row0];
+                    nre = in_off[row0 + 1];
+                    nob = off[row0];
+                    noe = off[row0 + 1];
+                }
                 for (int32_t u = row0; u < n; u += groups) {
-                    float acc = 0.f, comp = 0.f;
-                    const int32_t rb = in_off[u], re = in_off[u + 1];
-                    if (nbig > 0 && re - rb >= kMultiBig) continue;  // group-uniform
-                    for (int32_t j0 = rb + lane; j0 < re; j0 += kMultiU * kMultiGroup) {
-                        int32_t ii[kMultiU];  // independent loads first, then the adds in order
-#pragma unroll
-                        for (int k = 0; k < kMultiU; ++k) {
-                            const int32_t j = j0 + k * kMultiGroup;
-                            ii[k] = j < re ? in_idx[j] : -1;
-                        }
-#pragma unroll
-                        for (int k = 0; k < kMultiU; ++k) {
-                            if (ii[k] < 0) break;
-                            const float yk = s_c[ii[k]] - comp;
-                            const float tk = acc + yk;
-                            comp = (tk - acc) - yk;
-                            acc = tk;
-                        }
+                    double acc = 0.0;
+                    const int32_t rb = nrb, re = nre, ob = nob, oe = noe;
+                    if (u + groups < n) {
+                        nrb = in_off[u + groups];
+                        nre = in_off[u + groups + 1];
+                        nob = off[u + groups];
+                        noe = off[u + groups + 1];
                     }
+                    if (nbig > 0 && re - rb >= kMultiBig) continue;  // group-uniform
+                    for (int32_t j0 = rb + lane; j0 < re; j0 += kMultiPullU * kMultiGroup)
+                        gather_row_slots<kMultiGroup, kMultiPullU>(in_idx, s_c, &s_zero, j0, re, acc);
 #pragma unroll
                     for (int s = kMultiGroup / 2; s > 0; s >>= 1) acc += __shfl_xor(acc, s);
                     if (lane == 0) {
-                        const float y = base + acc;
-                        const int32_t d = off[u + 1] - off[u];
+                        const float y = (float)((double)base + acc);
+                        const int32_t d = oe - ob;
                         s_y[u] = d > 0 ? a.f * y / (float)d : 0.f;
                         if (last) a.x[e.vbase + u] = y;
                     }
@@ -206,21 +220,32 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                             if (ii[k] >= 0) atomicAdd(&s_acc[ii[k]], (double)cv);
                     }
                 }
+                // the contribution and offsets of the group's next row load
+                // while this row is scattered
+                float ncv = 0.f;
+                int32_t nb = 0, ne = 0;
+                if (row0 < n) {
+                    ncv = c[row0];
+                    nb = off[row0];
+                    ne = off[row0 + 1];
+                }
                 for (int32_t v = row0; v < n; v += groups) {
-                    const float cv = c[v];
+                    const float cv = ncv;
+                    const int32_t rb = nb, re = ne;
+                    if (v + groups < n) {
+                        ncv = c[v + groups];
+                        nb = off[v + groups];
+                        ne = off[v + groups + 1];
+                    }
                     if (cv == 0.f) continue;
-                    const int32_t rb = off[v], re = off[v + 1];
                     if (nbig > 0 && re - rb >= kMultiBig) continue;
                     for (int32_t j0 = rb + lane; j0 < re; j0 += kMultiU * kMultiGroup) {
-                        int32_t ii[kMultiU];
+                        int32_t ii[kMultiU];  // clamped to the row's last slot
 #pragma unroll
-                        for (int k = 0; k < kMultiU; ++k) {
-                            const int32_t j = j0 + k * kMultiGroup;
-                            ii[k] = j < re ? idx[j] : -1;
-                        }
+                        for (int k = 0; k < kMultiU; ++k) ii[k] = (int32_t)idx[min(j0 + k * kMultiGroup, re - 1)];
 #pragma unroll
                         for (int k = 0; k < kMultiU; ++k)
-                            if (ii[k] >= 0) atomicAdd(&s_acc[ii[k]], (double)cv);
+                            if (j0 + k * kMultiGroup < re) atomicAdd(&s_acc[ii[k]], (double)cv);
                     }
                 }
                 __syncthreads();
@@ -295,7 +320,7 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
 #pragma unroll
                     for (int k = 0; k < kMultiU; ++k) {
                         const int32_t u = ii[k];
-                        if (u < 0) continue;
+                        if (u < 0 || u >= n) continue;  // ids past the graph are ignored
                         const uint32_t b = 1u << (u & 31);
                         if (s_vis[u >> 5] & b) continue;
                         const uint32_t old = atomicOr(&s_vis[u >> 5], b);
@@ -384,8 +409,8 @@ PP_EXPORT size_t pp_multi_workspace_bytes(int32_t num_graphs, int64_t total_vert
 }
 
 PP_EXPORT pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, const int64_t* graph_nnz,
-                                 const int32_t* off, const int32_t* idx, const int32_t* in_off,
-                                 const int32_t* in_idx, pp_dir pr_dir, int32_t pr_iters, float f, float* x,
+                                 const int32_t* off, const uint16_t* idx, const int32_t* in_off,
+                                 const uint16_t* in_idx, pp_dir pr_dir, int32_t pr_iters, float f, float* x,
                                  int32_t bfs_policy, int32_t bfs_root, float alpha, float beta, int32_t* level,
                                  int32_t* parent, void* ws, size_t ws_bytes, void* stream) {
     clear_error();

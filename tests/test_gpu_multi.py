@@ -59,6 +59,11 @@ def test_size_limit_and_errors():
     mg = pp.MultiGraph([H.path(5)])
     with pytest.raises(pp.PPError):
         mg.run(bfs_root=7)
+    bad = H.path(5)
+    bad.idx = bad.idx.copy()
+    bad.idx[3] = 5  # an id past the graph's last vertex
+    with pytest.raises(pp.PPError):
+        pp.MultiGraph([bad])
 
 
 @pytest.mark.slow
