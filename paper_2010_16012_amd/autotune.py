@@ -185,11 +185,11 @@ def main():
             cache = json.load(fh)
     k = key(host.n, host.nnz)
     only = set(filter(None, a.only.split(",")))
+    cfg = dict(cache.get(k, {})) if only else {}
     if only:
-        cfg = dict(cache.get(k, {}))
         apply(cfg)
     if not only or "pagerank" in only:
-        cfg = tune_pagerank(host, base=tune_bins(host))
+        cfg.update(tune_pagerank(host, base=tune_bins(host)))
     if not only or "bfs" in only:
         cfg.update(tune_bfs_switch(host, gg.pick_vertices(host, a.roots, seed=1)))
     if a.ppr_k and (not only or "ppr" in only):

@@ -158,26 +158,75 @@ __device__ __forceinline__ int wave_unit_bin(const int32_t* wo, int32_t u) {
     return b;
 }
 
-// Unit lu of bin `bin`: kWave/G rows, G lanes each, U loads per lane.
+// What a lane needs to run one wavefront unit of the pull sweep.  Bins 0-4:
+// the row of the lane's group (-1 past the bin's end), its slot range and
+// 1/s of the row (for the next contribution).  Bin 5: the chunk's row and
+// slot range.
+struct PullTask {
+    int32_t bin;  // -1: no unit
+    int32_t lu;   // unit within its bin
+    int32_t row;
+    int32_t b, e;
+    float inv_s;
+};
+
+// First stage of a unit: its bin and the row from the bin's vertex list (or
+// the chunk's row from the chunk table).
+__device__ __forceinline__ PullTask pull_task(const PullArgs& a, int32_t unit, int lane) {
+    PullTask t{-1, 0, -1, 0, 0, 0.f};
+    if (unit >= a.units) return t;
+    t.bin = wave_unit_bin(a.wave_off, unit);
+    t.lu = unit - a.wave_off[t.bin];
+    if (t.bin == PP_NUM_BINS - 1) {
+        t.row = a.tab[t.lu];
+    } else {
+        int g = kPullLanes[0];
+#pragma unroll
+        for (int b = 1; b < PP_NUM_BINS - 1; ++b)
+            if (t.bin == b) g = kPullLanes[b];
+        const int32_t i = t.lu * (kWave / g) + lane / g;
+        const int32_t count = a.sp.list_off[t.bin + 1] - a.sp.list_off[t.bin];
+        t.row = (i < count) ? a.list[a.sp.list_off[t.bin] + i] : -1;
+    }
+    return t;
+}
+
+// Second stage: the slot range (and, bins 0-4, 1/s of the row).
+__device__ __forceinline__ void pull_bounds(const PullArgs& a, PullTask& t) {
+    if (t.bin == PP_NUM_BINS - 1) {
+        t.b = a.tab[a.tab_cap + t.lu];
+        t.e = a.tab[2 * a.tab_cap + t.lu];
+    } else if (t.bin >= 0 && t.row >= 0) {
+        t.b = a.off[t.row];
+        t.e = a.off[t.row + 1];
+        if (a.c_next) t.inv_s = a.inv_s[t.row];
+    }
+}
+
+// Unit of bin BIN (0-4): kWave/G rows, G lanes each, U loads per lane.
 template <int BIN, bool W, bool HOT>
-__device__ __forceinline__ void pull_unit(const PullArgs& a, int32_t lu, int lane, const float* s_c) {
+__device__ __forceinline__ void pull_unit(const PullArgs& a, const PullTask& t, int lane, const float* s_c) {
     constexpr int G = kPullLanes[BIN];
     constexpr int U = kPullLoads[BIN];
-    const int32_t i = lu * (kWave / G) + lane / G;
-    const int32_t count = a.sp.list_off[BIN + 1] - a.sp.list_off[BIN];
-    if (i >= count) return;  // whole groups leave together
-    const int32_t u = a.list[a.sp.list_off[BIN] + i];
-    if (u < a.skip_below) return;  // likewise
+    if (t.row < 0 || t.row < a.skip_below) return;  // whole groups leave together
     const int gl = lane & (G - 1);
-    float acc = gather_row<G, U, W, HOT>(a.idx, a.wt, a.c, a.off[u], a.off[u + 1], gl, s_c, a.hot);
+    float acc = gather_row<G, U, W, HOT>(a.idx, a.wt, a.c, t.b, t.e, gl, s_c, a.hot);
     acc = group_reduce<G>(acc);
-    if (gl == 0) pull_finish(a, u, acc);
+    if (gl == 0) {
+        const float yv = a.base + acc;
+        if (a.y) a.y[user_id(a.perm, t.row)] = yv;
+        if (a.c_next) a.c_next[t.row] = a.f * yv * t.inv_s;
+    }
 }
 
 // Persistent pull sweep: every workgroup first copies c[0, hot) -- the
 // contributions of the heaviest vertices, which most gathers hit -- into
 // LDS, then its wavefronts take units w, w + W, ... (W = wavefronts in the
-// grid).  No atomics: every output has exactly one writer.
+// grid).  No atomics: every output has exactly one writer.  The units of a
+// wavefront are pipelined: while unit t gathers, the row bounds of unit
+// t + W and the list entry of unit t + 2W are already on their way, so a
+// unit waits for two memory round trips (indices, then gathers) instead of
+// four.
 template <bool W, bool HOT>
 __global__ __launch_bounds__(1024) void k_pr_pull(PullArgs a) {
     extern __shared__ float s_c[];
@@ -187,23 +236,30 @@ __global__ __launch_bounds__(1024) void k_pr_pull(PullArgs a) {
     }
     const int lane = threadIdx.x & (kWave - 1);
     const int32_t nw = gridDim.x * (blockDim.x / kWave);
-    for (int32_t unit = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; unit < a.units; unit += nw) {
-        const int bin = wave_unit_bin(a.wave_off, unit);
-        const int32_t lu = unit - a.wave_off[bin];
-        switch (bin) {
+    // the unit number is wavefront-uniform: keep it (and the bin) in scalar registers
+    const int32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+    PullTask next = pull_task(a, first, lane);
+    pull_bounds(a, next);
+    PullTask after = pull_task(a, first + nw, lane);
+    for (int32_t unit = first; unit < a.units; unit += nw) {
+        const PullTask t = next;
+        next = after;
+        pull_bounds(a, next);
+        after = pull_task(a, unit + 2 * nw, lane);
+        switch (t.bin) {
             case 5: {  // one chunk of a very long row -> partial sum, finished by k_pr_pull_fix
-                if (a.tab[lu] < a.skip_below) break;
-                const int32_t b = a.tab[a.tab_cap + lu], e = a.tab[2 * a.tab_cap + lu];
-                float acc = gather_row<kPullLanes[5], kPullLoads[5], W, HOT>(a.idx, a.wt, a.c, b, e, lane, s_c, a.hot);
+                if (t.row < a.skip_below) break;
+                float acc =
+                    gather_row<kPullLanes[5], kPullLoads[5], W, HOT>(a.idx, a.wt, a.c, t.b, t.e, lane, s_c, a.hot);
                 acc = group_reduce<kWave>(acc);
-                if (lane == 0) a.part[lu] = acc;
+                if (lane == 0) a.part[t.lu] = acc;
                 break;
             }
-            case 4: pull_unit<4, W, HOT>(a, lu, lane, s_c); break;
-            case 3: pull_unit<3, W, HOT>(a, lu, lane, s_c); break;
-            case 2: pull_unit<2, W, HOT>(a, lu, lane, s_c); break;
-            case 1: pull_unit<1, W, HOT>(a, lu, lane, s_c); break;
-            default: pull_unit<0, W, HOT>(a, lu, lane, s_c); break;
+            case 4: pull_unit<4, W, HOT>(a, t, lane, s_c); break;
+            case 3: pull_unit<3, W, HOT>(a, t, lane, s_c); break;
+            case 2: pull_unit<2, W, HOT>(a, t, lane, s_c); break;
+            case 1: pull_unit<1, W, HOT>(a, t, lane, s_c); break;
+            default: pull_unit<0, W, HOT>(a, t, lane, s_c); break;
         }
     }
 }
