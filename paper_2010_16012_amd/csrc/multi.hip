@@ -220,32 +220,56 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                             if (ii[k] >= 0) atomicAdd(&s_acc[ii[k]], (double)cv);
                     }
                 }
-                // the contribution and offsets of the group's next row load
-                // while this row is scattered
-                float ncv = 0.f;
-                int32_t nb = 0, ne = 0;
-                if (row0 < n) {
-                    ncv = c[row0];
-                    nb = off[row0];
-                    ne = off[row0 + 1];
-                }
-                for (int32_t v = row0; v < n; v += groups) {
-                    const float cv = ncv;
-                    const int32_t rb = nb, re = ne;
-                    if (v + groups < n) {
-                        ncv = c[v + groups];
-                        nb = off[v + groups];
-                        ne = off[v + groups + 1];
+                // two rows per group and round (v and v + groups), their index
+                // loads issued together; the contributions and offsets of the
+                // group's next two rows load while these are scattered
+                float pc[2];
+                int32_t pb[2], pe[2];
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int32_t w = row0 + r * groups;
+                    pc[r] = 0.f;
+                    pb[r] = pe[r] = 0;
+                    if (w < n) {
+                        pc[r] = c[w];
+                        pb[r] = off[w];
+                        pe[r] = off[w + 1];
                     }
-                    if (cv == 0.f) continue;
-                    if (nbig > 0 && re - rb >= kMultiBig) continue;
-                    for (int32_t j0 = rb + lane; j0 < re; j0 += kMultiU * kMultiGroup) {
-                        int32_t ii[kMultiU];  // clamped to the row's last slot
+                }
+                for (int32_t v = row0; v < n; v += 2 * groups) {
+                    float cv[2];
+                    int32_t rb[2], re[2];
 #pragma unroll
-                        for (int k = 0; k < kMultiU; ++k) ii[k] = (int32_t)idx[min(j0 + k * kMultiGroup, re - 1)];
+                    for (int r = 0; r < 2; ++r) {
+                        cv[r] = pc[r];
+                        rb[r] = pb[r];
+                        re[r] = pe[r];
+                        const int32_t w = v + (2 + r) * groups;
+                        if (w < n) {
+                            pc[r] = c[w];
+                            pb[r] = off[w];
+                            pe[r] = off[w + 1];
+                        }
+                        // nothing to scatter here: past the graph, a zero
+                        // contribution, or a long row (done above)
+                        if (v + r * groups >= n || cv[r] == 0.f || (nbig > 0 && re[r] - rb[r] >= kMultiBig))
+                            re[r] = rb[r];
+                    }
+                    const int32_t len = max(re[0] - rb[0], re[1] - rb[1]);
+                    for (int32_t d = lane; d < len; d += kMultiU * kMultiGroup) {
+                        // clamped into [0, re - 1]: a finished or empty row
+                        // rereads a valid slot (the graph has edges, or len = 0)
+                        int32_t ii[2][kMultiU];
 #pragma unroll
-                        for (int k = 0; k < kMultiU; ++k)
-                            if (j0 + k * kMultiGroup < re) atomicAdd(&s_acc[ii[k]], (double)cv);
+                        for (int r = 0; r < 2; ++r)
+#pragma unroll
+                            for (int k = 0; k < kMultiU; ++k)
+                                ii[r][k] = idx[(uint32_t)max(min(rb[r] + d + k * kMultiGroup, re[r] - 1), 0)];
+#pragma unroll
+                        for (int r = 0; r < 2; ++r)
+#pragma unroll
+                            for (int k = 0; k < kMultiU; ++k)
+                                if (rb[r] + d + k * kMultiGroup < re[r]) atomicAdd(&s_acc[ii[r][k]], (double)cv[r]);
                     }
                 }
                 __syncthreads();
