@@ -335,18 +335,21 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                 if (!bit_of(s_front, v)) continue;
                 const int32_t rb = off[v], re = off[v + 1];
                 for (int32_t j0 = rb + lane; j0 < re; j0 += kMultiU * kMultiGroup) {
+                    // index loads clamped to the row's last slot, then every
+                    // visited probe issued before the first claim (a probe only
+                    // filters: the atomic OR decides)
                     int32_t ii[kMultiU];
 #pragma unroll
-                    for (int k = 0; k < kMultiU; ++k) {
-                        const int32_t j = j0 + k * kMultiGroup;
-                        ii[k] = j < re ? idx[j] : -1;
-                    }
+                    for (int k = 0; k < kMultiU; ++k) ii[k] = idx[(uint32_t)min(j0 + k * kMultiGroup, re - 1)];
+                    uint32_t seen[kMultiU];
+#pragma unroll
+                    for (int k = 0; k < kMultiU; ++k) seen[k] = s_vis[min(ii[k], n - 1) >> 5];
 #pragma unroll
                     for (int k = 0; k < kMultiU; ++k) {
                         const int32_t u = ii[k];
-                        if (u < 0 || u >= n) continue;  // ids past the graph are ignored
+                        if (j0 + k * kMultiGroup >= re || u >= n) continue;  // ids past the graph are ignored
                         const uint32_t b = 1u << (u & 31);
-                        if (s_vis[u >> 5] & b) continue;
+                        if (seen[k] & b) continue;
                         const uint32_t old = atomicOr(&s_vis[u >> 5], b);
                         if (!(old & b)) {
                             atomicOr(&s_next[u >> 5], b);
@@ -367,16 +370,22 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                 // kMultiU steps of kMultiGroup in-neighbours per round; the
                 // first frontier member in stored order wins
                 for (int32_t jb = b0; jb < e0 && hit == INT32_MAX; jb += kMultiU * kMultiGroup) {
+                    // index loads clamped to the row's last slot, frontier words
+                    // read together (ids past the graph read a valid word and
+                    // are then ignored)
                     int32_t ii[kMultiU];
 #pragma unroll
-                    for (int k = 0; k < kMultiU; ++k) {
-                        const int32_t j = jb + k * kMultiGroup + lane;
-                        ii[k] = j < e0 ? in_idx[j] : -1;
-                    }
+                    for (int k = 0; k < kMultiU; ++k)
+                        ii[k] = in_idx[(uint32_t)min(jb + k * kMultiGroup + lane, e0 - 1)];
+                    uint32_t fw[kMultiU];
+#pragma unroll
+                    for (int k = 0; k < kMultiU; ++k) fw[k] = s_front[min(ii[k], n - 1) >> 5];
                     int32_t pos = INT32_MAX;
 #pragma unroll
-                    for (int k = kMultiU - 1; k >= 0; --k)
-                        if (ii[k] >= 0 && bit_of(s_front, ii[k])) pos = jb + k * kMultiGroup + lane;
+                    for (int k = kMultiU - 1; k >= 0; --k) {
+                        const int32_t j = jb + k * kMultiGroup + lane;
+                        if (j < e0 && ii[k] < n && ((fw[k] >> (ii[k] & 31)) & 1u)) pos = j;
+                    }
 #pragma unroll
                     for (int s = kMultiGroup / 2; s > 0; s >>= 1) pos = min(pos, __shfl_xor(pos, s));
                     hit = pos;
