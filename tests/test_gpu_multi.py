@@ -80,3 +80,17 @@ def test_batch_of_512_rmat_graphs():
             assert np.abs(xs[i].astype(np.float64) - want_x[i]).sum() <= PR_L1_TOL
             assert np.array_equal(lvs[i], want_l[i])
             assert H.bfs_violations_fast(gs[i], 0, lvs[i], ps[i]) == []
+
+
+def test_largest_ids_and_repeatable_pull():
+    # ids up to 16383 (the 16-bit arena's top graph size): a star centred on the
+    # last vertex, a long path, and a graph with an empty row 0; the pull sums
+    # rows in a fixed order, so a second launch gives the same bits
+    n = 16384
+    star = gg.from_edges(n, np.full(n - 1, n - 1), np.arange(n - 1), True)
+    gs = [star, H.path(n), gg.from_edges(40, [5, 6, 39], [6, 7, 1], True)]
+    _check(gs, policies=(pp.PP_SWITCH, pp.PP_PULL))
+    mg = pp.MultiGraph(gs)
+    x1, _, _ = mg.run(pr_iters=20, f=F, pr_dir=pp.PP_PULL, bfs_policy=-1)
+    x2, _, _ = mg.run(pr_iters=20, f=F, pr_dir=pp.PP_PULL, bfs_policy=-1)
+    assert torch.equal(x1, x2)
