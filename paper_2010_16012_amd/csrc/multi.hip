@@ -29,6 +29,12 @@ constexpr int32_t kMultiMaxN = 16384;
 // wavefront holding the hubs running long after the others.
 constexpr int32_t kMultiBig = 512;
 constexpr int32_t kMultiBigCap = 512;
+// Rows of kMultiMid..kMultiBig-1 edges go to 16-lane groups (four per
+// wavefront, up to kMultiMidCap of them per graph): in an 8-lane group such a
+// row takes several rounds while the wavefront's other rows wait.
+constexpr int32_t kMultiMid = 64;
+constexpr int32_t kMultiMidCap = 4096;
+constexpr int kMultiMidLanes = 16;
 
 struct MultiEntry {
     int64_t vbase;  // first vertex of the graph in the vertex arenas (x, level, parent)
@@ -108,6 +114,8 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
     // ---------------------------------------------------------------- PageRank
     __shared__ int32_t s_big[kMultiBigCap];
     __shared__ int32_t s_nbig;
+    __shared__ int32_t s_mid[kMultiMidCap];
+    __shared__ int32_t s_nmid;
     __shared__ float s_zero;
     if (a.pr_iters > 0) {
         const float base = (1.0f - a.f) / (float)n;
@@ -115,17 +123,32 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
         const int32_t* roff = (a.pr_dir == PP_PULL) ? in_off : off;
         if (tid == 0) {
             s_nbig = 0;
+            s_nmid = 0;
             s_zero = 0.f;
         }
         __syncthreads();
-        for (int32_t u = tid; u < n; u += kMultiBlock)
-            if (roff[u + 1] - roff[u] >= kMultiBig) {
+        for (int32_t u = tid; u < n; u += kMultiBlock) {
+            const int32_t d = roff[u + 1] - roff[u];
+            if (d >= kMultiBig) {
                 const int32_t at = atomicAdd(&s_nbig, 1);
                 if (at < kMultiBigCap) s_big[at] = u;
+            } else if (d >= kMultiMid) {
+                const int32_t at = atomicAdd(&s_nmid, 1);
+                if (at < kMultiMidCap) s_mid[at] = u;
             }
+        }
         __syncthreads();
-        // more long rows than the list holds: all rows stay with the groups
+        // more long (middle) rows than a list holds: those rows stay with the
+        // 8-lane groups
         const int32_t nbig = (s_nbig <= kMultiBigCap) ? s_nbig : 0;
+        const int32_t nmid = (s_nmid <= kMultiMidCap) ? s_nmid : 0;
+        // does row length d belong to the 8-lane groups?
+        auto grouped = [&](int32_t d) {
+            return !((nbig > 0 && d >= kMultiBig) || (nmid > 0 && d >= kMultiMid && d < kMultiBig));
+        };
+        const int hl = wl & (kMultiMidLanes - 1);  // lane within a middle-row group
+        const int32_t mslot = (kWave / kMultiMidLanes) * wv + wl / kMultiMidLanes;  // its group
+        constexpr int32_t mgroups = kMultiBlock / kMultiMidLanes;
         if (a.pr_dir == PP_PULL) {
             float* s_c = lds;       // contributions of the current iterate
             float* s_y = lds + n;   // contributions of the next one
@@ -152,6 +175,39 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                         if (last) a.x[e.vbase + u] = y;
                     }
                 }
+                // middle in-rows: 16 lanes each; the next row's offsets load
+                // while this one is summed
+                {
+                    int32_t nu = 0, nrb = 0, nre = 0, nob = 0, noe = 0;
+                    if (mslot < nmid) {
+                        nu = s_mid[mslot];
+                        nrb = in_off[nu];
+                        nre = in_off[nu + 1];
+                        nob = off[nu];
+                        noe = off[nu + 1];
+                    }
+                    for (int32_t i = mslot; i < nmid; i += mgroups) {
+                        const int32_t u = nu, rb = nrb, re = nre, ob = nob, oe = noe;
+                        if (i + mgroups < nmid) {
+                            nu = s_mid[i + mgroups];
+                            nrb = in_off[nu];
+                            nre = in_off[nu + 1];
+                            nob = off[nu];
+                            noe = off[nu + 1];
+                        }
+                        double acc = 0.0;
+                        for (int32_t j0 = rb + hl; j0 < re; j0 += kMultiU * kMultiMidLanes)
+                            gather_row_slots<kMultiMidLanes, kMultiU>(in_idx, s_c, &s_zero, j0, re, acc);
+#pragma unroll
+                        for (int s = kMultiMidLanes / 2; s > 0; s >>= 1) acc += __shfl_xor(acc, s);
+                        if (hl == 0) {
+                            const float y = (float)((double)base + acc);
+                            const int32_t d = oe - ob;
+                            s_y[u] = d > 0 ? a.f * y / (float)d : 0.f;
+                            if (last) a.x[e.vbase + u] = y;
+                        }
+                    }
+                }
                 // other rows: the group owning u gathers over its in-row (FP64
                 // sum per lane, 8 lanes per row); the offsets and out-degree of
                 // the group's next row load while this row is summed
@@ -171,7 +227,7 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                         nob = off[u + groups];
                         noe = off[u + groups + 1];
                     }
-                    if (nbig > 0 && re - rb >= kMultiBig) continue;  // group-uniform
+                    if (!grouped(re - rb)) continue;  // group-uniform
                     for (int32_t j0 = rb + lane; j0 < re; j0 += kMultiPullU * kMultiGroup)
                         gather_row_slots<kMultiGroup, kMultiPullU>(in_idx, s_c, &s_zero, j0, re, acc);
 #pragma unroll
@@ -220,6 +276,37 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                             if (ii[k] >= 0) atomicAdd(&s_acc[ii[k]], (double)cv);
                     }
                 }
+                // middle out-rows: 16 lanes each
+                {
+                    int32_t nv = 0, nb = 0, ne = 0;
+                    float ncv = 0.f;
+                    if (mslot < nmid) {
+                        nv = s_mid[mslot];
+                        ncv = c[nv];
+                        nb = off[nv];
+                        ne = off[nv + 1];
+                    }
+                    for (int32_t i = mslot; i < nmid; i += mgroups) {
+                        const float cv = ncv;
+                        const int32_t rb = nb, re = ne;
+                        if (i + mgroups < nmid) {
+                            nv = s_mid[i + mgroups];
+                            ncv = c[nv];
+                            nb = off[nv];
+                            ne = off[nv + 1];
+                        }
+                        if (cv == 0.f) continue;
+                        for (int32_t j0 = rb + hl; j0 < re; j0 += kMultiU * kMultiMidLanes) {
+                            int32_t ii[kMultiU];  // clamped to the row's last slot
+#pragma unroll
+                            for (int k = 0; k < kMultiU; ++k)
+                                ii[k] = idx[(uint32_t)min(j0 + k * kMultiMidLanes, re - 1)];
+#pragma unroll
+                            for (int k = 0; k < kMultiU; ++k)
+                                if (j0 + k * kMultiMidLanes < re) atomicAdd(&s_acc[ii[k]], (double)cv);
+                        }
+                    }
+                }
                 // two rows per group and round (v and v + groups), their index
                 // loads issued together; the contributions and offsets of the
                 // group's next two rows load while these are scattered
@@ -252,8 +339,7 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                         }
                         // nothing to scatter here: past the graph, a zero
                         // contribution, or a long row (done above)
-                        if (v + r * groups >= n || cv[r] == 0.f || (nbig > 0 && re[r] - rb[r] >= kMultiBig))
-                            re[r] = rb[r];
+                        if (v + r * groups >= n || cv[r] == 0.f || !grouped(re[r] - rb[r])) re[r] = rb[r];
                     }
                     const int32_t len = max(re[0] - rb[0], re[1] - rb[1]);
                     for (int32_t d = lane; d < len; d += kMultiU * kMultiGroup) {
