@@ -20,17 +20,17 @@
 namespace pp {
 
 constexpr int kMultiBlock = 1024;
-constexpr int kMultiGroup = 8;  // lanes per row
+constexpr int kMultiGroup = 4;  // lanes per row
 constexpr int kMultiU = 8;      // index loads in flight per lane
 constexpr int kMultiPullU = 8;  // slots per lane and round of a pull row
 constexpr int32_t kMultiMaxN = 16384;
 // PageRank rows at least kMultiBig long get a whole wavefront each (up to
-// kMultiBigCap of them per graph); eight lanes per row would leave the
+// kMultiBigCap of them per graph); a small group per row would leave the
 // wavefront holding the hubs running long after the others.
 constexpr int32_t kMultiBig = 512;
 constexpr int32_t kMultiBigCap = 512;
 // Rows of kMultiMid..kMultiBig-1 edges go to 16-lane groups (four per
-// wavefront, up to kMultiMidCap of them per graph): in an 8-lane group such a
+// wavefront, up to kMultiMidCap of them per graph): in a small group such a
 // row takes several rounds while the wavefront's other rows wait.
 constexpr int32_t kMultiMid = 64;
 constexpr int32_t kMultiMidCap = 4096;
@@ -106,9 +106,9 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
     constexpr int groups = kMultiBlock / kMultiGroup;
     constexpr int kWaves = kMultiBlock / kWave;
     const int wl = tid & (kWave - 1), wv = tid / kWave;
-    // PageRank rows of 8-lane groups: consecutive rows go to different
-    // wavefronts (row 16 q' + w for wavefront w, group q of it, q' = q + 8 k),
-    // so neighbouring ids -- the hubs of an R-MAT graph -- are spread out
+    // PageRank rows of the small groups: consecutive rows go to different
+    // wavefronts (rows 16 q + w + k * groups for group q of wavefront w), so
+    // neighbouring ids -- the hubs of an R-MAT graph -- are spread out
     const int32_t row0 = kWaves * ((tid % kWave) / kMultiGroup) + wv;
 
     // ---------------------------------------------------------------- PageRank
@@ -139,10 +139,10 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
         }
         __syncthreads();
         // more long (middle) rows than a list holds: those rows stay with the
-        // 8-lane groups
+        // small groups
         const int32_t nbig = (s_nbig <= kMultiBigCap) ? s_nbig : 0;
         const int32_t nmid = (s_nmid <= kMultiMidCap) ? s_nmid : 0;
-        // does row length d belong to the 8-lane groups?
+        // does row length d belong to the small groups?
         auto grouped = [&](int32_t d) {
             return !((nbig > 0 && d >= kMultiBig) || (nmid > 0 && d >= kMultiMid && d < kMultiBig));
         };
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                     }
                 }
                 // other rows: the group owning u gathers over its in-row (FP64
-                // sum per lane, 8 lanes per row); the offsets and out-degree of
+                // sum per lane, kMultiGroup lanes per row); the offsets and out-degree of
                 // the group's next row load while this row is summed
                 int32_t nrb = 0, nre = 0, nob = 0, noe = 0;
                 if (row0 < n) {
