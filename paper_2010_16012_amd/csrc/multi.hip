@@ -23,6 +23,7 @@ constexpr int kMultiBlock = 1024;
 constexpr int kMultiGroup = 4;  // lanes per row
 constexpr int kMultiU = 8;      // index loads in flight per lane
 constexpr int kMultiPullU = 8;  // slots per lane and round of a pull row
+constexpr int kMultiPullGroup = 2;  // lanes per short pull row (the push and BFS use kMultiGroup)
 constexpr int32_t kMultiMaxN = 16384;
 // PageRank rows at least kMultiBig long get a whole wavefront each (up to
 // kMultiBigCap of them per graph); a small group per row would leave the
@@ -209,30 +210,34 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                     }
                 }
                 // other rows: the group owning u gathers over its in-row (FP64
-                // sum per lane, kMultiGroup lanes per row); the offsets and out-degree of
-                // the group's next row load while this row is summed
+                // sum per lane, kMultiPullGroup lanes per row, rows spread over
+                // the wavefronts as above); the offsets and out-degree of the
+                // group's next row load while this row is summed
+                const int plane = tid % kMultiPullGroup;
+                const int32_t prow0 = kWaves * ((tid % kWave) / kMultiPullGroup) + wv;
+                constexpr int32_t pgroups = kMultiBlock / kMultiPullGroup;
                 int32_t nrb = 0, nre = 0, nob = 0, noe = 0;
-                if (row0 < n) {
-                    nrb = in_off[row0];
-                    nre = in_off[row0 + 1];
-                    nob = off[row0];
-                    noe = off[row0 + 1];
+                if (prow0 < n) {
+                    nrb = in_off[prow0];
+                    nre = in_off[prow0 + 1];
+                    nob = off[prow0];
+                    noe = off[prow0 + 1];
                 }
-                for (int32_t u = row0; u < n; u += groups) {
+                for (int32_t u = prow0; u < n; u += pgroups) {
                     double acc = 0.0;
                     const int32_t rb = nrb, re = nre, ob = nob, oe = noe;
-                    if (u + groups < n) {
-                        nrb = in_off[u + groups];
-                        nre = in_off[u + groups + 1];
-                        nob = off[u + groups];
-                        noe = off[u + groups + 1];
+                    if (u + pgroups < n) {
+                        nrb = in_off[u + pgroups];
+                        nre = in_off[u + pgroups + 1];
+                        nob = off[u + pgroups];
+                        noe = off[u + pgroups + 1];
                     }
                     if (!grouped(re - rb)) continue;  // group-uniform
-                    for (int32_t j0 = rb + lane; j0 < re; j0 += kMultiPullU * kMultiGroup)
-                        gather_row_slots<kMultiGroup, kMultiPullU>(in_idx, s_c, &s_zero, j0, re, acc);
+                    for (int32_t j0 = rb + plane; j0 < re; j0 += kMultiPullU * kMultiPullGroup)
+                        gather_row_slots<kMultiPullGroup, kMultiPullU>(in_idx, s_c, &s_zero, j0, re, acc);
 #pragma unroll
-                    for (int s = kMultiGroup / 2; s > 0; s >>= 1) acc += __shfl_xor(acc, s);
-                    if (lane == 0) {
+                    for (int s = kMultiPullGroup / 2; s > 0; s >>= 1) acc += __shfl_xor(acc, s);
+                    if (plane == 0) {
                         const float y = (float)((double)base + acc);
                         const int32_t d = oe - ob;
                         s_y[u] = d > 0 ? a.f * y / (float)d : 0.f;
