@@ -94,3 +94,13 @@ def test_largest_ids_and_repeatable_pull():
     x1, _, _ = mg.run(pr_iters=20, f=F, pr_dir=pp.PP_PULL, bfs_policy=-1)
     x2, _, _ = mg.run(pr_iters=20, f=F, pr_dir=pp.PP_PULL, bfs_policy=-1)
     assert torch.equal(x1, x2)
+
+
+def test_row_lists_that_overflow():
+    # more rows of 512+ edges than the hub list holds (K_700), and more rows of
+    # 64-511 edges than the middle-row list holds (5,000 vertices of degree
+    # ~80): those rows fall back to the small groups, results unchanged
+    dense = H.random_graph(5000, 200_000, 3, symmetric=True)
+    deg = np.diff(dense.off)
+    assert ((deg >= 64) & (deg < 512)).sum() > 4096
+    _check([H.complete(700), dense, H.path(50)], policies=(pp.PP_SWITCH,))
