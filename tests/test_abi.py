@@ -57,3 +57,20 @@ def test_host_side_queries_and_validation():
 def test_binding_has_a_function_for_every_export():
     from paper_2010_16012_amd import _lib
     assert [n for n in _lib.EXPORTS if not callable(getattr(_lib, n, None))] == []
+
+
+def test_many_graph_arena_checks_ids_on_the_host():
+    # the arena stores 16-bit local ids; an id outside 0..n-1 is refused while
+    # the arena is built, before anything reaches a device
+    import numpy as np
+    import graphgen as gg
+    import paper_2010_16012_amd as pp
+    bad = gg.from_edges(6, [0, 1], [1, 2], True)
+    bad.idx = bad.idx.copy()
+    bad.idx[0] = 6
+    with pytest.raises(pp.PPError):
+        pp.MultiGraph([bad], device="cpu")
+    good = gg.from_edges(6, [0, 1], [1, 2], True)
+    mg = pp.MultiGraph([good, good], device="cpu")
+    assert mg.idx.dtype.itemsize == 2 and int(mg.idx.max()) < 6
+    assert np.array_equal(mg.off.numpy(), np.concatenate([good.off, good.off]))
