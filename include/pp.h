@@ -215,6 +215,24 @@ pp_status pp_bfs_run(pp_graph g, int32_t root, pp_dir policy, float alpha, float
                      int32_t* level, int32_t* parent, void* state, size_t state_bytes,
                      pp_bfs_stats* stats, void* stream);
 
+/* One entry of a BFS level log: how frontier l was expanded (Sec. 4.3; the
+ * statistics are those the switch rule of pp_bfs_run reads). */
+typedef struct {
+    int32_t dir;            /* PP_PUSH (top-down) or PP_PULL (bottom-up) */
+    int32_t frontier;       /* n_f = |F_l| */
+    int64_t frontier_edges; /* m_f = out-edges of F_l: the edges a top-down
+                               expansion of F_l examines */
+} pp_bfs_level;
+
+/* pp_bfs_run that also writes entry l of `log` (DEVICE array of log_cap
+ * entries, caller-owned) for every expanded frontier l < log_cap; pass
+ * log_cap >= n + 1 to log every level of any run (a graph of n vertices has
+ * at most n non-empty frontiers).  Entries past the last level are left
+ * untouched.  log may be NULL only when log_cap is 0.  SYNC. */
+pp_status pp_bfs_run_log(pp_graph g, int32_t root, pp_dir policy, float alpha, float beta,
+                         int32_t* level, int32_t* parent, void* state, size_t state_bytes,
+                         pp_bfs_level* log, int32_t log_cap, pp_bfs_stats* stats, void* stream);
+
 /* ------------------------------------------------------ personalised PR */
 /* Scratch bytes for pp_ppr_run / pp_ppr_adjoint with k columns processed in
  * tiles of k_tile (0 when an argument is invalid). */
@@ -270,9 +288,12 @@ size_t pp_multi_workspace_bytes(int32_t num_graphs, int64_t total_vertices);
  * = out-adjacency, CSC = in-adjacency; may alias for symmetric graphs);
  * idx/in_idx each graph's local neighbour ids back to back as uint16 (a
  * graph has at most 16384 vertices, so 16 bits hold every id; half the
- * bytes of int32 ids per sweep); every id must lie below its graph's n
- * (not checked: the BFS skips larger ids, PageRank results are then
- * undefined); x (float),
+ * bytes of int32 ids per sweep).  Before any sweep a device pass checks
+ * every graph: its offsets start at 0, never decrease and end at
+ * graph_nnz[i], and every id lies below its n (both adjacencies unless they
+ * alias); on failure nothing is computed, the outputs are left as they were
+ * and the call returns PP_E_GRAPH.  The arena arrays themselves must be as
+ * long as graph_n and graph_nnz say.  x (float),
  * level and parent (int32) each graph's n entries back to back.  Runs
  * pr_iters Jacobi steps of the PageRank equation (Sec. 3.1; x_0 = 1/n) in
  * direction pr_dir, then, unless bfs_policy is -1, a BFS from local vertex

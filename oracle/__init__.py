@@ -12,6 +12,8 @@ are stated at the top of ``oracle.c``:
 
 * ``pagerank`` / ``pagerank_push`` -- the PageRank equation of Sec. 3.1 as a
   Jacobi iteration in its pulling and pushing forms (Sec. 4.1);
+* ``pagerank_threads`` -- the pulling form with its rows split over threads
+  (bit-identical; times the oracle on all host cores);
 * ``pagerank_step_at`` -- one update at chosen vertices from a given iterate;
 * ``ppr`` / ``ppr_adjoint`` / ``ppr_adjoint_unrolled`` -- personalised (and
   weighted) PageRank and its adjoint with respect to edge weights, at the
@@ -36,10 +38,12 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile ``liboracle.so`` with gcc (plain -O2, single-threaded)."""
+    """Compile ``liboracle.so`` with gcc (plain -O2; OpenMP only for
+    ``pagerank_threads``, every other function is single-threaded)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC, "-lm"], check=True)
+        subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-fopenmp", "-o", tmp, _SRC, "-lm"],
+                       check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -55,6 +59,7 @@ def _load():
     sigs = {
         "orc_pagerank": [i64, P, P, f64, i32, P, P],
         "orc_pagerank_push": [i64, P, P, f64, i32, P, P],
+        "orc_pagerank_threads": [i64, P, P, f64, i32, P, P, P],
         "orc_pagerank_step_at": [i64, P, P, f64, P, i64, P, P],
         "orc_ppr": [i64, P, P, P, i64, P, f64, i32, f64, P, P],
         "orc_ppr_adjoint": [i64, P, P, P, i64, P, P, f64, i32, f64, P, P, P],
@@ -100,6 +105,18 @@ def pagerank(off, idx, f=0.85, T=20, x0=None) -> np.ndarray:
     x0 = None if x0 is None else _arr(x0, np.float64)
     _check(_load().orc_pagerank(n, _p(off), _p(idx), f, T, _p(x0), _p(out)), "orc_pagerank")
     return out
+
+
+def pagerank_threads(off, idx, f=0.85, T=20, x0=None):
+    """``pagerank`` with its row loop split over OpenMP threads (bit-identical
+    result).  Returns (x, threads used)."""
+    n, off, idx = _graph(off, idx)
+    out = np.empty(n, dtype=np.float64)
+    x0 = None if x0 is None else _arr(x0, np.float64)
+    th = np.zeros(1, dtype=np.int32)
+    _check(_load().orc_pagerank_threads(n, _p(off), _p(idx), f, T, _p(x0), _p(out), _p(th)),
+           "orc_pagerank_threads")
+    return out, int(th[0])
 
 
 def pagerank_push(off, idx, f=0.85, T=20, x0=None) -> np.ndarray:

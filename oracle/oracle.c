@@ -31,6 +31,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <omp.h>
 
 /* In-adjacency (transpose) by a counting sort over destinations, scanning
  * sources in ascending order so each in-row lists sources ascending.
@@ -100,6 +101,48 @@ int orc_pagerank(int64_t n, const int64_t* off, const int32_t* idx, double f, in
         }
         double* tmp = x; x = y; y = tmp;
     }
+    memcpy(x_out, x, (size_t)n * sizeof(double));
+    free(x); free(y); free(in_off); free(in_idx);
+    return 0;
+}
+
+/* The pulling form above with its row loop split over threads (OpenMP).
+ * Every row is still summed by one thread in in-row order, so the result is
+ * bit-identical to orc_pagerank; only the wall time differs.  Used to time the
+ * oracle on all host cores (the pulling form has no write conflicts, Sec. 4.1).
+ * *threads_out (nullable) receives the number of threads of the team. */
+int orc_pagerank_threads(int64_t n, const int64_t* off, const int32_t* idx, double f, int T,
+                         const double* x0, double* x_out, int* threads_out) {
+    int rc = check_graph(n, off, idx);
+    if (rc) return rc;
+    if (T < 0 || !x_out) return -1;
+    int64_t* in_off;
+    int32_t* in_idx;
+    if ((rc = transpose(n, off, idx, &in_off, &in_idx, NULL))) return rc;
+    double* x = (double*)malloc((size_t)n * sizeof(double));
+    double* y = (double*)malloc((size_t)n * sizeof(double));
+    if (!x || !y) { free(x); free(y); free(in_off); free(in_idx); return -3; }
+    for (int64_t v = 0; v < n; ++v) x[v] = x0 ? x0[v] : 1.0 / (double)n;
+    const double base = (1.0 - f) / (double)n;
+    int team = 1;
+    for (int t = 0; t < T; ++t) {
+#pragma omp parallel
+        {
+#pragma omp single
+            team = omp_get_num_threads();
+#pragma omp for schedule(dynamic, 4096)
+            for (int64_t u = 0; u < n; ++u) {
+                double acc = 0.0;
+                for (int64_t j = in_off[u]; j < in_off[u + 1]; ++j) {
+                    int32_t v = in_idx[j];
+                    acc += x[v] / (double)(off[v + 1] - off[v]);
+                }
+                y[u] = base + f * acc;
+            }
+        }
+        double* tmp = x; x = y; y = tmp;
+    }
+    if (threads_out) *threads_out = (T > 0) ? team : omp_get_max_threads();
     memcpy(x_out, x, (size_t)n * sizeof(double));
     free(x); free(y); free(in_off); free(in_idx);
     return 0;

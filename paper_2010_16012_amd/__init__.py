@@ -113,6 +113,21 @@ class BfsRun:
     def run(self, root, policy=PP_SWITCH, alpha=14.0, beta=24.0, stream=None) -> BfsStats:
         return _lib.pp_bfs_run(self.g.handle, root, policy, alpha, beta, self.level, self.parent, self.state, stream)
 
+    def run_logged(self, root, policy=PP_SWITCH, alpha=14.0, beta=24.0, stream=None):
+        """``run`` with the whole per-level log: returns (stats, dirs, n_f, m_f),
+        one entry per expanded frontier (numpy arrays)."""
+        import numpy as np
+        if getattr(self, "_log", None) is None:
+            self._log_cap = self.g.n + 1
+            self._log = torch.empty(2 * self._log_cap, dtype=torch.int64, device=self.g.device)
+        st = _lib.pp_bfs_run_log(self.g.handle, root, policy, alpha, beta, self.level, self.parent, self.state,
+                                 self._log, self._log_cap, stream)
+        raw = self._log[:2 * st.levels].cpu().numpy()
+        head = raw[0::2]
+        dirs = (head & 0xFFFFFFFF).astype(np.int64).astype(np.int32)
+        nf = (head >> 32).astype(np.int32)
+        return st, dirs, nf, raw[1::2].copy()
+
     def init(self, root, stream=None):
         _lib.pp_bfs_init(self.g.handle, root, self.level, self.parent, self.state, stream)
 

@@ -77,6 +77,8 @@ _SIGS = {
     "pp_bfs_step_pull": ([_P, _P, _P, _P, _I32, _P], ctypes.c_int),
     "pp_bfs_frontier": ([_P, _P, ctypes.POINTER(_I32), _P], ctypes.c_int),
     "pp_bfs_run": ([_P, _I32, ctypes.c_int, _F32, _F32, _P, _P, _P, _SZ, ctypes.POINTER(BfsStats), _P], ctypes.c_int),
+    "pp_bfs_run_log": ([_P, _I32, ctypes.c_int, _F32, _F32, _P, _P, _P, _SZ, _P, _I32, ctypes.POINTER(BfsStats), _P],
+                       ctypes.c_int),
     "pp_ppr_scratch_bytes": ([_P, _I32, _I32], _SZ),
     "pp_multi_workspace_bytes": ([_I32, _I64], _SZ),
     "pp_multi_run": ([_I32, _P, _P, _P, _P, _P, _P, ctypes.c_int, _I32, _F32, _P, _I32, _I32, _F32, _F32, _P, _P, _P,
@@ -223,6 +225,20 @@ def pp_bfs_run(h, root, policy, alpha, beta, level, parent, state, stream=None) 
     st = BfsStats()
     _check(_lib.pp_bfs_run(h, root, policy, alpha, beta, _ptr(level), _ptr(parent), _ptr(state), state.numel(),
                            ctypes.byref(st), _stream(stream)))
+    return st
+
+
+# pp_bfs_level: int32 dir, int32 frontier, int64 frontier_edges (16 bytes)
+BFS_LEVEL_BYTES = 16
+
+
+def pp_bfs_run_log(h, root, policy, alpha, beta, level, parent, state, log, log_cap, stream=None) -> BfsStats:
+    """log: device tensor of at least log_cap * 16 bytes (pp_bfs_level entries)."""
+    if log is not None and log.numel() * log.element_size() < log_cap * BFS_LEVEL_BYTES:
+        raise ValueError("log tensor smaller than log_cap entries")
+    st = BfsStats()
+    _check(_lib.pp_bfs_run_log(h, root, policy, alpha, beta, _ptr(level), _ptr(parent), _ptr(state), state.numel(),
+                               _ptr(log), log_cap, ctypes.byref(st), _stream(stream)))
     return st
 
 

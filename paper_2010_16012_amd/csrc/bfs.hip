@@ -158,6 +158,8 @@ struct BfsArgs {
     uint64_t* fb[3];
     uint64_t* visited;
     int32_t* items;         // (v, begin, end) chunk items of long rows
+    pp_bfs_level* log;      // per-level log (caller device memory; nullable)
+    int32_t log_cap;        // entries of log
 };
 
 static BfsArgs bfs_args(pp_graph g, void* state, int32_t* level, int32_t* parent) {
@@ -196,6 +198,8 @@ static BfsArgs bfs_args(pp_graph g, void* state, int32_t* level, int32_t* parent
     a.fb[2] = reinterpret_cast<uint64_t*>(s + L.fb2);
     a.visited = reinterpret_cast<uint64_t*>(s + L.visited);
     a.items = reinterpret_cast<int32_t*>(s + L.items);
+    a.log = nullptr;
+    a.log_cap = 0;
     return a;
 }
 
@@ -858,6 +862,7 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
             h->log_dir[lvl] = (int8_t)dir;
             h->log_n[lvl] = nf;
         }
+        if (lvl < a.log_cap) a.log[lvl] = pp_bfs_level{dir, nf, cur.m};
         h->levels = lvl + 1;
         h->last = lvl + 1;
         h->reached += nf;
@@ -1024,11 +1029,8 @@ static pp_status check_state(pp_graph g, void* state, size_t bytes) {
 // Lets the staging kernels take LDS beyond the default 64 KiB.
 static void allow_stage_lds(const BfsArgs& a) {
     const int bytes = (a.stage_words + a.sum_words) * 8;
-    if (bytes <= 65536) return;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bfs_level), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              bytes);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bfs_chunks),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    allow_dynamic_lds(reinterpret_cast<const void*>(&k_bfs_level), (size_t)bytes);
+    allow_dynamic_lds(reinterpret_cast<const void*>(&k_bfs_chunks), (size_t)bytes);
 }
 
 // Dynamic LDS of the chunk kernel: the bottom-up summary or the top-down
@@ -1064,7 +1066,7 @@ static pp_status bfs_graph(pp_graph g, BfsArgs a, int32_t policy, float alpha, f
                            const void* state, hipGraphExec_t* out) {
     for (auto& e : g->bfs_graphs)
         if (e.state == state && e.level == a.level && e.parent == a.parent && e.policy == policy &&
-            e.alpha == alpha && e.beta == beta && e.batch == batch) {
+            e.alpha == alpha && e.beta == beta && e.batch == batch && e.log == a.log && e.log_cap == a.log_cap) {
             *out = e.exec;
             return PP_OK;
         }
@@ -1110,7 +1112,7 @@ static pp_status bfs_graph(pp_graph g, BfsArgs a, int32_t policy, float alpha, f
         (void)hipGraphDestroy(graph);
         return hip_error(e, "BFS level graph");
     }
-    g->bfs_graphs.push_back({state, a.level, a.parent, policy, alpha, beta, batch, exec, graph});
+    g->bfs_graphs.push_back({state, a.level, a.parent, policy, alpha, beta, batch, a.log, a.log_cap, exec, graph});
     *out = exec;
     return PP_OK;
 }
@@ -1177,15 +1179,25 @@ PP_EXPORT pp_status pp_bfs_frontier(pp_graph g, void* state, int32_t* size, void
 
 PP_EXPORT pp_status pp_bfs_run(pp_graph g, int32_t root, pp_dir policy, float alpha, float beta, int32_t* level,
                                int32_t* parent, void* state, size_t state_bytes, pp_bfs_stats* stats, void* stream) {
+    return pp_bfs_run_log(g, root, policy, alpha, beta, level, parent, state, state_bytes, nullptr, 0, stats, stream);
+}
+
+PP_EXPORT pp_status pp_bfs_run_log(pp_graph g, int32_t root, pp_dir policy, float alpha, float beta, int32_t* level,
+                                   int32_t* parent, void* state, size_t state_bytes, pp_bfs_level* log,
+                                   int32_t log_cap, pp_bfs_stats* stats, void* stream) {
     clear_error();
     if (policy != PP_PUSH && policy != PP_PULL && policy != PP_SWITCH)
         return set_error(PP_E_RANGE, "policy must be PP_PUSH, PP_PULL or PP_SWITCH");
+    if (log_cap < 0) return set_error(PP_E_RANGE, "log_cap must be >= 0");
+    if (log_cap > 0 && !log) return set_error(PP_E_NULL, "log is required when log_cap > 0");
     if (!(alpha > 0.f)) alpha = 14.f;
     if (!(beta > 0.f)) beta = 24.f;
     pp_status s = pp_bfs_init(g, root, level, parent, state, state_bytes, stream);
     if (s != PP_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     BfsArgs a = bfs_args(g, state, level, parent);
+    a.log = log;
+    a.log_cap = log_cap;
     // Levels go out in batches with the level index kept on the device;
     // kernels past the last level find an empty frontier and return at once,
     // so only termination needs a read, which takes the whole header (the

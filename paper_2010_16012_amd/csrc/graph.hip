@@ -5,7 +5,10 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "pp_common.h"
@@ -25,6 +28,18 @@ pp_status hip_error(hipError_t e, const char* what) {
 }
 
 void clear_error() { g_last_error.clear(); }
+
+void allow_dynamic_lds(const void* fn, size_t bytes) {
+    if (bytes <= 65536) return;
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, size_t> done;  // (kernel, device) -> bytes allowed
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;  // the launch will report the error
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& have = done[{fn, dev}];
+    if (have >= bytes) return;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess) have = bytes;
+}
 
 Tuning& tuning() {
     static Tuning t;

@@ -62,6 +62,7 @@ struct MultiArgs {
     float alpha, beta;
     int32_t* level;
     int32_t* parent;
+    const int32_t* err;       // set by k_multi_check when the arena is malformed
 };
 
 __device__ __forceinline__ uint32_t bit_of(const uint32_t* bm, int32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
@@ -89,12 +90,44 @@ __device__ __forceinline__ void gather_row_slots(const I* __restrict__ ids, cons
     for (int k = 0; k < U; ++k) acc += (double)cv[k];
 }
 
+// Validates the arena before any sweep reads it, one workgroup per graph:
+// the graph's n+1 offsets start at 0, never decrease and end at its nnz, and
+// each of its nnz local ids lies below its n.  Both adjacencies are checked
+// unless they alias.  Every read stays inside the graph's own offsets and
+// slots, so a malformed arena is reported (PP_E_GRAPH), never walked.
+constexpr int kCheckBlock = 256;
+
+__device__ __forceinline__ bool offsets_ok(const int32_t* off, int32_t n, int32_t nnz) {
+    bool ok = true;
+    for (int32_t v = threadIdx.x; v < n; v += kCheckBlock) ok &= off[v] <= off[v + 1];
+    if (threadIdx.x == 0) ok &= (off[0] == 0) && (off[n] == nnz);
+    return ok;
+}
+
+__device__ __forceinline__ bool ids_ok(const uint16_t* idx, int32_t n, int32_t nnz) {
+    uint32_t mx = 0;
+    for (int32_t j = threadIdx.x; j < nnz; j += kCheckBlock) mx = max(mx, (uint32_t)idx[j]);
+    return nnz == 0 || mx < (uint32_t)n;
+}
+
+__global__ __launch_bounds__(kCheckBlock) void k_multi_check(const MultiEntry* __restrict__ table,
+                                                             const int32_t* __restrict__ off,
+                                                             const uint16_t* __restrict__ idx,
+                                                             const int32_t* __restrict__ in_off,
+                                                             const uint16_t* __restrict__ in_idx, int32_t* err) {
+    const MultiEntry e = table[blockIdx.x];
+    bool ok = offsets_ok(off + e.obase, e.n, e.nnz) && ids_ok(idx + e.ebase, e.n, e.nnz);
+    if (in_off != off || in_idx != idx)
+        ok = ok && offsets_ok(in_off + e.obase, e.n, e.nnz) && ids_ok(in_idx + e.ebase, e.n, e.nnz);
+    if (!ok) atomicOr(err, 1);
+}
+
 __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
     extern __shared__ float lds[];
     __shared__ int32_t s_cnt[4];
     __shared__ int64_t s_m[2];
     const int32_t gi = blockIdx.x;
-    if (gi >= a.count) return;
+    if (gi >= a.count || *a.err) return;  // a malformed arena is never walked
     const MultiEntry e = a.table[gi];
     const int32_t n = e.n;
     const int32_t* off = a.off + e.obase;
@@ -511,14 +544,17 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
 }
 
 // ------------------------------------------------------------------ host side
+// Workspace: the graph table (LPT order) and the validation error word, both
+// written by one host copy, then the push contributions (one float per vertex).
 struct MultiLayout {
-    size_t table, cbuf, total;
+    size_t table, err, cbuf, total;
 };
 
 static MultiLayout multi_layout(int32_t count, int64_t total_n) {
     MultiLayout L{};
     L.table = 0;
-    L.cbuf = align_up((size_t)std::max(count, 1) * sizeof(MultiEntry), 256);
+    L.err = (size_t)std::max(count, 1) * sizeof(MultiEntry);
+    L.cbuf = align_up(L.err + sizeof(int32_t), 256);
     L.total = L.cbuf + align_up((size_t)std::max<int64_t>(total_n, 1) * 4, 256);
     return L;
 }
@@ -574,7 +610,9 @@ PP_EXPORT pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, con
     std::stable_sort(order.begin(), order.end(), [&](int32_t p, int32_t q) {
         return (int64_t)ent[p].nnz + ent[p].n > (int64_t)ent[q].nnz + ent[q].n;
     });
-    std::vector<MultiEntry> dev(num_graphs);
+    // the table in LPT order followed by a zero error word, copied together
+    std::vector<char> head(ML.err + sizeof(int32_t), 0);
+    MultiEntry* dev = reinterpret_cast<MultiEntry*>(head.data());
     for (int32_t i = 0; i < num_graphs; ++i) dev[i] = ent[order[i]];
     int dev_id = 0, lds_cu = 0;
     PP_HIP(hipGetDevice(&dev_id));
@@ -583,7 +621,13 @@ PP_EXPORT pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, con
     if (lds > (size_t)lds_cu) return set_error(PP_E_UNSUPPORTED, "graphs too large for one workgroup's LDS");
     hipStream_t st = static_cast<hipStream_t>(stream);
     MultiEntry* table = static_cast<MultiEntry*>(ws);
-    PP_HIP(hipMemcpyAsync(table, dev.data(), sizeof(MultiEntry) * num_graphs, hipMemcpyHostToDevice, st));
+    int32_t* err = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + ML.err);
+    PP_HIP(hipMemcpyAsync(table, head.data(), head.size(), hipMemcpyHostToDevice, st));
+    const uint16_t* idx_chk = idx ? idx : in_idx;  // both NULL only when no graph has edges
+    const uint16_t* in_idx_chk = in_idx ? in_idx : idx;
+    hipLaunchKernelGGL(k_multi_check, dim3(num_graphs), dim3(kCheckBlock), 0, st, (const MultiEntry*)table, off,
+                       idx_chk, in_off, in_idx_chk, err);
+    PP_LAUNCH_CHECK("k_multi_check");
     MultiArgs a;
     a.table = table;
     a.count = num_graphs;
@@ -602,12 +646,14 @@ PP_EXPORT pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, con
     a.beta = beta;
     a.level = level;
     a.parent = parent;
-    if (lds > 65536)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_multi), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
+    a.err = err;
+    allow_dynamic_lds(reinterpret_cast<const void*>(&k_multi), lds);
     hipLaunchKernelGGL(k_multi, dim3(num_graphs), dim3(kMultiBlock), lds, st, a);
     PP_LAUNCH_CHECK("k_multi");
+    int32_t herr = 0;
+    PP_HIP(hipMemcpyAsync(&herr, err, sizeof(herr), hipMemcpyDeviceToHost, st));
     // the host table must outlive the asynchronous copy
     PP_HIP(hipStreamSynchronize(st));
+    if (herr) return set_error(PP_E_GRAPH, "a graph of the arena has malformed offsets or an id past its n");
     return PP_OK;
 }

@@ -118,6 +118,8 @@ struct pp_graph_s {
         int32_t policy;
         float alpha, beta;
         int32_t batch;
+        const void* log;
+        int32_t log_cap;
         hipGraphExec_t exec;
         hipGraph_t graph;
     };
@@ -136,6 +138,11 @@ namespace pp {
 pp_status set_error(pp_status s, const std::string& msg);
 pp_status hip_error(hipError_t e, const char* what);
 void clear_error();
+
+// Lets kernel `fn` take `bytes` of dynamic LDS beyond the default 64 KiB on
+// the current device.  The attribute is raised once per kernel and device
+// (to the largest size asked for so far), so launch loops pay for it once.
+void allow_dynamic_lds(const void* fn, size_t bytes);
 
 #define PP_HIP(call)                                             \
     do {                                                         \

@@ -529,12 +529,7 @@ pp_status launch_hyb_push(pp_graph g, const float* c, int32_t hot, hipStream_t s
     const int32_t grid =
         std::max(1, std::min(std::min(g->num_cu * per_cu, ceil_div(a.units, tpb / kWave)), g->tune.push_blocks));
     *parts = grid;
-    if (lds > 65536) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_hyb_push<true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_hyb_push<false>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    }
+    allow_dynamic_lds(reinterpret_cast<const void*>(g->weighted ? &k_pr_hyb_push<true> : &k_pr_hyb_push<false>), lds);
     if (g->weighted) hipLaunchKernelGGL((k_pr_hyb_push<true>), dim3(grid), dim3(tpb), lds, st, a);
     else hipLaunchKernelGGL((k_pr_hyb_push<false>), dim3(grid), dim3(tpb), lds, st, a);
     PP_LAUNCH_CHECK("k_pr_hyb_push");
@@ -573,12 +568,9 @@ pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float
         int32_t per_cu = std::max(2048 / tpb, 1);
         if (lds > 0) per_cu = std::max(1, std::min<int32_t>(per_cu, (int32_t)(g->lds_per_cu / lds)));
         const int32_t grid = std::max(1, std::min(g->num_cu * per_cu, ceil_div(a.units, tpb / kWave)));
-        if (lds > 65536) {  // allow the LDS beyond the default 64 KiB (no-op where not needed)
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_pull<true, true>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_pull<false, true>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        }
+        if (hot)
+            allow_dynamic_lds(
+                reinterpret_cast<const void*>(g->weighted ? &k_pr_pull<true, true> : &k_pr_pull<false, true>), lds);
         if (g->weighted) {
             if (hot) hipLaunchKernelGGL((k_pr_pull<true, true>), dim3(grid), dim3(tpb), lds, st, a);
             else hipLaunchKernelGGL((k_pr_pull<true, false>), dim3(grid), dim3(tpb), 0, st, a);
@@ -617,15 +609,8 @@ pp_status launch_push(pp_graph g, const float* c, float* y, hipStream_t st) {
     const int32_t sub = wide ? 4 : 1;
     const int32_t grid = std::max(1, std::min(ceil_div(a.units, sub), g->tune.push_blocks));
     if (wide) {
-        static bool attr_set = false;  // LDS beyond the default 64 KiB (same for every device)
-        if (!attr_set) {
-            const int mx = kHotMax * (int)sizeof(float);
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_push<4, true, true>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_push<4, false, true>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-            attr_set = true;
-        }
+        allow_dynamic_lds(
+            reinterpret_cast<const void*>(g->weighted ? &k_pr_push<4, true, true> : &k_pr_push<4, false, true>), lds);
         if (g->weighted) hipLaunchKernelGGL((k_pr_push<4, true, true>), dim3(grid), dim3(4 * kBlock), lds, st, a);
         else hipLaunchKernelGGL((k_pr_push<4, false, true>), dim3(grid), dim3(4 * kBlock), lds, st, a);
     } else if (g->weighted) {

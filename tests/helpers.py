@@ -150,3 +150,50 @@ def bfs_violations_fast(g, root, level, parent):
     if np.any(keys[pos] != want):
         errs.append("parent is not an in-neighbour")
     return errs
+
+
+class BfsValidator:
+    """``bfs_violations_fast`` with the per-edge arrays of one graph built once
+    (for many runs on a large graph).  Rows must be sorted ascending, as
+    ``graphgen`` writes them, so the edge keys v*n+u are sorted."""
+
+    def __init__(self, g):
+        self.g = g
+        n = g.n
+        deg = np.diff(g.off)
+        self.src = np.repeat(np.arange(n, dtype=np.int32), deg)
+        self.dst = np.ascontiguousarray(g.idx, dtype=np.int32)
+        self.keys = self.src.astype(np.int64) * n + self.dst
+        if len(self.keys) > 1 and not np.all(self.keys[1:] > self.keys[:-1]):
+            raise ValueError("rows must be strictly ascending")
+
+    def __call__(self, root, level, parent):
+        n = self.g.n
+        level = np.asarray(level).astype(np.int64)
+        parent = np.asarray(parent).astype(np.int64)
+        errs = []
+        if level[root] != 0 or parent[root] != root:
+            errs.append("root not level 0 / own parent")
+        reached = level >= 0
+        if np.any(level < -1):
+            errs.append("level below -1")
+        if np.any(parent[~reached] != -1):
+            errs.append("unreached vertex with a parent")
+        lr = level[self.src]
+        lt = level[self.dst]
+        bad = (lr >= 0) & ((lt < 0) | (lt > lr + 1))
+        if np.any(bad):
+            errs.append(f"{int(bad.sum())} edges leave the reached set or skip a level")
+        del lr, lt, bad
+        v = np.nonzero(reached & (np.arange(n) != root))[0]
+        p = parent[v]
+        if np.any((p < 0) | (p >= n)):
+            errs.append("parent out of range")
+            return errs
+        if np.any(level[p] != level[v] - 1):
+            errs.append("parent not one level up")
+        want = np.sort(p * n + v)
+        pos = np.minimum(np.searchsorted(self.keys, want), len(self.keys) - 1)
+        if len(want) and np.any(self.keys[pos] != want):
+            errs.append("parent is not an in-neighbour")
+        return errs

@@ -189,18 +189,33 @@ def test_bad_root_raises():
 
 
 @pytest.mark.slow
-def test_rmat22_roots():
-    host = gg.workload("rmat22")
-    roots = gg.pick_vertices(host, 64, seed=1)
-    announce(f"BFS rmat22 nnz={host.nnz}")
-    # every policy on a few roots, the switch policy on more
-    _check(host, roots[:2], fast=True, relabel=(True,))
-    _check(host, roots[2:6], policies=[pp.PP_SWITCH], fast=True, relabel=(True,))
-    _check(host, roots[6:7], fast=True, relabel=(False,))
-
-
-@pytest.mark.slow
 def test_grid4096_corner_many_levels():
     host = gg.workload("grid4096")
     announce(f"BFS grid n={host.n}")
     _check(host, [0], policies=[pp.PP_PUSH, pp.PP_SWITCH], fast=True, relabel=(True,))
+
+
+@pytest.mark.parametrize("maker,root", [(lambda: H.path(300), 0), (lambda: gg.workload("rmat14"), 0),
+                                        (lambda: H.full_grid(40, 60), 0)], ids=["path300", "rmat14", "grid40x60"])
+def test_level_log_covers_every_level(maker, root):
+    # The caller-sized log holds every level, also past the 64 the stats keep:
+    # n_f and m_f per level equal the level sizes and out-edge sums of the
+    # oracle's levels, and the first 64 entries agree with the stats.
+    host = maker()
+    want, _, nlev = oracle.bfs(host.off, host.idx, root)
+    deg = np.diff(host.off)
+    g = pp.Graph(host)
+    r = pp.BfsRun(g)
+    for pol in POLICIES:
+        announce(f"BFS level log {host.name} policy={pol}")
+        st, dirs, nf, mf = r.run_logged(root, pol)
+        assert st.levels == nlev == len(dirs)
+        assert np.array_equal(nf, np.bincount(want[want >= 0], minlength=nlev))
+        assert np.array_equal(mf, np.bincount(want[want >= 0], weights=deg[want >= 0], minlength=nlev).astype(np.int64))
+        if pol != pp.PP_SWITCH:
+            assert np.all(dirs == pol)
+        assert set(np.unique(dirs)) <= {pp.PP_PUSH, pp.PP_PULL}
+        m = min(nlev, 64)
+        assert list(dirs[:m]) == [st.dir[i] for i in range(m)]
+        assert list(nf[:m]) == [st.frontier[i] for i in range(m)]
+        assert np.array_equal(r.level.cpu().numpy(), want)

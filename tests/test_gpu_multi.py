@@ -6,6 +6,7 @@ import torch
 import graphgen as gg
 import oracle
 import paper_2010_16012_amd as pp
+from paper_2010_16012_amd import _lib
 from tests import helpers as H
 from tests.gpu_util import F, PR_L1_TOL, announce
 
@@ -47,10 +48,62 @@ def test_directed_batch():
 
 
 def test_pr_only_and_bfs_only():
+    # pr_iters = 0 runs the BFS alone, bfs_policy = -1 the PageRank alone
     gs = gg.rmat_batch(6, 8, 10, seed=9)
     mg = pp.MultiGraph(gs)
-    x, _, _ = mg.run(pr_iters=0, bfs_policy=pp.PP_SWITCH)
-    _, lv, _ = mg.run(pr_iters=5, f=F, bfs_policy=-1)
+    _, lv, par = mg.run(pr_iters=0, bfs_policy=pp.PP_SWITCH)
+    for h, li, pi in zip(gs, mg.split(lv.cpu().numpy()), mg.split(par.cpu().numpy())):
+        assert np.array_equal(li, oracle.bfs(h.off, h.idx, 0)[0]), h.name
+        assert H.bfs_violations(h, 0, li, pi) == [], h.name
+    for d in (pp.PP_PULL, pp.PP_PUSH):
+        x, _, _ = mg.run(pr_iters=5, f=F, pr_dir=d, bfs_policy=-1)
+        for h, xi in zip(gs, mg.split(x.cpu().numpy())):
+            want = oracle.pagerank(h.off, h.idx, F, 5)
+            assert np.abs(xi.astype(np.float64) - want).sum() <= PR_L1_TOL, h.name
+
+
+def _raw_run(n, nnz, off, idx, x, level, parent, ws):
+    """pp_multi_run through the C ABI with the arena exactly as given (the
+    Python MultiGraph would reject a bad id before the call)."""
+    _lib.pp_multi_run(n, nnz, off, idx, off, idx, pp.PP_PULL, 5, F, x, pp.PP_SWITCH, 0, 14.0, 24.0, level, parent,
+                      ws)
+
+
+def test_malformed_arena_is_rejected_on_the_device():
+    # Two graphs (a 5-path and a 4-cycle).  Each corruption is caught by the
+    # device check before any sweep: PP_E_GRAPH, outputs untouched; the same
+    # workspace then runs the intact arena correctly.
+    gs = [H.path(5), H.cycle(4)]
+    n = np.array([h.n for h in gs], dtype=np.int32)
+    nnz = np.array([h.nnz for h in gs], dtype=np.int64)
+    off0 = np.concatenate([h.off for h in gs]).astype(np.int32)
+    idx0 = np.concatenate([h.idx for h in gs]).astype(np.int16)
+    dev = torch.device("cuda")
+    ws = torch.empty(_lib.pp_multi_workspace_bytes(2, int(n.sum())), dtype=torch.uint8, device=dev)
+    cases = []
+    o = off0.copy(); o[2] = o[3] + 1; cases.append(("offsets decrease", o, idx0))          # noqa: E702
+    o = off0.copy(); o[6 + 4] += 1; cases.append(("end past nnz", o, idx0))                # noqa: E702
+    o = off0.copy(); o[6] = 1; cases.append(("second graph starts at 1", o, idx0))         # noqa: E702
+    i = idx0.copy(); i[3] = 5; cases.append(("id equals n", off0, i))                      # noqa: E702
+    i = idx0.copy(); i[-1] = -1; cases.append(("id 65535 in 16 bits", off0, i))            # noqa: E702
+    for name, o, i in cases:
+        announce(f"multi malformed arena: {name}")
+        x = torch.full((int(n.sum()),), -7.0, device=dev)
+        lv = torch.full((int(n.sum()),), -9, dtype=torch.int32, device=dev)
+        par = lv.clone()
+        with pytest.raises(pp.PPError) as ei:
+            _raw_run(n, nnz, torch.as_tensor(o).to(dev), torch.as_tensor(i).to(dev), x, lv, par, ws)
+        assert ei.value.status == _lib.PP_E_GRAPH, name
+        assert bool((x == -7.0).all()) and bool((lv == -9).all()) and bool((par == -9).all()), name
+    x = torch.empty(int(n.sum()), device=dev)
+    lv = torch.empty(int(n.sum()), dtype=torch.int32, device=dev)
+    par = torch.empty_like(lv)
+    _raw_run(n, nnz, torch.as_tensor(off0).to(dev), torch.as_tensor(idx0).to(dev), x, lv, par, ws)
+    bounds = np.concatenate([[0], np.cumsum(n)])
+    for k, h in enumerate(gs):
+        xs = x.cpu().numpy()[bounds[k]:bounds[k + 1]].astype(np.float64)
+        assert np.abs(xs - oracle.pagerank(h.off, h.idx, F, 5)).sum() <= PR_L1_TOL
+        assert np.array_equal(lv.cpu().numpy()[bounds[k]:bounds[k + 1]], oracle.bfs(h.off, h.idx, 0)[0])
 
 
 def test_size_limit_and_errors():

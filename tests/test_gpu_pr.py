@@ -301,15 +301,3 @@ def test_rmat22_sampled_step_and_mass_balance():
         # isolated vertices sit exactly at the teleport value
         iso = np.nonzero(deg == 0)[0][:1000]
         assert np.all(x20h[iso] == np.float32((1 - F) / host.n))  # F is FP32-exact
-
-
-@pytest.mark.slow
-def test_rmat22_full_run_against_oracle():
-    host = gg.workload("rmat22")
-    g = pp.Graph(host)
-    want = oracle.pagerank(host.off, host.idx, F, 20)
-    for d, name in zip(DIRS, DIR_IDS):
-        announce(f"PR rmat22 full {name}")
-        got = pr_gpu(g, d, 20).astype(np.float64)
-        l1 = np.abs(got - want).sum()
-        assert l1 <= PR_L1_TOL, f"{name}: L1 {l1:.3e}"
