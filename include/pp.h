@@ -310,6 +310,25 @@ pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, const int64_t
                        int32_t bfs_policy, int32_t bfs_root, float alpha, float beta,
                        int32_t* level, int32_t* parent, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as pp_multi_run, with its scratch (graph table, validation word,
+ * push contributions) in a fixed array of PP_MULTI_STATIC_BYTES inside the
+ * library instead of a caller workspace.  Each device the library runs on
+ * holds one such array for the life of the process.  The call allocates
+ * nothing; it fails with PP_E_WORKSPACE when
+ * pp_multi_workspace_bytes(num_graphs, total vertices) exceeds
+ * PP_MULTI_STATIC_BYTES (16 MiB: about 4 million vertices in all).  All calls
+ * on one device share its array, so calls that overlap on one device (other
+ * threads, other streams) race; order them.  Arguments, errors and results
+ * as pp_multi_run.  SYNC. */
+#define PP_MULTI_STATIC_BYTES ((size_t)16 << 20)
+pp_status pp_multi_run_static(int32_t num_graphs, const int32_t* graph_n, const int64_t* graph_nnz,
+                              const int32_t* off, const uint16_t* idx, const int32_t* in_off, const uint16_t* in_idx,
+                              pp_dir pr_dir, int32_t pr_iters, float f, float* x,
+                              int32_t bfs_policy, int32_t bfs_root, float alpha, float beta,
+                              int32_t* level, int32_t* parent, void* stream);
+
 /* Scratch bytes for pp_ppr_adjoint_unrolled (k columns, tiles of k_tile, T
  * steps: it keeps T iterates of one tile). */
 size_t pp_ppr_unrolled_scratch_bytes(pp_graph g, int32_t k, int32_t k_tile, int32_t T);

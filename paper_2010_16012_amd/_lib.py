@@ -83,6 +83,8 @@ _SIGS = {
     "pp_multi_workspace_bytes": ([_I32, _I64], _SZ),
     "pp_multi_run": ([_I32, _P, _P, _P, _P, _P, _P, ctypes.c_int, _I32, _F32, _P, _I32, _I32, _F32, _F32, _P, _P, _P,
                       _SZ, _P], ctypes.c_int),
+    "pp_multi_run_static": ([_I32, _P, _P, _P, _P, _P, _P, ctypes.c_int, _I32, _F32, _P, _I32, _I32, _F32, _F32, _P,
+                             _P, _P], ctypes.c_int),
     "pp_ppr_run": ([_P, ctypes.c_int, _I32, _P, _I32, _F32, _F32, _I32, _P, _P, _SZ, ctypes.POINTER(_I32), _P],
                    ctypes.c_int),
     "pp_ppr_adjoint": ([_P, ctypes.c_int, _I32, _P, _P, _I32, _F32, _F32, _I32, _P, _P, _P, _SZ,
@@ -273,6 +275,20 @@ def pp_multi_run(graph_n, graph_nnz, off, idx, in_off, in_idx, pr_dir, pr_iters,
     _check(_lib.pp_multi_run(len(gn), ctypes.c_void_p(gn.ctypes.data), ctypes.c_void_p(ge.ctypes.data), _ptr(off),
                              _ptr(idx), _ptr(in_off), _ptr(in_idx), pr_dir, pr_iters, f, _ptr(x), bfs_policy,
                              bfs_root, alpha, beta, _ptr(level), _ptr(parent), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+PP_MULTI_STATIC_BYTES = 16 << 20
+
+
+def pp_multi_run_static(graph_n, graph_nnz, off, idx, in_off, in_idx, pr_dir, pr_iters, f, x, bfs_policy, bfs_root,
+                        alpha, beta, level, parent, stream=None) -> None:
+    """pp_multi_run with the library's fixed scratch (no workspace argument)."""
+    import numpy as np
+    gn = np.ascontiguousarray(graph_n, dtype=np.int32)
+    ge = np.ascontiguousarray(graph_nnz, dtype=np.int64)
+    _check(_lib.pp_multi_run_static(len(gn), ctypes.c_void_p(gn.ctypes.data), ctypes.c_void_p(ge.ctypes.data),
+                                    _ptr(off), _ptr(idx), _ptr(in_off), _ptr(in_idx), pr_dir, pr_iters, f, _ptr(x),
+                                    bfs_policy, bfs_root, alpha, beta, _ptr(level), _ptr(parent), _stream(stream)))
 
 
 def pp_tc_workspace_bytes(h) -> int:

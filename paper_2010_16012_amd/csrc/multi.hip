@@ -12,7 +12,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "pp_common.h"
@@ -559,6 +561,37 @@ static MultiLayout multi_layout(int32_t count, int64_t total_n) {
     return L;
 }
 
+// Scratch of pp_multi_run_static (for callers that cannot allocate device
+// memory): the graph table, the validation word and the push contributions of
+// one call live in this file-scope array, of which every device the library
+// runs on holds one copy for the life of the process.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in symbol): the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kMultiStaticBytes = PP_MULTI_STATIC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kMultiStaticBytes];
+
+constexpr int kMaxDevices = 64;
+
+// Device address of this device's copy of `scratch` (looked up on the first
+// call on each device, with that device current).
+static pp_status static_scratch(void** out) {
+    static std::mutex mu;
+    static void* ptr[kMaxDevices] = {};
+    int dev = 0;
+    PP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(PP_E_UNSUPPORTED, "device ordinal beyond the static table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return set_error(PP_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    return PP_OK;
+}
+
 }  // namespace pp
 
 using namespace pp;
@@ -568,16 +601,20 @@ PP_EXPORT size_t pp_multi_workspace_bytes(int32_t num_graphs, int64_t total_vert
     return multi_layout(num_graphs, total_vertices).total;
 }
 
-PP_EXPORT pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, const int64_t* graph_nnz,
-                                 const int32_t* off, const uint16_t* idx, const int32_t* in_off,
-                                 const uint16_t* in_idx, pp_dir pr_dir, int32_t pr_iters, float f, float* x,
-                                 int32_t bfs_policy, int32_t bfs_root, float alpha, float beta, int32_t* level,
-                                 int32_t* parent, void* ws, size_t ws_bytes, void* stream) {
+namespace pp {
+
+// The call behind pp_multi_run and pp_multi_run_static: ws is the workspace
+// (caller memory, or the static scratch of this file).
+static pp_status multi_run(int32_t num_graphs, const int32_t* graph_n, const int64_t* graph_nnz, const int32_t* off,
+                           const uint16_t* idx, const int32_t* in_off, const uint16_t* in_idx, pp_dir pr_dir,
+                           int32_t pr_iters, float f, float* x, int32_t bfs_policy, int32_t bfs_root, float alpha,
+                           float beta, int32_t* level, int32_t* parent, void* ws, size_t ws_bytes, bool static_ws,
+                           void* stream) {
     clear_error();
     if (num_graphs < 0) return set_error(PP_E_SIZE, "num_graphs must be >= 0");
     if (num_graphs == 0) return PP_OK;
     if (!graph_n || !graph_nnz) return set_error(PP_E_NULL, "graph_n and graph_nnz (host arrays) are required");
-    if (!off || !in_off || !ws) return set_error(PP_E_NULL, "off, in_off and ws are required");
+    if (!off || !in_off || (!ws && !static_ws)) return set_error(PP_E_NULL, "off, in_off and ws are required");
     if (pr_dir != PP_PUSH && pr_dir != PP_PULL) return set_error(PP_E_RANGE, "pr_dir must be PP_PUSH or PP_PULL");
     if (pr_iters < 0) return set_error(PP_E_RANGE, "pr_iters must be >= 0");
     if (pr_iters > 0 && !x) return set_error(PP_E_NULL, "x is required when pr_iters > 0");
@@ -603,6 +640,15 @@ PP_EXPORT pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, con
     }
     if (total_nnz > 0 && (!idx || !in_idx)) return set_error(PP_E_NULL, "idx and in_idx are required");
     const MultiLayout ML = multi_layout(num_graphs, vb);
+    if (static_ws && ML.total > kMultiStaticBytes)
+        return set_error(PP_E_WORKSPACE, "pp_multi_run_static: the graphs need " + std::to_string(ML.total) +
+                                             " bytes of scratch, more than its " + std::to_string(kMultiStaticBytes) +
+                                             " (use pp_multi_run with a caller workspace)");
+    if (static_ws) {
+        pp_status st_ptr = static_scratch(&ws);
+        if (st_ptr != PP_OK) return st_ptr;
+        ws_bytes = kMultiStaticBytes;
+    }
     if (ws_bytes < ML.total) return set_error(PP_E_WORKSPACE, "workspace too small");
     // largest graphs first (workgroups are dispatched roughly in index order)
     std::vector<int32_t> order(num_graphs);
@@ -656,4 +702,24 @@ PP_EXPORT pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, con
     PP_HIP(hipStreamSynchronize(st));
     if (herr) return set_error(PP_E_GRAPH, "a graph of the arena has malformed offsets or an id past its n");
     return PP_OK;
+}
+
+}  // namespace pp
+
+PP_EXPORT pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, const int64_t* graph_nnz,
+                                 const int32_t* off, const uint16_t* idx, const int32_t* in_off,
+                                 const uint16_t* in_idx, pp_dir pr_dir, int32_t pr_iters, float f, float* x,
+                                 int32_t bfs_policy, int32_t bfs_root, float alpha, float beta, int32_t* level,
+                                 int32_t* parent, void* ws, size_t ws_bytes, void* stream) {
+    return multi_run(num_graphs, graph_n, graph_nnz, off, idx, in_off, in_idx, pr_dir, pr_iters, f, x, bfs_policy,
+                     bfs_root, alpha, beta, level, parent, ws, ws_bytes, false, stream);
+}
+
+PP_EXPORT pp_status pp_multi_run_static(int32_t num_graphs, const int32_t* graph_n, const int64_t* graph_nnz,
+                                        const int32_t* off, const uint16_t* idx, const int32_t* in_off,
+                                        const uint16_t* in_idx, pp_dir pr_dir, int32_t pr_iters, float f, float* x,
+                                        int32_t bfs_policy, int32_t bfs_root, float alpha, float beta,
+                                        int32_t* level, int32_t* parent, void* stream) {
+    return multi_run(num_graphs, graph_n, graph_nnz, off, idx, in_off, in_idx, pr_dir, pr_iters, f, x, bfs_policy,
+                     bfs_root, alpha, beta, level, parent, nullptr, 0, true, stream);
 }
