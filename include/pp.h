@@ -137,6 +137,23 @@ pp_status pp_set_push_tuning(int32_t hot, int32_t push_blocks);
  * pp_graph_create. */
 pp_status pp_set_pull_tuning(int32_t pull_hot, int32_t pull_block);
 
+/* Tiled pull (relabelled unweighted graphs): the in-edges of the heaviest
+ * rows -- a prefix [0, R) of the degree-ordered ids, R at most `rows`, every
+ * such row with at least max(16, S/2) in-edges -- are regrouped at
+ * registration by source slice of `width` ids (S slices).  A pull sweep then
+ * stages one slice of contributions in LDS per tile of rows, so those rows
+ * gather only from LDS through 16-bit offsets, writes one partial sum per
+ * (slice, row) and adds each row's partials in slice order; the other rows
+ * are pulled as usual in the same launch.  Same sum in a different fixed
+ * order: still bit-reproducible.  rows = 0 turns it off (default 0); width a
+ * multiple of 64 in [64, 32768] (default 32768: offsets within a slice take
+ * 15 bits of a 16-bit entry).  Takes effect at the next
+ * pp_graph_create; the workspace query accounts for it. */
+pp_status pp_set_pull_slices(int32_t rows, int32_t width);
+
+/* The tiled-pull plan of g: info[0..4) = R, width, S, tiles (R = 0: off). */
+pp_status pp_graph_slices(pp_graph g, int32_t* info);
+
 /* --------------------------------------------------------------- PageRank */
 /* One Jacobi step of the PageRank equation (Sec. 3.1):
  *   y[u] = (1-f)/n + f * sum over edges (v,u) of P_uv * x[v],

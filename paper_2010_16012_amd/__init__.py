@@ -73,6 +73,10 @@ class Graph:
         _lib.pp_graph_relabel_map(self.handle, perm)
         return perm
 
+    def slices(self):
+        """(R, width, S, tiles) of the tiled pull (R = 0: plain pull only)."""
+        return _lib.pp_graph_slices(self.handle)
+
     def bins(self, direction=PP_PULL):
         return _lib.pp_graph_bins(self.handle, direction)
 

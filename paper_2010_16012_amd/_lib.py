@@ -85,6 +85,8 @@ _SIGS = {
                       _SZ, _P], ctypes.c_int),
     "pp_multi_run_static": ([_I32, _P, _P, _P, _P, _P, _P, ctypes.c_int, _I32, _F32, _P, _I32, _I32, _F32, _F32, _P,
                              _P, _P], ctypes.c_int),
+    "pp_set_pull_slices": ([_I32, _I32], ctypes.c_int),
+    "pp_graph_slices": ([_P, _P], ctypes.c_int),
     "pp_ppr_run": ([_P, ctypes.c_int, _I32, _P, _I32, _F32, _F32, _I32, _P, _P, _SZ, ctypes.POINTER(_I32), _P],
                    ctypes.c_int),
     "pp_ppr_adjoint": ([_P, ctypes.c_int, _I32, _P, _P, _I32, _F32, _F32, _I32, _P, _P, _P, _SZ,
@@ -228,6 +230,17 @@ def pp_bfs_run(h, root, policy, alpha, beta, level, parent, state, stream=None) 
     _check(_lib.pp_bfs_run(h, root, policy, alpha, beta, _ptr(level), _ptr(parent), _ptr(state), state.numel(),
                            ctypes.byref(st), _stream(stream)))
     return st
+
+
+def pp_set_pull_slices(rows: int, width: int) -> None:
+    _check(_lib.pp_set_pull_slices(rows, width))
+
+
+def pp_graph_slices(h):
+    """(R, width, S, tiles) of the tiled pull of a registered graph (R = 0: off)."""
+    info = (_I32 * 4)()
+    _check(_lib.pp_graph_slices(h, info))
+    return tuple(info)
 
 
 # pp_bfs_level: int32 dir, int32 frontier, int64 frontier_edges (16 bytes)

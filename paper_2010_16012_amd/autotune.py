@@ -26,7 +26,8 @@ import torch
 from . import PP_PULL, PP_PUSH, PP_SWITCH, BfsRun, Graph, _lib, pagerank_into, ppr
 
 DEFAULTS = {"upper": [4, 16, 64, 1024, 4096], "split_chunk": 4096, "hot": 8192, "push_blocks": 1024,
-            "pull_hot": 32768, "pull_block": 1024, "alpha": 14.0, "beta": 24.0, "k_tile": 32}
+            "pull_hot": 32768, "pull_block": 1024, "slice_rows": 0, "slice_width": 32768, "alpha": 14.0,
+            "beta": 24.0, "k_tile": 32}
 
 
 def arch() -> str:
@@ -47,6 +48,7 @@ def apply(cfg: dict) -> None:
     _lib.pp_set_bin_thresholds(c["upper"], c["split_chunk"])
     _lib.pp_set_push_tuning(c["hot"], c["push_blocks"])
     _lib.pp_set_pull_tuning(c["pull_hot"], c["pull_block"])
+    _lib.pp_set_pull_slices(c["slice_rows"], c["slice_width"])
 
 
 def load(path: str, n: int, nnz: int, gpu_arch: str | None = None) -> dict:

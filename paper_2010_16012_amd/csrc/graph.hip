@@ -8,6 +8,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -343,9 +344,20 @@ __global__ void k_zero_i32(int32_t n, int32_t* p) {
 // ------------------------------------------------------------------ host side
 struct WsLayout {
     size_t inv_s, out_deg, pull_list, push_list, buf0, buf1, buf2, csc_w, csc_row, split_tab, split_part, hot_part, err,
-        tiles, keys, perm, iperm, r_csr_off, r_csr_idx, r_csc_off, r_csc_idx, r_csr_w, total;
+        tiles, keys, perm, iperm, r_csr_off, r_csc_off, r_csr_idx, r_csc_idx, r_csr_w, sl_idx, sl_prow,
+        sl_units, sl_segs, sl_wg, sl_part, sl_cpart, sl_cbeg, total;
     int32_t split_cap;
+    int64_t sl_rows_cap, sl_slices_cap, sl_pairs_cap, sl_units_cap, sl_chunks_cap, sl_idx_cap;
 };
+
+// Tiled pull: rows qualify while their in-degree is at least
+// max(kTileMinDeg, S/2) (the partial sums cost 8 bytes per slice and row).
+constexpr int32_t kTileMinDeg = 16;
+constexpr int32_t kTileMaxGroups = 4096;
+
+static bool sliced_layout(uint32_t flags, const Tuning& t) {
+    return (flags & PP_GRAPH_RELABEL) && !(flags & PP_GRAPH_WEIGHTED) && t.slice_rows > 0 && t.slice_width > 0;
+}
 
 static int32_t split_capacity(int64_t nnz, const Tuning& t) {
     int64_t cap = (nnz + t.split_chunk - 1) / t.split_chunk + nnz / ((int64_t)t.upper[PP_NUM_BINS - 2] + 1) + 1;
@@ -393,6 +405,29 @@ static WsLayout layout(int32_t n, int64_t nnz, uint32_t flags, const Tuning& t, 
             L.r_csc_idx = take(nz * 4);
         }
         if (weighted) L.r_csr_w = take(nz * 4);
+    }
+    if (sliced_layout(flags, t)) {
+        // rows that qualify have at least kTileMinDeg in-edges: at most nnz / kTileMinDeg of them
+        const int64_t R = std::min<int64_t>(std::min<int64_t>(t.slice_rows, n), std::max<int64_t>(nnz / kTileMinDeg, 1));
+        const int64_t S = ceil_div(n, t.slice_width);
+        const int64_t P = std::min<int64_t>(S * R, std::max<int64_t>(nnz, 1));
+        L.sl_rows_cap = R;
+        L.sl_slices_cap = S;
+        L.sl_pairs_cap = P;
+        L.sl_chunks_cap = 2 * (nnz / kSegChunk) + 1;
+        // a unit closes when the next segment does not fit: two consecutive
+        // units hold more than kUnitEdges edges or the first kUnitPairs pairs
+        L.sl_units_cap = 2 * (nnz / kUnitEdges) + P / kUnitPairs + 2 * S + 8;
+        // every unit and chunk starts 8-aligned; 16 spare entries past the end
+        L.sl_idx_cap = nz + 8 * (L.sl_units_cap + L.sl_chunks_cap) + 16;
+        L.sl_idx = take((size_t)L.sl_idx_cap * 2);
+        L.sl_prow = take((size_t)P * 4);
+        L.sl_units = take((size_t)(L.sl_units_cap + L.sl_chunks_cap) * sizeof(SliceUnit));
+        L.sl_segs = take((size_t)(kTileMaxGroups + S) * sizeof(SliceSeg));
+        L.sl_wg = take((size_t)(kTileMaxGroups + 1) * 4);
+        L.sl_part = take((size_t)(S * R) * 4);
+        L.sl_cpart = take((size_t)L.sl_chunks_cap * 4);
+        L.sl_cbeg = take((size_t)(R + 1) * 4);
     }
     L.total = p;
     return L;
@@ -505,6 +540,243 @@ static pp_status bins_for(pp_graph g, const int32_t* off, int32_t* list, int32_t
     return PP_OK;
 }
 
+// Runs fn(lo, hi) over [0, count) split into contiguous ranges on a few host threads.
+template <typename F>
+static void parallel_ranges(int64_t count, const F& fn) {
+    const int64_t nt = std::max<int64_t>(1, std::min<int64_t>(std::thread::hardware_concurrency(), 16));
+    if (count < 4096 || nt == 1) {
+        fn((int64_t)0, count);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int64_t i = 0; i < nt; ++i) th.emplace_back([&, i] { fn(count * i / nt, count * (i + 1) / nt); });
+    for (auto& t : th) t.join();
+}
+
+// Builds the tiled-pull plan (SlicePlan) from the relabelled in-adjacency on
+// the host (once, at registration) and uploads it into the workspace.
+static pp_status build_slices(pp_graph g, const WsLayout& L, char* base, hipStream_t st) {
+    SlicePlan& sp = g->slices;
+    sp = SlicePlan{};
+    const Tuning& t = g->tune;
+    if (!sliced_layout(g->flags, t) || L.sl_rows_cap <= 0) return PP_OK;
+    const int32_t n = g->d.n;
+    const int32_t W = t.slice_width;
+    const int32_t waves = std::max(t.pull_block / kWave, 1);
+    if (tiled_lds_bytes(W, waves) > (size_t)g->max_lds) return PP_OK;  // does not fit this device's LDS
+    const int64_t Rc = L.sl_rows_cap;
+    std::vector<int32_t> roff((size_t)Rc + 1);
+    PP_HIP(hipMemcpyAsync(roff.data(), g->d.csc_off, roff.size() * 4, hipMemcpyDeviceToHost, st));
+    PP_HIP(hipStreamSynchronize(st));
+    const int64_t E_cap = roff[Rc];
+    std::vector<int32_t> idx((size_t)std::max<int64_t>(E_cap, 1));
+    if (E_cap > 0) PP_HIP(hipMemcpyAsync(idx.data(), g->d.csc_idx, (size_t)E_cap * 4, hipMemcpyDeviceToHost, st));
+    PP_HIP(hipStreamSynchronize(st));
+    // slices that hold a source of the candidate rows
+    int32_t maxv = 0;
+    for (int64_t j = 0; j < E_cap; ++j) maxv = std::max(maxv, idx[j]);
+    const int32_t S = std::min<int32_t>(maxv / W + 1, (int32_t)L.sl_slices_cap);
+    // the qualifying prefix of rows
+    const int32_t min_deg = std::max(kTileMinDeg, S / 2);
+    int32_t R = 0;
+    while (R < Rc && roff[R + 1] - roff[R] >= min_deg) ++R;
+    if (R == 0) return PP_OK;
+    // segment lengths, slice-major (s * R + u), and every row's sources
+    // grouped by slice in stored order (row-major scratch)
+    std::vector<int32_t> seg((size_t)S * R, 0);
+    parallel_ranges(R, [&](int64_t lo, int64_t hi) {
+        for (int64_t u = lo; u < hi; ++u)
+            for (int64_t j = roff[u]; j < roff[u + 1]; ++j) ++seg[(size_t)(idx[j] / W) * R + u];
+    });
+    std::vector<int32_t> rstart((size_t)R * S);  // where segment (s, u) starts in the row-major scratch
+    std::vector<uint16_t> scratch((size_t)std::max<int64_t>(roff[R], 1));
+    parallel_ranges(R, [&](int64_t lo, int64_t hi) {
+        for (int64_t u = lo; u < hi; ++u) {
+            int32_t at = roff[u];
+            for (int32_t s2 = 0; s2 < S; ++s2) {
+                rstart[(size_t)u * S + s2] = at;
+                at += seg[(size_t)s2 * R + u];
+            }
+            std::vector<int32_t> cur(rstart.begin() + u * S, rstart.begin() + (u + 1) * S);
+            for (int64_t j = roff[u]; j < roff[u + 1]; ++j) {
+                const int32_t v = idx[j], s2 = v / W;
+                scratch[cur[s2]++] = (uint16_t)(v - s2 * W);
+            }
+        }
+    });
+    // chunks of long segments, numbered row by row (the combine adds a row's
+    // chunks [cbeg[u], cbeg[u+1]) after its slice partials)
+    std::vector<int32_t> cbeg((size_t)R + 1, 0);
+    int64_t nchunks = 0;
+    for (int32_t u = 0; u < R; ++u) {
+        cbeg[u] = (int32_t)nchunks;
+        for (int32_t s2 = 0; s2 < S; ++s2) {
+            const int32_t len = seg[(size_t)s2 * R + u];
+            if (len >= kSegLong) nchunks += (len + kSegChunk - 1) / kSegChunk;
+        }
+    }
+    cbeg[R] = (int32_t)nchunks;
+    if (nchunks > L.sl_chunks_cap) return set_error(PP_E_WORKSPACE, "tiled pull: chunk table overflow");
+    // units, slice by slice: segments packed whole into units of at most
+    // kUnitEdges edges and kUnitPairs segments, each unit 8-aligned
+    std::vector<uint16_t> out;
+    out.reserve((size_t)roff[R] + 8 * 1024);
+    std::vector<int32_t> prow;
+    std::vector<SliceUnit> units;
+    std::vector<int64_t> cost;
+    constexpr int64_t kUnitCost = 64;  // fixed cost of a unit, in edges
+    for (int32_t s2 = 0; s2 < S; ++s2) {
+        const int32_t* sg = seg.data() + (size_t)s2 * R;
+        int32_t u = 0;
+        while (u < R) {
+            if (sg[u] == 0 || sg[u] >= kSegLong) {
+                ++u;
+                continue;
+            }
+            while (out.size() % 8) out.push_back(0);  // pads sit past the previous unit's end
+            const int32_t a = (int32_t)out.size(), p0 = (int32_t)prow.size();
+            int32_t edges = 0, pairs = 0;
+            for (; u < R; ++u) {
+                const int32_t len = sg[u];
+                if (len == 0 || len >= kSegLong) continue;
+                if (edges + len > kUnitEdges || pairs == kUnitPairs) break;
+                const uint16_t* src = scratch.data() + rstart[(size_t)u * S + s2];
+                out.push_back((uint16_t)(src[0] | kSegHead));
+                out.insert(out.end(), src + 1, src + len);
+                prow.push_back(u);
+                edges += len;
+                ++pairs;
+            }
+            units.push_back(SliceUnit{s2, a, a + edges, p0});
+            cost.push_back(kUnitCost + edges + 4 * pairs);
+        }
+    }
+    const int64_t unit_count = (int64_t)units.size();
+    // chunk units, slice by slice after all units (each chunk 8-aligned)
+    std::vector<int32_t> cnext(cbeg.begin(), cbeg.end() - 1);
+    std::vector<SliceUnit> cunits;
+    for (int32_t u = 0; u < R; ++u)
+        for (int32_t s2 = 0; s2 < S; ++s2) {
+            const int32_t len = seg[(size_t)s2 * R + u];
+            if (len < kSegLong) continue;
+            const uint16_t* src = scratch.data() + rstart[(size_t)u * S + s2];
+            for (int32_t c0 = 0; c0 < len; c0 += kSegChunk) {
+                const int32_t c1 = std::min(c0 + kSegChunk, len);
+                while (out.size() % 8) out.push_back(0);
+                const int32_t a = (int32_t)out.size();
+                out.insert(out.end(), src + c0, src + c1);
+                cunits.push_back(SliceUnit{s2, a, a + (c1 - c0), -(cnext[u]++) - 1});
+            }
+        }
+    // merge: per slice, its chunk units then its units (both were built in
+    // slice order)
+    std::vector<SliceUnit> all;
+    std::vector<int64_t> all_cost;
+    {
+        std::stable_sort(cunits.begin(), cunits.end(),
+                         [](const SliceUnit& x, const SliceUnit& y) { return x.slice < y.slice; });
+        size_t i = 0, j = 0;
+        for (int32_t s2 = 0; s2 < S; ++s2) {
+            for (; j < cunits.size() && cunits[j].slice == s2; ++j) {
+                all.push_back(cunits[j]);
+                all_cost.push_back(kUnitCost + (cunits[j].b - cunits[j].a));
+            }
+            for (; i < units.size() && units[i].slice == s2; ++i) {
+                all.push_back(units[i]);
+                all_cost.push_back(cost[i]);
+            }
+        }
+    }
+    for (int k = 0; k < 16; ++k) out.push_back(0);  // wide loads may read past the last unit
+    if ((int64_t)out.size() > L.sl_idx_cap || (int64_t)prow.size() > L.sl_pairs_cap ||
+        unit_count > L.sl_units_cap || (int64_t)cunits.size() > L.sl_chunks_cap)
+        return set_error(PP_E_WORKSPACE, "tiled pull: unit table overflow");
+    // contiguous unit ranges of about equal cost, one per workgroup, split
+    // into runs of one slice each
+    const int32_t groups = std::max(1, std::min(g->num_cu, kTileMaxGroups));
+    int64_t total = 0;
+    for (int64_t c : all_cost) total += c;
+    std::vector<int32_t> wg((size_t)groups + 1, 0);
+    std::vector<SliceSeg> segs;
+    {
+        int64_t run = 0;
+        size_t k = 0;
+        for (int32_t w = 0; w < groups; ++w) {
+            wg[w] = (int32_t)segs.size();
+            const size_t k0 = k;
+            const int64_t goal = total * (w + 1) / groups;
+            while (k < all.size() && (w == groups - 1 || run + all_cost[k] / 2 <= goal)) run += all_cost[k++];
+            for (size_t a = k0; a < k;) {
+                size_t b = a;
+                while (b < k && all[b].slice == all[a].slice) ++b;
+                segs.push_back(SliceSeg{all[a].slice, (int32_t)a, (int32_t)b, 0});
+                a = b;
+            }
+        }
+        wg[groups] = (int32_t)segs.size();
+    }
+    if ((int64_t)segs.size() > kTileMaxGroups + S) return set_error(PP_E_WORKSPACE, "tiled pull: run table overflow");
+    // upload; the dense partials start (and, where no unit writes, stay) zero
+    GraphDev& d = g->d;
+    d.sl_idx = reinterpret_cast<uint16_t*>(base + L.sl_idx);
+    d.sl_prow = reinterpret_cast<int32_t*>(base + L.sl_prow);
+    d.sl_units = reinterpret_cast<SliceUnit*>(base + L.sl_units);
+    d.sl_segs = reinterpret_cast<SliceSeg*>(base + L.sl_segs);
+    d.sl_wg = reinterpret_cast<int32_t*>(base + L.sl_wg);
+    d.sl_part = reinterpret_cast<float*>(base + L.sl_part);
+    d.sl_cpart = reinterpret_cast<float*>(base + L.sl_cpart);
+    d.sl_cbeg = reinterpret_cast<int32_t*>(base + L.sl_cbeg);
+    PP_HIP(hipMemcpyAsync(d.sl_idx, out.data(), out.size() * 2, hipMemcpyHostToDevice, st));
+    if (!prow.empty()) PP_HIP(hipMemcpyAsync(d.sl_prow, prow.data(), prow.size() * 4, hipMemcpyHostToDevice, st));
+    if (!all.empty())
+        PP_HIP(hipMemcpyAsync(d.sl_units, all.data(), all.size() * sizeof(SliceUnit), hipMemcpyHostToDevice, st));
+    if (!segs.empty())
+        PP_HIP(hipMemcpyAsync(d.sl_segs, segs.data(), segs.size() * sizeof(SliceSeg), hipMemcpyHostToDevice, st));
+    PP_HIP(hipMemcpyAsync(d.sl_wg, wg.data(), wg.size() * 4, hipMemcpyHostToDevice, st));
+    PP_HIP(hipMemcpyAsync(d.sl_cbeg, cbeg.data(), cbeg.size() * 4, hipMemcpyHostToDevice, st));
+    PP_HIP(hipMemsetAsync(d.sl_part, 0, (size_t)S * R * sizeof(float), st));
+    // the pull plan without rows < R: they come first within each bin's list
+    // (the partition is stable and ids ascend), and bin-5 rows < R own the
+    // first split-table entries
+    const BinPlan& pp_ = g->pull_plan;
+    std::vector<int32_t> list((size_t)n);
+    PP_HIP(hipMemcpyAsync(list.data(), d.pull_list, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+    std::vector<int32_t> first((size_t)pp_.count[5] + 1);
+    const int32_t* tab_first = d.split_tab + 3 * (size_t)g->split_cap;
+    PP_HIP(hipMemcpyAsync(first.data(), tab_first, first.size() * 4, hipMemcpyDeviceToHost, st));
+    PP_HIP(hipStreamSynchronize(st));
+    int32_t counts[PP_NUM_BINS];
+    for (int b = 0; b < PP_NUM_BINS; ++b) {
+        int32_t k = 0;
+        while (k < pp_.count[b] && list[pp_.list_off[b] + k] < R) ++k;
+        for (int32_t i = k; i < pp_.count[b]; ++i)
+            if (list[pp_.list_off[b] + i] < R) return set_error(PP_E_UNSUPPORTED, "tiled pull: bin lists out of order");
+        sp.list_skip[b] = k;
+        counts[b] = pp_.count[b] - k;
+    }
+    sp.fix0 = sp.list_skip[5];
+    sp.tab0 = first[sp.fix0];
+    sp.nsplit = pp_.count[5] - sp.fix0;
+    int32_t waves_b[PP_NUM_BINS];
+    waves_b[5] = g->split_pull_entries - sp.tab0;
+    for (int b = 0; b < PP_NUM_BINS - 1; ++b) waves_b[b] = ceil_div(counts[b], kWave / kPullLanes[b]);
+    int32_t at = 0;
+    for (int b = PP_NUM_BINS - 1; b >= 0; --b) {
+        sp.wave_off[b] = at;
+        at += waves_b[b];
+    }
+    sp.wave_off[PP_NUM_BINS] = at;
+    sp.units = at;
+    sp.rows = R;
+    sp.width = W;
+    sp.slices = S;
+    sp.tiles = (int32_t)all.size();
+    sp.pairs = (int32_t)prow.size();
+    sp.chunks = (int32_t)nchunks;
+    sp.groups = groups;
+    return PP_OK;
+}
+
 static pp_status check_arrays(int32_t n, int64_t nnz, const int32_t* off, const int32_t* idx, int32_t* err,
                               int32_t* host, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, 2, err);
@@ -581,6 +853,26 @@ PP_EXPORT pp_status pp_set_pull_tuning(int32_t pull_hot, int32_t pull_block) {
     return PP_OK;
 }
 
+PP_EXPORT pp_status pp_set_pull_slices(int32_t rows, int32_t width) {
+    clear_error();
+    if (rows < 0) return set_error(PP_E_RANGE, "rows must be >= 0");
+    if (width < 64 || width > kSliceMax || width % 64 != 0)
+        return set_error(PP_E_RANGE, "width must be a multiple of 64 in [64, 32768]");
+    tuning().slice_rows = rows;
+    tuning().slice_width = width;
+    return PP_OK;
+}
+
+PP_EXPORT pp_status pp_graph_slices(pp_graph g, int32_t* info) {
+    clear_error();
+    if (!g || !info) return set_error(PP_E_NULL, "graph or info is NULL");
+    info[0] = g->slices.rows;
+    info[1] = g->slices.width;
+    info[2] = g->slices.slices;
+    info[3] = g->slices.tiles;
+    return PP_OK;
+}
+
 PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_off, const int32_t* csr_idx,
                                     const int32_t* csc_off, const int32_t* csc_idx, const float* csr_w,
                                     const int32_t* csc_to_csr, uint32_t flags, void* ws, size_t ws_bytes,
@@ -637,6 +929,14 @@ PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_o
     d.split_part = static_cast<float*>(at(L.split_part));
     d.hot_part = static_cast<float*>(at(L.hot_part));
     d.err = static_cast<int32_t*>(at(L.err));
+    d.sl_idx = nullptr;
+    d.sl_prow = nullptr;
+    d.sl_units = nullptr;
+    d.sl_segs = nullptr;
+    d.sl_wg = nullptr;
+    d.sl_part = nullptr;
+    d.sl_cpart = nullptr;
+    d.sl_cbeg = nullptr;
     int32_t* tiles = static_cast<int32_t*>(at(L.tiles));
     uint8_t* keys = static_cast<uint8_t*>(at(L.keys));
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -731,6 +1031,8 @@ PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_o
     s = bins_for(g, d.csc_off, d.pull_list, tab_pull, cap, tiles, keys, g->pull_plan, g->split_pull_entries, st);
     if (s != PP_OK) return fail(s);
     s = bins_for(g, d.csr_off, d.push_list, tab_push, cap, tiles, keys, g->push_plan, g->split_push_entries, st);
+    if (s != PP_OK) return fail(s);
+    s = build_slices(g, L, base, st);
     if (s != PP_OK) return fail(s);
     *out = g;
     return PP_OK;

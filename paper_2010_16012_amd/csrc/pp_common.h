@@ -31,6 +31,14 @@ constexpr int kPullLoads[PP_NUM_BINS] = {4, 16, 16, 16, 16, 16};
 // in LDS by each workgroup of the persistent push sweep (160 KB of LDS).
 constexpr int kHotMax = 40960;
 
+// A slice of the tiled pull holds at most kSliceMax sources (15-bit offsets);
+// besides it the kernel keeps a zero word and 1 KB per wavefront in LDS.
+constexpr int kSliceMax = 32768;
+constexpr int kTiledWaveLds = 1024;
+inline size_t tiled_lds_bytes(int32_t width, int32_t waves) {
+    return (size_t)width * 4 + 16 + (size_t)waves * kTiledWaveLds;
+}
+
 struct Tuning {
     int32_t upper[PP_NUM_BINS - 1] = {4, 16, 64, 1024, 4096};
     int32_t split_chunk = 4096;
@@ -38,8 +46,64 @@ struct Tuning {
     int32_t push_blocks = 1024;  // workgroups of the persistent push sweep
     int32_t pull_hot = 32768;    // contributions staged in LDS by the pull sweep (0 = off)
     int32_t pull_block = 1024;   // threads per workgroup of the persistent pull sweep
+    int32_t slice_rows = 0;      // rows of the tiled pull (0 = off); see SlicePlan
+    int32_t slice_width = kSliceMax; // sources per slice of the tiled pull
 };
 Tuning& tuning();
+
+// Tiled pull sweep (relabelled unweighted graphs).  The in-edges of rows
+// [0, rows) -- the heaviest rows -- are regrouped by source slice: slice s
+// holds sources [s*width, (s+1)*width), and segment (s, u) lists the sources
+// of row u that fall in slice s as offsets from s*width.  A workgroup stages
+// one slice's contributions in LDS and its wavefronts sum segments into one
+// partial per (slice, row); a combine kernel adds the partials of each row in
+// slice order.  The other rows are pulled as usual ("rest").
+//
+// Index layout (16 bits per edge): the non-empty segments of a slice, rows
+// ascending, packed into wavefront units of at most kUnitEdges edges and
+// kUnitPairs segments, each unit starting 8-aligned; bit 15 marks the first
+// edge of a segment, bits 0-14 hold the source offset (width <= 2^15).
+// Segments of kSegLong or more edges are cut into chunks of kSegChunk edges,
+// stored 8-aligned after all units.
+constexpr int32_t kUnitEdges = 1024;  // 16 per lane
+constexpr int32_t kUnitPairs = 256;   // 4 per lane
+constexpr int32_t kSegLong = 1024;
+constexpr int32_t kSegChunk = 1024;
+constexpr uint32_t kSegHead = 0x8000u;
+
+// One wavefront's work: edges [a, b) of slice `slice`; p0 >= 0: a unit whose
+// segments are pairs p0, p0 + 1, ... of the pair list (their rows in
+// prow[]); p0 < 0: chunk -p0-1 of a long segment.
+struct SliceUnit {
+    int32_t slice;
+    int32_t a, b;
+    int32_t p0;
+};
+
+// A workgroup's units of one slice: [u0, u1).
+struct SliceSeg {
+    int32_t slice;
+    int32_t u0, u1;
+    int32_t pad;
+};
+
+struct SlicePlan {
+    int32_t rows = 0;    // R (0: the tiled pull is off)
+    int32_t width = 0;   // W
+    int32_t slices = 0;  // S
+    int32_t tiles = 0;   // work units
+    int32_t pairs = 0;   // non-empty segments
+    int32_t chunks = 0;  // chunks of long segments
+    int32_t groups = 0;  // workgroups the units are divided among (the launch's grid)
+    // the pull plan restricted to rows >= R: per bin, rows to skip at the
+    // front of the bin's list; split-table entries and split rows to skip
+    int32_t list_skip[PP_NUM_BINS] = {};
+    int32_t tab0 = 0;
+    int32_t fix0 = 0;
+    int32_t wave_off[PP_NUM_BINS + 1] = {};
+    int32_t units = 0;
+    int32_t nsplit = 0;
+};
 
 // Work decomposition of one binned sweep launch: every bin owns a contiguous
 // range of work units; heavy bins come first so the longest rows start first.
@@ -86,6 +150,18 @@ struct GraphDev {
     float* buf1;
     float* buf2;
     int32_t* err;             // device error word / counters
+    // tiled pull (SlicePlan): 16-bit sources, the row of every unit segment,
+    // work units, per-workgroup slice runs [groups+1 firsts], partial sums
+    // [S*R] (zero where a segment is empty or chunked), chunk partials and
+    // each row's first chunk [R+1]
+    uint16_t* sl_idx;
+    int32_t* sl_prow;
+    SliceUnit* sl_units;
+    SliceSeg* sl_segs;
+    int32_t* sl_wg;
+    float* sl_part;
+    float* sl_cpart;
+    int32_t* sl_cbeg;
 };
 
 // Caller id of internal vertex i.
@@ -100,6 +176,7 @@ struct pp_graph_s {
     bool relabelled;
     pp::BinPlan pull_plan;
     pp::BinPlan push_plan;
+    pp::SlicePlan slices;
     int32_t split_pull_entries;  // rows of the pull split table
     int32_t split_push_entries;
     int32_t split_cap;           // capacity of each split table
@@ -134,6 +211,25 @@ struct pp_graph_s {
 };
 
 namespace pp {
+
+// Teleport term and output layout of a pull sweep: y[u] = base + [u == vertex]
+// * extra + f * (gathered sum), written to y[caller id * y_stride].  PageRank:
+// base (1-f)/n, no vertex; one personalised column of an n x k matrix: base
+// 0, vertex the source, extra 1-f, stride k.
+struct Teleport {
+    float base;
+    int32_t vertex;  // internal id, -1: none
+    float extra;
+    int64_t y_stride;
+};
+Teleport uniform_teleport(int32_t n, float f);
+
+// Pull and push sweeps of one vector (pr.hip).  c: contributions (internal
+// ids); pull writes the next contributions and/or y; push accumulates into y
+// (internal ids, pre-set to the teleport).
+pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float f, hipStream_t st,
+                      int32_t skip_below = 0, const Teleport* tp = nullptr);
+pp_status launch_push(pp_graph g, const float* c, float* y, hipStream_t st);
 
 pp_status set_error(pp_status s, const std::string& msg);
 pp_status hip_error(hipError_t e, const char* what);

@@ -121,7 +121,9 @@ constexpr int unroll_for() {
 
 // ------------------------------------------------------------------ pull
 struct PullArgs {
-    SweepPlan sp;
+    SweepPlan sp;          // used by the hybrid push part (out-degree bins)
+    int32_t list_beg[PP_NUM_BINS];      // first entry of each bin's rows in `list`
+    int32_t list_cnt[PP_NUM_BINS];      // rows of each bin this sweep covers
     int32_t wave_off[PP_NUM_BINS + 1];  // wavefront units per bin (persistent sweep)
     int32_t units;
     int32_t hot;           // contributions below this id are staged in LDS
@@ -131,21 +133,30 @@ struct PullArgs {
     const int32_t* list;   // vertices grouped by in-degree bin
     const int32_t* tab;    // bin-5 chunk table (v | begin | end | first)
     int32_t tab_cap;
-    float* part;           // bin-5 partial sums
+    int32_t tab0;          // first chunk-table entry of this sweep's bin-5 units
+    float* part;           // bin-5 partial sums (indexed like the chunk table)
     const float* c;        // contributions of the current iterate
     const float* inv_s;
     const int32_t* perm;   // internal -> caller id (nullable)
     float* c_next;         // contributions of the new iterate (nullable)
     float* y;              // new iterate, caller ids (nullable)
-    float base;            // (1-f)/n
+    int64_t y_stride;      // y[caller id * y_stride]: 1, or k for a column of an n x k matrix
+    float base;            // teleport term of every row: (1-f)/n, or 0 when personalised
+    int32_t tele_v;        // internal id of the personalised teleport row (-1: none)
+    float tele;            // (1-f) added to row tele_v
     float f;
     int32_t skip_below;    // rows u < skip_below are left to the hybrid's push part (0: none)
 };
 
-// Owner of u writes y = base + acc and the next contribution.
+// Teleport term of row u.
+__device__ __forceinline__ float row_base(const PullArgs& a, int32_t u) {
+    return a.base + ((u == a.tele_v) ? a.tele : 0.f);
+}
+
+// Owner of u writes y = teleport + acc and the next contribution.
 __device__ __forceinline__ void pull_finish(const PullArgs& a, int32_t u, float acc) {
-    const float yv = a.base + acc;
-    if (a.y) a.y[user_id(a.perm, u)] = yv;
+    const float yv = row_base(a, u) + acc;
+    if (a.y) a.y[(int64_t)user_id(a.perm, u) * a.y_stride] = yv;
     if (a.c_next) a.c_next[u] = a.f * yv * a.inv_s[u];
 }
 
@@ -178,15 +189,14 @@ __device__ __forceinline__ PullTask pull_task(const PullArgs& a, int32_t unit, i
     t.bin = wave_unit_bin(a.wave_off, unit);
     t.lu = unit - a.wave_off[t.bin];
     if (t.bin == PP_NUM_BINS - 1) {
-        t.row = a.tab[t.lu];
+        t.row = a.tab[a.tab0 + t.lu];
     } else {
         int g = kPullLanes[0];
 #pragma unroll
         for (int b = 1; b < PP_NUM_BINS - 1; ++b)
             if (t.bin == b) g = kPullLanes[b];
         const int32_t i = t.lu * (kWave / g) + lane / g;
-        const int32_t count = a.sp.list_off[t.bin + 1] - a.sp.list_off[t.bin];
-        t.row = (i < count) ? a.list[a.sp.list_off[t.bin] + i] : -1;
+        t.row = (i < a.list_cnt[t.bin]) ? a.list[a.list_beg[t.bin] + i] : -1;
     }
     return t;
 }
@@ -194,8 +204,8 @@ __device__ __forceinline__ PullTask pull_task(const PullArgs& a, int32_t unit, i
 // Second stage: the slot range (and, bins 0-4, 1/s of the row).
 __device__ __forceinline__ void pull_bounds(const PullArgs& a, PullTask& t) {
     if (t.bin == PP_NUM_BINS - 1) {
-        t.b = a.tab[a.tab_cap + t.lu];
-        t.e = a.tab[2 * a.tab_cap + t.lu];
+        t.b = a.tab[a.tab_cap + a.tab0 + t.lu];
+        t.e = a.tab[2 * a.tab_cap + a.tab0 + t.lu];
     } else if (t.bin >= 0 && t.row >= 0) {
         t.b = a.off[t.row];
         t.e = a.off[t.row + 1];
@@ -213,31 +223,20 @@ __device__ __forceinline__ void pull_unit(const PullArgs& a, const PullTask& t, 
     float acc = gather_row<G, U, W, HOT>(a.idx, a.wt, a.c, t.b, t.e, gl, s_c, a.hot);
     acc = group_reduce<G>(acc);
     if (gl == 0) {
-        const float yv = a.base + acc;
-        if (a.y) a.y[user_id(a.perm, t.row)] = yv;
+        const float yv = row_base(a, t.row) + acc;
+        if (a.y) a.y[(int64_t)user_id(a.perm, t.row) * a.y_stride] = yv;
         if (a.c_next) a.c_next[t.row] = a.f * yv * t.inv_s;
     }
 }
 
-// Persistent pull sweep: every workgroup first copies c[0, hot) -- the
-// contributions of the heaviest vertices, which most gathers hit -- into
-// LDS, then its wavefronts take units w, w + W, ... (W = wavefronts in the
-// grid).  No atomics: every output has exactly one writer.  The units of a
-// wavefront are pipelined: while unit t gathers, the row bounds of unit
-// t + W and the list entry of unit t + 2W are already on their way, so a
-// unit waits for two memory round trips (indices, then gathers) instead of
-// four.
+// The wavefront units of a persistent pull sweep: this wavefront takes units
+// first, first + nw, ...  The units are pipelined: while unit t gathers, the
+// row bounds of unit t + nw and the list entry of unit t + 2 nw are already
+// on their way, so a unit waits for two memory round trips (indices, then
+// gathers) instead of four.  No atomics: every output has exactly one writer.
 template <bool W, bool HOT>
-__global__ __launch_bounds__(1024) void k_pr_pull(PullArgs a) {
-    extern __shared__ float s_c[];
-    if (HOT) {
-        for (int32_t i = threadIdx.x; i < a.hot; i += blockDim.x) s_c[i] = a.c[i];
-        __syncthreads();
-    }
+__device__ __forceinline__ void pull_sweep(const PullArgs& a, const float* s_c, int32_t first, int32_t nw) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int32_t nw = gridDim.x * (blockDim.x / kWave);
-    // the unit number is wavefront-uniform: keep it (and the bin) in scalar registers
-    const int32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
     PullTask next = pull_task(a, first, lane);
     pull_bounds(a, next);
     PullTask after = pull_task(a, first + nw, lane);
@@ -252,7 +251,7 @@ __global__ __launch_bounds__(1024) void k_pr_pull(PullArgs a) {
                 float acc =
                     gather_row<kPullLanes[5], kPullLoads[5], W, HOT>(a.idx, a.wt, a.c, t.b, t.e, lane, s_c, a.hot);
                 acc = group_reduce<kWave>(acc);
-                if (lane == 0) a.part[t.lu] = acc;
+                if (lane == 0) a.part[a.tab0 + t.lu] = acc;
                 break;
             }
             case 4: pull_unit<4, W, HOT>(a, t, lane, s_c); break;
@@ -264,15 +263,248 @@ __global__ __launch_bounds__(1024) void k_pr_pull(PullArgs a) {
     }
 }
 
-// Sums the chunk partials of every split row in chunk order (deterministic).
-__global__ void k_pr_pull_fix(PullArgs a, int32_t nsplit) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nsplit) return;
+// Copies c[0, count) into LDS (float4 loads, four in flight per thread).
+__device__ __forceinline__ void stage_lds(float* dst, const float* __restrict__ src, int32_t count) {
+    const int32_t n4 = count >> 2;
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+    float4* d4 = reinterpret_cast<float4*>(dst);
+    const int32_t bd = blockDim.x;
+    for (int32_t i0 = threadIdx.x; i0 < n4; i0 += 4 * bd) {
+        float4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = s4[min(i0 + k * bd, n4 - 1)];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i0 + k * bd < n4) d4[i0 + k * bd] = v[k];
+    }
+    for (int32_t i = 4 * n4 + threadIdx.x; i < count; i += bd) dst[i] = src[i];
+}
+
+// Persistent pull sweep: every workgroup first copies c[0, hot) -- the
+// contributions of the heaviest vertices, which most gathers hit -- into
+// LDS, then its wavefronts take units w, w + W, ... (W = wavefronts in the
+// grid).
+template <bool W, bool HOT>
+__global__ __launch_bounds__(1024) void k_pr_pull(PullArgs a) {
+    extern __shared__ float s_c[];
+    if (HOT) {
+        if ((reinterpret_cast<uintptr_t>(a.c) & 15) == 0) stage_lds(s_c, a.c, a.hot);
+        else for (int32_t i = threadIdx.x; i < a.hot; i += blockDim.x) s_c[i] = a.c[i];
+        __syncthreads();
+    }
+    const int32_t nw = gridDim.x * (blockDim.x / kWave);
+    // the unit number is wavefront-uniform: keep it (and the bin) in scalar registers
+    const int32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+    pull_sweep<W, HOT>(a, s_c, first, nw);
+}
+
+// Sums the chunk partials of split rows fix0, fix0 + 1, ... in chunk order
+// (deterministic).
+__global__ void k_pr_pull_fix(PullArgs a, int32_t nsplit, int32_t fix0) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x + fix0;
+    if (i >= nsplit + fix0) return;
     const int32_t* first = a.tab + 3 * a.tab_cap;
     if (a.tab[first[i]] < a.skip_below) return;
     float acc = 0.f;
     for (int32_t e = first[i]; e < first[i + 1]; ++e) acc += a.part[e];
     pull_finish(a, a.tab[first[i]], acc);
+}
+
+// ------------------------------------------------------------ tiled pull
+// The heaviest rows [0, R) pull their in-edges slice by slice (SlicePlan in
+// pp_common.h): a workgroup stages the contributions of one source slice in
+// LDS and each wavefront sums the segments of a unit -- at most 1,024
+// consecutive 16-bit entries, lane l holding entries 16l .. 16l+15 (two
+// 16-byte loads) -- so every gather is an LDS read.  A segment's partial is
+// the in-lane sum of its entries plus, when it runs on, the sums of the next
+// lanes up to the lane where the next segment starts (a segmented scan
+// across the wavefront).  Each (slice, row) gets one partial (long segments
+// one per chunk); k_pr_tiled_combine adds a row's partials in slice order,
+// then its chunks in order.  The same sum as the plain pull in another fixed
+// order: bit-reproducible.
+struct TileArgs {
+    const uint16_t* idx;      // units and chunks (bit 15: first entry of a segment)
+    const int32_t* prow;      // row of every unit segment, in unit order
+    const SliceUnit* units;
+    const SliceSeg* segs;     // runs of one slice; workgroup b: runs [wg[b], wg[b+1])
+    const int32_t* wg;
+    float* part;              // partial sums [S*R], slice-major
+    float* cpart;             // chunk partial sums
+    const int32_t* cbeg;      // chunks of row u: [cbeg[u], cbeg[u+1])
+    const float* c;           // contributions
+    int32_t n, R, W, S, P;    // P: segments in prow
+};
+
+// What a lane loads for one unit ahead of running it: its 16 entries and the
+// rows of segments lane, lane + 64, lane + 128, lane + 192 of the unit.
+struct UnitData {
+    SliceUnit d;
+    uint4 q0, q1;
+    int32_t rows[4];
+};
+
+__device__ __forceinline__ SliceUnit no_unit() { return SliceUnit{0, 0, 0, 0}; }
+
+__device__ __forceinline__ UnitData unit_load(const TileArgs& t, const SliceUnit& d, int lane) {
+    UnitData U;
+    U.d = d;
+    U.q0 = make_uint4(0, 0, 0, 0);
+    U.q1 = U.q0;
+    const int32_t base = d.a + 16 * lane;
+    if (base < d.b) {  // d.a is 8-aligned: two aligned 16-byte loads
+        const uint4* q = reinterpret_cast<const uint4*>(t.idx + base);
+        U.q0 = q[0];
+        U.q1 = q[1];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) U.rows[i] = (d.p0 >= 0) ? t.prow[min(d.p0 + lane + 64 * i, t.P - 1)] : 0;
+    return U;
+}
+
+// Entry j (0..15) of a lane's two loads.
+__device__ __forceinline__ uint32_t unit_entry(const UnitData& U, int j) {
+    const uint32_t w[8] = {U.q0.x, U.q0.y, U.q0.z, U.q0.w, U.q1.x, U.q1.y, U.q1.z, U.q1.w};
+    return (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+}
+
+// Runs one unit (sums: this wavefront's 256 LDS words).
+__device__ __forceinline__ void unit_run(const TileArgs& t, const UnitData& U, int lane, const float* lds, float* sums) {
+    const SliceUnit& d = U.d;
+    if (d.b <= d.a) return;
+    const int32_t nvalid = min(max(d.b - (d.a + 16 * lane), 0), 16);
+    float v[16];
+    uint32_t heads = 0;  // bit j: entry j starts a segment
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const uint32_t e = unit_entry(U, j);
+        const bool ok = j < nvalid;
+        v[j] = lds[ok ? (e & (kSegHead - 1)) : (uint32_t)t.W];  // lds[W] is zero
+        if (ok && (e & kSegHead)) heads |= 1u << j;
+    }
+    if (d.p0 < 0) {  // a chunk of one long segment: sum everything
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc += v[j];
+        acc = group_reduce<kWave>(acc);
+        if (lane == 0) t.cpart[-d.p0 - 1] = acc;
+        return;
+    }
+    // segment ordinals: exclusive prefix count of heads over the lanes
+    const int nh = __popc(heads);
+    int pref = nh;
+#pragma unroll
+    for (int st = 1; st < kWave; st <<= 1) {
+        const int o = __shfl_up(pref, st);
+        if (lane >= st) pref += o;
+    }
+    const int total = __shfl(pref, kWave - 1);
+    pref -= nh;
+    // in-lane sums: segments that end inside the lane go to sums[ordinal];
+    // `lead` (entries before the lane's first head) belongs to a segment of an
+    // earlier lane, `tail` (entries from the last head on) may run on
+    float run = 0.f, lead = 0.f;
+    int k = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (heads & (1u << j)) {
+            if (k == 0) lead = run;
+            else sums[pref + k - 1] = run;
+            run = 0.f;
+            ++k;
+        }
+        run += v[j];
+    }
+    // backward segmented scan of what each lane hands to the segment running
+    // in from its left: all of it without a head, else its lead; it stops at
+    // the first lane with a head (or past the unit's end)
+    float val = nh ? lead : run;
+    int stop = (nh > 0 || nvalid == 0) ? 1 : 0;
+#pragma unroll
+    for (int st = 1; st < kWave; st <<= 1) {
+        const float ov = __shfl_down(val, st);
+        const int os = __shfl_down(stop, st);
+        if (!stop && lane + st < kWave) {
+            val += ov;
+            stop = os;
+        }
+    }
+    float from_right = __shfl_down(val, 1);
+    if (lane == kWave - 1) from_right = 0.f;
+    if (nh) sums[pref + nh - 1] = run + from_right;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float* part = t.part + (size_t)d.slice * t.R;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (lane + 64 * i < total) part[U.rows[i]] = sums[lane + 64 * i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // sums[] is rewritten by the next unit
+}
+
+// Tiles first: for each run of this workgroup's units (one slice each) the
+// slice is staged, then wavefront w runs units u0 + w, u0 + w + waves, ...,
+// each unit's loads issued while the previous one is summed.  Then the plain
+// pull of the rows >= R with c[0, hot) staged.
+template <bool HOT>
+__global__ __launch_bounds__(1024) void k_pr_tiled(TileArgs t, PullArgs a) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t waves = blockDim.x / kWave;
+    const int32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    float* sums = lds + t.W + 4 + wv * (kTiledWaveLds / 4);
+    int32_t cur = -1;
+    const int32_t r_end = t.wg[blockIdx.x + 1];
+    for (int32_t r = t.wg[blockIdx.x]; r < r_end; ++r) {
+        const SliceSeg run = t.segs[r];
+        if (run.slice != cur) {
+            __syncthreads();  // every wavefront is done with the staged slice
+            const int32_t s0 = run.slice * t.W;
+            stage_lds(lds, t.c + s0, min(t.W, t.n - s0));
+            if (threadIdx.x == 0) lds[t.W] = 0.f;
+            __syncthreads();
+            cur = run.slice;
+        }
+        int32_t k = run.u0 + wv;
+        UnitData u_cur = unit_load(t, (k < run.u1) ? t.units[k] : no_unit(), lane);
+        SliceUnit d_next = (k + waves < run.u1) ? t.units[k + waves] : no_unit();
+        for (; k < run.u1; k += waves) {
+            const UnitData u_next = unit_load(t, d_next, lane);
+            d_next = (k + 2 * waves < run.u1) ? t.units[k + 2 * waves] : no_unit();
+            unit_run(t, u_cur, lane, lds, sums);
+            u_cur = u_next;
+        }
+    }
+    if (a.units == 0) return;
+    if (HOT) {
+        __syncthreads();
+        stage_lds(lds, a.c, a.hot);
+    }
+    __syncthreads();
+    const int32_t nw = gridDim.x * waves;
+    const int32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * waves + wv);
+    pull_sweep<false, HOT>(a, lds, first, nw);
+}
+
+// Rows [0, R): y = teleport + the S slice partials in slice order (eight
+// loads in flight) + the row's chunk partials in order, then the next
+// contribution.
+__global__ __launch_bounds__(256) void k_pr_tiled_combine(TileArgs t, PullArgs a) {
+    const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= t.R) return;
+    const float* p = t.part + u;
+    float acc = 0.f;
+    int32_t s = 0;
+    for (; s + 8 <= t.S; s += 8) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = p[(size_t)(s + k) * t.R];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += v[k];
+    }
+    for (; s < t.S; ++s) acc += p[(size_t)s * t.R];
+    for (int32_t ch = t.cbeg[u]; ch < t.cbeg[u + 1]; ++ch) acc += t.cpart[ch];
+    pull_finish(a, u, acc);
 }
 
 // ------------------------------------------------------------------ push
@@ -440,6 +672,8 @@ __global__ void k_pr_push_epilogue(int32_t n, const float* __restrict__ y, const
 // ------------------------------------------------------------------ launchers
 static float teleport(int32_t n, float f) { return (float)((1.0 - (double)f) / (double)n); }
 
+Teleport uniform_teleport(int32_t n, float f) { return Teleport{teleport(n, f), -1, 0.f, 1}; }
+
 // ------------------------------------------------------------------ hybrid
 // The hybrid sweep's push part, laid out like the pull sweep (persistent
 // wavefront units over the out-degree bins, G lanes per row, U loads in
@@ -536,9 +770,10 @@ pp_status launch_hyb_push(pp_graph g, const float* c, int32_t hot, hipStream_t s
     return PP_OK;
 }
 
-pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float f, hipStream_t st,
-                      int32_t skip_below = 0) {
-    PullArgs a;
+// Fields common to every pull launch.
+static PullArgs pull_args(pp_graph g, const float* c, float* c_next, float* y, float f, int32_t skip_below,
+                          const Teleport& tp) {
+    PullArgs a{};
     a.skip_below = skip_below;
     a.sp = sweep_plan(g->pull_plan);
     a.off = g->d.csc_off;
@@ -547,22 +782,65 @@ pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float
     a.list = g->d.pull_list;
     a.tab_cap = g->split_cap;
     a.tab = g->d.split_tab;
+    a.tab0 = 0;
     a.part = g->d.split_part;
     a.c = c;
     a.inv_s = g->d.inv_s;
     a.perm = g->d.perm;
     a.c_next = c_next;
     a.y = y;
-    a.base = teleport(g->d.n, f);
+    a.y_stride = tp.y_stride;
+    a.base = tp.base;
+    a.tele_v = tp.vertex;
+    a.tele = tp.extra;
     a.f = f;
-    for (int b = 0; b <= PP_NUM_BINS; ++b) a.wave_off[b] = g->pull_plan.wave_off[b];
-    a.units = g->pull_plan.total_wave_units;
-    const int32_t tpb = g->tune.pull_block;
     const int32_t lds_cap = std::max(g->max_lds, 0) / (int32_t)sizeof(float);
     a.hot = std::min(std::min(g->tune.pull_hot, g->d.n), lds_cap);
+    return a;
+}
+
+pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float f, hipStream_t st,
+                      int32_t skip_below, const Teleport* tpp) {
+    const Teleport tp = tpp ? *tpp : uniform_teleport(g->d.n, f);
+    PullArgs a = pull_args(g, c, c_next, y, f, skip_below, tp);
+    const int32_t tpb = g->tune.pull_block;
+    const SlicePlan& sl = g->slices;
+    const BinPlan& pp_ = g->pull_plan;
+    const bool hot = a.hot > 0;
+    if (sl.rows > 0 && skip_below == 0 && !g->weighted) {
+        // tiled rows [0, R), then the plain pull of the other rows in the same launch
+        for (int b = 0; b < PP_NUM_BINS; ++b) {
+            a.list_beg[b] = pp_.list_off[b] + sl.list_skip[b];
+            a.list_cnt[b] = pp_.count[b] - sl.list_skip[b];
+        }
+        for (int b = 0; b <= PP_NUM_BINS; ++b) a.wave_off[b] = sl.wave_off[b];
+        a.units = sl.units;
+        a.tab0 = sl.tab0;
+        TileArgs t{g->d.sl_idx, g->d.sl_prow, g->d.sl_units, g->d.sl_segs, g->d.sl_wg, g->d.sl_part,
+                   g->d.sl_cpart, g->d.sl_cbeg, c, g->d.n, sl.rows, sl.width, sl.slices, std::max(sl.pairs, 1)};
+        // the slice with its per-wavefront words, or the hot range of the rest
+        const size_t lds = std::max(tiled_lds_bytes(sl.width, tpb / kWave), (size_t)a.hot * sizeof(float));
+        if (hot) {
+            allow_dynamic_lds(reinterpret_cast<const void*>(&k_pr_tiled<true>), lds);
+            hipLaunchKernelGGL((k_pr_tiled<true>), dim3(sl.groups), dim3(tpb), lds, st, t, a);
+        } else {
+            allow_dynamic_lds(reinterpret_cast<const void*>(&k_pr_tiled<false>), lds);
+            hipLaunchKernelGGL((k_pr_tiled<false>), dim3(sl.groups), dim3(tpb), lds, st, t, a);
+        }
+        hipLaunchKernelGGL(k_pr_tiled_combine, dim3(ceil_div(sl.rows, 256)), dim3(256), 0, st, t, a);
+        if (sl.nsplit > 0)
+            hipLaunchKernelGGL(k_pr_pull_fix, dim3(ceil_div(sl.nsplit, 64)), dim3(64), 0, st, a, sl.nsplit, sl.fix0);
+        PP_LAUNCH_CHECK("k_pr_tiled");
+        return PP_OK;
+    }
+    for (int b = 0; b < PP_NUM_BINS; ++b) {
+        a.list_beg[b] = pp_.list_off[b];
+        a.list_cnt[b] = pp_.count[b];
+    }
+    for (int b = 0; b <= PP_NUM_BINS; ++b) a.wave_off[b] = pp_.wave_off[b];
+    a.units = pp_.total_wave_units;
     if (a.units > 0) {
         // one workgroup per compute unit (more when they are small), never more than the work
-        const bool hot = a.hot > 0;
         const size_t lds = hot ? (size_t)a.hot * sizeof(float) : 0;
         // as many workgroups per compute unit as 32 wavefronts and the LDS allow
         int32_t per_cu = std::max(2048 / tpb, 1);
@@ -579,8 +857,8 @@ pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float
             else hipLaunchKernelGGL((k_pr_pull<false, false>), dim3(grid), dim3(tpb), 0, st, a);
         }
     }
-    const int32_t nsplit = g->pull_plan.count[5];
-    if (nsplit > 0) hipLaunchKernelGGL(k_pr_pull_fix, dim3(ceil_div(nsplit, 64)), dim3(64), 0, st, a, nsplit);
+    const int32_t nsplit = pp_.count[5];
+    if (nsplit > 0) hipLaunchKernelGGL(k_pr_pull_fix, dim3(ceil_div(nsplit, 64)), dim3(64), 0, st, a, nsplit, 0);
     PP_LAUNCH_CHECK("k_pr_pull");
     return PP_OK;
 }

@@ -14,6 +14,7 @@ def default_bins():
     _lib.pp_set_bin_thresholds([4, 16, 64, 1024, 4096], 4096)
     _lib.pp_set_push_tuning(8192, 1024)
     _lib.pp_set_pull_tuning(32768, 1024)
+    _lib.pp_set_pull_slices(0, 32768)
 
 
 def tiny_bins():

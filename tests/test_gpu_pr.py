@@ -301,3 +301,85 @@ def test_rmat22_sampled_step_and_mass_balance():
         # isolated vertices sit exactly at the teleport value
         iso = np.nonzero(deg == 0)[0][:1000]
         assert np.all(x20h[iso] == np.float32((1 - F) / host.n))  # F is FP32-exact
+
+
+# ---------------------------------------------------------------- tiled pull
+@pytest.mark.parametrize("rows,width,pull_hot", [(4096, 512, 32768), (100000, 1024, 32768), (64, 64, 32768),
+                                                 (16384, 32768, 40960), (2000, 256, 0), (300, 4096, 300)])
+def test_tiled_pull_rmat14(rows, width, pull_hot):
+    # the heavy rows pull slice by slice from LDS (many slices and tiles, a
+    # ragged last slice), the rest as usual; against the oracle, repeatable
+    # bit for bit, and within FP32 rounding of the plain pull
+    host = gg.workload("rmat14")
+    want = oracle.pagerank(host.off, host.idx, F, 20)
+    _lib.pp_set_pull_tuning(pull_hot, 1024)
+    plain = pr_gpu(pp.Graph(host), pp.PP_PULL, 20).astype(np.float64)
+    _lib.pp_set_pull_slices(rows, width)
+    g = pp.Graph(host)
+    R, W, S, T = g.slices()
+    announce(f"tiled pull rmat14 R={R} W={W} S={S} tiles={T} pull_hot={pull_hot}")
+    assert R > 0 and W == width and S >= 1 and T >= 1
+    got = pr_gpu(g, pp.PP_PULL, 20)
+    assert np.abs(got.astype(np.float64) - want).sum() <= PR_L1_TOL
+    assert np.array_equal(got, pr_gpu(g, pp.PP_PULL, 20))
+    assert np.abs(got - plain).max() <= 1e-5 * plain.max()
+    # the one-step entry point takes the same path
+    x0 = torch.full((host.n,), 1.0 / host.n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x0)
+    _lib.pp_pr_pull(g.handle, x0, y, F)
+    want1 = oracle.pagerank(host.off, host.idx, F, 1)
+    assert np.abs(y.cpu().numpy().astype(np.float64) - want1).sum() <= PR_L1_TOL
+
+
+def test_tiled_pull_long_segments_in_chunks():
+    # a star's hub row has 59,999 in-edges: its segments in slice 0 (32,767
+    # sources) and slice 1 (27,232) are cut into 1,024-edge chunks whose
+    # partials the combine adds in order
+    host = H.star(60000)
+    _lib.pp_set_pull_slices(8, 32768)
+    g = pp.Graph(host)
+    R, W, S, T = g.slices()
+    assert R == 1 and S == 2 and T == 32 + 27
+    want = oracle.pagerank(host.off, host.idx, F, 20)
+    got = pr_gpu(g, pp.PP_PULL, 20).astype(np.float64)
+    assert np.abs(got - want).sum() <= PR_L1_TOL
+
+
+def _directed_rmat(scale, seed):
+    """R-MAT with each directed edge kept with probability 0.6: hubs with
+    different in- and out-degrees."""
+    h = gg.rmat(scale, 16, seed=seed)
+    src = np.repeat(np.arange(h.n), np.diff(h.off))
+    keep = np.random.default_rng(seed).random(h.nnz) < 0.6
+    d = gg.from_edges(h.n, src[keep], h.idx[keep], False, f"drmat{scale}_{seed}")
+    d.ensure_transpose()
+    return d
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_tiled_pull_directed_and_split_rest_rows(seed):
+    # directed: rows pull over in-edges; tiny bins leave split rows (bin 5)
+    # beyond the tiled prefix, which the plain part still sums in chunks
+    host = _directed_rmat(14, seed)
+    tiny_bins()
+    _lib.pp_set_pull_slices(16, 128)
+    g = pp.Graph(host)
+    R, W, S, T = g.slices()
+    announce(f"tiled pull directed R={R} S={S} tiles={T} bin5={g.bins(pp.PP_PULL)[5]}")
+    assert R == 16 and g.bins(pp.PP_PULL)[5] > R
+    want = oracle.pagerank(host.off, host.idx, F, 20)
+    got = pr_gpu(g, pp.PP_PULL, 20).astype(np.float64)
+    assert np.abs(got - want).sum() <= PR_L1_TOL
+
+
+def test_tiled_pull_off_for_weighted_and_unrelabelled_graphs():
+    host = gg.workload("rmat14")
+    _lib.pp_set_pull_slices(4096, 1024)
+    assert pp.Graph(host, relabel=False).slices()[0] == 0
+    with pytest.raises(pp.PPError):
+        _lib.pp_set_pull_slices(4096, 40960)  # offsets in a slice have 15 bits
+    gw = gg.rmat(12, 16, seed=3)
+    gg.with_weights(gw, seed=1)
+    assert pp.Graph(gw).slices()[0] == 0
+    # a grid has no heavy rows: nothing qualifies
+    assert pp.Graph(H.full_grid(60, 60)).slices()[0] == 0
