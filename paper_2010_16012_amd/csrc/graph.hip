@@ -687,6 +687,7 @@ static pp_status build_slices(pp_graph g, const WsLayout& L, char* base, hipStre
             }
         }
     }
+    while (out.size() % 8) out.push_back(0);
     for (int k = 0; k < 16; ++k) out.push_back(0);  // wide loads may read past the last unit
     if ((int64_t)out.size() > L.sl_idx_cap || (int64_t)prow.size() > L.sl_pairs_cap ||
         unit_count > L.sl_units_cap || (int64_t)cunits.size() > L.sl_chunks_cap)
@@ -773,6 +774,7 @@ static pp_status build_slices(pp_graph g, const WsLayout& L, char* base, hipStre
     sp.tiles = (int32_t)all.size();
     sp.pairs = (int32_t)prow.size();
     sp.chunks = (int32_t)nchunks;
+    sp.idx_size = (int32_t)out.size();
     sp.groups = groups;
     return PP_OK;
 }

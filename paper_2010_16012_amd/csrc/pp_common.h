@@ -94,6 +94,7 @@ struct SlicePlan {
     int32_t tiles = 0;   // work units
     int32_t pairs = 0;   // non-empty segments
     int32_t chunks = 0;  // chunks of long segments
+    int32_t idx_size = 0;  // 16-bit entries of the layout (a multiple of 8, 16 spare at the end)
     int32_t groups = 0;  // workgroups the units are divided among (the launch's grid)
     // the pull plan restricted to rows >= R: per bin, rows to skip at the
     // front of the bin's list; split-table entries and split rows to skip

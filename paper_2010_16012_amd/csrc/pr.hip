@@ -333,6 +333,7 @@ struct TileArgs {
     const int32_t* cbeg;      // chunks of row u: [cbeg[u], cbeg[u+1])
     const float* c;           // contributions
     int32_t n, R, W, S, P;    // P: segments in prow
+    int32_t idx_last;         // last 8-aligned start with 16 entries behind it
 };
 
 // What a lane loads for one unit ahead of running it: its 16 entries and the
@@ -340,24 +341,36 @@ struct TileArgs {
 struct UnitData {
     SliceUnit d;
     uint4 q0, q1;
-    int32_t rows[4];
+    uint32_t rows[4];
 };
 
 __device__ __forceinline__ SliceUnit no_unit() { return SliceUnit{0, 0, 0, 0}; }
 
+// Descriptors are wavefront-uniform: read them through the constant address
+// space so they become scalar loads.  A vector load here would make the next
+// wait on its value also wait for every index load in flight.
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T* p, int32_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) T* cptr;
+    return ((cptr)p)[i];
+#else
+    return p[i];  // host pass: never executed
+#endif
+}
+
+// Every load is unconditional, at an address clamped into its array (what a
+// lane should not use is masked when the unit runs): the compiler then knows
+// how many loads are in flight and waits only for the older unit's.
 __device__ __forceinline__ UnitData unit_load(const TileArgs& t, const SliceUnit& d, int lane) {
     UnitData U;
     U.d = d;
-    U.q0 = make_uint4(0, 0, 0, 0);
-    U.q1 = U.q0;
-    const int32_t base = d.a + 16 * lane;
-    if (base < d.b) {  // d.a is 8-aligned: two aligned 16-byte loads
-        const uint4* q = reinterpret_cast<const uint4*>(t.idx + base);
-        U.q0 = q[0];
-        U.q1 = q[1];
-    }
+    // d.a is 8-aligned: two aligned 16-byte loads
+    const uint4* q = reinterpret_cast<const uint4*>(t.idx + min(d.a + 16 * lane, t.idx_last));
+    U.q0 = q[0];
+    U.q1 = q[1];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) U.rows[i] = (d.p0 >= 0) ? t.prow[min(d.p0 + lane + 64 * i, t.P - 1)] : 0;
+    for (int i = 0; i < 4; ++i) U.rows[i] = (uint32_t)t.prow[min(max(d.p0 + lane + 64 * i, 0), t.P - 1)];
     return U;
 }
 
@@ -437,7 +450,7 @@ __device__ __forceinline__ void unit_run(const TileArgs& t, const UnitData& U, i
     float* part = t.part + (size_t)d.slice * t.R;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-        if (lane + 64 * i < total) part[U.rows[i]] = sums[lane + 64 * i];
+        if (lane + 64 * i < total) part[(size_t)U.rows[i]] = sums[lane + 64 * i];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();  // sums[] is rewritten by the next unit
 }
@@ -454,9 +467,9 @@ __global__ __launch_bounds__(1024) void k_pr_tiled(TileArgs t, PullArgs a) {
     const int32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     float* sums = lds + t.W + 4 + wv * (kTiledWaveLds / 4);
     int32_t cur = -1;
-    const int32_t r_end = t.wg[blockIdx.x + 1];
-    for (int32_t r = t.wg[blockIdx.x]; r < r_end; ++r) {
-        const SliceSeg run = t.segs[r];
+    const int32_t r_end = uniform_load(t.wg, (int32_t)blockIdx.x + 1);
+    for (int32_t r = uniform_load(t.wg, (int32_t)blockIdx.x); r < r_end; ++r) {
+        const SliceSeg run = uniform_load(t.segs, r);
         if (run.slice != cur) {
             __syncthreads();  // every wavefront is done with the staged slice
             const int32_t s0 = run.slice * t.W;
@@ -465,14 +478,23 @@ __global__ __launch_bounds__(1024) void k_pr_tiled(TileArgs t, PullArgs a) {
             __syncthreads();
             cur = run.slice;
         }
+        // two unit buffers used in turn (never copied: a copy of registers a
+        // load is still filling would wait for every load in flight)
         int32_t k = run.u0 + wv;
-        UnitData u_cur = unit_load(t, (k < run.u1) ? t.units[k] : no_unit(), lane);
-        SliceUnit d_next = (k + waves < run.u1) ? t.units[k + waves] : no_unit();
-        for (; k < run.u1; k += waves) {
-            const UnitData u_next = unit_load(t, d_next, lane);
-            d_next = (k + 2 * waves < run.u1) ? t.units[k + 2 * waves] : no_unit();
-            unit_run(t, u_cur, lane, lds, sums);
-            u_cur = u_next;
+        if (k >= run.u1) continue;
+        UnitData ua = unit_load(t, uniform_load(t.units, k), lane), ub;
+        SliceUnit dn = (k + waves < run.u1) ? uniform_load(t.units, k + waves) : no_unit();
+        for (;;) {
+            ub = unit_load(t, dn, lane);
+            dn = (k + 2 * waves < run.u1) ? uniform_load(t.units, k + 2 * waves) : no_unit();
+            unit_run(t, ua, lane, lds, sums);
+            k += waves;
+            if (k >= run.u1) break;
+            ua = unit_load(t, dn, lane);
+            dn = (k + 2 * waves < run.u1) ? uniform_load(t.units, k + 2 * waves) : no_unit();
+            unit_run(t, ub, lane, lds, sums);
+            k += waves;
+            if (k >= run.u1) break;
         }
     }
     if (a.units == 0) return;
@@ -817,7 +839,8 @@ pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float
         a.units = sl.units;
         a.tab0 = sl.tab0;
         TileArgs t{g->d.sl_idx, g->d.sl_prow, g->d.sl_units, g->d.sl_segs, g->d.sl_wg, g->d.sl_part,
-                   g->d.sl_cpart, g->d.sl_cbeg, c, g->d.n, sl.rows, sl.width, sl.slices, std::max(sl.pairs, 1)};
+                   g->d.sl_cpart, g->d.sl_cbeg, c, g->d.n, sl.rows, sl.width, sl.slices, std::max(sl.pairs, 1),
+                   sl.idx_size - 16};
         // the slice with its per-wavefront words, or the hot range of the rest
         const size_t lds = std::max(tiled_lds_bytes(sl.width, tpb / kWave), (size_t)a.hot * sizeof(float));
         if (hot) {
