@@ -11,12 +11,16 @@ value = traversed edges per second over the step, in GTEPS: a PageRank step
 traverses nnz edges; a BFS traverses the undirected edges of the root's
 component (sum of reached degrees / 2).  Per-part rates are in "parts".
 
-The roofline object covers the pull sweep kernel: algorithmic bytes per launch
-(4*nnz + 16*n: offsets, indices, gathered contributions, 1/d, next
-contributions) over the average launch time measured with HIP events around
-the 20-step pull run.  roofline_bfs_push does the same per top-down BFS run
-for the BFS level kernels (4*E + 8*R + 12*(R-1) bytes).  The CPU baseline is
-the FP64 C oracle on a bounded sample (one PageRank step and two BFS roots).
+The roofline object covers one pull step (the sweep's kernels): algorithmic
+bytes per step (4*nnz + 20*n: offsets, indices, gathered contributions, 1/d,
+the iterate and the next contributions) over the average step time measured
+with HIP events around the 20-step pull run, against the published 8 TB/s and
+against a measured device-to-device copy.  roofline_bfs_{push,pull,switch} do
+the same per BFS run for the level kernels.  "batched" holds the measured
+speedups of the batched forms over their sequential counterparts: PPR with
+k = 256 sources on R-MAT 20 against 256 single-vector runs, and the 512-graph
+launch against the graphs run one by one.  The CPU baseline is the FP64 C
+oracle on the host's cores on a bounded sample of the same work.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -45,6 +49,7 @@ def parse():
     p.add_argument("--roots", type=int, default=N_ROOTS)
     p.add_argument("--only", default="", help="comma list of parts to run (pr_pull,pr_push,bfs_push,bfs_pull,bfs_switch)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential measurements")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     p.add_argument("--workload", default="rmat22",
@@ -68,8 +73,8 @@ def source_hash(*names):
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_src_hash, launch_algo_bytes):
-    """HBM traffic per launch from a committed counter summary, if it still
+def load_traffic(kernel_src_hash):
+    """HBM traffic per pull step from a committed counter summary, if it still
     describes the current kernel source."""
     path = os.path.join(ROOT, "profiles", "pr_pull_rmat22_counters.json")
     if not os.path.exists(path):
@@ -81,46 +86,53 @@ def load_traffic(kernel_src_hash, launch_algo_bytes):
     return d.get("traffic_bytes_per_launch")
 
 
-PULL_KERNEL = "pp::k_pr_pull<"
+# kernels of one pull step: the sweep (one dispatch per step) and its fix-ups
+STEP_SWEEP = ("pp::k_pr_tiled<", "pp::k_pr_pull<")
+STEP_AUX = ("pp::k_pr_tiled_combine(", "pp::k_pr_pull_fix(")
 CALIB_BYTES = 1 << 30  # the calibration kernel reads 1 GiB and writes 1 GiB
 
 
 def counters_summary(fetch_csv, write_csv, sizes_csv=None):
-    """HBM bytes per pull launch from FETCH_SIZE / WRITE_SIZE (KiB per
-    dispatch), each divided by what the same counter reads for the plain
-    1 GiB-in / 1 GiB-out calibration kernel over 1 GiB."""
+    """HBM bytes per pull step from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), summed over the step's kernels and each divided by what the
+    same counter reads for the plain 1 GiB-in / 1 GiB-out calibration kernel
+    over 1 GiB."""
     import csv
 
-    def per_kernel(path, counter, scale=1024.0):
-        pull, calib = [], []
+    def per_step(path, counter, scale=1024.0):
+        total, sweeps, calib = 0.0, 0, []
         with open(path) as fh:
             for r in csv.DictReader(fh):
                 if r["Counter_Name"] != counter:
                     continue
                 v = float(r["Counter_Value"]) * scale
-                if PULL_KERNEL in r["Kernel_Name"]:
-                    pull.append(v)
-                elif "neg_kernel" in r["Kernel_Name"]:
+                name = r["Kernel_Name"]
+                if any(k in name for k in STEP_SWEEP):
+                    total += v
+                    sweeps += 1
+                elif any(k in name for k in STEP_AUX):
+                    total += v
+                elif "neg_kernel" in name:
                     calib.append(v)
-        if not pull or len(calib) != 1:
-            raise SystemExit(f"{path}: expected pull dispatches and one calibration dispatch "
-                             f"(got {len(pull)} and {len(calib)})")
-        return sum(pull) / len(pull), calib[0]
+        if not sweeps or len(calib) != 1:
+            raise SystemExit(f"{path}: expected pull sweeps and one calibration dispatch "
+                             f"(got {sweeps} and {len(calib)})")
+        return total / sweeps, calib[0]
 
-    f_pull, f_cal = per_kernel(fetch_csv, "FETCH_SIZE")
-    w_pull, w_cal = per_kernel(write_csv, "WRITE_SIZE")
+    f_step, f_cal = per_step(fetch_csv, "FETCH_SIZE")
+    w_step, w_cal = per_step(write_csv, "WRITE_SIZE")
     k_f, k_w = f_cal / CALIB_BYTES, w_cal / CALIB_BYTES
-    traffic = f_pull / k_f + w_pull / k_w
-    out = {"kernel": "k_pr_pull", "workload": "rmat22_ef16_seed1_sym", "source_hash": source_hash("pr.hip"),
-           "fetch_bytes_per_launch_raw": round(f_pull), "write_bytes_per_launch_raw": round(w_pull),
+    traffic = f_step / k_f + w_step / k_w
+    out = {"kernels": list(STEP_SWEEP + STEP_AUX), "per": "pull step", "workload": "rmat22_ef16_seed1_sym",
+           "source_hash": source_hash("pr.hip"),
+           "fetch_bytes_per_launch_raw": round(f_step), "write_bytes_per_launch_raw": round(w_step),
            "fetch_calibration_factor": round(k_f, 4), "write_calibration_factor": round(k_w, 4),
            "traffic_bytes_per_launch": round(traffic)}
     if sizes_csv:
         # read requests from L2 to memory by size; bytes = sum(size * count)
         by = {}
         for sz in (32, 64, 128):
-            p_req, c_req = per_kernel(sizes_csv, f"TCC_EA0_RDREQ_{sz}B_sum", 1.0)
-            by[sz] = (p_req, c_req)
+            by[sz] = per_step(sizes_csv, f"TCC_EA0_RDREQ_{sz}B_sum", 1.0)
         out["read_requests_per_launch"] = {f"{sz}B": round(by[sz][0]) for sz in by}
         out["read_bytes_per_launch_by_size"] = round(sum(sz * by[sz][0] for sz in by))
         out["calibration_read_bytes_by_size"] = round(sum(sz * by[sz][1] for sz in by))
@@ -130,6 +142,167 @@ def counters_summary(fetch_csv, write_csv, sizes_csv=None):
         json.dump(out, fh, indent=1)
         fh.write("\n")
     print(json.dumps(out))
+
+
+def _median(xs):
+    xs = sorted(xs)
+    return xs[len(xs) // 2]
+
+
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=5):
+    """Device-to-device streaming rate (GB/s, bytes read + written) of a plain
+    copy and of an elementwise kernel over 1 GiB; the faster of the two."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    best = (0.0, "")
+    for kind, fn in (("copy_", lambda: b.copy_(a)), ("neg", lambda: torch.neg(a, out=b))):
+        fn()
+        ms = _median([_events_ms(fn) for _ in range(reps)])
+        gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+        if gbs > best[0]:
+            best = (gbs, f"{kind} of 1 GiB")
+    del a, b
+    torch.cuda.empty_cache()
+    return best
+
+
+def bfs_replay_bytes(n, fr, ex, di, dirs):
+    """Algorithmic bytes of a BFS run from the oracle's replay of its direction
+    schedule: top-down steps 4*E + 8*|F| + 12*|new|; bottom-up steps
+    4*E + 8*|unvisited| + 8*|new| + 3*ceil(n/8) (three bitmaps)."""
+    tot, visited = 0, 1
+    for step in range(len(ex)):
+        if dirs[step] == 0:
+            tot += 4 * ex[step] + 8 * fr[step] + 12 * di[step]
+        else:
+            tot += 4 * ex[step] + 8 * (n - visited) + 8 * di[step] + 3 * ((n + 7) // 8)
+        visited += di[step]
+    return int(tot)
+
+
+def cpu_leg(args, host, roots, root_edges, runs, policy, alpha, beta, parts):
+    """The FP64 oracle timed on the host's cores (a bounded sample of the
+    step), plus the oracle's replay of the GPU's BFS direction schedules for
+    two roots, which gives the algorithmic bytes of the pull and switch runs."""
+    import oracle
+
+    n, nnz = host.n, host.nnz
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+
+    def timed(fn):
+        t = time.perf_counter()
+        r = fn()
+        return time.perf_counter() - t, r
+
+    # each call builds its own in-adjacency first: the per-step time is the
+    # difference of a 21-step and a 1-step run (median of three each)
+    t1 = _median([timed(lambda: oracle.pagerank_threads(host.off, host.idx, F, 1))[0] for _ in range(3)])
+    t21s, threads = [], 1
+    for _ in range(3):
+        dt, (_, threads) = timed(lambda: oracle.pagerank_threads(host.off, host.idx, F, 21))
+        t21s.append(dt)
+    t_iter_mt = (_median(t21s) - t1) / 20
+    if t_iter_mt <= 0:
+        raise RuntimeError("CPU baseline: the 21-step run was not slower than the 1-step run")
+    s1, _ = timed(lambda: oracle.pagerank(host.off, host.idx, F, 1))
+    s3, _ = timed(lambda: oracle.pagerank(host.off, host.idx, F, 3))
+    t_iter_st = (s3 - s1) / 2
+    if t_iter_st <= 0:
+        raise RuntimeError("CPU baseline: the 3-step run was not slower than the 1-step run")
+    t_bfs, _ = timed(lambda: [oracle.bfs(host.off, host.idx, int(r)) for r in roots[:2]])
+    bfs_edges = float(root_edges[:2].sum())
+    cpu = {"value": round(nnz / t_iter_mt / 1e9, 5), "unit": "GTEPS", "cores": threads, "kind": "oracle",
+           "sample": f"FP64 pulling PageRank step on the same rmat{args.scale} graph over {threads} threads "
+                     f"({t_iter_mt * 1e3:.1f} ms per step: 21-step minus 1-step run, median of 3)",
+           "nproc": os.cpu_count(), "cpu_model": model,
+           "single_thread_pr_gteps": round(nnz / t_iter_st / 1e9, 5),
+           "single_thread_bfs_gteps": round(bfs_edges / t_bfs / 1e9, 5),
+           "single_thread_sample": f"one PageRank step ({t_iter_st:.2f} s, 3-step minus 1-step run) and FIFO BFS "
+                                   f"from 2 of the {len(roots)} roots ({t_bfs:.2f} s)"}
+
+    out = {}
+    for p, name in (("bfs_pull", "pull"), ("bfs_switch", "switch")):
+        if p not in parts:
+            continue
+        tot_bytes, tot_ms = 0, 0.0
+        for root in roots[:2]:
+            r = runs[p]
+            _, dirs, _, _ = r.run_logged(int(root), policy[p], alpha, beta)
+            tot_ms += _median([_events_ms(lambda: r.run(int(root), policy[p], alpha, beta)) for _ in range(3)])
+            fr, ex, di = oracle.bfs_replay(host.off, host.idx, int(root), dirs)
+            tot_bytes += bfs_replay_bytes(n, fr, ex, di, dirs)
+        achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
+        out[name] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"k_bfs_level+k_bfs_chunks, {name} runs",
+                     "algorithmic_bytes_per_run": round(tot_bytes / 2), "run_ms": round(tot_ms / 2, 4),
+                     "roots": 2, "bytes_from": "oracle replay of the GPU direction schedule"}
+    return cpu, out
+
+
+def batched_speedups(args, torch, gg, pp, autotune):
+    """Measured (not extrapolated) speedups of the batched forms."""
+    return {"ppr_rmat20_k256": ppr_speedup(args, torch, gg, pp, autotune),
+            "multi512": multi_speedup(torch, gg, pp, autotune)}
+
+
+def ppr_speedup(args, torch, gg, pp, autotune):
+    """PPR on R-MAT 20 with k = 256 seeded sources, 30 sweeps, in k-column
+    tiles, against the 256 columns run one after another with the
+    single-vector sweep (k_tile = 1), pull and push."""
+    host = gg.rmat(20, 16, seed=1)
+    src = gg.pick_vertices(host, 256, seed=2)
+    tuned = autotune.load(args.tuned, host.n, host.nnz)
+    autotune.apply(tuned)
+    kt = tuned.get("k_tile", 64)
+    g = pp.Graph(host)
+    work = host.nnz * len(src) * 30
+    ppr = {"n": host.n, "nnz": host.nnz, "k": len(src), "iters": 30, "k_tile": kt}
+    for d, name in ((pp.PP_PULL, "pull"), (pp.PP_PUSH, "push")):
+        pp.ppr(g, src[:kt], iters=2, k_tile=kt, direction=d)
+        ms_b = _median([_events_ms(lambda: pp.ppr(g, src, iters=30, k_tile=kt, direction=d)) for _ in range(3)])
+        pp.ppr(g, src[:2], iters=2, k_tile=1, direction=d)
+        ms_s = _events_ms(lambda: pp.ppr(g, src, iters=30, k_tile=1, direction=d))
+        ppr[name] = {"batched_ms": round(ms_b, 2), "batched_gteps": round(work / (ms_b * 1e-3) / 1e9, 2),
+                     "sequential_ms": round(ms_s, 2), "sequential_gteps": round(work / (ms_s * 1e-3) / 1e9, 2),
+                     "speedup": round(ms_s / ms_b, 2)}
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    return ppr
+
+
+def multi_speedup(torch, gg, pp, autotune):
+    """512 R-MAT graphs (scales 8-14) in one launch (PageRank x20 pull, BFS
+    switch from vertex 0) against the same work graph by graph."""
+    autotune.apply({})
+    gs = gg.rmat_batch(512, 8, 14, seed=1)
+    mg = pp.MultiGraph(gs)
+    mg.run(pr_iters=20, pr_dir=pp.PP_PULL, bfs_policy=pp.PP_SWITCH)
+    ms_one = _median([_events_ms(lambda: mg.run(pr_iters=20, pr_dir=pp.PP_PULL, bfs_policy=pp.PP_SWITCH))
+                      for _ in range(3)])
+    graphs = [pp.Graph(h) for h in gs]
+    bruns = [pp.BfsRun(gr) for gr in graphs]
+    xs = [torch.empty(h.n, dtype=torch.float32, device="cuda") for h in gs]
+
+    def seq():
+        for gr, r, x, h in zip(graphs, bruns, xs, gs):
+            x.fill_(1.0 / h.n)
+            pp.pagerank_into(gr, x, 20, 0.85, pp.PP_PULL)
+            r.run(0, pp.PP_SWITCH)
+    seq()
+    ms_seq = _events_ms(seq)
+    out = {"graphs": len(gs), "total_nnz": int(sum(h.nnz for h in gs)), "pr_iters": 20,
+           "one_launch_ms": round(ms_one, 3), "graph_by_graph_ms": round(ms_seq, 2),
+           "speedup": round(ms_seq / ms_one, 2)}
+    for gr in graphs:
+        gr.close()
+    return out
 
 
 def main():
@@ -234,34 +407,41 @@ def main():
 
     roofline = None
     if "pr_pull" in parts:
-        # one pull launch reads offsets (4n), indices (4 nnz), the gathered
-        # contribution (4n) and 1/d (4n), and writes the next contribution (4n)
-        algo = 4 * nnz + 16 * n
+        # one pull step reads offsets (4n), indices (4 nnz), the gathered
+        # contribution (4n) and 1/d (4n) and writes the iterate (4n) and the
+        # next contribution (4n).  The library writes the iterate only after
+        # the last step, so 4 nnz + 16n is reported beside it.
+        algo = 4 * nnz + 20 * n
+        algo_min = 4 * nnz + 16 * n
         t_launch = part_ms["pr_pull"] * 1e-3 / PR_ITERS
         achieved = algo / t_launch / 1e9
-        src_hash = source_hash("pr.hip")
+        tiled = g.slices()[0] > 0
+        copy_gbs, copy_kind = copy_bandwidth(torch, dev)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(src_hash, algo),
-                    "kernel": "k_pr_pull", "algorithmic_bytes_per_launch": algo,
-                    "launch_us": round(t_launch * 1e6, 2)}
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(source_hash("pr.hip")),
+                    "kernel": ("k_pr_tiled+k_pr_tiled_combine+k_pr_pull_fix" if tiled else "k_pr_pull+k_pr_pull_fix"),
+                    "per": "pull step", "algorithmic_bytes_per_launch": algo, "launch_us": round(t_launch * 1e6, 2),
+                    "frac_without_x_write": round(algo_min / t_launch / 1e9 / HBM_PEAK_GBS, 4),
+                    "copy_gbs": round(copy_gbs, 1), "copy_kind": copy_kind,
+                    "frac_of_copy": round(achieved / copy_gbs, 4)}
 
-    # The BFS level kernels take most of the step, but their work changes from
-    # level to level, so their roofline is stated per run: a top-down BFS
-    # examines every out-edge of every frontier vertex once, i.e. per run
+    # The BFS level kernels take much of the step, but their work changes from
+    # level to level, so their roofline is stated per run.  A top-down BFS
+    # examines every out-edge of every frontier vertex once: per run
     # 4*E (indices) + 8*R (frontier offsets) + 12*(R-1) (level, parent, queue
     # of every new vertex), with E the out-edges of the R reached vertices.
-    roofline_bfs = None
+    roofline_bfs = {}
     if "bfs_push" in parts:
         tot = 0
         for root in roots:  # outside the timed region: statistics only
             st = runs["bfs_push"].run(int(root), pp.PP_PUSH, alpha, beta)
             tot += 4 * st.edges_reached + 8 * st.reached + 12 * (st.reached - 1)
         achieved = tot / (part_ms["bfs_push"] * 1e-3) / 1e9
-        roofline_bfs = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                        "kernel": "k_bfs_level+k_bfs_chunks, top-down runs",
-                        "algorithmic_bytes_per_run": round(tot / len(roots)),
-                        "run_ms": round(part_ms["bfs_push"] / len(roots), 4)}
+        roofline_bfs["push"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                                "kernel": "k_bfs_level+k_bfs_chunks, top-down runs",
+                                "algorithmic_bytes_per_run": round(tot / len(roots)),
+                                "run_ms": round(part_ms["bfs_push"] / len(roots), 4), "roots": len(roots)}
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -270,20 +450,12 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    batched = None if args.no_batched else batched_speedups(args, torch, gg, pp, autotune)
+
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        t = time.perf_counter()
-        oracle.pagerank(host.off, host.idx, F, 1)
-        t_pr = time.perf_counter() - t
-        t = time.perf_counter()
-        for root in roots[:2]:
-            oracle.bfs(host.off, host.idx, int(root))
-        t_bfs = time.perf_counter() - t
-        e = nnz + float(root_edges[:2].sum())
-        cpu = {"value": round(e / (t_pr + t_bfs) / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": f"one FP64 PageRank step ({t_pr:.2f}s) + FIFO BFS from 2 of the 64 roots ({t_bfs:.2f}s) "
-                         f"on the same rmat{args.scale} graph, single thread"}
+        cpu, replay_rooflines = cpu_leg(args, host, roots, root_edges, runs, policy, alpha, beta, parts)
+        roofline_bfs.update(replay_rooflines)
 
     line = {
         "metric": "GTEPS per PageRank iter & BFS, push vs pull; % of HBM roofline",
@@ -303,7 +475,8 @@ def main():
                    "n": n, "nnz": nnz, "parts": parts, "tuning": tuned or "defaults"},
         "parts": out_parts,
         "roofline": roofline,
-        "roofline_bfs_push": roofline_bfs,
+        "roofline_bfs": roofline_bfs or None,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -332,51 +505,9 @@ def supplementary(args):
     w = args.workload
     line = {"workload": w, "n_gpus": 1, "data": "synthetic"}
     if w == "ppr20":
-        # personalised PageRank, R-MAT 20, k = 256 seeded non-isolated sources, 30 sweeps
-        host = gg.rmat(20, 16, seed=1)
-        src = gg.pick_vertices(host, 256, seed=2)
-        tuned = autotune.load(args.tuned, host.n, host.nnz)
-        autotune.apply(tuned)
-        kt = tuned.get("k_tile", 32)
-        g = pp.Graph(host)
-        for d, name in ((pp.PP_PULL, "pull"), (pp.PP_PUSH, "push"), (pp.PP_SWITCH, "switch")):
-            pp.ppr(g, src, iters=2, k_tile=kt, direction=d)
-            ms = _events_ms(lambda: pp.ppr(g, src, iters=30, k_tile=kt, direction=d))
-            # sequential baseline: k single-vector sweeps of the same form (the
-            # PageRank sweep does the same per-edge work for one vector)
-            x = torch.full((host.n,), 1.0 / host.n, dtype=torch.float32, device="cuda")
-            seq_dir = pp.PP_PUSH if d == pp.PP_PUSH else pp.PP_PULL
-            ms_sweep = _events_ms(lambda: pp.pagerank_into(g, x, 20, 0.85, seq_dir)) / 20
-            ms_seq = ms_sweep * 30 * len(src)
-            work = host.nnz * len(src) * 30
-            line[name] = {"ms": round(ms, 2), "gteps": round(work / (ms * 1e-3) / 1e9, 2),
-                          "sequential_ms_est": round(ms_seq, 1),
-                          "sequential_gteps": round(work / (ms_seq * 1e-3) / 1e9, 2),
-                          "speedup_vs_sequential": round(ms_seq / ms, 2), "k_tile": kt}
-        line.update({"n": host.n, "nnz": host.nnz, "k": 256, "iters": 30})
+        line.update(ppr_speedup(args, torch, gg, pp, autotune))
     elif w == "multi512":
-        gs = gg.rmat_batch(512, 8, 14, seed=1)
-        mg = pp.MultiGraph(gs)
-        nnz = int(sum(h.nnz for h in gs))
-        for d, name in ((pp.PP_PULL, "pull"), (pp.PP_PUSH, "push")):
-            mg.run(pr_iters=20, pr_dir=d, bfs_policy=pp.PP_SWITCH)
-            ms = _events_ms(lambda: mg.run(pr_iters=20, pr_dir=d, bfs_policy=pp.PP_SWITCH))
-            line[name] = {"ms_one_launch": round(ms, 3)}
-        # baseline: the same work graph by graph through the single-graph calls (first 64 graphs, scaled)
-        sub = gs[:64]
-        graphs = [pp.Graph(h) for h in sub]
-        runs = [pp.BfsRun(g) for g in graphs]
-
-        def seq():
-            for g, r in zip(graphs, runs):
-                pp.pagerank(g, 20, 0.85, pp.PP_PULL)
-                r.run(0, pp.PP_SWITCH)
-        seq()
-        ms_sub = _events_ms(seq)
-        share = sum(h.nnz for h in sub) / nnz
-        line["sequential_ms_est"] = round(ms_sub / share, 2)
-        line["speedup_vs_sequential_pull"] = round(ms_sub / share / line["pull"]["ms_one_launch"], 2)
-        line.update({"graphs": 512, "total_nnz": nnz, "pr_iters": 20})
+        line.update(multi_speedup(torch, gg, pp, autotune))
     elif w in ("grid4096", "er22"):
         host = gg.workload(w)
         g = pp.Graph(host)

@@ -252,7 +252,8 @@ pp_status pp_bfs_run_log(pp_graph g, int32_t root, pp_dir policy, float alpha, f
 
 /* ------------------------------------------------------ personalised PR */
 /* Scratch bytes for pp_ppr_run / pp_ppr_adjoint with k columns processed in
- * tiles of k_tile (0 when an argument is invalid). */
+ * tiles of k_tile (pp_ppr_run also takes k_tile = 1; 0 when an argument is
+ * invalid). */
 size_t pp_ppr_scratch_bytes(pp_graph g, int32_t k, int32_t k_tile);
 
 /* Personalised PageRank for k sources at once (the PageRank equation of
@@ -273,6 +274,10 @@ size_t pp_ppr_scratch_bytes(pp_graph g, int32_t k, int32_t k_tile);
  * is at most tol times the iterate's L1 norm (tol = 0: exactly iters; each
  * check synchronises the stream; PP_SWITCH also synchronises after each
  * sparse sweep).  iters_done (host, nullable): most sweeps any tile ran.
+ * k_tile = 1 runs the columns one after another with the single-vector
+ * PageRank sweeps of pp_pr_run (PP_PUSH or PP_PULL, tol = 0 only; it uses
+ * the graph's iterate buffers, so it must not overlap pp_pr_run on the same
+ * graph): the k sequential solves that batching is measured against.
  * SYNC when tol > 0 or dir = PP_SWITCH (and once to validate the sources). */
 pp_status pp_ppr_run(pp_graph g, pp_dir dir, int32_t k, const int32_t* sources, int32_t iters, float tol,
                      float f, int32_t k_tile, float* X, void* scratch, size_t scratch_bytes,

@@ -3,9 +3,11 @@
 Searches, per (GPU architecture, graph size class):
   * degree-bin thresholds and the split chunk of the longest rows (both
     sweeps);
-  * pull sweep: LDS-staged contributions and workgroup size;
+  * pull sweep: LDS-staged contributions, workgroup size and how many of the
+    heaviest rows take the tiled (source-sliced) sweep;
   * push sweep: LDS-privatised targets and persistent workgroups;
-  * BFS direction switch: the alpha/beta constants of the switch rule;
+  * BFS direction switch: the alpha/beta constants of the switch rule (on
+    roots of their own seed);
   * personalised PageRank: the column tile width for a given k.
 Every candidate is timed with HIP events on the device; the fastest wins.
 The cache maps "arch|size class" to the chosen values; ``apply`` installs a
@@ -24,6 +26,8 @@ import numpy as np
 import torch
 
 from . import PP_PULL, PP_PUSH, PP_SWITCH, BfsRun, Graph, _lib, pagerank_into, ppr
+
+TUNE_ROOT_SEED = 11  # BFS roots the switch constants are tuned on
 
 DEFAULTS = {"upper": [4, 16, 64, 1024, 4096], "split_chunk": 4096, "hot": 8192, "push_blocks": 1024,
             "pull_hot": 32768, "pull_block": 1024, "slice_rows": 0, "slice_width": 32768, "alpha": 14.0,
@@ -73,6 +77,8 @@ def _time(fn, reps=3) -> float:
     return best
 
 
+SLICE_ROWS = (65536, 131072, 262144, 524288)
+
 BIN_CANDIDATES = (
     ([4, 16, 64, 1024, 4096], 4096),
     ([8, 32, 128, 1024, 4096], 4096),
@@ -113,16 +119,20 @@ def tune_pagerank(host, iters=5, log=print, base=None) -> dict:
         return _time(f)
 
     best = None
-    for pull_hot in (16384, 32768, 40960):
+    # tiled rows: none, or the heaviest R rows (only for graphs with more
+    # rows than one source slice holds)
+    slice_rows = [0] + [r for r in SLICE_ROWS if host.n > 2 * 32768 and r < host.n]
+    for pull_hot in (32768, 40960):
         for block in (512, 1024):
-            apply({**out, "pull_hot": pull_hot, "pull_block": block})
-            g = Graph(host)
-            t = run(g, PP_PULL)
-            g.close()
-            log(f"pull hot={pull_hot} block={block}: {t / iters * 1e3:.1f} us/iter")
-            if best is None or t < best[0]:
-                best = (t, pull_hot, block)
-    out["pull_hot"], out["pull_block"] = best[1], best[2]
+            for rows in slice_rows:
+                apply({**out, "pull_hot": pull_hot, "pull_block": block, "slice_rows": rows, "slice_width": 32768})
+                g = Graph(host)
+                t = run(g, PP_PULL)
+                g.close()
+                log(f"pull hot={pull_hot} block={block} slice_rows={rows}: {t / iters * 1e3:.1f} us/iter")
+                if best is None or t < best[0]:
+                    best = (t, pull_hot, block, rows)
+    out["pull_hot"], out["pull_block"], out["slice_rows"], out["slice_width"] = best[1], best[2], best[3], 32768
     best = None
     for hot in (8192, 16384, 32768, 40960):
         for blocks in ((512, 1024, 2048) if hot <= 16384 else (256, 512)):
@@ -193,7 +203,9 @@ def main():
     if not only or "pagerank" in only:
         cfg.update(tune_pagerank(host, base=tune_bins(host)))
     if not only or "bfs" in only:
-        cfg.update(tune_bfs_switch(host, gg.pick_vertices(host, a.roots, seed=1)))
+        # roots drawn with a seed of their own: the benchmark's roots (seed 1)
+        # are not the ones the constants are chosen on
+        cfg.update(tune_bfs_switch(host, gg.pick_vertices(host, a.roots, seed=TUNE_ROOT_SEED)))
     if a.ppr_k and (not only or "ppr" in only):
         cfg.update(tune_ppr_tile(host, a.ppr_k))
     cache[k] = cfg

@@ -231,6 +231,10 @@ Teleport uniform_teleport(int32_t n, float f);
 pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float f, hipStream_t st,
                       int32_t skip_below = 0, const Teleport* tp = nullptr);
 pp_status launch_push(pp_graph g, const float* c, float* y, hipStream_t st);
+// One personalised PageRank column with the single-vector sweeps (pr.hip):
+// x_0 = e_s (s internal), iters steps, x written to x_out[caller id * x_stride].
+pp_status run_single_ppr(pp_graph g, pp_dir dir, int32_t s, int32_t iters, float f, float* x_out, int64_t x_stride,
+                         hipStream_t st);
 
 pp_status set_error(pp_status s, const std::string& msg);
 pp_status hip_error(hipError_t e, const char* what);

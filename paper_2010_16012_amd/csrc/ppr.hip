@@ -1056,12 +1056,54 @@ static pp_status check_ppr(pp_graph g, pp_dir dir, int32_t k, int32_t iters, flo
     return PP_OK;
 }
 
+// k_tile = 1: the columns one after another, each with the single-vector
+// pull or push sweep (the "k sequential sweeps" a batched run is measured
+// against).  Scratch: the sources' internal ids and a flag.
+static size_t single_scratch_bytes(int32_t k) { return align_up((size_t)std::max(k, 1) * 4, 256) + 256; }
+
+static pp_status ppr_single(pp_graph g, pp_dir dir, int32_t k, const int32_t* sources, int32_t iters, float tol,
+                            float f, float* X, void* scratch, size_t scratch_bytes, int32_t* iters_done,
+                            hipStream_t st) {
+    if (!g) return set_error(PP_E_NULL, "graph handle is NULL");
+    if (dir != PP_PUSH && dir != PP_PULL) return set_error(PP_E_RANGE, "k_tile 1 runs PP_PUSH or PP_PULL sweeps");
+    if (k < 0) return set_error(PP_E_SIZE, "k must be >= 0");
+    if (iters < 0) return set_error(PP_E_RANGE, "iters must be >= 0");
+    if (tol != 0.f) return set_error(PP_E_RANGE, "k_tile 1 runs a fixed number of sweeps (tol must be 0)");
+    if (!(f >= 0.f && f < 1.f)) return set_error(PP_E_RANGE, "f must lie in [0, 1)");
+    if (!scratch) return set_error(PP_E_NULL, "scratch is NULL");
+    if (scratch_bytes < single_scratch_bytes(k)) return set_error(PP_E_WORKSPACE, "PPR scratch too small");
+    if (reinterpret_cast<uintptr_t>(scratch) % 256 != 0) return set_error(PP_E_RANGE, "scratch must be 256-byte aligned");
+    if (k > 0 && (!sources || !X)) return set_error(PP_E_NULL, "sources and X are required");
+    if (iters_done) *iters_done = 0;
+    if (k == 0) return PP_OK;
+    int32_t* src_int = static_cast<int32_t*>(scratch);
+    int32_t* flag = reinterpret_cast<int32_t*>(static_cast<char*>(scratch) + align_up((size_t)k * 4, 256));
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, st, (int64_t)1, reinterpret_cast<float*>(flag));
+    hipLaunchKernelGGL(k_sources_internal, dim3(ceil_div(k, 256)), dim3(256), 0, st, k, k, sources, g->d.iperm,
+                       g->d.n, src_int, flag);
+    PP_LAUNCH_CHECK("ppr sources");
+    std::vector<int32_t> s_int(k);
+    int32_t bad = 0;
+    PP_HIP(hipMemcpyAsync(s_int.data(), src_int, (size_t)k * 4, hipMemcpyDeviceToHost, st));
+    PP_HIP(hipMemcpyAsync(&bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    PP_HIP(hipStreamSynchronize(st));
+    if (bad) return set_error(PP_E_RANGE, "a source lies outside [0, n)");
+    for (int32_t j = 0; j < k; ++j) {
+        pp_status s = run_single_ppr(g, dir, s_int[j], iters, f, X + j, k, st);
+        if (s != PP_OK) return s;
+    }
+    if (iters_done) *iters_done = iters;
+    return PP_OK;
+}
+
 }  // namespace pp
 
 using namespace pp;
 
 PP_EXPORT size_t pp_ppr_scratch_bytes(pp_graph g, int32_t k, int32_t k_tile) {
-    if (!g || !valid_kt(k_tile) || k < 0) return 0;
+    if (!g || k < 0) return 0;
+    if (k_tile == 1) return single_scratch_bytes(k);
+    if (!valid_kt(k_tile)) return 0;
     return ppr_layout(g->d.n, g->d.nnz, g->split_cap, k, k_tile, max_units(g, k_tile)).total;
 }
 
@@ -1069,6 +1111,9 @@ PP_EXPORT pp_status pp_ppr_run(pp_graph g, pp_dir dir, int32_t k, const int32_t*
                                float f, int32_t k_tile, float* X, void* scratch, size_t scratch_bytes,
                                int32_t* iters_done, void* stream) {
     clear_error();
+    if (k_tile == 1)
+        return ppr_single(g, dir, k, sources, iters, tol, f, X, scratch, scratch_bytes, iters_done,
+                          static_cast<hipStream_t>(stream));
     const size_t need = pp_ppr_scratch_bytes(g, k, k_tile);
     pp_status s = check_ppr(g, dir, k, iters, tol, f, k_tile, scratch, scratch_bytes, need);
     if (s != PP_OK) return s;

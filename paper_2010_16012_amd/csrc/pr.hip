@@ -679,16 +679,31 @@ __global__ void k_pr_prologue(int32_t n, const float* __restrict__ x, const int3
 }
 
 // After a push sweep: c[u] = f * y[u] / s(u); reset the other accumulator to
-// base; copy the iterate out (caller ids) on the last step.
+// the teleport term (base, plus tele on row tele_v); copy the iterate out
+// (caller ids, x_out[id * x_stride]) on the last step.
 __global__ void k_pr_push_epilogue(int32_t n, const float* __restrict__ y, const float* __restrict__ inv_s, float f,
-                                   float* __restrict__ c, float* __restrict__ y_reset, float base,
-                                   float* __restrict__ x_out, const int32_t* __restrict__ perm) {
+                                   float* __restrict__ c, float* __restrict__ y_reset, float base, int32_t tele_v,
+                                   float tele, float* __restrict__ x_out, int64_t x_stride,
+                                   const int32_t* __restrict__ perm) {
     const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
     const float yv = y[u];
     if (c) c[u] = f * yv * inv_s[u];
-    if (y_reset) y_reset[u] = base;
-    if (x_out) x_out[user_id(perm, u)] = yv;
+    if (y_reset) y_reset[u] = base + ((u == tele_v) ? tele : 0.f);
+    if (x_out) x_out[(int64_t)user_id(perm, u) * x_stride] = yv;
+}
+
+// Start of a personalised run from x_0 = e_s (s internal): c = f x_0 / s(.),
+// and, for the push form, the accumulator preset to the teleport (1-f) e_s.
+// With x_out (iters = 0) x_0 itself is written out instead.
+__global__ void k_ppr1_init(int32_t n, int32_t s, const float* __restrict__ inv_s, float f, float* __restrict__ c,
+                            float* __restrict__ y_init, float* __restrict__ x_out, int64_t x_stride,
+                            const int32_t* __restrict__ perm) {
+    const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    c[u] = (u == s) ? f * inv_s[u] : 0.f;
+    if (y_init) y_init[u] = (u == s) ? 1.f - f : 0.f;
+    if (x_out) x_out[(int64_t)user_id(perm, u) * x_stride] = (u == s) ? 1.f : 0.f;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -927,6 +942,54 @@ pp_status launch_push(pp_graph g, const float* c, float* y, hipStream_t st) {
     return PP_OK;
 }
 
+// One personalised column with the single-vector sweeps: x_0 = e_s (s
+// internal), iters steps of x <- (1-f) e_s + f P x in direction dir (PP_PULL
+// or PP_PUSH), x_iters written to x_out[caller id * x_stride].  Uses the
+// graph's iterate buffers, like pp_pr_run.
+pp_status run_single_ppr(pp_graph g, pp_dir dir, int32_t s, int32_t iters, float f, float* x_out, int64_t x_stride,
+                         hipStream_t st) {
+    const int32_t n = g->d.n;
+    const dim3 vb(ceil_div(n, 256)), vt(256);
+    const float tele = 1.f - f;
+    float* c = g->d.buf0;
+    if (iters == 0) {
+        hipLaunchKernelGGL(k_ppr1_init, vb, vt, 0, st, n, s, g->d.inv_s, f, c, (float*)nullptr, x_out, x_stride,
+                           g->d.perm);
+        PP_LAUNCH_CHECK("k_ppr1_init");
+        return PP_OK;
+    }
+    if (dir == PP_PULL) {
+        const Teleport tp{0.f, s, tele, x_stride};
+        float* cn = g->d.buf1;
+        hipLaunchKernelGGL(k_ppr1_init, vb, vt, 0, st, n, s, g->d.inv_s, f, c, (float*)nullptr, (float*)nullptr,
+                           (int64_t)0, g->d.perm);
+        PP_LAUNCH_CHECK("k_ppr1_init");
+        for (int32_t t = 0; t < iters; ++t) {
+            const bool last = (t == iters - 1);
+            pp_status r = launch_pull(g, c, last ? nullptr : cn, last ? x_out : nullptr, f, st, 0, &tp);
+            if (r != PP_OK) return r;
+            std::swap(c, cn);
+        }
+        return PP_OK;
+    }
+    float* ya = g->d.buf1;
+    float* yb = g->d.buf2;
+    hipLaunchKernelGGL(k_ppr1_init, vb, vt, 0, st, n, s, g->d.inv_s, f, c, ya, (float*)nullptr, (int64_t)0,
+                       g->d.perm);
+    PP_LAUNCH_CHECK("k_ppr1_init");
+    for (int32_t t = 0; t < iters; ++t) {
+        const bool last = (t == iters - 1);
+        pp_status r = launch_push(g, c, ya, st);
+        if (r != PP_OK) return r;
+        hipLaunchKernelGGL(k_pr_push_epilogue, vb, vt, 0, st, n, (const float*)ya, g->d.inv_s, f,
+                           last ? nullptr : c, last ? nullptr : yb, 0.f, s, tele, last ? x_out : nullptr, x_stride,
+                           g->d.perm);
+        PP_LAUNCH_CHECK("k_pr_push_epilogue");
+        std::swap(ya, yb);
+    }
+    return PP_OK;
+}
+
 static pp_status check_pr_args(pp_graph g, const void* x, const void* y, float f) {
     if (!g) return set_error(PP_E_NULL, "graph handle is NULL");
     if (!x || !y) return set_error(PP_E_NULL, "x and y are required");
@@ -964,7 +1027,7 @@ PP_EXPORT pp_status pp_pr_push(pp_graph g, const float* x, float* y, float f, vo
     s = launch_push(g, g->d.buf0, g->d.buf1, st);
     if (s != PP_OK) return s;
     hipLaunchKernelGGL(k_pr_push_epilogue, vb, vt, 0, st, n, (const float*)g->d.buf1, g->d.inv_s, f, (float*)nullptr,
-                       (float*)nullptr, 0.f, y, g->d.perm);
+                       (float*)nullptr, 0.f, -1, 0.f, y, (int64_t)1, g->d.perm);
     PP_LAUNCH_CHECK("k_pr_push_epilogue");
     return PP_OK;
 }
@@ -1040,7 +1103,8 @@ PP_EXPORT pp_status pp_pr_run(pp_graph g, pp_dir dir, int32_t iters, float f, fl
         pp_status s = launch_push(g, c, ya, st);
         if (s != PP_OK) return s;
         hipLaunchKernelGGL(k_pr_push_epilogue, vb, vt, 0, st, n, (const float*)ya, g->d.inv_s, f,
-                           last ? nullptr : c, last ? nullptr : yb, base, last ? x_inout : nullptr, g->d.perm);
+                           last ? nullptr : c, last ? nullptr : yb, base, -1, 0.f, last ? x_inout : nullptr,
+                           (int64_t)1, g->d.perm);
         PP_LAUNCH_CHECK("k_pr_push_epilogue");
         float* tmp = ya;
         ya = yb;

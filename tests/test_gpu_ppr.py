@@ -45,6 +45,49 @@ def test_batched_ppr_matches_oracle_columns(kt, k):
             _cols_close(X.cpu().numpy(), want)
 
 
+@pytest.mark.parametrize("tiled", [False, True])
+def test_sequential_single_vector_columns(tiled):
+    # k_tile = 1: each column with the single-vector sweep (the sequential
+    # baseline of the batched runs), tiled pull rows included
+    host = gg.workload("rmat14")
+    src = gg.pick_vertices(host, 12, seed=5)
+    want, _ = oracle.ppr(host.off, host.idx, src, F, T=30)
+    if tiled:
+        pp._lib.pp_set_pull_slices(2048, 4096)
+    try:
+        g = pp.Graph(host)
+        if tiled:
+            assert g.slices()[0] > 0
+        for d in DIRS:
+            announce(f"PPR k_tile=1 tiled={tiled} dir={d}")
+            X, done = pp.ppr(g, src, iters=30, f=F, k_tile=1, direction=d)
+            assert done == 30
+            _cols_close(X.cpu().numpy(), want)
+            X0, _ = pp.ppr(g, src[:2], iters=0, f=F, k_tile=1, direction=d)
+            e = np.zeros((host.n, 2), dtype=np.float32)
+            e[src[:2], [0, 1]] = 1
+            assert np.array_equal(X0.cpu().numpy(), e)
+    finally:
+        pp._lib.pp_set_pull_slices(0, 32768)
+
+
+def test_sequential_single_vector_weighted_directed():
+    host = H.random_graph(3000, 9000, 12, symmetric=False, connected=True)
+    gg.with_weights(host, seed=2)
+    src = np.array([3, 700, 2999], dtype=np.int32)
+    want, _ = oracle.ppr(host.off, host.idx, src, F, T=25, weights=host.weights)
+    g = pp.Graph(host)
+    for d in DIRS:
+        X, _ = pp.ppr(g, src, iters=25, f=F, k_tile=1, direction=d)
+        _cols_close(X.cpu().numpy(), want)
+    with pytest.raises(pp.PPError):
+        pp.ppr(g, src, iters=25, f=F, k_tile=1, direction=pp.PP_SWITCH)
+    with pytest.raises(pp.PPError):
+        pp.ppr(g, src, iters=25, f=F, k_tile=1, tol=1e-6)
+    with pytest.raises(pp.PPError):
+        pp.ppr(g, np.array([3000], dtype=np.int32), iters=2, f=F, k_tile=1)
+
+
 @pytest.mark.parametrize("name,kt,k", [("rmat14", 32, 64), ("grid64", 16, 20), ("grid200", 8, 8),
                                         ("star5000", 8, 3)])
 def test_switch_sparse_push_then_dense_pull(name, kt, k):
