@@ -174,12 +174,161 @@ __device__ __forceinline__ float kt_block_sum(float v, float* red) {
     return t;
 }
 
+// The pull sweep moves float4s: a row is owned by KT/4 lanes, lane q holding
+// columns 4q..4q+3, so one neighbour costs one 16-byte load per lane (a
+// KT-float row per group) and a wavefront keeps 256/KT rows going at once.
+template <int KT>
+constexpr int kq_lanes() { return KT / 4; }
+
+__device__ __forceinline__ float4 f4_add(float4 x, float4 y) {
+    return make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w);
+}
+
+__device__ __forceinline__ float4 f4_scale(float4 x, float s) { return make_float4(x.x * s, x.y * s, x.z * s, x.w * s); }
+
+// One group of KT/4 lanes sums src[idx[j]] (x wt[j]) over j = b + g,
+// b + g + stride, ...: U index loads, then U float4 gathers in flight, summed
+// pairwise before they join the running sum (fixed order, and a hub row of
+// thousands of slots keeps its FP32 rounding error near log2(U) + slots/U
+// steps).  Loads past the row's end are exec-masked, not clamped: a clamped
+// gather would still move KT floats.
+template <int KT, int U, bool W>
+__device__ __forceinline__ float4 kt_gather4(const KArgs& a, int32_t b, int32_t e, int32_t g, int32_t stride,
+                                             int q) {
+    const float4* __restrict__ src4 = reinterpret_cast<const float4*>(a.src);
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int32_t j0 = b + g; j0 < e; j0 += U * stride) {
+        int32_t vv[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) vv[k] = a.idx[min(j0 + k * stride, e - 1)];
+        float4 x[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            x[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j0 + k * stride < e) x[k] = src4[(size_t)vv[k] * kq_lanes<KT>() + q];
+        }
+        if (W) {
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                if (j0 + k * stride < e) x[k] = f4_scale(x[k], a.wt[j0 + k * stride]);
+        }
+#pragma unroll
+        for (int w = 1; w < U; w <<= 1) {
+#pragma unroll
+            for (int k = 0; k + w < U; k += 2 * w) x[k] = f4_add(x[k], x[k + w]);
+        }
+        acc = f4_add(acc, x[0]);
+    }
+    return acc;
+}
+
+// Sum over the groups of a workgroup as a fixed binary tree (thread q < KT/4
+// holds it): log2(G) rounding steps instead of G - 1 for a row spread over all
+// G groups.
+template <int KT>
+__device__ __forceinline__ float4 kt_block_sum4(float4 v, float4* red) {
+    constexpr int Q = kq_lanes<KT>();
+    constexpr int G = kBlock / Q;
+    static_assert((G & (G - 1)) == 0, "group count must be a power of two");
+    const int grp = threadIdx.x / Q;
+    red[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = G / 2; s >= 1; s >>= 1) {
+        if (grp < s) red[threadIdx.x] = f4_add(red[threadIdx.x], red[threadIdx.x + s * Q]);
+        __syncthreads();
+    }
+    const float4 t = (threadIdx.x < Q) ? red[threadIdx.x] : make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    return t;
+}
+
+// kt_epilogue for columns 4q..4q+3 of row u.
+template <int KT>
+__device__ __forceinline__ float2 kt_epilogue4(const KArgs& a, int32_t u, int q, float4 acc) {
+    const float in[4] = {acc.x, acc.y, acc.z, acc.w};
+    float val[4];
+    const int c0 = a.col0 + 4 * q;
+    if (a.kind == kEpiForward) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) val[c] = in[c] + ((a.src_int[c0 + c] == u) ? 1.0f - a.f : 0.f);
+        if (a.out_scaled) {
+            const float sc = a.f * a.inv_s[u];
+            reinterpret_cast<float4*>(a.out_scaled)[(size_t)u * kq_lanes<KT>() + q] =
+                make_float4(sc * val[0], sc * val[1], sc * val[2], sc * val[3]);
+        }
+    } else if (a.kind == kEpiAdjoint) {
+        const int32_t uc = user_id(a.perm, u);
+        const float sc = a.f * a.inv_s[u];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float gv = (c0 + c < a.k) ? a.g_caller[(size_t)uc * a.k + c0 + c] : 0.f;
+            val[c] = gv + sc * in[c];
+        }
+    } else {
+        const float is = a.inv_s[u];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) val[c] = is * in[c];  // (P^T Lambda)(u)
+    }
+    reinterpret_cast<float4*>(a.out_tile)[(size_t)u * kq_lanes<KT>() + q] = make_float4(val[0], val[1], val[2], val[3]);
+    if (a.out_caller) {
+        const int32_t uc = user_id(a.perm, u);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c0 + c < a.k) a.out_caller[(size_t)uc * a.k + c0 + c] = val[c];
+    }
+    float2 r = make_float2(0.f, 0.f);
+    if (a.prev) {
+        const float4 p4 = reinterpret_cast<const float4*>(a.prev)[(size_t)u * kq_lanes<KT>() + q];
+        const float pv[4] = {p4.x, p4.y, p4.z, p4.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            r.x += fabsf(val[c] - pv[c]);
+            r.y += fabsf(val[c]);
+        }
+    }
+    return r;
+}
+
+// Units of bin b in a plan: bins run 5, 4, ..., 0, so bin b ends where bin
+// b - 1 starts (bin 0 at the end of the plan).
+static int32_t kplan_bin_units(const KPlan& kp, int b) {
+    return (b == 0 ? kp.units : kp.unit_off[b - 1]) - kp.unit_off[b];
+}
+
+// Units of the float4 pull over the row-unit plan kp: bins 0-2 put
+// kBlock/(KT/4) rows in a unit, bins 3-4 one row, bin 5 one chunk.
+static KPlan kplan_pull4(const KPlan& kp, int kt) {
+    KPlan k = kp;
+    int32_t at = 0;
+    for (int b = PP_NUM_BINS - 1; b >= 0; --b) {
+        const int32_t rows = kp.list_off[b + 1] - kp.list_off[b];
+        const int32_t units = (b <= 2) ? ceil_div(rows, kBlock / (kt / 4)) : kplan_bin_units(kp, b);
+        k.unit_off[b] = at;
+        at += units;
+    }
+    k.unit_off[PP_NUM_BINS] = at;
+    k.units = at;
+    return k;
+}
+
+// A plan's bins must tile [0, units) in launch order with no negative count.
+static bool kplan_valid(const KPlan& kp) {
+    int32_t at = 0;
+    for (int b = PP_NUM_BINS - 1; b >= 0; --b) {
+        if (kp.unit_off[b] != at || kplan_bin_units(kp, b) < 0) return false;
+        at += kplan_bin_units(kp, b);
+    }
+    return at == kp.units && kp.unit_off[PP_NUM_BINS] == kp.units;
+}
+
 template <int KT, bool W>
 __global__ __launch_bounds__(kBlock) void k_kcol_pull(KArgs a) {
-    __shared__ float red[2 * kBlock];
-    constexpr int G = kBlock / KT;
-    const int lane = threadIdx.x % KT;
-    const int grp = threadIdx.x / KT;
+    __shared__ float4 red4[kBlock];
+    constexpr int Q = kq_lanes<KT>();
+    constexpr int G = kBlock / Q;
+    const int q = threadIdx.x % Q;
+    const int grp = threadIdx.x / Q;
     const int32_t unit = blockIdx.x;
     const int bin = kunit_bin(a.kp, unit);
     const int32_t lu = unit - a.kp.unit_off[bin];
@@ -188,21 +337,22 @@ __global__ __launch_bounds__(kBlock) void k_kcol_pull(KArgs a) {
         const int32_t i = lu * G + grp;
         if (i < a.kp.list_off[bin + 1] - a.kp.list_off[bin]) {
             const int32_t u = a.list[a.kp.list_off[bin] + i];
-            const float acc = kt_gather<KT, W>(a, a.off[u], a.off[u + 1], 0, 1, lane);
-            res = kt_epilogue<KT>(a, u, lane, acc);
+            const float4 acc = (bin == 0) ? kt_gather4<KT, 4, W>(a, a.off[u], a.off[u + 1], 0, 1, q)
+                                          : kt_gather4<KT, 8, W>(a, a.off[u], a.off[u + 1], 0, 1, q);
+            res = kt_epilogue4<KT>(a, u, q, acc);
         }
     } else if (bin <= 4) {
         const int32_t u = a.list[a.kp.list_off[bin] + lu];
-        float acc = kt_gather<KT, W>(a, a.off[u], a.off[u + 1], grp, G, lane);
-        acc = kt_block_sum<KT>(acc, red);
-        if (threadIdx.x < KT) res = kt_epilogue<KT>(a, u, lane, acc);
+        float4 acc = kt_gather4<KT, 8, W>(a, a.off[u], a.off[u + 1], grp, G, q);
+        acc = kt_block_sum4<KT>(acc, red4);
+        if (threadIdx.x < Q) res = kt_epilogue4<KT>(a, u, q, acc);
     } else {
         const int32_t b = a.tab[a.tab_cap + lu], e = a.tab[2 * a.tab_cap + lu];
-        float acc = kt_gather<KT, W>(a, b, e, grp, G, lane);
-        acc = kt_block_sum<KT>(acc, red);
-        if (threadIdx.x < KT) a.part[(size_t)lu * KT + lane] = acc;
+        float4 acc = kt_gather4<KT, 8, W>(a, b, e, grp, G, q);
+        acc = kt_block_sum4<KT>(acc, red4);
+        if (threadIdx.x < Q) reinterpret_cast<float4*>(a.part)[(size_t)lu * Q + q] = acc;
     }
-    if (a.resid_part) resid_flush(res, red, a.resid_part, unit);
+    if (a.resid_part) resid_flush(res, reinterpret_cast<float*>(red4), a.resid_part, unit);
 }
 
 // Finishes the chunked rows: partials in chunk order, then the epilogue.
@@ -590,15 +740,23 @@ static int32_t max_units(pp_graph g, int kt) {
 
 static bool valid_kt(int32_t kt) { return kt == 8 || kt == 16 || kt == 32 || kt == 64; }
 
+// Launches a pull sweep over the row-unit plan a.kp; returns the residual
+// slots written (units, then the fix-up's blocks) when a.resid_part is set.
 template <int KT>
-static void launch_kpull(const KArgs& a, int32_t nsplit, float* resid_fix, hipStream_t st, bool weighted) {
+static int32_t launch_kpull(const KArgs& a_rows, int32_t nsplit, hipStream_t st, bool weighted) {
+    KArgs a = a_rows;
+    a.kp = kplan_pull4(a_rows.kp, KT);
+    if (!kplan_valid(a_rows.kp) || !kplan_valid(a.kp) || kplan_bin_units(a.kp, 5) != kplan_bin_units(a_rows.kp, 5))
+        return -1;  // never launch over an inconsistent plan
     if (a.kp.units > 0) {
         if (weighted) hipLaunchKernelGGL((k_kcol_pull<KT, true>), dim3(a.kp.units), dim3(kBlock), 0, st, a);
         else hipLaunchKernelGGL((k_kcol_pull<KT, false>), dim3(a.kp.units), dim3(kBlock), 0, st, a);
     }
+    float* resid_fix = a.resid_part ? a.resid_part + 2 * (size_t)a.kp.units : nullptr;
     if (nsplit > 0)
         hipLaunchKernelGGL((k_kcol_fix<KT>), dim3(ceil_div(nsplit, kBlock / KT)), dim3(kBlock), 0, st, a, nsplit,
                            resid_fix);
+    return a.kp.units + (nsplit > 0 ? ceil_div(nsplit, kBlock / KT) : 0);
 }
 
 template <int KT>
@@ -803,8 +961,8 @@ static pp_status run_tile(pp_graph g, bool adjoint, pp_dir dir, int32_t k, int32
             a.tab_cap = g->split_cap;
             a.part = part;
             a.src = moved;
-            launch_kpull<KT>(a, w.nsplit, w.nsplit > 0 ? resid + 2 * (size_t)w.kp.units : nullptr, st, g->weighted);
-            nres = w.kp.units + (w.nsplit > 0 ? ceil_div(w.nsplit, kBlock / KT) : 0);
+            nres = launch_kpull<KT>(a, w.nsplit, st, g->weighted);
+            if (nres < 0) return set_error(PP_E_GRAPH, "inconsistent k-column sweep plan");
         } else {
             // forward push scatters along CSR; the adjoint push scatters along CSC
             const Walk w = adjoint ? walk_csc(g, KT) : walk_csr(g, KT);
@@ -862,7 +1020,8 @@ static pp_status adjoint_grad(pp_graph g, int32_t k, int32_t col0, float f, cons
     a.tab_cap = g->split_cap;
     a.part = part;
     a.src = lam;
-    launch_kpull<KT>(a, w.nsplit, nullptr, st, g->weighted);
+    if (launch_kpull<KT>(a, w.nsplit, st, g->weighted) < 0)
+        return set_error(PP_E_GRAPH, "inconsistent k-column sweep plan");
     GradArgs ga{};
     ga.kp = w.kp;
     ga.off = w.off;
@@ -928,7 +1087,8 @@ static pp_status unrolled_tile(pp_graph g, int32_t k, int32_t col0, int32_t T, f
             a.tab_cap = g->split_cap;
             a.part = part;
             a.src = c_cur;
-            launch_kpull<KT>(a, w.nsplit, nullptr, st, g->weighted);
+            if (launch_kpull<KT>(a, w.nsplit, st, g->weighted) < 0)
+                return set_error(PP_E_GRAPH, "inconsistent k-column sweep plan");
             std::swap(c_cur, c_nxt);
         }
         PP_LAUNCH_CHECK("ppr unrolled forward");
