@@ -151,6 +151,19 @@ pp_status pp_set_pull_tuning(int32_t pull_hot, int32_t pull_block);
  * pp_graph_create; the workspace query accounts for it. */
 pp_status pp_set_pull_slices(int32_t rows, int32_t width);
 
+/* Deep-graph BFS (pp_bfs_run / pp_bfs_run_log with PP_PUSH or PP_SWITCH):
+ * while a top-down frontier has at most max_frontier vertices and
+ * max_edges out-edges, and the switch rule keeps top-down, whole levels run
+ * inside one launch on one workgroup (frontier in LDS, no launch per level;
+ * the per-level cost of Sec. 4.3 that grows with the diameter D).  Larger
+ * frontiers go back to the grid-wide level kernels.  Levels and statistics
+ * do not depend on it.  One compute unit sustains only so many misses in
+ * flight, so this pays for narrow frontiers (a path: 3.4 against 6.7 us per
+ * level) and not for frontiers of thousands of vertices.  Defaults 256 and
+ * 1024; max_frontier is capped by the LDS of a workgroup (6144 on gfx950);
+ * 0 turns it off.  Takes effect at the next pp_graph_create. */
+pp_status pp_set_bfs_multi(int32_t max_frontier, int32_t max_edges);
+
 /* The tiled-pull plan of g: info[0..4) = R, width, S, tiles (R = 0: off). */
 pp_status pp_graph_slices(pp_graph g, int32_t* info);
 

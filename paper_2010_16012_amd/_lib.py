@@ -86,6 +86,7 @@ _SIGS = {
     "pp_multi_run_static": ([_I32, _P, _P, _P, _P, _P, _P, ctypes.c_int, _I32, _F32, _P, _I32, _I32, _F32, _F32, _P,
                              _P, _P], ctypes.c_int),
     "pp_set_pull_slices": ([_I32, _I32], ctypes.c_int),
+    "pp_set_bfs_multi": ([_I32, _I32], ctypes.c_int),
     "pp_graph_slices": ([_P, _P], ctypes.c_int),
     "pp_ppr_run": ([_P, ctypes.c_int, _I32, _P, _I32, _F32, _F32, _I32, _P, _P, _SZ, ctypes.POINTER(_I32), _P],
                    ctypes.c_int),
@@ -234,6 +235,10 @@ def pp_bfs_run(h, root, policy, alpha, beta, level, parent, state, stream=None) 
 
 def pp_set_pull_slices(rows: int, width: int) -> None:
     _check(_lib.pp_set_pull_slices(rows, width))
+
+
+def pp_set_bfs_multi(max_frontier: int, max_edges: int) -> None:
+    _check(_lib.pp_set_bfs_multi(max_frontier, max_edges))
 
 
 def pp_graph_slices(h):

@@ -1018,6 +1018,279 @@ __global__ __launch_bounds__(kBfsBlock, 8) void k_bfs_chunks(BfsArgs a) {
     flush_stats(cnt, deg, &h->slot[sn]);
 }
 
+// ------------------------------------------------------------ deep graphs
+// Top-down levels with small frontiers, many per launch, on ONE workgroup.
+// A deep graph (a grid: thousands of levels of a few thousand vertices)
+// spends its time on per-level launch latency, not on bytes.  This kernel
+// keeps the frontier in LDS as (vertex, row begin, degree -> prefix) sets,
+// claims targets with workgroup-scope atomics on the visited bitmap (only
+// this workgroup runs, so they resolve in the local L2), and loads the row
+// bounds of a vertex when it is claimed, so a level costs two dependent
+// memory round trips (target ids, claims; the row bounds ride with the
+// claims) and a few workgroup barriers.  It runs levels while the frontier
+// has at most qcap vertices and ecap out-edges and the switch rule keeps
+// top-down, then hands the state back exactly as a queue-driven top-down
+// level kernel would have left it (queue pages, frontier bitmap, slots,
+// level index, statistics), so the grid-wide kernels continue from there.
+// It takes over only a compact top-down frontier (few queue pages, bitmap
+// words of the previous frontier already clear) and otherwise returns at
+// once without touching anything.
+constexpr int32_t kMultiLevels = 32768;   // levels per launch (bounds its duration)
+constexpr int32_t kMultiPages = 64;       // queue pages a taken-over frontier may span
+constexpr int kMultiB = 8;                // edges a lane handles per round
+
+struct MultiSet {
+    int32_t* v;  // vertex
+    int32_t* b;  // CSR row begin
+    int32_t* p;  // degree, then exclusive prefix of the degrees ([nf] = total)
+};
+
+__device__ __forceinline__ MultiSet multi_set(int32_t* base, int32_t qcap, int which) {
+    int32_t* s = base + (size_t)which * (3 * qcap + 1);
+    return MultiSet{s, s + qcap, s + 2 * qcap};
+}
+
+// Would a level kernel expand frontier `lvl` (nf vertices, m out-edges,
+// mu_base, built by dir_prev from n_prev vertices) top-down?
+__device__ __forceinline__ bool multi_push(int32_t policy, float alpha, float beta, int32_t n, int32_t lvl,
+                                           int32_t nf, int64_t m, int64_t mu_base, int32_t dir_prev, int32_t n_prev) {
+    if (policy == PP_PUSH) return true;
+    if (policy != PP_SWITCH) return false;
+    const int64_t mu = mu_base - m;
+    if (lvl == 0 || dir_prev == PP_PUSH) return !((double)m > (double)mu / (double)alpha);
+    return (double)nf < (double)n / (double)beta && nf < n_prev;
+}
+
+// Exclusive prefix of p[0, cnt) in place (p[cnt] = total).  Workgroup-collective.
+__device__ __forceinline__ void multi_scan(int32_t* p, int32_t cnt, int32_t* s_w) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const int32_t per = (cnt + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
+    const int32_t i0 = min((int32_t)threadIdx.x * per, cnt), i1 = min(i0 + per, cnt);
+    int32_t s = 0;
+    for (int32_t i = i0; i < i1; ++i) s += p[i];
+    int32_t incl = s;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
+    }
+    if (lane == kWave - 1) s_w[w] = incl;
+    __syncthreads();
+    int32_t base = 0;
+    for (int i = 0; i < w; ++i) base += s_w[i];
+    int32_t at = base + incl - s;
+    for (int32_t i = i0; i < i1; ++i) {
+        const int32_t d = p[i];
+        p[i] = at;
+        at += d;
+    }
+    if (threadIdx.x == blockDim.x - 1) p[cnt] = base + incl;
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kBfsBlock) void k_bfs_multi(BfsArgs a, int32_t policy, float alpha, float beta,
+                                                         int32_t qcap, int32_t ecap) {
+    extern __shared__ int32_t s_sets[];
+    __shared__ int32_t s_start[kBfsBlock];  // first frontier entry of each thread's edge range
+    __shared__ int32_t s_w[kBfsWaves];
+    __shared__ int64_t s_m[kBfsWaves];
+    __shared__ int32_t s_cnt;
+    __shared__ int32_t s_hdr[8];
+    __shared__ int64_t s_hdr64[2];
+    BfsHdr* h = a.hdr;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    if (threadIdx.x == 0) {
+        const int32_t lvl = h->lv[0];
+        const SlotView cur = view(h->slot[lvl % 3]);
+        const bool ok = !h->finished && cur.n > 0 && cur.n <= qcap && cur.m <= ecap && cur.dir_prev == PP_PUSH &&
+                        cur.n_prev <= a.words && cur.pages - a.static_pages <= kMultiPages &&
+                        multi_push(policy, alpha, beta, a.n, lvl, cur.n, cur.m, cur.mu_base, cur.dir_prev, cur.n_prev);
+        s_hdr[0] = ok;
+        s_hdr[1] = lvl;
+        s_hdr[2] = cur.n;
+        s_hdr[3] = cur.n_prev;
+        s_hdr[4] = cur.pages;
+        s_hdr64[0] = cur.m;
+        s_hdr64[1] = cur.mu_base;
+        s_cnt = 0;
+    }
+    __syncthreads();
+    if (!s_hdr[0]) return;
+    int32_t lvl = s_hdr[1], nf = s_hdr[2], n_prev = s_hdr[3];
+    int64_t m = s_hdr64[0], mu_base = s_hdr64[1];
+    // take over frontier lvl: its queue pages into set 0, its bitmap words
+    // cleared (as a queue-driven level clears them), row bounds loaded
+    int cur = 0;
+    {
+        const MultiSet A = multi_set(s_sets, qcap, 0);
+        const int32_t* q = a.queue[lvl & 1];
+        const int32_t* fill = a.fill[lvl & 1];
+        const int32_t pages = min(s_hdr[4], a.page_cap);
+        for (int32_t p = a.static_pages + w; p < pages; p += kBfsWaves) {
+            const int32_t f = min(fill[p], kPage);
+            int32_t base = 0;
+            if (lane == 0 && f > 0) base = atomicAdd(&s_cnt, f);
+            base = __shfl(base, 0);
+            for (int32_t s = lane; s < f; s += kWave)
+                if (base + s < qcap) A.v[base + s] = q[(size_t)p * kPage + s];
+        }
+        __syncthreads();
+        // a frontier that does not match its slot (never expected) is left to
+        // the level kernels, untouched
+        if (s_cnt != nf) return;
+        for (int32_t i = threadIdx.x; i < nf; i += blockDim.x) {
+            const int32_t v = A.v[i];
+            const int32_t rb = a.csr_off[v], re = a.csr_off[v + 1];
+            A.b[i] = rb;
+            A.p[i] = re - rb;
+            a.fb[lvl % 3][v >> 6] = 0ull;
+        }
+        __syncthreads();
+        multi_scan(A.p, nf, s_w);
+    }
+    int64_t reached = 0, edges = 0;
+    for (int32_t run = 0;; ++run) {
+        const MultiSet A = multi_set(s_sets, qcap, cur), B = multi_set(s_sets, qcap, cur ^ 1);
+        // stop before a level that is empty, too large for the sets, past the
+        // launch's budget, or one the switch rule would expand bottom-up
+        if (nf == 0 || nf > qcap || m > ecap || run >= kMultiLevels ||
+            !multi_push(policy, alpha, beta, a.n, lvl, nf, m, mu_base, PP_PUSH, n_prev))
+            break;
+        if (threadIdx.x == 0) {
+            if (lvl < PP_BFS_MAX_LOG) {
+                h->log_dir[lvl] = (int8_t)PP_PUSH;
+                h->log_n[lvl] = nf;
+            }
+            if (lvl < a.log_cap) a.log[lvl] = pp_bfs_level{PP_PUSH, nf, m};
+            s_cnt = 0;
+        }
+        reached += nf;
+        edges += m;
+        // thread t walks edges [t*c, t*c + c) of the frontier's out-edges;
+        // s_start[t] is the entry holding edge t*c
+        const int32_t mi = (int32_t)m;
+        const int32_t c = max((mi + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x, 1);
+        for (int32_t i = threadIdx.x; i < nf; i += blockDim.x) {
+            const int32_t lo = A.p[i], hi = A.p[i + 1];
+            for (int32_t t = (lo + c - 1) / c; t * c < hi; ++t) s_start[t] = i;
+        }
+        __syncthreads();
+        const int32_t k0 = (int32_t)threadIdx.x * c, k1 = min(k0 + c, mi);
+        int32_t e = (k0 < mi) ? s_start[threadIdx.x] : 0;
+        uint64_t* fb_next = a.fb[(lvl + 1) % 3];
+        int32_t* q_next = a.queue[(lvl + 1) & 1];
+        int64_t mloc = 0;
+        for (int32_t kb = k0; kb - k0 < c; kb += kMultiB) {  // c is uniform: every lane takes every round
+            int32_t u[kMultiB], pv[kMultiB];
+#pragma unroll
+            for (int r = 0; r < kMultiB; ++r) {
+                const int32_t k = kb + r;
+                u[r] = -1;
+                pv[r] = -1;
+                if (k < k1) {
+                    while (A.p[e + 1] <= k) ++e;
+                    pv[r] = A.v[e];
+                    u[r] = a.csr_idx[A.b[e] + (k - A.p[e])];
+                }
+            }
+            bool claimed[kMultiB];
+#pragma unroll
+            for (int r = 0; r < kMultiB; ++r) {
+                claimed[r] = false;
+                if (u[r] >= 0) {
+                    const uint64_t bit = 1ull << (u[r] & 63);
+                    const uint64_t old = __hip_atomic_fetch_or(reinterpret_cast<unsigned long long*>(&a.visited[u[r] >> 6]),
+                                                               (unsigned long long)bit, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                    claimed[r] = !(old & bit);
+                }
+            }
+            // one LDS counter atomic per wavefront and round
+            int32_t rank[kMultiB], tot = 0;
+#pragma unroll
+            for (int r = 0; r < kMultiB; ++r) {
+                const uint64_t bal = __ballot(claimed[r]);
+                rank[r] = tot + __popcll(bal & lanes_below(lane));
+                tot += __popcll(bal);
+            }
+            int32_t base = 0;
+            if (lane == 0 && tot) base = atomicAdd(&s_cnt, tot);
+            base = __shfl(base, 0);
+#pragma unroll
+            for (int r = 0; r < kMultiB; ++r) {
+                if (!claimed[r]) continue;
+                const int32_t x = u[r];
+                const int32_t rb = a.csr_off[x], re = a.csr_off[x + 1];
+                const int32_t uid = user_id(a.perm, x), pid = user_id(a.perm, pv[r]);
+                a.level[uid] = lvl + 1;
+                a.parent[uid] = pid;
+                mloc += re - rb;
+                const int32_t slot = base + rank[r];
+                if (slot < qcap) {
+                    B.v[slot] = x;
+                    B.b[slot] = rb;
+                    B.p[slot] = re - rb;
+                } else {  // the next frontier outgrows the sets: it goes to the level kernels
+                    q_next[(size_t)a.static_pages * kPage + slot] = x;
+                    atomicOr(reinterpret_cast<unsigned long long*>(&fb_next[x >> 6]),
+                             (unsigned long long)(1ull << (x & 63)));
+                }
+            }
+        }
+        mloc = wave_sum(mloc);
+        if (lane == 0) s_m[w] = mloc;
+        __syncthreads();
+        int64_t mn = 0;
+        for (int i = 0; i < kBfsWaves; ++i) mn += s_m[i];
+        const int32_t nn = s_cnt;
+        mu_base -= m;
+        n_prev = nf;
+        nf = nn;
+        m = mn;
+        ++lvl;
+        cur ^= 1;
+        if (nf <= qcap && m <= ecap) multi_scan(B.p, nf, s_w);
+        else __syncthreads();  // everyone has read s_cnt and s_m
+    }
+    // hand frontier lvl back: queue pages, fills and bitmap bits, as a
+    // queue-driven top-down level leaves them
+    const MultiSet A = multi_set(s_sets, qcap, cur);
+    int32_t* q = a.queue[lvl & 1];
+    int32_t* fill = a.fill[lvl & 1];
+    const int32_t inl = min(nf, qcap);
+    for (int32_t i = threadIdx.x; i < inl; i += blockDim.x) {
+        const int32_t v = A.v[i];
+        q[(size_t)a.static_pages * kPage + i] = v;
+        atomicOr(reinterpret_cast<unsigned long long*>(&a.fb[lvl % 3][v >> 6]), (unsigned long long)(1ull << (v & 63)));
+    }
+    const int32_t np = (nf + kPage - 1) / kPage;
+    for (int32_t p = threadIdx.x; p < np; p += blockDim.x) fill[a.static_pages + p] = min(kPage, nf - p * kPage);
+    if (threadIdx.x == 0) {
+        BfsSlot fresh{};
+        fresh.pages = a.static_pages;
+        BfsSlot s = fresh;
+        s.n = nf;
+        s.dir_prev = PP_PUSH;
+        s.n_prev = n_prev;
+        s.pages = a.static_pages + np;
+        s.m = m;
+        s.mu_base = mu_base;
+        h->slot[lvl % 3] = s;
+        h->slot[(lvl + 1) % 3] = fresh;
+        h->slot[(lvl + 2) % 3] = fresh;
+        h->lv[0] = lvl;
+        h->lv[1] = lvl;
+        h->c_lvl = -1;
+        h->levels = lvl;
+        h->last = lvl;
+        h->reached += reached;
+        h->edges += edges;
+        if (nf == 0) h->finished = 1;
+    }
+}
+
 static pp_status check_state(pp_graph g, void* state, size_t bytes) {
     if (!g) return set_error(PP_E_NULL, "graph handle is NULL");
     if (!state) return set_error(PP_E_NULL, "state is NULL");
@@ -1039,6 +1312,18 @@ static size_t chunk_lds(const BfsArgs& a) { return (size_t)std::max(a.sum_words,
 
 // Workgroups of the chunk kernel: two per compute unit (its LDS is small).
 static int32_t chunk_blocks(pp_graph g) { return std::max(1, std::min(ceil_div(g->d.n, 4096), 2 * g->num_cu)); }
+
+// Frontier sets of the one-workgroup launch: vertices per set (qcap) and
+// out-edges per level (ecap) it takes on; 0 when it is off for this policy.
+static void multi_caps(pp_graph g, int32_t policy, int32_t* qcap, int32_t* ecap) {
+    constexpr int32_t kStatic = 8192;  // its static LDS (edge-range starts, reductions), rounded up
+    const int32_t fit = std::max(0, (g->max_lds - kStatic) / 24 - 1);
+    *qcap = (policy == PP_PULL) ? 0 : std::min(g->tune.bfs_multi_n, fit);
+    *ecap = (*qcap > 0) ? g->tune.bfs_multi_m : 0;
+    if (*ecap <= 0) *qcap = 0;
+}
+
+static size_t multi_lds(int32_t qcap) { return (size_t)(6 * qcap + 2) * 4; }
 
 // Does a level of this policy on this graph ever queue chunk items?
 static bool needs_chunks(pp_graph g, int32_t policy) {
@@ -1096,6 +1381,15 @@ static pp_status bfs_graph(pp_graph g, BfsArgs a, int32_t policy, float alpha, f
         return e;
     };
     hipError_t e = hipSuccess;
+    // small top-down frontiers first go through the one-workgroup launch,
+    // which returns at once when the frontier is not one it takes on
+    int32_t qcap = 0, ecap = 0;
+    multi_caps(g, policy, &qcap, &ecap);
+    if (qcap > 0) {
+        allow_dynamic_lds(reinterpret_cast<const void*>(&k_bfs_multi), multi_lds(qcap));
+        void* margs[] = {&a, &policy, &alpha, &beta, &qcap, &ecap};
+        e = add(reinterpret_cast<const void*>(&k_bfs_multi), margs, 1, (unsigned)multi_lds(qcap));
+    }
     int32_t lvl = -1;
     for (int32_t i = 0; i < batch && e == hipSuccess; ++i) {
         int32_t parity = i & 1;

@@ -865,6 +865,14 @@ PP_EXPORT pp_status pp_set_pull_slices(int32_t rows, int32_t width) {
     return PP_OK;
 }
 
+PP_EXPORT pp_status pp_set_bfs_multi(int32_t max_frontier, int32_t max_edges) {
+    clear_error();
+    if (max_frontier < 0 || max_edges < 0) return set_error(PP_E_RANGE, "BFS multi-level caps must be >= 0");
+    tuning().bfs_multi_n = max_frontier;
+    tuning().bfs_multi_m = max_edges;
+    return PP_OK;
+}
+
 PP_EXPORT pp_status pp_graph_slices(pp_graph g, int32_t* info) {
     clear_error();
     if (!g || !info) return set_error(PP_E_NULL, "graph or info is NULL");

@@ -48,6 +48,8 @@ struct Tuning {
     int32_t pull_block = 1024;   // threads per workgroup of the persistent pull sweep
     int32_t slice_rows = 0;      // rows of the tiled pull (0 = off); see SlicePlan
     int32_t slice_width = kSliceMax; // sources per slice of the tiled pull
+    int32_t bfs_multi_n = 256;   // frontier vertices a one-workgroup BFS launch takes on (0 = off)
+    int32_t bfs_multi_m = 1024;  // frontier out-edges per level it takes on
 };
 Tuning& tuning();
 

@@ -219,3 +219,75 @@ def test_level_log_covers_every_level(maker, root):
         assert list(dirs[:m]) == [st.dir[i] for i in range(m)]
         assert list(nf[:m]) == [st.frontier[i] for i in range(m)]
         assert np.array_equal(r.level.cpu().numpy(), want)
+
+
+# ----------------------------------------------------------------- deep graphs
+# Small top-down frontiers run whole levels inside one one-workgroup launch and
+# hand larger ones back to the grid-wide level kernels.  Levels, parents, the
+# statistics and the per-level log must not depend on it: each case is run with
+# the default caps, with the launch off (0, 0), with tiny caps (64 vertices,
+# 256 out-edges) that force hand-overs in both directions and frontiers that
+# outgrow the LDS sets part-way through a level, and with the largest sets.
+MULTI_CAPS = [(256, 1024), (0, 0), (64, 256), (6144, 32768)]
+
+
+def _directed(n, m, seed):
+    host = H.random_graph(n, m, seed, symmetric=False, connected=True)
+    host.ensure_transpose()
+    return host
+
+
+def _run_caps(host, root, policy, caps, relabel=True):
+    from paper_2010_16012_amd import _lib
+    _lib.pp_set_bfs_multi(*caps)
+    try:
+        g = pp.Graph(host, relabel=relabel)
+    finally:
+        _lib.pp_set_bfs_multi(*MULTI_CAPS[0])
+    r = pp.BfsRun(g)
+    st, dirs, nf, mf = r.run_logged(root, policy)
+    torch.cuda.synchronize()
+    out = (r.level.cpu().numpy(), r.parent.cpu().numpy(), st, dirs, nf, mf)
+    g.close()
+    return out
+
+
+@pytest.mark.parametrize("maker", [lambda: H.path(5000), lambda: H.full_grid(200, 200),
+                                   lambda: gg.grid(256, 256, 0.05, seed=3), lambda: gg.workload("rmat14"),
+                                   lambda: _directed(3000, 9000, 4)],
+                         ids=["path5000", "grid200", "grid256_holes", "rmat14", "directed3000"])
+def test_multi_level_launch_matches_level_kernels(maker):
+    host = maker()
+    for root in (0, host.n // 3):
+        want, _, nlev = oracle.bfs(host.off, host.idx, root)
+        deg = np.diff(host.off)
+        for pol, name in ((pp.PP_PUSH, "push"), (pp.PP_SWITCH, "switch")):
+            ref = None
+            for caps in MULTI_CAPS:
+                announce(f"BFS multi {host.name} root={root} {name} caps={caps}")
+                lv, par, st, dirs, nf, mf = _run_caps(host, root, pol, caps)
+                assert np.array_equal(lv, want), f"{name} caps {caps}: levels differ"
+                assert H.bfs_violations_fast(host, root, lv, par) == []
+                assert st.levels == nlev == len(dirs)
+                assert st.reached == int((want >= 0).sum())
+                assert st.edges_reached == int(deg[want >= 0].sum())
+                assert np.array_equal(nf, np.bincount(want[want >= 0], minlength=nlev))
+                log = (list(dirs), list(nf), list(mf))
+                if ref is None:
+                    ref = log
+                else:  # the switch rule sees the same statistics either way
+                    assert log == ref, f"{name} caps {caps}: level log differs"
+
+
+def test_multi_level_launch_budget_and_retake():
+    # 40,000 levels: more than one launch takes (32,768), so the level kernels
+    # run a few levels in between and the next batch's launch takes over again
+    host = H.path(40000)
+    want, _, nlev = oracle.bfs(host.off, host.idx, 0)
+    for relabel in (True, False):
+        announce(f"BFS multi path40000 relabel={relabel}")
+        lv, par, st, dirs, nf, mf = _run_caps(host, 0, pp.PP_PUSH, MULTI_CAPS[0], relabel=relabel)
+        assert np.array_equal(lv, want)
+        assert H.bfs_violations_fast(host, 0, lv, par) == []
+        assert st.levels == nlev == 40000
+        assert np.all(dirs == pp.PP_PUSH) and np.all(nf == 1)
