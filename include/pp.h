@@ -129,6 +129,22 @@ pp_status pp_set_bin_thresholds(const int32_t* upper5, int32_t split_chunk);
  * next pp_graph_create. */
 pp_status pp_set_push_tuning(int32_t hot, int32_t push_blocks);
 
+/* Binned push (on = 1, the default) or global atomics (on = 0) for the
+ * updates a push sweep sends to targets past the `hot` privatised ones.
+ * Binned: the sweep appends each such update as a (target, value) pair to its
+ * workgroup's slice of the target's bin (32768 consecutive ids) with a plain
+ * store, and a second kernel sums every bin in LDS; the slice sizes come from
+ * one counting walk of the sweep's static work assignment at registration.
+ * No global atomics remain (the remote updates of Sec. 5's
+ * Partition-Awareness, buffered instead of applied one by one).  Needs hot >
+ * 0; its workspace (8 bytes per edge plus tables) is part of
+ * pp_graph_workspace_bytes.  Takes effect at the next pp_graph_create. */
+pp_status pp_set_push_bins(int32_t on);
+
+/* The binned-push layout of g: info[0..4) = bins (0: global atomics),
+ * first binned target, workgroups of the sweep, units of the summing kernel. */
+pp_status pp_graph_push_bins(pp_graph g, int32_t* info);
+
 /* Pull-sweep tuning: each workgroup of the persistent pull sweep stages the
  * contributions of the first `pull_hot` vertices (internal ids; with
  * PP_GRAPH_RELABEL the heaviest ones, which most gathers hit) in LDS, capped

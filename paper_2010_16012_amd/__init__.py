@@ -77,6 +77,11 @@ class Graph:
         """(R, width, S, tiles) of the tiled pull (R = 0: plain pull only)."""
         return _lib.pp_graph_slices(self.handle)
 
+    def push_bins(self):
+        """(bins, first binned target, sweep workgroups, summing units); bins = 0
+        when the push sweep uses global atomics."""
+        return _lib.pp_graph_push_bins(self.handle)
+
     def bins(self, direction=PP_PULL):
         return _lib.pp_graph_bins(self.handle, direction)
 

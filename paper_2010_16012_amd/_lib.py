@@ -87,6 +87,8 @@ _SIGS = {
                              _P, _P], ctypes.c_int),
     "pp_set_pull_slices": ([_I32, _I32], ctypes.c_int),
     "pp_set_bfs_multi": ([_I32, _I32], ctypes.c_int),
+    "pp_set_push_bins": ([_I32], ctypes.c_int),
+    "pp_graph_push_bins": ([_P, _P], ctypes.c_int),
     "pp_graph_slices": ([_P, _P], ctypes.c_int),
     "pp_ppr_run": ([_P, ctypes.c_int, _I32, _P, _I32, _F32, _F32, _I32, _P, _P, _SZ, ctypes.POINTER(_I32), _P],
                    ctypes.c_int),
@@ -235,6 +237,18 @@ def pp_bfs_run(h, root, policy, alpha, beta, level, parent, state, stream=None) 
 
 def pp_set_pull_slices(rows: int, width: int) -> None:
     _check(_lib.pp_set_pull_slices(rows, width))
+
+
+def pp_set_push_bins(on: int) -> None:
+    _check(_lib.pp_set_push_bins(on))
+
+
+def pp_graph_push_bins(h):
+    """(bins, first binned target, sweep workgroups, summing units) of a
+    registered graph (bins = 0: the push uses global atomics)."""
+    info = (_I32 * 4)()
+    _check(_lib.pp_graph_push_bins(h, info))
+    return tuple(info)
 
 
 def pp_set_bfs_multi(max_frontier: int, max_edges: int) -> None:

@@ -345,7 +345,8 @@ __global__ void k_zero_i32(int32_t n, int32_t* p) {
 struct WsLayout {
     size_t inv_s, out_deg, pull_list, push_list, buf0, buf1, buf2, csc_w, csc_row, split_tab, split_part, hot_part, err,
         tiles, keys, perm, iperm, r_csr_off, r_csc_off, r_csr_idx, r_csc_idx, r_csr_w, sl_idx, sl_prow,
-        sl_units, sl_segs, sl_wg, sl_part, sl_cpart, sl_cbeg, total;
+        sl_units, sl_segs, sl_wg, sl_part, sl_cpart, sl_cbeg, pb_base, pb_cnt, pb_fill, pb_units, pb_ulo, pb_pairs,
+        pb_part, total;
     int32_t split_cap;
     int64_t sl_rows_cap, sl_slices_cap, sl_pairs_cap, sl_units_cap, sl_chunks_cap, sl_idx_cap;
 };
@@ -358,6 +359,9 @@ constexpr int32_t kTileMaxGroups = 4096;
 static bool sliced_layout(uint32_t flags, const Tuning& t) {
     return (flags & PP_GRAPH_RELABEL) && !(flags & PP_GRAPH_WEIGHTED) && t.slice_rows > 0 && t.slice_width > 0;
 }
+
+// The binned push needs privatised targets (its bins start past them).
+static bool push_binned(const Tuning& t, int32_t n) { return t.push_bins && t.hot > 0 && n > t.hot; }
 
 static int32_t split_capacity(int64_t nnz, const Tuning& t) {
     int64_t cap = (nnz + t.split_chunk - 1) / t.split_chunk + nnz / ((int64_t)t.upper[PP_NUM_BINS - 2] + 1) + 1;
@@ -391,6 +395,17 @@ static WsLayout layout(int32_t n, int64_t nnz, uint32_t flags, const Tuning& t, 
     L.split_tab = take((size_t)2 * (4 * (size_t)L.split_cap + 1) * 4);
     L.split_part = take((size_t)L.split_cap * 4);
     L.hot_part = take((size_t)t.push_blocks * (size_t)std::max(t.hot, 1) * 4);
+    if (push_binned(t, n)) {
+        const size_t slices = (size_t)t.push_blocks * push_bins_cap(n);
+        const size_t units = push_units_cap(n, nnz);
+        L.pb_base = take(slices * 4);
+        L.pb_cnt = take(slices * 4);
+        L.pb_fill = take(slices * 4);
+        L.pb_units = take(units * 3 * 4);
+        L.pb_ulo = take(((size_t)push_bins_cap(n) + 1) * 4);
+        L.pb_pairs = take(nz * 8);
+        L.pb_part = take(units * kPushBinW * 4);
+    }
     L.err = take(64 * 4);
     const size_t tiles = std::max<size_t>((size_t)ceil_div(n, kTile) * kMaxKeys, (size_t)ceil_div(n, kScanTile) + 1);
     L.tiles = take(tiles * 4);
@@ -865,6 +880,23 @@ PP_EXPORT pp_status pp_set_pull_slices(int32_t rows, int32_t width) {
     return PP_OK;
 }
 
+PP_EXPORT pp_status pp_set_push_bins(int32_t on) {
+    clear_error();
+    if (on != 0 && on != 1) return set_error(PP_E_RANGE, "push bins: 0 or 1");
+    tuning().push_bins = on;
+    return PP_OK;
+}
+
+PP_EXPORT pp_status pp_graph_push_bins(pp_graph g, int32_t* info) {
+    clear_error();
+    if (!g || !info) return set_error(PP_E_NULL, "graph or info is NULL");
+    info[0] = g->pbins.nbins;
+    info[1] = g->pbins.hot;
+    info[2] = g->pbins.groups;
+    info[3] = g->pbins.units;
+    return PP_OK;
+}
+
 PP_EXPORT pp_status pp_set_bfs_multi(int32_t max_frontier, int32_t max_edges) {
     clear_error();
     if (max_frontier < 0 || max_edges < 0) return set_error(PP_E_RANGE, "BFS multi-level caps must be >= 0");
@@ -938,6 +970,19 @@ PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_o
     d.split_tab = static_cast<int32_t*>(at(L.split_tab));
     d.split_part = static_cast<float*>(at(L.split_part));
     d.hot_part = static_cast<float*>(at(L.hot_part));
+    if (push_binned(t, n)) {
+        d.pb_base = static_cast<int32_t*>(at(L.pb_base));
+        d.pb_cnt = static_cast<int32_t*>(at(L.pb_cnt));
+        d.pb_fill = static_cast<int32_t*>(at(L.pb_fill));
+        d.pb_units = static_cast<int32_t*>(at(L.pb_units));
+        d.pb_ulo = static_cast<int32_t*>(at(L.pb_ulo));
+        d.pb_pairs = static_cast<int2*>(at(L.pb_pairs));
+        d.pb_part = static_cast<float*>(at(L.pb_part));
+    } else {
+        d.pb_base = d.pb_cnt = d.pb_fill = d.pb_units = d.pb_ulo = nullptr;
+        d.pb_pairs = nullptr;
+        d.pb_part = nullptr;
+    }
     d.err = static_cast<int32_t*>(at(L.err));
     d.sl_idx = nullptr;
     d.sl_prow = nullptr;
@@ -1044,6 +1089,10 @@ PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_o
     if (s != PP_OK) return fail(s);
     s = build_slices(g, L, base, st);
     if (s != PP_OK) return fail(s);
+    if (d.pb_base) {
+        s = build_push_bins(g, st);
+        if (s != PP_OK) return fail(s);
+    }
     *out = g;
     return PP_OK;
 }

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -48,6 +50,7 @@ struct Tuning {
     int32_t pull_block = 1024;   // threads per workgroup of the persistent pull sweep
     int32_t slice_rows = 0;      // rows of the tiled pull (0 = off); see SlicePlan
     int32_t slice_width = kSliceMax; // sources per slice of the tiled pull
+    int32_t push_bins = 1;       // binned push for targets past the privatised ones (0 = global atomics)
     int32_t bfs_multi_n = 256;   // frontier vertices a one-workgroup BFS launch takes on (0 = off)
     int32_t bfs_multi_m = 1024;  // frontier out-edges per level it takes on
 };
@@ -108,6 +111,32 @@ struct SlicePlan {
     int32_t nsplit = 0;
 };
 
+// Binned push (pr.hip).  Updates to targets past the privatised ones (ids >=
+// hot, "cold") are not global atomics: the push sweep appends them as
+// (target offset, value) pairs to its workgroup's slice of the target's bin
+// (kPushBinW consecutive ids), and a second kernel sums each bin in LDS.  The
+// slices are sized at registration by walking the sweep's static work
+// assignment once, so a sweep needs no global atomic at all.
+constexpr int32_t kPushBinShift = 15;
+constexpr int32_t kPushBinW = 1 << kPushBinShift;
+constexpr int32_t kPushBinUnits = 512;  // target number of second-kernel units
+constexpr int32_t kPushBinMinUnit = 4096;  // pairs a unit takes at least
+
+struct PushBins {
+    int32_t nbins = 0;   // 0: the push sweep uses global atomics
+    int32_t hot = 0;     // first binned target id
+    int32_t sub = 0;     // push launch shape the slices were sized for
+    int32_t groups = 0;
+    int32_t units = 0;   // units of the bin-summing kernel
+};
+
+// Most bins the binned push keeps in LDS state for (pp_graph_workspace_bytes
+// sizes its tables with it).
+inline int32_t push_bins_cap(int32_t n) { return (int32_t)(((int64_t)n + kPushBinW - 1) / kPushBinW) + 1; }
+inline int32_t push_units_cap(int32_t n, int64_t nnz) {
+    return (int32_t)std::min<int64_t>(kPushBinUnits, nnz / kPushBinMinUnit + 1) + push_bins_cap(n);
+}
+
 // Work decomposition of one binned sweep launch: every bin owns a contiguous
 // range of work units; heavy bins come first so the longest rows start first.
 struct BinPlan {
@@ -149,6 +178,16 @@ struct GraphDev {
     int32_t* split_tab;       // bin-5 chunk tables (pull, then push)
     float* split_part;        // bin-5 partial sums (pull)
     float* hot_part;          // push privatisation partials [push_blocks][hot]
+    // binned push: per (workgroup, bin) slice start and size (pairs), pairs
+    // written by the last sweep, second-kernel units (bin, first and end
+    // workgroup), first unit of each bin [nbins+1], the pairs, unit partials
+    int32_t* pb_base;
+    int32_t* pb_cnt;
+    int32_t* pb_fill;
+    int32_t* pb_units;
+    int32_t* pb_ulo;
+    int2* pb_pairs;
+    float* pb_part;
     float* buf0;              // PageRank scratch vectors, n floats each
     float* buf1;
     float* buf2;
@@ -180,6 +219,7 @@ struct pp_graph_s {
     pp::BinPlan pull_plan;
     pp::BinPlan push_plan;
     pp::SlicePlan slices;
+    pp::PushBins pbins;
     int32_t split_pull_entries;  // rows of the pull split table
     int32_t split_push_entries;
     int32_t split_cap;           // capacity of each split table
@@ -233,6 +273,8 @@ Teleport uniform_teleport(int32_t n, float f);
 pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float f, hipStream_t st,
                       int32_t skip_below = 0, const Teleport* tp = nullptr);
 pp_status launch_push(pp_graph g, const float* c, float* y, hipStream_t st);
+// Sizes the binned push's slices (registration; sets g->pbins).
+pp_status build_push_bins(pp_graph g, hipStream_t st);
 // One personalised PageRank column with the single-vector sweeps (pr.hip):
 // x_0 = e_s (s internal), iters steps, x written to x_out[caller id * x_stride].
 pp_status run_single_ppr(pp_graph g, pp_dir dir, int32_t s, int32_t iters, float f, float* x_out, int64_t x_stride,

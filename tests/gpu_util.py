@@ -16,6 +16,7 @@ def default_bins():
     _lib.pp_set_pull_tuning(32768, 1024)
     _lib.pp_set_pull_slices(0, 32768)
     _lib.pp_set_bfs_multi(256, 1024)
+    _lib.pp_set_push_bins(1)
 
 
 def tiny_bins():

@@ -383,3 +383,47 @@ def test_tiled_pull_off_for_weighted_and_unrelabelled_graphs():
     assert pp.Graph(gw).slices()[0] == 0
     # a grid has no heavy rows: nothing qualifies
     assert pp.Graph(H.full_grid(60, 60)).slices()[0] == 0
+
+
+@pytest.mark.parametrize("hot,blocks", [(8192, 1024), (1, 7), (40960, 256), (100, 333)])
+def test_binned_push_matches_oracle_and_atomic_push(hot, blocks):
+    # Updates to targets past the privatised ones go to per-workgroup slices of
+    # 32768-id bins (summed in LDS by a second kernel) instead of global
+    # atomics.  R-MAT 17 spans several bins (uniform PageRank); a weighted
+    # directed graph runs single-source PPR, whose first sweeps skip the rows
+    # with zero contribution (slices left part-filled).  Both layouts agree
+    # with the oracle and with each other.
+    rmat = gg.rmat(17, 16, seed=1)
+    wdir = H.random_graph(70000, 400000, 3, symmetric=False, connected=True)
+    gg.with_weights(wdir, seed=2)
+    src = gg.pick_vertices(wdir, 3, seed=5)
+    want_r = oracle.pagerank(rmat.off, rmat.idx, F, 20)
+    want_w, _ = oracle.ppr(wdir.off, wdir.idx, src, F, T=20, weights=wdir.weights)
+    _lib.pp_set_push_tuning(hot, blocks)
+    try:
+        for rl in (True, False):
+            got = {}
+            for on in (1, 0):
+                _lib.pp_set_push_bins(on)
+                g = pp.Graph(rmat, relabel=rl)
+                gw = pp.Graph(wdir, relabel=rl)
+                for gr, host in ((g, rmat), (gw, wdir)):
+                    info = gr.push_bins()
+                    if on:
+                        assert info[0] == -(-(host.n - info[1]) // 32768) >= (2 if host is rmat else 1), info
+                    else:
+                        assert info[0] == 0, info
+                announce(f"binned push={on} hot={hot} blocks={blocks} relabel={rl}")
+                x = pr_gpu(g, pp.PP_PUSH, 20).astype(np.float64)
+                X, _ = pp.ppr(gw, src, iters=20, f=F, k_tile=1, direction=pp.PP_PUSH)
+                X = X.cpu().numpy().astype(np.float64)
+                g.close()
+                gw.close()
+                assert np.abs(x - want_r).sum() <= PR_L1_TOL, (hot, blocks, rl, on)
+                assert np.abs(X - want_w).sum(axis=0).max() <= PR_L1_TOL, (hot, blocks, rl, on)
+                got[on] = (x, X)
+            assert np.abs(got[1][0] - got[0][0]).sum() <= PR_L1_TOL
+            assert np.abs(got[1][1] - got[0][1]).sum(axis=0).max() <= PR_L1_TOL
+    finally:
+        _lib.pp_set_push_tuning(8192, 1024)
+        _lib.pp_set_push_bins(1)
