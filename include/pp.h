@@ -102,6 +102,16 @@ pp_status pp_graph_create(int32_t n, int64_t nnz,
  * output, perm[i] = caller id of internal vertex i. */
 pp_status pp_graph_relabel_map(pp_graph g, int32_t* perm, void* stream);
 
+/* New edge weights for a graph registered with PP_GRAPH_WEIGHTED, in place:
+ * csr_w (DEVICE float[nnz], caller CSR slot order, > 0, same structure) is
+ * re-derived into the relabelled and CSC slot orders and the out-strengths
+ * s(v) of the Sec. 3.1 transition P_uv = w(v->u)/s(v), as at registration,
+ * without re-registering the graph.  Without PP_GRAPH_RELABEL the handle
+ * keeps using csr_w itself, so it must stay valid and unchanged while the
+ * graph is used; the csc_to_csr map given at registration must still be
+ * valid.  PP_E_UNSUPPORTED for unweighted graphs.  ASYNC on `stream`. */
+pp_status pp_graph_set_weights(pp_graph g, const float* csr_w, void* stream);
+
 /* Frees the host handle (device memory stays with the caller). */
 pp_status pp_graph_destroy(pp_graph g);
 
@@ -132,7 +142,7 @@ pp_status pp_set_push_tuning(int32_t hot, int32_t push_blocks);
 /* Binned push (on = 1, the default) or global atomics (on = 0) for the
  * updates a push sweep sends to targets past the `hot` privatised ones.
  * Binned: the sweep appends each such update as a (target, value) pair to its
- * workgroup's slice of the target's bin (32768 consecutive ids) with a plain
+ * workgroup's slice of the target's bin (16384 consecutive ids) with a plain
  * store, and a second kernel sums every bin in LDS; the slice sizes come from
  * one counting walk of the sweep's static work assignment at registration.
  * No global atomics remain (the remote updates of Sec. 5's

@@ -85,6 +85,19 @@ class Graph:
     def bins(self, direction=PP_PULL):
         return _lib.pp_graph_bins(self.handle, direction)
 
+    def set_weights(self, w, stream=None):
+        """Replace the edge weights (float[nnz], CSR slot order, same structure)
+        of a weighted graph in place.  The values are copied into a buffer the
+        graph owns, so later changes to ``w`` do not reach it."""
+        if not self.weighted:
+            raise ValueError("graph was registered without weights")
+        w = torch.as_tensor(w, device=self.device).reshape(-1)
+        if w.numel() != self.nnz:
+            raise ValueError(f"expected {self.nnz} weights, got {w.numel()}")
+        if self.nnz:
+            self.csr_w.copy_(w.detach().to(torch.float32))
+        _lib.pp_graph_set_weights(self.handle, self.csr_w, stream)
+
     def close(self):
         if getattr(self, "handle", None) is not None:
             _lib.pp_graph_destroy(self.handle)
@@ -197,33 +210,62 @@ def ppr_adjoint_unrolled(g: Graph, sources, dLdXT, T=30, f=0.85, k_tile=32, stre
 
 class PPRFunction(torch.autograd.Function):
     """X = PPR(w): personalised PageRank at convergence as a function of the
-    per-slot edge weights w (CSR slot order of `structure`, a HostGraph-like
-    object).  backward() runs the library's adjoint: the transposed sweep
-    solves (I - f P^T) Lambda = dL/dX and a per-slot kernel forms dL/dw.
+    per-slot edge weights w (CSR slot order of `structure`).  backward() runs
+    the library's adjoint: the transposed sweep solves (I - f P^T) Lambda =
+    dL/dX and a per-slot kernel forms dL/dw.
+
+    ``structure`` is a HostGraph-like object or a weighted ``Graph``.  A
+    HostGraph is registered on the device once per (device, relabel) and kept
+    on the object; every later call only replaces the weights in place
+    (``Graph.set_weights``), so a training loop pays one pass over the edges
+    per step, not a host round trip and a registration.  backward() puts the
+    forward's weights back first if another forward changed them meanwhile.
 
     ``forward_dir`` / ``adjoint_dir`` pick push or pull for each solve (the
     adjoint of a forward push is a pull over the same CSR rows, and vice
     versa)."""
 
     @staticmethod
+    def _graph(structure, w, relabel):
+        if isinstance(structure, Graph):
+            return structure
+        cache = structure.__dict__.setdefault("_pp_graphs", {})
+        key = (str(w.device), bool(relabel))
+        g = cache.get(key)
+        if g is None or g.handle is None:
+            import copy
+            host = copy.copy(structure)
+            host.__dict__.pop("_pp_graphs", None)
+            host.weights = w.detach().float().cpu().numpy()
+            host.ensure_transpose()
+            g = Graph(host, device=w.device, weighted=True, relabel=relabel)
+            cache[key] = g
+            g._pp_w_version = None
+        return g
+
+    @staticmethod
     def forward(ctx, w, structure, sources, f=0.85, iters=3000, tol=1e-9, k_tile=32,
                 forward_dir=PP_PULL, adjoint_dir=PP_PULL, relabel=True):
-        import copy
-        host = copy.copy(structure)
-        host.weights = w.detach().float().cpu().numpy()
-        host.ensure_transpose()
-        g = Graph(host, device=w.device, weighted=True, relabel=relabel)
+        g = PPRFunction._graph(structure, w, relabel)
+        wd = w.detach()
+        g.set_weights(wd)
+        g._pp_w_version = (wd.data_ptr(), wd._version)
         X, _ = ppr(g, sources, iters=iters, f=f, k_tile=k_tile, direction=forward_dir, tol=tol)
         ctx.g = g
         ctx.cfg = (f, iters, tol, k_tile, adjoint_dir)
-        ctx.save_for_backward(X)
+        ctx.w_version = g._pp_w_version
+        ctx.save_for_backward(X, wd)
         return X
 
     @staticmethod
     def backward(ctx, dX):
-        (X,) = ctx.saved_tensors
+        X, wd = ctx.saved_tensors
         f, iters, tol, k_tile, adir = ctx.cfg
-        _, grad, _ = ppr_adjoint(ctx.g, X, dX.float(), iters=iters, f=f, k_tile=k_tile, direction=adir, tol=tol)
+        g = ctx.g
+        if getattr(g, "_pp_w_version", None) != ctx.w_version:
+            g.set_weights(wd)
+            g._pp_w_version = ctx.w_version
+        _, grad, _ = ppr_adjoint(g, X, dX.float(), iters=iters, f=f, k_tile=k_tile, direction=adir, tol=tol)
         return grad, None, None, None, None, None, None, None, None, None
 
 

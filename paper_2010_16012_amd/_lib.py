@@ -88,6 +88,7 @@ _SIGS = {
     "pp_set_pull_slices": ([_I32, _I32], ctypes.c_int),
     "pp_set_bfs_multi": ([_I32, _I32], ctypes.c_int),
     "pp_set_push_bins": ([_I32], ctypes.c_int),
+    "pp_graph_set_weights": ([_P, _P, _P], ctypes.c_int),
     "pp_graph_push_bins": ([_P, _P], ctypes.c_int),
     "pp_graph_slices": ([_P, _P], ctypes.c_int),
     "pp_ppr_run": ([_P, ctypes.c_int, _I32, _P, _I32, _F32, _F32, _I32, _P, _P, _SZ, ctypes.POINTER(_I32), _P],
@@ -237,6 +238,10 @@ def pp_bfs_run(h, root, policy, alpha, beta, level, parent, state, stream=None) 
 
 def pp_set_pull_slices(rows: int, width: int) -> None:
     _check(_lib.pp_set_pull_slices(rows, width))
+
+
+def pp_graph_set_weights(h, csr_w, stream=None) -> None:
+    _check(_lib.pp_graph_set_weights(h, _ptr(csr_w), _stream(stream)))
 
 
 def pp_set_push_bins(on: int) -> None:

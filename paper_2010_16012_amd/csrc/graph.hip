@@ -957,6 +957,8 @@ PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_o
     d.csc_off = csc_off;
     d.csc_idx = csc_idx;
     d.csr_w = weighted ? csr_w : nullptr;
+    d.user_csc_to_csr = weighted ? csc_to_csr : nullptr;
+    d.aliased = aliased;
     d.perm = d.iperm = nullptr;
     d.inv_s = static_cast<float*>(at(L.inv_s));
     d.out_deg = static_cast<int32_t*>(at(L.out_deg));
@@ -1094,6 +1096,36 @@ PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_o
         if (s != PP_OK) return fail(s);
     }
     *out = g;
+    return PP_OK;
+}
+
+PP_EXPORT pp_status pp_graph_set_weights(pp_graph g, const float* csr_w, void* stream) {
+    clear_error();
+    if (!g) return set_error(PP_E_NULL, "graph handle is NULL");
+    if (!g->weighted) return set_error(PP_E_UNSUPPORTED, "graph was registered without PP_GRAPH_WEIGHTED");
+    GraphDev& d = g->d;
+    const int32_t n = d.n;
+    const int64_t nnz = d.nnz;
+    if (nnz > 0 && !csr_w) return set_error(PP_E_NULL, "csr_w is required");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (nnz > 0) {
+        if (g->relabelled) {
+            // the relabelled CSR rows keep their stored order, so the new
+            // weights follow their slots exactly as at registration
+            const int32_t row_blocks = std::max(std::min<int32_t>(ceil_div(n, 4), 16384), 1);
+            float* r_w = const_cast<float*>(d.csr_w);
+            hipLaunchKernelGGL(k_relabel_rows, dim3(row_blocks), dim3(256), 0, st, n, d.perm, d.iperm, d.user_csr_off,
+                               d.user_csr_idx, d.csr_off, (int32_t*)nullptr, csr_w, (const int32_t*)nullptr, r_w);
+            hipLaunchKernelGGL(k_relabel_rows, dim3(row_blocks), dim3(256), 0, st, n, d.perm, d.iperm, d.user_csc_off,
+                               d.user_csc_idx, d.csc_off, (int32_t*)nullptr, csr_w, d.user_csc_to_csr, d.csc_w);
+        } else {
+            d.csr_w = csr_w;
+            hipLaunchKernelGGL(k_gather_weights, dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz, csr_w,
+                               d.user_csc_to_csr, d.csc_w);
+        }
+    }
+    hipLaunchKernelGGL(k_degrees, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, d.csr_off, d.csr_w, d.out_deg, d.inv_s);
+    PP_LAUNCH_CHECK("pp_graph_set_weights");
     return PP_OK;
 }
 

@@ -117,7 +117,7 @@ struct SlicePlan {
 // (kPushBinW consecutive ids), and a second kernel sums each bin in LDS.  The
 // slices are sized at registration by walking the sweep's static work
 // assignment once, so a sweep needs no global atomic at all.
-constexpr int32_t kPushBinShift = 15;
+constexpr int32_t kPushBinShift = 14;
 constexpr int32_t kPushBinW = 1 << kPushBinShift;
 constexpr int32_t kPushBinUnits = 512;  // target number of second-kernel units
 constexpr int32_t kPushBinMinUnit = 4096;  // pairs a unit takes at least
@@ -170,6 +170,8 @@ struct GraphDev {
     const int32_t* user_csr_idx;
     const int32_t* user_csc_off;
     const int32_t* user_csc_idx;
+    const int32_t* user_csc_to_csr;  // weighted: CSR slot of each caller CSC slot
+    bool aliased;             // CSC given as the CSR arrays (symmetric graph)
     int32_t* csc_row;         // the row (in-row owner) of every CSC slot
     float* inv_s;             // 1/d(v) or 1/s(v); 0 when nothing leaves v
     int32_t* out_deg;         // d(v)

@@ -366,3 +366,57 @@ def test_unrolled_adjoint_finite_differences_rmat10():
     fd = np.array([(loss(w64 + h * np.eye(1, host.nnz, e)[0]) - loss(w64 - h * np.eye(1, host.nnz, e)[0])) / (2 * h)
                    for e in edges])
     assert np.linalg.norm(gh[edges] - fd) / np.linalg.norm(fd) <= 1e-5
+
+
+@pytest.mark.parametrize("relabel", [True, False])
+def test_set_weights_in_place_matches_a_fresh_registration(relabel):
+    # New weights on a registered graph give bit-identical pull results (and
+    # push results within the bar) to registering the graph with them.
+    host = H.random_graph(3000, 20000, 8, symmetric=False, connected=True)
+    gg.with_weights(host, seed=1)
+    w2 = gg.uniform(host.nnz, 0.1, 1.0, 99, stream=3).astype(np.float32)
+    src = gg.pick_vertices(host, 16, seed=2)
+    g = pp.Graph(host, relabel=relabel)
+    g.set_weights(torch.as_tensor(w2, device="cuda"))
+    import copy
+    fresh_host = copy.copy(host)
+    fresh_host.weights = w2
+    fresh = pp.Graph(fresh_host, relabel=relabel)
+    want, _ = oracle.ppr(host.off, host.idx, src, F, T=25, weights=w2)
+    for d in (pp.PP_PULL, pp.PP_PUSH):
+        a, _ = pp.ppr(g, src, iters=25, f=F, k_tile=16, direction=d)
+        b, _ = pp.ppr(fresh, src, iters=25, f=F, k_tile=16, direction=d)
+        if d == pp.PP_PULL:
+            assert torch.equal(a, b)
+        _cols_close(a.cpu().numpy(), want)
+        _cols_close(b.cpu().numpy(), want)
+    with pytest.raises(ValueError):
+        g.set_weights(torch.ones(host.nnz + 1, device="cuda"))
+    unweighted = pp.Graph(H.path(10))
+    with pytest.raises(ValueError):
+        unweighted.set_weights(torch.ones(18, device="cuda"))
+
+
+def test_autograd_function_registers_once_and_keeps_each_forwards_weights():
+    # Two forwards with different weights before either backward: the graph is
+    # registered once, and each backward uses its own forward's weights.
+    host = H.random_graph(200, 900, 21, symmetric=True, connected=True)
+    gg.with_weights(host, seed=4)
+    src = np.arange(8, dtype=np.int32) * 11
+    c = torch.as_tensor(gg.normal(host.n * 8, seed=1).reshape(host.n, 8), device="cuda")
+    w1 = torch.tensor(host.weights, device="cuda", requires_grad=True)
+    w2 = torch.tensor(host.weights * 1.5 + 0.05, device="cuda", requires_grad=True)
+    X1 = pp.PPRFunction.apply(w1, host, src)
+    X2 = pp.PPRFunction.apply(w2, host, src)
+    assert len(host._pp_graphs) == 1
+    (X1 * c).sum().backward()
+    (X2 * c).sum().backward()
+    assert len(host._pp_graphs) == 1
+    for w, Xg in ((w1, X1), (w2, X2)):
+        wn = w.detach().cpu().numpy().astype(np.float32)
+        Xo, _ = oracle.ppr(host.off, host.idx, src, F, T=20000, tol=1e-15, weights=wn)
+        assert np.abs(Xg.detach().cpu().numpy() - Xo).sum(axis=0).max() <= 1e-6
+        _, grad_o, _ = oracle.ppr_adjoint(host.off, host.idx, Xo, c.cpu().numpy().astype(np.float64), F, T=20000,
+                                          tol=1e-15, weights=wn)
+        gh = w.grad.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(gh - grad_o) / np.linalg.norm(grad_o) <= 1e-5

@@ -388,7 +388,7 @@ def test_tiled_pull_off_for_weighted_and_unrelabelled_graphs():
 @pytest.mark.parametrize("hot,blocks", [(8192, 1024), (1, 7), (40960, 256), (100, 333)])
 def test_binned_push_matches_oracle_and_atomic_push(hot, blocks):
     # Updates to targets past the privatised ones go to per-workgroup slices of
-    # 32768-id bins (summed in LDS by a second kernel) instead of global
+    # 16384-id bins (summed in LDS by a second kernel) instead of global
     # atomics.  R-MAT 17 spans several bins (uniform PageRank); a weighted
     # directed graph runs single-source PPR, whose first sweeps skip the rows
     # with zero contribution (slices left part-filled).  Both layouts agree
@@ -410,7 +410,7 @@ def test_binned_push_matches_oracle_and_atomic_push(hot, blocks):
                 for gr, host in ((g, rmat), (gw, wdir)):
                     info = gr.push_bins()
                     if on:
-                        assert info[0] == -(-(host.n - info[1]) // 32768) >= (2 if host is rmat else 1), info
+                        assert info[0] == -(-(host.n - info[1]) // 16384) >= (2 if host is rmat else 1), info
                     else:
                         assert info[0] == 0, info
                 announce(f"binned push={on} hot={hot} blocks={blocks} relabel={rl}")
