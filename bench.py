@@ -248,7 +248,7 @@ def cpu_leg(args, host, roots, root_edges, runs, policy, alpha, beta, parts):
 def batched_speedups(args, torch, gg, pp, autotune):
     """Measured (not extrapolated) speedups of the batched forms."""
     return {"ppr_rmat20_k256": ppr_speedup(args, torch, gg, pp, autotune),
-            "multi512": multi_speedup(torch, gg, pp, autotune)}
+            "multi512": multi_speedup(args, torch, gg, pp, autotune)}
 
 
 def ppr_speedup(args, torch, gg, pp, autotune):
@@ -277,11 +277,14 @@ def ppr_speedup(args, torch, gg, pp, autotune):
     return ppr
 
 
-def multi_speedup(torch, gg, pp, autotune):
+def multi_speedup(args, torch, gg, pp, autotune):
     """512 R-MAT graphs (scales 8-14) in one launch (PageRank x20 pull, BFS
-    switch from vertex 0) against the same work graph by graph."""
-    autotune.apply({})
+    switch from vertex 0) against the same work graph by graph.  The launch
+    mapping comes from the autotuner's entry for this batch's size class."""
     gs = gg.rmat_batch(512, 8, 14, seed=1)
+    tuned = autotune.load_key(args.tuned, autotune.multi_key(len(gs), sum(h.n for h in gs),
+                                                                 sum(int(h.nnz) for h in gs)))
+    autotune.apply(tuned)
     mg = pp.MultiGraph(gs)
     mg.run(pr_iters=20, pr_dir=pp.PP_PULL, bfs_policy=pp.PP_SWITCH)
     ms_one = _median([_events_ms(lambda: mg.run(pr_iters=20, pr_dir=pp.PP_PULL, bfs_policy=pp.PP_SWITCH))
@@ -507,7 +510,7 @@ def supplementary(args):
     if w == "ppr20":
         line.update(ppr_speedup(args, torch, gg, pp, autotune))
     elif w == "multi512":
-        line.update(multi_speedup(torch, gg, pp, autotune))
+        line.update(multi_speedup(args, torch, gg, pp, autotune))
     elif w in ("grid4096", "er22"):
         host = gg.workload(w)
         g = pp.Graph(host)

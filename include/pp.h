@@ -371,6 +371,14 @@ pp_status pp_multi_run(int32_t num_graphs, const int32_t* graph_n, const int64_t
                        int32_t bfs_policy, int32_t bfs_root, float alpha, float beta,
                        int32_t* level, int32_t* parent, void* ws, size_t ws_bytes, void* stream);
 
+/* Work mapping of pp_multi_run / pp_multi_run_static, chosen by the
+ * autotuner: PageRank rows of at least `big` edges take a whole wavefront,
+ * rows of mid..big-1 edges a group of mid_lanes lanes (8, 16 or 32), the
+ * other pull rows pull_group lanes (1, 2 or 4).  Results do not depend on
+ * it beyond FP64 summation order.  Defaults 512, 64, 2, 16.  Takes effect at
+ * the next call. */
+pp_status pp_set_multi_tuning(int32_t big, int32_t mid, int32_t pull_group, int32_t mid_lanes);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * computation as pp_multi_run, with its scratch (graph table, validation word,

@@ -88,6 +88,7 @@ _SIGS = {
     "pp_set_pull_slices": ([_I32, _I32], ctypes.c_int),
     "pp_set_bfs_multi": ([_I32, _I32], ctypes.c_int),
     "pp_set_push_bins": ([_I32], ctypes.c_int),
+    "pp_set_multi_tuning": ([_I32, _I32, _I32, _I32], ctypes.c_int),
     "pp_graph_set_weights": ([_P, _P, _P], ctypes.c_int),
     "pp_graph_push_bins": ([_P, _P], ctypes.c_int),
     "pp_graph_slices": ([_P, _P], ctypes.c_int),
@@ -242,6 +243,10 @@ def pp_set_pull_slices(rows: int, width: int) -> None:
 
 def pp_graph_set_weights(h, csr_w, stream=None) -> None:
     _check(_lib.pp_graph_set_weights(h, _ptr(csr_w), _stream(stream)))
+
+
+def pp_set_multi_tuning(big: int, mid: int, pull_group: int, mid_lanes: int) -> None:
+    _check(_lib.pp_set_multi_tuning(big, mid, pull_group, mid_lanes))
 
 
 def pp_set_push_bins(on: int) -> None:

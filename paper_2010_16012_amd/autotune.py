@@ -8,7 +8,10 @@ Searches, per (GPU architecture, graph size class):
   * push sweep: LDS-privatised targets and persistent workgroups;
   * BFS direction switch: the alpha/beta constants of the switch rule (on
     roots of their own seed);
-  * personalised PageRank: the column tile width for a given k.
+  * personalised PageRank: the column tile width for a given k;
+  * the many-graph launch: which PageRank rows take a wavefront, a middle
+    group or a small group, and the group widths (on a batch of its own
+    seed, stored under a key of its own: graph count and size class).
 Every candidate is timed with HIP events on the device; the fastest wins.
 The cache maps "arch|size class" to the chosen values; ``apply`` installs a
 cached entry through the library's tuning entry points.
@@ -31,7 +34,10 @@ TUNE_ROOT_SEED = 11  # BFS roots the switch constants are tuned on
 
 DEFAULTS = {"upper": [4, 16, 64, 1024, 4096], "split_chunk": 4096, "hot": 8192, "push_blocks": 1024,
             "pull_hot": 32768, "pull_block": 1024, "slice_rows": 0, "slice_width": 32768, "alpha": 14.0,
-            "beta": 24.0, "k_tile": 32}
+            "beta": 24.0, "k_tile": 32, "multi_big": 512, "multi_mid": 64, "multi_pull_group": 2,
+            "multi_mid_lanes": 16}
+
+TUNE_BATCH_SEED = 11  # many-graph batch the launch mapping is tuned on
 
 
 def arch() -> str:
@@ -46,6 +52,10 @@ def key(n: int, nnz: int, gpu_arch: str | None = None) -> str:
     return f"{gpu_arch or arch()}|{size_class(n, nnz)}"
 
 
+def multi_key(count: int, total_n: int, total_nnz: int, gpu_arch: str | None = None) -> str:
+    return f"{gpu_arch or arch()}|multi{count}_{size_class(total_n, total_nnz)}"
+
+
 def apply(cfg: dict) -> None:
     c = dict(DEFAULTS)
     c.update(cfg or {})
@@ -53,14 +63,19 @@ def apply(cfg: dict) -> None:
     _lib.pp_set_push_tuning(c["hot"], c["push_blocks"])
     _lib.pp_set_pull_tuning(c["pull_hot"], c["pull_block"])
     _lib.pp_set_pull_slices(c["slice_rows"], c["slice_width"])
+    _lib.pp_set_multi_tuning(c["multi_big"], c["multi_mid"], c["multi_pull_group"], c["multi_mid_lanes"])
 
 
 def load(path: str, n: int, nnz: int, gpu_arch: str | None = None) -> dict:
     """Cached entry for this GPU (or ``gpu_arch``) and size class (empty when absent)."""
+    return load_key(path, key(n, nnz, gpu_arch))
+
+
+def load_key(path: str, k: str) -> dict:
     if not path or not os.path.exists(path):
         return {}
     with open(path) as fh:
-        return json.load(fh).get(key(n, nnz, gpu_arch), {})
+        return json.load(fh).get(k, {})
 
 
 def _time(fn, reps=3) -> float:
@@ -179,6 +194,27 @@ def tune_ppr_tile(host, k, iters=3, log=print) -> dict:
     return {"k_tile": best[1]}
 
 
+MULTI_GRID = [(big, mid, pg, ml) for big in (256, 512, 1024) for mid in (32, 64, 128) for pg in (1, 2, 4)
+              for ml in (8, 16, 32) if mid < big]
+
+
+def tune_multi(hosts, log=print) -> dict:
+    """Many-graph mapping with the lowest PageRank x20 (pull, then push) plus
+    switching-BFS launch time over the batch."""
+    from . import MultiGraph
+    mg = MultiGraph(hosts)
+    best = None
+    for big, mid, pg, ml in MULTI_GRID:
+        _lib.pp_set_multi_tuning(big, mid, pg, ml)
+        t = sum(_time(lambda: mg.run(pr_iters=20, pr_dir=d, bfs_policy=PP_SWITCH)) for d in (PP_PULL, PP_PUSH))
+        log(f"multi big={big} mid={mid} pull_group={pg} mid_lanes={ml}: {t:.3f} ms pull+push")
+        if best is None or t < best[0]:
+            best = (t, big, mid, pg, ml)
+    out = {"multi_big": best[1], "multi_mid": best[2], "multi_pull_group": best[3], "multi_mid_lanes": best[4]}
+    apply(out)
+    return out
+
+
 def main():
     import graphgen as gg
 
@@ -189,7 +225,21 @@ def main():
     p.add_argument("--out", required=True)
     p.add_argument("--only", default="", help="comma list of searches to rerun (pagerank, bfs, ppr); the cached "
                    "entry keeps the other settings, which also apply while searching")
+    p.add_argument("--multi", type=int, default=0, metavar="GRAPHS",
+                   help="instead: tune the many-graph launch on GRAPHS R-MAT graphs of scales 8-14")
     a = p.parse_args()
+    if a.multi:
+        cache = {}
+        if os.path.exists(a.out):
+            with open(a.out) as fh:
+                cache = json.load(fh)
+        hosts = gg.rmat_batch(a.multi, 8, 14, seed=TUNE_BATCH_SEED)
+        k = multi_key(len(hosts), sum(h.n for h in hosts), sum(int(h.nnz) for h in hosts))
+        cache[k] = tune_multi(hosts)
+        with open(a.out, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        print(json.dumps({k: cache[k]}))
+        return
     host = gg.rmat(a.scale, 16, seed=1)
     cache = {}
     if os.path.exists(a.out):

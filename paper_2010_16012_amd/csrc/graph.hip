@@ -897,6 +897,20 @@ PP_EXPORT pp_status pp_graph_push_bins(pp_graph g, int32_t* info) {
     return PP_OK;
 }
 
+PP_EXPORT pp_status pp_set_multi_tuning(int32_t big, int32_t mid, int32_t pull_group, int32_t mid_lanes) {
+    clear_error();
+    if (mid < 1 || big < mid) return set_error(PP_E_RANGE, "many-graph tuning: need 1 <= mid <= big");
+    if (pull_group != 1 && pull_group != 2 && pull_group != 4)
+        return set_error(PP_E_RANGE, "many-graph tuning: pull_group must be 1, 2 or 4");
+    if (mid_lanes != 8 && mid_lanes != 16 && mid_lanes != 32)
+        return set_error(PP_E_RANGE, "many-graph tuning: mid_lanes must be 8, 16 or 32");
+    tuning().multi_big = big;
+    tuning().multi_mid = mid;
+    tuning().multi_pull_group = pull_group;
+    tuning().multi_mid_lanes = mid_lanes;
+    return PP_OK;
+}
+
 PP_EXPORT pp_status pp_set_bfs_multi(int32_t max_frontier, int32_t max_edges) {
     clear_error();
     if (max_frontier < 0 || max_edges < 0) return set_error(PP_E_RANGE, "BFS multi-level caps must be >= 0");

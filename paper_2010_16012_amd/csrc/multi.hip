@@ -15,6 +15,7 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "pp_common.h"
@@ -25,19 +26,18 @@ constexpr int kMultiBlock = 1024;
 constexpr int kMultiGroup = 4;  // lanes per row
 constexpr int kMultiU = 8;      // index loads in flight per lane
 constexpr int kMultiPullU = 8;  // slots per lane and round of a pull row
-constexpr int kMultiPullGroup = 2;  // lanes per short pull row (the push and BFS use kMultiGroup)
 constexpr int32_t kMultiMaxN = 16384;
-// PageRank rows at least kMultiBig long get a whole wavefront each (up to
-// kMultiBigCap of them per graph); a small group per row would leave the
-// wavefront holding the hubs running long after the others.
-constexpr int32_t kMultiBig = 512;
+// PageRank rows at least `big` long (tuned; 512 by default) get a whole
+// wavefront each (up to kMultiBigCap of them per graph); a small group per
+// row would leave the wavefront holding the hubs running long after the
+// others.
 constexpr int32_t kMultiBigCap = 512;
-// Rows of kMultiMid..kMultiBig-1 edges go to 16-lane groups (four per
-// wavefront, up to kMultiMidCap of them per graph): in a small group such a
-// row takes several rounds while the wavefront's other rows wait.
-constexpr int32_t kMultiMid = 64;
+// Rows of `mid`..`big`-1 edges (64 by default) go to groups of ML lanes
+// (tuned; 16 by default), up to kMultiMidCap of them per graph: in a small
+// group such a row takes several rounds while the wavefront's other rows
+// wait.  The short pull rows take PG lanes each (tuned; 2 by default; the
+// push and BFS use kMultiGroup).
 constexpr int32_t kMultiMidCap = 4096;
-constexpr int kMultiMidLanes = 16;
 
 struct MultiEntry {
     int64_t vbase;  // first vertex of the graph in the vertex arenas (x, level, parent)
@@ -65,6 +65,7 @@ struct MultiArgs {
     int32_t* level;
     int32_t* parent;
     const int32_t* err;       // set by k_multi_check when the arena is malformed
+    int32_t big, mid;         // row-length thresholds of the wavefront and middle groups
 };
 
 __device__ __forceinline__ uint32_t bit_of(const uint32_t* bm, int32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
@@ -124,12 +125,14 @@ __global__ __launch_bounds__(kCheckBlock) void k_multi_check(const MultiEntry* _
     if (!ok) atomicOr(err, 1);
 }
 
+template <int PG, int ML>
 __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
     extern __shared__ float lds[];
     __shared__ int32_t s_cnt[4];
     __shared__ int64_t s_m[2];
     const int32_t gi = blockIdx.x;
     if (gi >= a.count || *a.err) return;  // a malformed arena is never walked
+    const int32_t big = a.big, mid = a.mid;
     const MultiEntry e = a.table[gi];
     const int32_t n = e.n;
     const int32_t* off = a.off + e.obase;
@@ -165,10 +168,10 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
         __syncthreads();
         for (int32_t u = tid; u < n; u += kMultiBlock) {
             const int32_t d = roff[u + 1] - roff[u];
-            if (d >= kMultiBig) {
+            if (d >= big) {
                 const int32_t at = atomicAdd(&s_nbig, 1);
                 if (at < kMultiBigCap) s_big[at] = u;
-            } else if (d >= kMultiMid) {
+            } else if (d >= mid) {
                 const int32_t at = atomicAdd(&s_nmid, 1);
                 if (at < kMultiMidCap) s_mid[at] = u;
             }
@@ -179,12 +182,12 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
         const int32_t nbig = (s_nbig <= kMultiBigCap) ? s_nbig : 0;
         const int32_t nmid = (s_nmid <= kMultiMidCap) ? s_nmid : 0;
         // does row length d belong to the small groups?
-        auto grouped = [&](int32_t d) {
-            return !((nbig > 0 && d >= kMultiBig) || (nmid > 0 && d >= kMultiMid && d < kMultiBig));
+        auto grouped = [=](int32_t d) {
+            return !((nbig > 0 && d >= big) || (nmid > 0 && d >= mid && d < big));
         };
-        const int hl = wl & (kMultiMidLanes - 1);  // lane within a middle-row group
-        const int32_t mslot = (kWave / kMultiMidLanes) * wv + wl / kMultiMidLanes;  // its group
-        constexpr int32_t mgroups = kMultiBlock / kMultiMidLanes;
+        const int hl = wl & (ML - 1);  // lane within a middle-row group
+        const int32_t mslot = (kWave / ML) * wv + wl / ML;  // its group
+        constexpr int32_t mgroups = kMultiBlock / ML;
         if (a.pr_dir == PP_PULL) {
             float* s_c = lds;       // contributions of the current iterate
             float* s_y = lds + n;   // contributions of the next one
@@ -232,10 +235,10 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                             noe = off[nu + 1];
                         }
                         double acc = 0.0;
-                        for (int32_t j0 = rb + hl; j0 < re; j0 += kMultiU * kMultiMidLanes)
-                            gather_row_slots<kMultiMidLanes, kMultiU>(in_idx, s_c, &s_zero, j0, re, acc);
+                        for (int32_t j0 = rb + hl; j0 < re; j0 += kMultiU * ML)
+                            gather_row_slots<ML, kMultiU>(in_idx, s_c, &s_zero, j0, re, acc);
 #pragma unroll
-                        for (int s = kMultiMidLanes / 2; s > 0; s >>= 1) acc += __shfl_xor(acc, s);
+                        for (int s = ML / 2; s > 0; s >>= 1) acc += __shfl_xor(acc, s);
                         if (hl == 0) {
                             const float y = (float)((double)base + acc);
                             const int32_t d = oe - ob;
@@ -245,12 +248,12 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                     }
                 }
                 // other rows: the group owning u gathers over its in-row (FP64
-                // sum per lane, kMultiPullGroup lanes per row, rows spread over
+                // sum per lane, PG lanes per row, rows spread over
                 // the wavefronts as above); the offsets and out-degree of the
                 // group's next row load while this row is summed
-                const int plane = tid % kMultiPullGroup;
-                const int32_t prow0 = kWaves * ((tid % kWave) / kMultiPullGroup) + wv;
-                constexpr int32_t pgroups = kMultiBlock / kMultiPullGroup;
+                const int plane = tid % PG;
+                const int32_t prow0 = kWaves * ((tid % kWave) / PG) + wv;
+                constexpr int32_t pgroups = kMultiBlock / PG;
                 int32_t nrb = 0, nre = 0, nob = 0, noe = 0;
                 if (prow0 < n) {
                     nrb = in_off[prow0];
@@ -268,10 +271,10 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                         noe = off[u + pgroups + 1];
                     }
                     if (!grouped(re - rb)) continue;  // group-uniform
-                    for (int32_t j0 = rb + plane; j0 < re; j0 += kMultiPullU * kMultiPullGroup)
-                        gather_row_slots<kMultiPullGroup, kMultiPullU>(in_idx, s_c, &s_zero, j0, re, acc);
+                    for (int32_t j0 = rb + plane; j0 < re; j0 += kMultiPullU * PG)
+                        gather_row_slots<PG, kMultiPullU>(in_idx, s_c, &s_zero, j0, re, acc);
 #pragma unroll
-                    for (int s = kMultiPullGroup / 2; s > 0; s >>= 1) acc += __shfl_xor(acc, s);
+                    for (int s = PG / 2; s > 0; s >>= 1) acc += __shfl_xor(acc, s);
                     if (plane == 0) {
                         const float y = (float)((double)base + acc);
                         const int32_t d = oe - ob;
@@ -336,14 +339,14 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
                             ne = off[nv + 1];
                         }
                         if (cv == 0.f) continue;
-                        for (int32_t j0 = rb + hl; j0 < re; j0 += kMultiU * kMultiMidLanes) {
+                        for (int32_t j0 = rb + hl; j0 < re; j0 += kMultiU * ML) {
                             int32_t ii[kMultiU];  // clamped to the row's last slot
 #pragma unroll
                             for (int k = 0; k < kMultiU; ++k)
-                                ii[k] = idx[(uint32_t)min(j0 + k * kMultiMidLanes, re - 1)];
+                                ii[k] = idx[(uint32_t)min(j0 + k * ML, re - 1)];
 #pragma unroll
                             for (int k = 0; k < kMultiU; ++k)
-                                if (j0 + k * kMultiMidLanes < re) atomicAdd(&s_acc[ii[k]], (double)cv);
+                                if (j0 + k * ML < re) atomicAdd(&s_acc[ii[k]], (double)cv);
                         }
                     }
                 }
@@ -546,6 +549,31 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi(MultiArgs a) {
 }
 
 // ------------------------------------------------------------------ host side
+template <int PG, int ML>
+static void launch_multi_k(const MultiArgs& a, int32_t grid, size_t lds, hipStream_t st) {
+    allow_dynamic_lds(reinterpret_cast<const void*>(&k_multi<PG, ML>), lds);
+    hipLaunchKernelGGL((k_multi<PG, ML>), dim3(grid), dim3(kMultiBlock), lds, st, a);
+}
+
+// The instantiation for the tuned group widths (false: none).
+static bool launch_multi(int32_t pg, int32_t ml, const MultiArgs& a, int32_t grid, size_t lds, hipStream_t st) {
+    auto by_ml = [&](auto pg_tag) {
+        constexpr int P = decltype(pg_tag)::value;
+        switch (ml) {
+            case 8: launch_multi_k<P, 8>(a, grid, lds, st); return true;
+            case 16: launch_multi_k<P, 16>(a, grid, lds, st); return true;
+            case 32: launch_multi_k<P, 32>(a, grid, lds, st); return true;
+            default: return false;
+        }
+    };
+    switch (pg) {
+        case 1: return by_ml(std::integral_constant<int, 1>{});
+        case 2: return by_ml(std::integral_constant<int, 2>{});
+        case 4: return by_ml(std::integral_constant<int, 4>{});
+        default: return false;
+    }
+}
+
 // Workspace: the graph table (LPT order) and the validation error word, both
 // written by one host copy, then the push contributions (one float per vertex).
 struct MultiLayout {
@@ -693,8 +721,11 @@ static pp_status multi_run(int32_t num_graphs, const int32_t* graph_n, const int
     a.level = level;
     a.parent = parent;
     a.err = err;
-    allow_dynamic_lds(reinterpret_cast<const void*>(&k_multi), lds);
-    hipLaunchKernelGGL(k_multi, dim3(num_graphs), dim3(kMultiBlock), lds, st, a);
+    const Tuning& t = tuning();
+    a.big = t.multi_big;
+    a.mid = t.multi_mid;
+    if (!launch_multi(t.multi_pull_group, t.multi_mid_lanes, a, num_graphs, lds, st))
+        return set_error(PP_E_RANGE, "many-graph tuning: unsupported group widths");
     PP_LAUNCH_CHECK("k_multi");
     int32_t herr = 0;
     PP_HIP(hipMemcpyAsync(&herr, err, sizeof(herr), hipMemcpyDeviceToHost, st));

@@ -51,6 +51,13 @@ struct Tuning {
     int32_t slice_rows = 0;      // rows of the tiled pull (0 = off); see SlicePlan
     int32_t slice_width = kSliceMax; // sources per slice of the tiled pull
     int32_t push_bins = 1;       // binned push for targets past the privatised ones (0 = global atomics)
+    // many-graph launch: rows of at least multi_big edges take a wavefront,
+    // rows of multi_mid..multi_big-1 a group of multi_mid_lanes lanes, the
+    // other pull rows multi_pull_group lanes
+    int32_t multi_big = 512;
+    int32_t multi_mid = 64;
+    int32_t multi_pull_group = 2;
+    int32_t multi_mid_lanes = 16;
     int32_t bfs_multi_n = 256;   // frontier vertices a one-workgroup BFS launch takes on (0 = off)
     int32_t bfs_multi_m = 1024;  // frontier out-edges per level it takes on
 };

@@ -28,7 +28,7 @@ def test_committed_cache_is_valid():
         cache = json.load(fh)
     for k, cfg in cache.items():
         arch, size = k.split("|")
-        assert arch.startswith("gfx") and size.startswith("n2^")
+        assert arch.startswith("gfx") and (size.startswith("n2^") or size.startswith("multi"))
         assert set(cfg) <= set(autotune.DEFAULTS)
         autotune.apply(cfg)  # every value is accepted by the library
     autotune.apply({})
@@ -45,3 +45,13 @@ def test_apply_rejects_out_of_range_values():
 def test_bin_candidates_are_increasing():
     for upper, chunk in autotune.BIN_CANDIDATES:
         assert all(a < b for a, b in zip(upper, upper[1:])) and chunk > 0
+
+
+def test_multi_key_and_mapping_settings():
+    assert autotune.multi_key(512, 2917543, 61503090, "gfx950") == "gfx950|multi512_n2^21_m2^26"
+    for big, mid, pg, ml in autotune.MULTI_GRID:
+        autotune.apply({"multi_big": big, "multi_mid": mid, "multi_pull_group": pg, "multi_mid_lanes": ml})
+    for bad in ({"multi_pull_group": 3}, {"multi_mid_lanes": 64}, {"multi_mid": 600}, {"multi_mid": 0}):
+        with pytest.raises(_lib.PPError):
+            autotune.apply(bad)
+    autotune.apply({})

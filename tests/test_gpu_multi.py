@@ -157,3 +157,15 @@ def test_row_lists_that_overflow():
     deg = np.diff(dense.off)
     assert ((deg >= 64) & (deg < 512)).sum() > 4096
     _check([H.complete(700), dense, H.path(50)], policies=(pp.PP_SWITCH,))
+
+
+@pytest.mark.parametrize("big,mid,pg,ml", [(512, 64, 2, 16), (256, 32, 1, 8), (1024, 128, 4, 32), (64, 8, 4, 8)])
+def test_every_tuned_mapping_matches_the_oracle(big, mid, pg, ml):
+    # the autotuner's search space: wavefront rows from `big` edges, middle rows
+    # from `mid` on `ml`-lane groups, short pull rows on `pg` lanes
+    _lib.pp_set_multi_tuning(big, mid, pg, ml)
+    try:
+        gs = gg.rmat_batch(16, 8, 13, seed=6) + [H.star(3000), H.complete(70), H.full_grid(40, 40)]
+        _check(gs, policies=(pp.PP_SWITCH,))
+    finally:
+        _lib.pp_set_multi_tuning(512, 64, 2, 16)
