@@ -328,7 +328,11 @@ pp_status pp_ppr_run(pp_graph g, pp_dir dir, int32_t k, const int32_t* sources, 
  *   Lambda = dLdX + f P^T Lambda,  (P^T z)(v) = (1/s(v)) sum over out-edges
  * (v,u) of w(v->u) z(u),
  * which is the transposed sweep: PP_PULL gathers along the CSR rows (the rows
- * the forward push scatters along), PP_PUSH scatters along CSC.  grad_w
+ * the forward push scatters along), PP_PUSH scatters along CSC.  PP_SWITCH
+ * (Sec. 5 Generic-Switch): Lambda's support starts at the nonzero rows of
+ * dLdX and grows along in-edges; while its in-edges number at most nnz/14
+ * the sweeps push from the support only, then dense pulls (a dense dLdX
+ * switches at once).  grad_w
  * (output, float[nnz], the caller's CSR slot order):
  *   dL/dw(v->u) = (f/s(v)) sum_j X[v,j] (Lambda[u,j] - (P^T Lambda)[v,j]).
  * Unweighted graphs differentiate with respect to implicit unit weights.

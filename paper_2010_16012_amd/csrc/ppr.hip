@@ -638,6 +638,18 @@ __global__ void k_sw_seed(SwState w, const int32_t* __restrict__ src_int, int32_
     if (c < kt && src_int[col0 + c] >= 0) sw_claim(w, src_int[col0 + c]);
 }
 
+// Adjoint: the support of Lambda_0 = dL/dX, i.e. every vertex whose row of
+// the tile's columns of g (caller layout n x k) holds a nonzero.
+__global__ void k_sw_seed_rhs(SwState w, int32_t n, int32_t k, int32_t col0, int32_t kt,
+                              const int32_t* __restrict__ perm, const float* __restrict__ g) {
+    for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+        const float* row = g + (size_t)user_id(perm, u) * k;
+        bool nz = false;
+        for (int32_t c = 0; c < kt && col0 + c < k; ++c) nz |= (row[col0 + c] != 0.f);
+        if (nz) sw_claim(w, u);
+    }
+}
+
 // One sparse push sweep: a group of KT lanes (one per column) per work unit
 // scatters c[v] along the unit's edges into the FP64 accumulator and claims
 // the targets for the next support.  The unit counts are read at launch.
@@ -814,14 +826,19 @@ __global__ void k_tile_to_caller(int32_t n, int32_t k, int32_t col0, const int32
 // below tol.  Forward state: t0/t1 iterates, t2/t3 scaled contributions;
 // adjoint state: t0/t1 Lambda; t4 is the push accumulator.  On return
 // *latest points at the newest iterate and *done holds the sweeps run.
-// Sparse sweeps of a forward tile while the support is small (PP_SWITCH).
-// On return *done = sweeps taken (negative if the tolerance was met, then no
-// dense sweep follows).  Buffers rotate as in the dense loop.
+// Sparse sweeps of a tile while the support is small (PP_SWITCH).  Forward:
+// the support starts at the sources and grows along out-edges; the sweep
+// pushes the scaled contributions along the CSR.  Adjoint: Lambda's support
+// starts at the nonzero rows of dL/dX and grows along in-edges (the
+// transposed sweep); the sweep pushes Lambda along the CSC and the epilogue
+// forms dL/dX + f/s(u) * sum.  On return *done = sweeps taken (negative if
+// the tolerance was met, then no dense sweep follows).  Buffers rotate as in
+// the dense loop.
 template <int KT>
-static pp_status sparse_phase(pp_graph g, int32_t k, int32_t col0, int32_t iters, float tol, float f,
-                              const int32_t* src_int, char* base, const PprLayout& L, float* prev, float* next,
-                              float* c_cur, float* c_nxt, double* t4, float* resid, float* scal, int32_t* done,
-                              hipStream_t st) {
+static pp_status sparse_phase(pp_graph g, bool adjoint, int32_t k, int32_t col0, int32_t iters, float tol, float f,
+                              const int32_t* src_int, const float* g_caller, char* base, const PprLayout& L,
+                              float* prev, float* next, float* c_cur, float* c_nxt, double* t4, float* resid,
+                              float* scal, int32_t* done, hipStream_t st) {
     const int32_t n = g->d.n;
     SwState w;
     w.bits = reinterpret_cast<uint64_t*>(base + L.sw_bits);
@@ -830,16 +847,21 @@ static pp_status sparse_phase(pp_graph g, int32_t k, int32_t col0, int32_t iters
     w.items = reinterpret_cast<int32_t*>(base + L.sw_items);
     w.cnt = reinterpret_cast<int32_t*>(base + L.sw_cnt);
     w.item_cap = L.sw_item_cap;
-    const Walk csr = walk_csr(g, KT);
+    const Walk csr = adjoint ? walk_csc(g, KT) : walk_csr(g, KT);  // the rows the sweep scatters along
     w.off = csr.off;
-    // the other two tiles start at zero: cells outside the support stay zero
+    // the other tiles start at zero: cells outside the support stay zero
     const int64_t cells = (int64_t)n * KT;
     hipLaunchKernelGGL(k_zero_f32, dim3(std::min<int64_t>(ceil_div(cells, 256), 65536)), dim3(256), 0, st, cells, next);
-    hipLaunchKernelGGL(k_zero_f32, dim3(std::min<int64_t>(ceil_div(cells, 256), 65536)), dim3(256), 0, st, cells,
-                       c_nxt);
+    if (!adjoint)
+        hipLaunchKernelGGL(k_zero_f32, dim3(std::min<int64_t>(ceil_div(cells, 256), 65536)), dim3(256), 0, st, cells,
+                           c_nxt);
     hipLaunchKernelGGL(k_sw_clear, dim3(std::max(1, std::min(ceil_div(ceil_div(n, 64), 256), 4096))), dim3(256), 0,
                        st, ceil_div(n, 64), w.bits, w.cnt);
-    hipLaunchKernelGGL(k_sw_seed, dim3(1), dim3(64), 0, st, w, src_int, col0, KT);
+    if (adjoint)
+        hipLaunchKernelGGL(k_sw_seed_rhs, dim3(std::max(1, std::min(ceil_div(n, 256), 4096))), dim3(256), 0, st, w, n,
+                           k, col0, KT, g->d.perm, g_caller);
+    else
+        hipLaunchKernelGGL(k_sw_seed, dim3(1), dim3(64), 0, st, w, src_int, col0, KT);
     PP_LAUNCH_CHECK("ppr sparse seed");
     int32_t h[8] = {};
     PP_HIP(hipMemcpyAsync(h, w.cnt, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -851,26 +873,30 @@ static pp_status sparse_phase(pp_graph g, int32_t k, int32_t col0, int32_t iters
         const int64_t m_s = (int64_t)((uint64_t)(uint32_t)h[4] | ((uint64_t)(uint32_t)h[5] << 32));
         if (m_s > m_switch) break;  // dense from here on
         const int32_t units = h[1] + std::min(h[2], w.item_cap);
+        // forward: the scaled contributions; adjoint: Lambda itself (the
+        // epilogue applies f / s(u))
+        const float* moved = adjoint ? prev : c_cur;
         if (units > 0) {
             const int32_t blocks = std::max(1, std::min(eb, ceil_div(units, kBlock / KT)));
             if (g->weighted)
                 hipLaunchKernelGGL((k_sw_scatter<KT, true>), dim3(blocks), dim3(kBlock), 0, st, w, csr.idx, csr.wt,
-                                   (const float*)c_cur, t4, h[1], std::min(h[2], w.item_cap));
+                                   moved, t4, h[1], std::min(h[2], w.item_cap));
             else
                 hipLaunchKernelGGL((k_sw_scatter<KT, false>), dim3(blocks), dim3(kBlock), 0, st, w, csr.idx, csr.wt,
-                                   (const float*)c_cur, t4, h[1], std::min(h[2], w.item_cap));
+                                   moved, t4, h[1], std::min(h[2], w.item_cap));
         }
         KArgs a{};
-        a.kind = kEpiForward;
+        a.kind = adjoint ? kEpiAdjoint : kEpiForward;
         a.inv_s = g->d.inv_s;
         a.perm = g->d.perm;
         a.f = f;
         a.k = k;
         a.col0 = col0;
         a.src_int = src_int;
+        a.g_caller = g_caller;
         a.prev = prev;
         a.out_tile = next;
-        a.out_scaled = c_nxt;
+        a.out_scaled = adjoint ? nullptr : c_nxt;
         a.resid_part = resid;
         hipLaunchKernelGGL(k_sw_epi<KT>, dim3(eb), dim3(kBlock), 0, st, a, w, t4);
         PP_LAUNCH_CHECK("ppr sparse sweep");
@@ -917,8 +943,8 @@ static pp_status run_tile(pp_graph g, bool adjoint, pp_dir dir, int32_t k, int32
     *done = 0;
     int32_t t0_dense = 0;  // first dense sweep
     if (dir == PP_SWITCH) {
-        pp_status s = sparse_phase<KT>(g, k, col0, iters, tol, f, src_int, base, L, prev, next, c_cur, c_nxt, t4,
-                                       resid, scal, done, st);
+        pp_status s = sparse_phase<KT>(g, adjoint, k, col0, iters, tol, f, src_int, g_caller, base, L, prev, next,
+                                       c_cur, c_nxt, t4, resid, scal, done, st);
         if (s != PP_OK) return s;
         t0_dense = *done;
         if (*done & 1) {  // the sparse sweeps swapped the buffers an odd number of times
@@ -1304,7 +1330,6 @@ PP_EXPORT pp_status pp_ppr_adjoint(pp_graph g, pp_dir dir, int32_t k, const floa
     const size_t need = pp_ppr_scratch_bytes(g, k, k_tile);
     pp_status s = check_ppr(g, dir, k, iters, tol, f, k_tile, scratch, scratch_bytes, need);
     if (s != PP_OK) return s;
-    if (dir == PP_SWITCH) return set_error(PP_E_RANGE, "the adjoint runs PP_PUSH or PP_PULL sweeps");
     if (k > 0 && (!X || !dLdX || !Lambda)) return set_error(PP_E_NULL, "X, dLdX and Lambda are required");
     if (g->d.nnz > 0 && !grad_w) return set_error(PP_E_NULL, "grad_w is required");
     if (iters_done) *iters_done = 0;

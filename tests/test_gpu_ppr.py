@@ -182,8 +182,8 @@ def test_ppr_edge_cases_and_errors():
         pp.ppr(g, [1] * 8, k_tile=12)
     with pytest.raises(pp.PPError):
         pp.ppr(g, [0, 1, 2, 3, 4, 5, 6, 10], k_tile=8)  # source out of range
-    with pytest.raises(pp.PPError):  # the adjoint has no sparse phase
-        pp.ppr_adjoint(g, X, torch.ones_like(X), iters=2, k_tile=8, direction=pp.PP_SWITCH)
+    with pytest.raises(pp.PPError):  # not a direction
+        pp.ppr_adjoint(g, X, torch.ones_like(X), iters=2, k_tile=8, direction=7)
 
 
 # ----------------------------------------------------------------------- adjoint
@@ -420,3 +420,44 @@ def test_autograd_function_registers_once_and_keeps_each_forwards_weights():
                                           tol=1e-15, weights=wn)
         gh = w.grad.cpu().numpy().astype(np.float64)
         assert np.linalg.norm(gh - grad_o) / np.linalg.norm(grad_o) <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["grid", "directed"])
+def test_adjoint_generic_switch_sparse_then_dense(name):
+    # PP_SWITCH for the adjoint: Lambda's support starts at the nonzero rows of
+    # dL/dX and grows along in-edges, pushed sparsely until it holds m/14
+    # edges, then dense pulls.  A loss on a few vertices keeps the first sweeps
+    # sparse; a dense loss switches at once.  Both match the oracle's Lambda
+    # and gradient, and T fixed sweeps equal T pull sweeps.
+    if name == "grid":
+        host = H.full_grid(60, 60)
+        gg.with_weights(host, seed=13)
+    else:
+        host = H.random_graph(2500, 7000, 17, symmetric=False, connected=True)
+        gg.with_weights(host, seed=14)
+    src = np.arange(8, dtype=np.int32) * 97
+    Xo = _forward_fixed_point(host, src)
+    sparse_c = np.zeros((host.n, 8))
+    rows = np.array([5, 700, 1400, 2100, 2498])
+    sparse_c[rows, :] = gg.normal(len(rows) * 8, seed=3).reshape(len(rows), 8)
+    dense_c = gg.normal(host.n * 8, seed=4).reshape(host.n, 8).astype(np.float64)
+    for rl in (True, False):
+        g = pp.Graph(host, relabel=rl)
+        X, _ = pp.ppr(g, src, iters=3000, f=F, k_tile=8, tol=1e-9)
+        for which, c in (("sparse", sparse_c), ("dense", dense_c)):
+            announce(f"adjoint switch {name} relabel={rl} loss={which}")
+            lam_o, grad_o, _ = oracle.ppr_adjoint(host.off, host.idx, Xo, c, F, T=20000, tol=1e-15,
+                                                  weights=host.weights)
+            ct = torch.as_tensor(c, dtype=torch.float32, device="cuda")
+            lam, grad, done = pp.ppr_adjoint(g, X, ct, iters=3000, f=F, k_tile=8, direction=pp.PP_SWITCH, tol=1e-9)
+            # (FP32 sweeps on a grid with a dense loss can cycle just above a
+            # 1e-9 relative change instead of stopping: accuracy is the bar)
+            gh = grad.cpu().numpy().astype(np.float64)
+            assert np.linalg.norm(gh - grad_o) / np.linalg.norm(grad_o) <= 1e-5
+            lh = lam.cpu().numpy().astype(np.float64)
+            assert np.abs(lh - lam_o).max() / np.abs(lam_o).max() <= 1e-5
+            # a fixed number of sweeps: the sparse sweeps are exact iterations
+            ls, _, _ = pp.ppr_adjoint(g, X, ct, iters=12, f=F, k_tile=8, direction=pp.PP_SWITCH)
+            lp, _, _ = pp.ppr_adjoint(g, X, ct, iters=12, f=F, k_tile=8, direction=pp.PP_PULL)
+            assert (ls - lp).abs().max().item() <= 1e-5 * lp.abs().max().item()
+        g.close()
