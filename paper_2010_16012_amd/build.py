@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libpp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["graph.hip", "pr.hip", "bfs.hip", "ppr.hip", "multi.hip", "tc.hip", "bc.hip"]
+SOURCES = ["graph.hip", "pr.hip", "push.hip", "bfs.hip", "ppr.hip", "multi.hip", "tc.hip", "bc.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}",
