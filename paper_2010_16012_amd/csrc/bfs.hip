@@ -745,12 +745,16 @@ __device__ __forceinline__ void level_bottom_up(const BfsArgs& a, int32_t lvl, c
 // most edges still belong to unvisited vertices.  Row by row, a wavefront
 // walks its bitmap words one after another, and the hub words (64 rows of
 // hundreds of edges each) serialise whole levels; streamed, every slot is
-// read once in memory order with kStreamU loads in flight per lane.  The
-// slots whose source is in the frontier are collected per wavefront in LDS
-// and resolved 64 at a time, one lane each: the vertex comes from csc_row and
-// is claimed with an atomic OR, so its parent is some frontier in-neighbour
-// (not necessarily the first in stored order).
-constexpr int kStreamU = 8;
+// read once in memory order with kStreamQ 16-byte loads (four slots each)
+// in flight per lane: 8 KB per wavefront, which a CU needs to keep the
+// stream near full bandwidth.  The slots whose source is in the frontier are
+// collected per wavefront in LDS and resolved 64 at a time, one lane each:
+// the vertex comes from csc_row and is claimed with an atomic OR, so its
+// parent is some frontier in-neighbour (not necessarily the first in stored
+// order).  An in-edge array that is not 16-byte aligned, and the slots past
+// the last whole quad, take 4-byte loads.
+constexpr int kStreamQ = 8;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // a native vector: non-temporal loads take it
 
 __device__ __forceinline__ void level_bottom_up_stream(const BfsArgs& a, int32_t lvl, const FbView& fv, WaveLds& sl,
                                                        int32_t* q_next, int32_t* fill_next, uint64_t* fb_next,
@@ -759,6 +763,7 @@ __device__ __forceinline__ void level_bottom_up_stream(const BfsArgs& a, int32_t
     const int w = threadIdx.x / kWave;
     const int64_t gwave = blockIdx.x * kBfsWaves + w;
     const int64_t nwaves = (int64_t)gridDim.x * kBfsWaves;
+    constexpr int kStreamU = 8;  // 4-byte loads per lane of the slot-by-slot loop
     constexpr int64_t kStep = kStreamU * kWave;
     int32_t nh = 0;  // hits held in sl.a / sl.b (wave-uniform)
     auto resolve = [&]() {
@@ -787,7 +792,53 @@ __device__ __forceinline__ void level_bottom_up_stream(const BfsArgs& a, int32_t
         wave_sync();
         nh = 0;
     };
-    for (int64_t e0 = gwave * kStep; e0 < a.nnz; e0 += nwaves * kStep) {
+    // collects the hit slots of one round (slot index, source), resolving
+    // the wavefront's list whenever the next hits would overflow it
+    auto collect = [&](bool h, int64_t e, int32_t src) {
+        const uint64_t m = __ballot(h);
+        if (!m) return;
+        const int32_t k = __popcll(m);
+        if (nh + k > kWave) resolve();
+        if (h) {
+            const int32_t at = nh + __popcll(m & lanes_below(lane));
+            sl.a[w][at] = (int32_t)e;
+            sl.b[w][at] = src;
+        }
+        nh += k;
+    };
+    const bool quads = (reinterpret_cast<uintptr_t>(a.csc_idx) & 15) == 0;
+    const int64_t nq = quads ? a.nnz / 4 : 0;  // whole quads streamed 16 bytes at a time
+    constexpr int64_t kQStep = kStreamQ * kWave;
+    const u32x4* q4 = reinterpret_cast<const u32x4*>(a.csc_idx);
+    for (int64_t q0 = gwave * kQStep; q0 < nq; q0 += nwaves * kQStep) {
+        u32x4 v[kStreamQ];
+#pragma unroll
+        for (int r = 0; r < kStreamQ; ++r) {
+            const int64_t q = q0 + r * kWave + lane;
+            v[r] = (q < nq) ? __builtin_nontemporal_load(q4 + q) : u32x4{~0u, ~0u, ~0u, ~0u};
+        }
+        bool hit[kStreamQ][4];
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < kStreamQ; ++r) {
+            const int32_t s4[4] = {(int32_t)v[r].x, (int32_t)v[r].y, (int32_t)v[r].z, (int32_t)v[r].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                hit[r][j] = (s4[j] >= 0) && fb_test(fv, s4[j]);
+                any = any || hit[r][j];
+            }
+        }
+        if (__ballot(any) == 0) continue;
+#pragma unroll
+        for (int r = 0; r < kStreamQ; ++r) {
+            const int32_t s4[4] = {(int32_t)v[r].x, (int32_t)v[r].y, (int32_t)v[r].z, (int32_t)v[r].w};
+            const int64_t e = 4 * (q0 + r * kWave + lane);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) collect(hit[r][j], e + j, s4[j]);
+        }
+    }
+    // the rest (everything when the array is not 16-byte aligned), slot by slot
+    for (int64_t e0 = 4 * nq + gwave * kStep; e0 < a.nnz; e0 += nwaves * kStep) {
         int32_t u[kStreamU];
 #pragma unroll
         for (int r = 0; r < kStreamU; ++r) {
@@ -803,18 +854,7 @@ __device__ __forceinline__ void level_bottom_up_stream(const BfsArgs& a, int32_t
         }
         if (__ballot(any) == 0) continue;
 #pragma unroll
-        for (int r = 0; r < kStreamU; ++r) {
-            const uint64_t m = __ballot(hit[r]);
-            if (!m) continue;
-            const int32_t k = __popcll(m);
-            if (nh + k > kWave) resolve();
-            if (hit[r]) {
-                const int32_t at = nh + __popcll(m & lanes_below(lane));
-                sl.a[w][at] = (int32_t)(e0 + r * kWave + lane);
-                sl.b[w][at] = u[r];
-            }
-            nh += k;
-        }
+        for (int r = 0; r < kStreamU; ++r) collect(hit[r], e0 + r * kWave + lane, u[r]);
     }
     if (nh) resolve();
 }
