@@ -353,6 +353,44 @@ __device__ __forceinline__ uint32_t unit_entry(const UnitData& U, int j) {
     return (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
 }
 
+// Cross-lane moves through DPP: the data moves within the VALU, with no LDS
+// round trip (the shuffles they replace were the tiled sweep's critical
+// path).  A lane whose source lane lies outside its row, or whose row is
+// masked off, gets 0.  Controls: row_shr:n = 0x110 + n; row_bcast:15 = 0x142
+// (lane 15 of each row to the next row; rows 1 and 3 written); row_bcast:31
+// = 0x143 (lane 31 to rows 2 and 3); wave_shr:1 = 0x138.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ int dpp_take(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp_takef(float x) {
+    return __int_as_float(dpp_take<CTRL, ROWS>(__float_as_int(x)));
+}
+
+// Inclusive prefix sum over the wavefront (all lanes active).
+__device__ __forceinline__ int wave_incl_sum(int x) {
+    x += dpp_take<0x111>(x);
+    x += dpp_take<0x112>(x);
+    x += dpp_take<0x114>(x);
+    x += dpp_take<0x118>(x);
+    x += dpp_take<0x142, 0xa>(x);
+    x += dpp_take<0x143, 0xc>(x);
+    return x;
+}
+
+// One step of an inclusive segmented scan: a lane that has not started a
+// segment since the source lane adds the source's sum in front of its own.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ void seg_step(float& x, int& fresh) {
+    const float xs = dpp_takef<CTRL, ROWS>(x);
+    const int fs = dpp_take<CTRL, ROWS>(fresh);
+    if (!fresh) {
+        x = xs + x;
+        fresh = fs;
+    }
+}
+
 // Runs one unit (sums: this wavefront's 256 LDS words).
 __device__ __forceinline__ void unit_run(const TileArgs& t, const UnitData& U, int lane, const float* lds, float* sums) {
     const SliceUnit& d = U.d;
@@ -377,17 +415,13 @@ __device__ __forceinline__ void unit_run(const TileArgs& t, const UnitData& U, i
     }
     // segment ordinals: exclusive prefix count of heads over the lanes
     const int nh = __popc(heads);
-    int pref = nh;
-#pragma unroll
-    for (int st = 1; st < kWave; st <<= 1) {
-        const int o = __shfl_up(pref, st);
-        if (lane >= st) pref += o;
-    }
-    const int total = __shfl(pref, kWave - 1);
-    pref -= nh;
+    const int incl = wave_incl_sum(nh);
+    const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
+    const int pref = incl - nh;
     // in-lane sums: segments that end inside the lane go to sums[ordinal];
-    // `lead` (entries before the lane's first head) belongs to a segment of an
-    // earlier lane, `tail` (entries from the last head on) may run on
+    // `lead` (entries before the lane's first head) closes a segment of an
+    // earlier lane, `run` ends as the tail (entries from the last head on),
+    // or the whole lane without a head
     float run = 0.f, lead = 0.f;
     int k = 0;
 #pragma unroll
@@ -400,23 +434,22 @@ __device__ __forceinline__ void unit_run(const TileArgs& t, const UnitData& U, i
         }
         run += v[j];
     }
-    // backward segmented scan of what each lane hands to the segment running
-    // in from its left: all of it without a head, else its lead; it stops at
-    // the first lane with a head (or past the unit's end)
-    float val = nh ? lead : run;
-    int stop = (nh > 0 || nvalid == 0) ? 1 : 0;
-#pragma unroll
-    for (int st = 1; st < kWave; st <<= 1) {
-        const float ov = __shfl_down(val, st);
-        const int os = __shfl_down(stop, st);
-        if (!stop && lane + st < kWave) {
-            val += ov;
-            stop = os;
-        }
-    }
-    float from_right = __shfl_down(val, 1);
-    if (lane == kWave - 1) from_right = 0.f;
-    if (nh) sums[pref + nh - 1] = run + from_right;
+    // forward segmented scan: `open` is what the segment open at the end of
+    // this lane holds so far (a lane with a head starts afresh from its
+    // tail).  A lane with a head closes the segment open at its start with
+    // its lead; the last lane closes the one still open (units hold whole
+    // segments).  Fixed order, no cancellation: the sum stays reproducible.
+    float open = run;
+    int fresh = nh ? 1 : 0;
+    seg_step<0x111>(open, fresh);
+    seg_step<0x112>(open, fresh);
+    seg_step<0x114>(open, fresh);
+    seg_step<0x118>(open, fresh);
+    seg_step<0x142, 0xa>(open, fresh);
+    seg_step<0x143, 0xc>(open, fresh);
+    const float before = dpp_takef<0x138>(open);  // the segment open at this lane's start
+    if (nh && pref > 0) sums[pref - 1] = before + lead;
+    if (lane == kWave - 1 && total > 0) sums[total - 1] = open;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
