@@ -742,9 +742,23 @@ pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float
         for (int b = 0; b <= PP_NUM_BINS; ++b) a.wave_off[b] = sl.wave_off[b];
         a.units = sl.units;
         a.tab0 = sl.tab0;
-        TileArgs t{g->d.sl_idx, g->d.sl_prow, g->d.sl_units, g->d.sl_segs, g->d.sl_wg, g->d.sl_part,
-                   g->d.sl_cpart, g->d.sl_cbeg, c, g->d.n, sl.rows, sl.width, sl.slices, std::max(sl.pairs, 1),
-                   sl.idx_size - 16};
+        // named fields: a positional initializer silently shifts when a field is added
+        TileArgs t{};
+        t.idx = g->d.sl_idx;
+        t.prow = g->d.sl_prow;
+        t.units = g->d.sl_units;
+        t.segs = g->d.sl_segs;
+        t.wg = g->d.sl_wg;
+        t.part = g->d.sl_part;
+        t.cpart = g->d.sl_cpart;
+        t.cbeg = g->d.sl_cbeg;
+        t.c = c;
+        t.n = g->d.n;
+        t.R = sl.rows;
+        t.W = sl.width;
+        t.S = sl.slices;
+        t.P = std::max(sl.pairs, 1);
+        t.idx_last = sl.idx_size - 16;
         // the slice with its per-wavefront words, or the hot range of the rest
         const size_t lds = std::max(tiled_lds_bytes(sl.width, tpb / kWave), (size_t)a.hot * sizeof(float));
         if (hot) {
