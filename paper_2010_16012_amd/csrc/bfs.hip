@@ -81,6 +81,8 @@ struct BfsHdr {
     int32_t lv[2];
     int32_t c_lvl;
     int32_t finished;  // an empty frontier was reached
+    int32_t busy;      // level-kernel launches that found a non-empty frontier
+    int32_t pad;
     int64_t reached;
     int64_t edges;
     int8_t log_dir[PP_BFS_MAX_LOG];
@@ -378,6 +380,7 @@ __global__ void k_bfs_init(BfsArgs a, int32_t root_user, int64_t nnz) {
         h->lv[1] = 0;
         h->c_lvl = -1;
         h->finished = 0;
+        h->busy = 0;
         h->root = root;
         h->overflow = 0;
         h->reached = 0;
@@ -909,6 +912,7 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
         h->edges += cur.m;
         h->lv[parity ^ 1] = lvl + 1;
         h->c_lvl = lvl;
+        h->busy += 1;
     }
     // the bitmap two levels ahead (frontier lvl - 1) is rewritten next level:
     // clear it now, unless level lvl - 1 was a queue-driven top-down level,
@@ -1535,17 +1539,19 @@ PP_EXPORT pp_status pp_bfs_run_log(pp_graph g, int32_t root, pp_dir policy, floa
     // Levels go out in batches with the level index kept on the device;
     // kernels past the last level find an empty frontier and return at once,
     // so only termination needs a read, which takes the whole header (the
-    // statistics come with it).  The first batch covers the previous run's
-    // depth on this graph plus the empty level, so a run of similar depth
-    // needs one host read.
-    constexpr int32_t kBatches[] = {4, 8, 12, 16, 24, 32, 48, 64, 128, 256};
-    constexpr int32_t kMaxBatch = 256;  // deep graphs (grids) take long batches
-    int32_t batch = kMaxBatch;
-    for (int32_t b : kBatches)
-        if (b >= g->bfs_last_levels + 2) {
-            batch = b;
-            break;
-        }
+    // statistics come with it).  The run is over when the newest frontier is
+    // empty, so no launch is spent on finding that out.  The first batch
+    // covers the most level-kernel launches that found work in the recent
+    // runs with this policy on this graph, so a run of similar depth needs
+    // one host read; a deeper run goes on in batches of 2, 4, 8, ...
+    static constexpr int32_t kMaxBatch = 256;  // deep graphs (grids) take long batches
+    int32_t* hist = g->bfs_hist[policy];
+    int32_t predicted = 0;
+    for (int i = 0; i < pp_graph_s::kBfsHist; ++i) predicted = std::max(predicted, hist[i]);
+    // batches are even (level kernels of parity 0, 1, 0, ...)
+    auto even = [](int32_t b) { return std::min(kMaxBatch, std::max<int32_t>(2, (b + 1) & ~1)); };
+    int32_t batch = predicted > 0 ? even(predicted) : 4;
+    int32_t extra = 2;
     int32_t launched = 0;
     const int32_t max_levels = g->d.n + 1;  // at most n non-empty frontiers, then an empty one
     BfsHdr h;
@@ -1564,10 +1570,16 @@ PP_EXPORT pp_status pp_bfs_run_log(pp_graph g, int32_t root, pp_dir policy, floa
         }
         s = read_hdr(g, state, &h, st);
         if (s != PP_OK) return s;
-        if (h.finished || launched >= max_levels) break;
-        batch = std::min<int32_t>(batch * 2, kMaxBatch);
+        if (h.finished || h.slot[h.last % 3].n == 0 || launched >= max_levels) break;
+        if (launched < predicted) {
+            batch = even(predicted - launched);
+        } else {
+            batch = even(extra);
+            extra = std::min(extra * 2, kMaxBatch);
+        }
     }
-    g->bfs_last_levels = h.levels;
+    hist[g->bfs_hist_pos[policy]] = h.busy;
+    g->bfs_hist_pos[policy] = (g->bfs_hist_pos[policy] + 1) % pp_graph_s::kBfsHist;
     if (stats) {
         stats->levels = h.levels;
         stats->reached = (int32_t)h.reached;

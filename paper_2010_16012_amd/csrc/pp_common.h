@@ -253,7 +253,11 @@ struct pp_graph_s {
         hipGraph_t graph;
     };
     std::vector<BfsGraph> bfs_graphs;
-    int32_t bfs_last_levels = 0;  // levels of the last BFS run on this graph (sizes the first batch)
+    // level-kernel launches that found a frontier, per policy, over the last
+    // kBfsHist runs on this graph (their maximum sizes a run's first batch)
+    static constexpr int kBfsHist = 8;
+    int32_t bfs_hist[3][kBfsHist] = {};
+    int32_t bfs_hist_pos[3] = {};
     ~pp_graph_s() {
         for (auto& e : bfs_graphs) {
             (void)hipGraphExecDestroy(e.exec);
