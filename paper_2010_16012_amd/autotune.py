@@ -92,7 +92,7 @@ def _time(fn, reps=3) -> float:
     return best
 
 
-SLICE_ROWS = (65536, 131072, 262144, 524288)
+SLICE_ROWS = (65536, 131072, 196608, 262144, 524288)
 
 BIN_CANDIDATES = (
     ([4, 16, 64, 1024, 4096], 4096),
