@@ -446,37 +446,46 @@ constexpr int64_t kProbeMin = 1 << 16;
 // issued together and their latencies overlap.  Wave-collective.
 constexpr int kTdU = 4;
 
+// ONE_PARENT: every edge of the batch leaves one vertex, pv[0] (a row or a
+// chunk of one), so its caller id is looked up once.
+template <bool ONE_PARENT = false>
 __device__ __forceinline__ void td_batch(const BfsArgs& a, const TdCtx& cx, Pager& pg, const int32_t (&u)[kTdU],
                                          const int32_t (&pv)[kTdU], int32_t& cnt, int64_t& deg, int lane) {
+    // Bits are tested and claimed in the 32-bit half of their 64-bit word
+    // (the same bit, little-endian), which halves the registers the loads
+    // and claims in flight take.  An atomic on one half is as atomic as one
+    // on the whole word for the other bits' owners.
+    const uint32_t* s_vis32 = reinterpret_cast<const uint32_t*>(cx.s_vis);
+    uint32_t* vis32 = reinterpret_cast<uint32_t*>(a.visited);
     bool cand[kTdU];
 #pragma unroll
     for (int r = 0; r < kTdU; ++r) {
         // a set bit in the LDS snapshot is final; a clear one is checked in memory
         const int32_t w = u[r] >> 6;
-        cand[r] = (u[r] >= 0) && (w >= cx.sw || !((cx.s_vis[w] >> (u[r] & 63)) & 1ull));
+        cand[r] = (u[r] >= 0) && (w >= cx.sw || !((s_vis32[u[r] >> 5] >> (u[r] & 31)) & 1u));
     }
-    uint64_t word[kTdU];
+    uint32_t word[kTdU];
 #pragma unroll
-    for (int r = 0; r < kTdU; ++r) word[r] = (cand[r] && cx.probe) ? a.visited[u[r] >> 6] : (cand[r] ? 0ull : ~0ull);
+    for (int r = 0; r < kTdU; ++r) word[r] = (cand[r] && cx.probe) ? vis32[u[r] >> 5] : (cand[r] ? 0u : ~0u);
     // the out-degree and the caller ids a claim needs are loaded in flight
     // with the claim itself
     bool need[kTdU];
     int32_t od[kTdU], uid[kTdU], pid[kTdU];
+    const int32_t pid1 = (ONE_PARENT && a.perm && pv[0] >= 0) ? a.perm[pv[0]] : pv[0];
 #pragma unroll
     for (int r = 0; r < kTdU; ++r) {
-        need[r] = cand[r] && !((word[r] >> (u[r] & 63)) & 1ull);
+        need[r] = cand[r] && !((word[r] >> (u[r] & 31)) & 1u);
         od[r] = need[r] ? a.out_deg[u[r]] : 0;
         uid[r] = (need[r] && a.perm) ? a.perm[u[r]] : u[r];
-        pid[r] = (need[r] && a.perm) ? a.perm[pv[r]] : pv[r];
+        pid[r] = ONE_PARENT ? pid1 : ((need[r] && a.perm) ? a.perm[pv[r]] : pv[r]);
     }
     bool claimed[kTdU];
 #pragma unroll
     for (int r = 0; r < kTdU; ++r) {
         claimed[r] = false;
-        const uint64_t bit = 1ull << (u[r] & 63);
+        const uint32_t bit = 1u << (u[r] & 31);
         if (need[r]) {
-            const uint64_t old =
-                atomicOr(reinterpret_cast<unsigned long long*>(&a.visited[u[r] >> 6]), (unsigned long long)bit);
+            const uint32_t old = atomicOr(&vis32[u[r] >> 5], bit);
             claimed[r] = !(old & bit);
         }
     }
@@ -485,8 +494,7 @@ __device__ __forceinline__ void td_batch(const BfsArgs& a, const TdCtx& cx, Page
         if (claimed[r]) {
             a.level[uid[r]] = cx.lvl + 1;
             a.parent[uid[r]] = pid[r];
-            atomicOr(reinterpret_cast<unsigned long long*>(&cx.fb_next[u[r] >> 6]),
-                     (unsigned long long)(1ull << (u[r] & 63)));
+            atomicOr(reinterpret_cast<uint32_t*>(cx.fb_next) + (u[r] >> 5), 1u << (u[r] & 31));
             cnt += 1;
             deg += od[r];
         }
@@ -509,7 +517,7 @@ __device__ __forceinline__ void td_row(const BfsArgs& a, const TdCtx& cx, Pager&
             u[r] = (j < e) ? a.csr_idx[j] : -1;
             pv[r] = v;
         }
-        td_batch(a, cx, pg, u, pv, cnt, deg, lane);
+        td_batch<true>(a, cx, pg, u, pv, cnt, deg, lane);
     }
 }
 

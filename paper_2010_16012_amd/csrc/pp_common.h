@@ -37,6 +37,21 @@ constexpr int kHotMax = 40960;
 // besides it the kernel keeps a zero word and 1 KB per wavefront in LDS.
 constexpr int kSliceMax = 32768;
 constexpr int kTiledWaveLds = 1024;
+// Wavefront-uniform descriptors (work-unit tables written before the kernel
+// starts) are read through the constant address space, so they become scalar
+// loads.  Vector memory operations complete in issue order, so a vector load
+// here would make the wait on its value also wait for every vector load,
+// store and atomic issued before it; a scalar load waits on its own counter.
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T* p, int32_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) T* cptr;
+    return ((cptr)p)[i];
+#else
+    return p[i];  // host pass: never executed
+#endif
+}
+
 inline size_t tiled_lds_bytes(int32_t width, int32_t waves) {
     return (size_t)width * 4 + 16 + (size_t)waves * kTiledWaveLds;
 }

@@ -319,18 +319,6 @@ struct UnitData {
 
 __device__ __forceinline__ SliceUnit no_unit() { return SliceUnit{0, 0, 0, 0}; }
 
-// Descriptors are wavefront-uniform: read them through the constant address
-// space so they become scalar loads.  A vector load here would make the next
-// wait on its value also wait for every index load in flight.
-template <typename T>
-__device__ __forceinline__ T uniform_load(const T* p, int32_t i) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    typedef const __attribute__((address_space(4))) T* cptr;
-    return ((cptr)p)[i];
-#else
-    return p[i];  // host pass: never executed
-#endif
-}
 
 // Every load is unconditional, at an address clamped into its array (what a
 // lane should not use is masked when the unit runs): the compiler then knows
