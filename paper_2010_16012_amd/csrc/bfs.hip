@@ -223,8 +223,21 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 // Copies bitmap words [0, sw) into LDS.  Workgroup-collective.
+// 16-byte loads, four in flight per thread (src is 256-byte aligned).
 __device__ __forceinline__ void stage_bits(uint64_t* s_bits, const uint64_t* src, int32_t sw) {
-    for (int32_t i = threadIdx.x; i < sw; i += blockDim.x) s_bits[i] = src[i];
+    const int32_t n2 = sw >> 1;
+    const ulonglong2* s2 = reinterpret_cast<const ulonglong2*>(src);
+    ulonglong2* d2 = reinterpret_cast<ulonglong2*>(s_bits);
+    const int32_t bd = blockDim.x;
+    for (int32_t i0 = threadIdx.x; i0 < n2; i0 += 4 * bd) {
+        ulonglong2 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = s2[min(i0 + k * bd, n2 - 1)];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i0 + k * bd < n2) d2[i0 + k * bd] = v[k];
+    }
+    if ((sw & 1) && threadIdx.x == 0) s_bits[sw - 1] = src[sw - 1];
     __syncthreads();
 }
 
@@ -238,11 +251,13 @@ struct FbView {
     const uint64_t* g_bits;
 };
 
+// Bits are read from the 32-bit half of their 64-bit word (the same bit,
+// little-endian): half the LDS bandwidth per test.
 __device__ __forceinline__ bool fb_test(const FbView& f, int32_t u) {
     const int32_t w = u >> 6;
-    if (w < f.sw) return (f.s_bits[w] >> (u & 63)) & 1ull;
-    if (w < f.lim && !((f.s_sum[w >> 6] >> (w & 63)) & 1ull)) return false;
-    return (f.g_bits[w] >> (u & 63)) & 1ull;
+    if (w < f.sw) return (reinterpret_cast<const uint32_t*>(f.s_bits)[u >> 5] >> (u & 31)) & 1u;
+    if (w < f.lim && !((reinterpret_cast<const uint32_t*>(f.s_sum)[w >> 5] >> (w & 31)) & 1u)) return false;
+    return (reinterpret_cast<const uint32_t*>(f.g_bits)[u >> 5] >> (u & 31)) & 1u;
 }
 
 // Summary bits of bitmap words [from rounded down to 64, 64 * sum_words)
@@ -250,12 +265,22 @@ __device__ __forceinline__ bool fb_test(const FbView& f, int32_t u) {
 // ends it with a barrier.
 __device__ __forceinline__ void build_summary(uint64_t* s_sum, const uint64_t* g_bits, int32_t words, int32_t from,
                                               int32_t sum_words) {
+    // eight words per lane in flight before their ballots
+    constexpr int kAhead = 8;
     const int lane = threadIdx.x & (kWave - 1);
     const int32_t nw = blockDim.x / kWave;
-    for (int32_t c = (from >> 6) + (int32_t)(threadIdx.x / kWave); c < sum_words; c += nw) {
-        const int32_t i = c * kWave + lane;
-        const uint64_t m = __ballot(i < words && g_bits[i] != 0ull);
-        if (lane == 0) s_sum[c] = m;
+    for (int32_t c0 = (from >> 6) + (int32_t)(threadIdx.x / kWave); c0 < sum_words; c0 += kAhead * nw) {
+        uint64_t v[kAhead];
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) {
+            const int32_t c = c0 + k * nw, i = c * kWave + lane;
+            v[k] = (c < sum_words && i < words) ? g_bits[i] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) {
+            const uint64_t m = __ballot(v[k] != 0ull);
+            if (lane == 0 && c0 + k * nw < sum_words) s_sum[c0 + k * nw] = m;
+        }
     }
 }
 
@@ -876,7 +901,7 @@ __device__ __forceinline__ void level_bottom_up_stream(const BfsArgs& a, int32_t
 // lvl_arg >= 0 names the level; -1 takes it from the header (lv[parity]).
 __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_arg, int32_t parity, int32_t policy,
                                                           float alpha, float beta) {
-    extern __shared__ uint64_t s_bits[];
+    extern __shared__ __align__(16) uint64_t s_bits[];  // staged with 16-byte stores
     __shared__ WaveLds s_wave;
     BfsHdr* h = a.hdr;
     // the three slots are read in the same round trip as the level index
@@ -975,7 +1000,7 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
 // Two workgroups per compute unit: 32 wavefronts, 8 per SIMD, which caps the
 // kernel at 64 VGPRs (the second bound is the minimum wavefronts per SIMD).
 __global__ __launch_bounds__(kBfsBlock, 8) void k_bfs_chunks(BfsArgs a) {
-    extern __shared__ uint64_t s_bits[];
+    extern __shared__ __align__(16) uint64_t s_bits[];  // staged with 16-byte stores
     BfsHdr* h = a.hdr;
     // slot fields read in the same round trip as the level index
     int32_t bigs[3], dirs[3], ns[3];
