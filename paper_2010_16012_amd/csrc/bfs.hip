@@ -137,6 +137,10 @@ struct BfsArgs {
     int32_t n;
     int64_t nnz;
     int32_t words;
+    // bitmap words that hold every vertex with an in-edge: only those can be
+    // discovered, so bottom-up levels (and frontiers read from a bitmap,
+    // which hold discovered vertices) stop there
+    int32_t act_words;
     int32_t page_cap;
     int32_t item_cap;
     int32_t stage_words;    // bitmap words a workgroup may stage in LDS
@@ -171,6 +175,7 @@ static BfsArgs bfs_args(pp_graph g, void* state, int32_t* level, int32_t* parent
     a.n = g->d.n;
     a.nnz = g->d.nnz;
     a.words = L.words;
+    a.act_words = ceil_div(g->in_active, 64);
     a.page_cap = L.page_cap;
     a.item_cap = L.item_cap;
     a.stage_words = L.stage_words;
@@ -634,7 +639,7 @@ __device__ __forceinline__ void level_top_down(const BfsArgs& a, const TdCtx& cx
     const int32_t gwave = blockIdx.x * kBfsWaves + threadIdx.x / kWave;
     const int32_t nwaves = gridDim.x * kBfsWaves;
     if (by_bitmap) {
-        for (int32_t unit = gwave; unit < a.words; unit += nwaves) {
+        for (int32_t unit = gwave; unit < a.act_words; unit += nwaves) {
             const uint64_t word = fb_cur[unit];
             if (word == 0) continue;
             td_unit(a, cx, sl, pg, ((word >> lane) & 1ull) ? unit * kWave + lane : -1, cnt, deg);
@@ -709,7 +714,7 @@ __device__ __forceinline__ void level_bottom_up(const BfsArgs& a, int32_t lvl, c
     const int lane = threadIdx.x & (kWave - 1);
     const int32_t gwave = blockIdx.x * kBfsWaves + threadIdx.x / kWave;
     const int32_t nwaves = gridDim.x * kBfsWaves;
-    for (int32_t w = gwave; w < a.words; w += nwaves) {
+    for (int32_t w = gwave; w < a.act_words; w += nwaves) {
         const uint64_t vis = a.visited[w];
         const int32_t v = w * kWave + lane;
         const bool unvisited = (v < a.n) && !((vis >> lane) & 1ull);

@@ -279,19 +279,22 @@ __global__ void k_gather_weights(int64_t nnz, const float* __restrict__ csr_w, c
 __global__ void k_max_deg(int32_t n, const int32_t* __restrict__ off, const int32_t* __restrict__ in_off,
                           int32_t* __restrict__ out) {
     const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t a = 0, b = 0;
+    int32_t a = 0, b = 0, c = 0;  // c: v + 1 for a vertex with in-edges
     if (v < n) {
         a = row_len(off, v);
         b = row_len(in_off, v);
+        c = (b > 0) ? v + 1 : 0;
     }
 #pragma unroll
     for (int s = 32; s > 0; s >>= 1) {
         a = max(a, __shfl_xor(a, s));
         b = max(b, __shfl_xor(b, s));
+        c = max(c, __shfl_xor(c, s));
     }
     if ((threadIdx.x & 63) == 0) {
         atomicMax(&out[0], a);
         atomicMax(&out[1], b);
+        atomicMax(&out[2], c);
     }
 }
 
@@ -1069,13 +1072,13 @@ PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_o
                        d.csc_off, d.csc_row);
     hipLaunchKernelGGL(k_degrees, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, d.csr_off, d.csr_w, d.out_deg,
                        d.inv_s);
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, 2, d.err + 48);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, 3, d.err + 48);
     hipLaunchKernelGGL(k_max_deg, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, d.csr_off, d.csc_off, d.err + 48);
     {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(hip_error(e, "graph degree kernels"));
     }
-    int32_t maxd[2];
+    int32_t maxd[3];
     {
         hipError_t e = hipMemcpyAsync(maxd, d.err + 48, sizeof(maxd), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1083,6 +1086,7 @@ PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_o
     }
     g->max_out_deg = maxd[0];
     g->max_in_deg = maxd[1];
+    g->in_active = maxd[2];
     {
         int dev = 0, cus = 0, lds = 0, lds_cu = 0;
         hipError_t e = hipGetDevice(&dev);

@@ -249,6 +249,9 @@ struct pp_graph_s {
     int32_t split_cap;           // capacity of each split table
     int32_t max_out_deg;
     int32_t max_in_deg;
+    // every vertex with an in-edge lies below this id (after degree
+    // relabelling, the vertices without in-edges form the tail of the ids)
+    int32_t in_active;
     int32_t num_cu;              // compute units of the device the graph lives on
     int32_t max_lds;             // LDS bytes one workgroup may allocate
     int32_t lds_per_cu;          // LDS bytes of one compute unit

@@ -52,6 +52,24 @@ def _check_graph(g, host, roots, policies, fast):
             assert st.edges_reached == int(deg[want >= 0].sum())
 
 
+def test_vertices_without_in_edges():
+    # Bottom-up levels (and frontiers read from a bitmap) stop at the last
+    # bitmap word that holds a vertex with an in-edge: vertices past it can
+    # never be discovered.  Directed graph: 300 sources with out-edges only,
+    # 700 isolated vertices, and a 3,000-vertex random core the sources
+    # point into; roots among the sources (in-degree 0, so past that word
+    # after relabelling), isolated, and in the core, under every policy.
+    rng = np.random.default_rng(7)
+    core = H.random_graph(3000, 12000, 21, symmetric=False, connected=True)
+    n = 3000 + 300 + 700
+    src = [np.repeat(np.arange(core.n), np.diff(core.off)), 3000 + np.repeat(np.arange(300), 20)]
+    dst = [core.idx, rng.integers(0, 3000, 300 * 20)]
+    host = gg.from_edges(n, np.concatenate(src), np.concatenate(dst), False, "sources_core_isolated")
+    host.ensure_transpose()
+    assert np.diff(host.in_off)[3000:].max() == 0
+    _check(host, [3000, 3299, 3400, n - 1, 0, 2999])
+
+
 @pytest.mark.parametrize("maker", [lambda: H.path(300), lambda: H.star(100), lambda: H.cycle(129),
                                    lambda: H.complete(12), lambda: H.full_grid(20, 33)],
                          ids=["path", "star", "cycle", "K12", "grid"])
