@@ -177,30 +177,39 @@ typedef int32_t i32x2 __attribute__((ext_vector_type(2)));  // non-temporal load
 // Binned push, second kernel: unit k sums the pairs of bin units[3k] written
 // by workgroups [units[3k+1], units[3k+2]) into an LDS accumulator of the
 // bin's kPushBinW targets (LDS float atomics), then writes it out whole as
-// the unit's partial.
+// the unit's partial.  Each wavefront sums whole slices (wavefront j takes
+// slices w0 + j, w0 + j + 16, ...): a slice holds about a thousand pairs,
+// so a workgroup working through one slice at a time left most lanes idle
+// and waited a round trip per slice.  The slice bounds are read through
+// scalar loads.
 __global__ __launch_bounds__(1024) void k_pr_push_bins(int32_t nbins, const int32_t* __restrict__ units,
                                                        const int32_t* __restrict__ base,
                                                        const int32_t* __restrict__ fill,
                                                        const int2* __restrict__ pairs, float* __restrict__ part) {
     extern __shared__ float acc[];
     const int32_t k = blockIdx.x;
-    const int32_t b = units[3 * k], w0 = units[3 * k + 1], w1 = units[3 * k + 2];
+    const int32_t b = uniform_load(units, 3 * k), w0 = uniform_load(units, 3 * k + 1),
+                  w1 = uniform_load(units, 3 * k + 2);
     const int32_t bd = blockDim.x;
     for (int32_t i = threadIdx.x; i < kPushBinW; i += bd) acc[i] = 0.f;
     __syncthreads();
-    for (int32_t w = w0; w < w1; ++w) {
-        const int32_t lo = base[(size_t)w * nbins + b], cnt = fill[(size_t)w * nbins + b];
-        for (int32_t i = threadIdx.x; i < cnt; i += 4 * bd) {
-            int2 e[4];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int32_t nwv = bd / kWave;
+    constexpr int kR = 4;  // pair loads in flight per lane
+    for (int32_t w = w0 + wv; w < w1; w += nwv) {
+        const int32_t lo = uniform_load(base + (size_t)w * nbins, b), cnt = uniform_load(fill + (size_t)w * nbins, b);
+        for (int32_t i = lane; i < cnt; i += kR * kWave) {
+            int2 e[kR];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+            for (int r = 0; r < kR; ++r) {
                 const i32x2 q = __builtin_nontemporal_load(reinterpret_cast<const i32x2*>(pairs) +
-                                                           (lo + min(i + r * bd, cnt - 1)));
+                                                           (lo + min(i + r * kWave, cnt - 1)));
                 e[r] = make_int2(q.x, q.y);
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (i + r * bd < cnt) atomicAdd(&acc[e[r].x & (kPushBinW - 1)], __int_as_float(e[r].y));
+            for (int r = 0; r < kR; ++r)
+                if (i + r * kWave < cnt) atomicAdd(&acc[e[r].x & (kPushBinW - 1)], __int_as_float(e[r].y));
         }
     }
     __syncthreads();
