@@ -35,6 +35,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 
 #include "pp_common.h"
 
@@ -1493,10 +1494,14 @@ static pp_status bfs_graph(pp_graph g, BfsArgs a, int32_t policy, float alpha, f
     return PP_OK;
 }
 
+// Through the graph's pinned buffer: a direct copy, no staging.
 static pp_status read_hdr(pp_graph g, void* state, BfsHdr* h, hipStream_t st) {
+    static_assert(sizeof(BfsHdr) <= pp_graph_s::kBfsHdrHost, "pinned header buffer too small");
     const BfsLayout L = bfs_layout(g);
-    PP_HIP(hipMemcpyAsync(h, static_cast<char*>(state) + L.hdr, sizeof(BfsHdr), hipMemcpyDeviceToHost, st));
+    PP_HIP(hipMemcpyAsync(g->bfs_hdr_host, static_cast<char*>(state) + L.hdr, sizeof(BfsHdr), hipMemcpyDeviceToHost,
+                          st));
     PP_HIP(hipStreamSynchronize(st));
+    std::memcpy(h, g->bfs_hdr_host, sizeof(BfsHdr));
     if (h->overflow) return set_error(PP_E_WORKSPACE, "BFS queue capacity exceeded");
     return PP_OK;
 }

@@ -1109,6 +1109,10 @@ PP_EXPORT pp_status pp_graph_create(int32_t n, int64_t nnz, const int32_t* csr_o
     if (s != PP_OK) return fail(s);
     s = build_slices(g, L, base, st);
     if (s != PP_OK) return fail(s);
+    {
+        const hipError_t e = hipHostMalloc(&g->bfs_hdr_host, pp_graph_s::kBfsHdrHost, hipHostMallocDefault);
+        if (e != hipSuccess) return fail(hip_error(e, "pinned BFS header buffer"));
+    }
     if (d.pb_base) {
         s = build_push_bins(g, st);
         if (s != PP_OK) return fail(s);

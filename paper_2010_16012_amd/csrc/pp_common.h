@@ -271,6 +271,10 @@ struct pp_graph_s {
         hipGraph_t graph;
     };
     std::vector<BfsGraph> bfs_graphs;
+    // pinned host buffer a BFS run reads its state header into (a copy to
+    // pageable memory goes through a staging buffer: slower per run)
+    static constexpr size_t kBfsHdrHost = 4096;
+    void* bfs_hdr_host = nullptr;
     // level-kernel launches that found a frontier, per policy, over the last
     // kBfsHist runs on this graph (their maximum sizes a run's first batch)
     static constexpr int kBfsHist = 8;
@@ -281,6 +285,7 @@ struct pp_graph_s {
             (void)hipGraphExecDestroy(e.exec);
             (void)hipGraphDestroy(e.graph);
         }
+        if (bfs_hdr_host) (void)hipHostFree(bfs_hdr_host);
     }
 };
 
