@@ -372,9 +372,8 @@ def main():
                 d = {"pr_pull": pp.PP_PULL, "pr_push": pp.PP_PUSH, "pr_hybrid": pp.PP_SWITCH}[p]
                 pp.pagerank_into(g, x, PR_ITERS, F, d)
             else:
-                r = runs[p]
-                for root in roots:
-                    r.run(int(root), policy[p], alpha, beta)
+                # every root in turn on the device, one host wait for all
+                runs[p].run_many(roots, policy[p], alpha, beta)
             e1 = ev()
             times.setdefault(p, []).append((e0, e1))
 

@@ -289,6 +289,21 @@ pp_status pp_bfs_run_log(pp_graph g, int32_t root, pp_dir policy, float alpha, f
                          int32_t* level, int32_t* parent, void* state, size_t state_bytes,
                          pp_bfs_level* log, int32_t log_cap, pp_bfs_stats* stats, void* stream);
 
+/* pp_bfs_run from each of the k roots (HOST array) in turn, without a host
+ * wait between them: every root's run goes to the device back to back (its
+ * level batch sized from the recent runs with the policy on this graph) and
+ * the host reads all the run headers after one wait.  A root whose run was
+ * deeper than its batch is run again on its own, so the results are those of
+ * pp_bfs_run.  stats[i] (HOST, k entries) describes the run from roots[i];
+ * level and parent (n each, caller ids) hold the run from roots[k-1] when
+ * the call returns.  The first call with a policy on a graph runs its first
+ * root on its own to size the batches; graphs of more than 256 levels go
+ * root by root.  Every root is checked before anything is launched
+ * (PP_E_RANGE).  k = 0 does nothing.  SYNC. */
+pp_status pp_bfs_run_many(pp_graph g, int32_t k, const int32_t* roots, pp_dir policy, float alpha, float beta,
+                          int32_t* level, int32_t* parent, void* state, size_t state_bytes,
+                          pp_bfs_stats* stats, void* stream);
+
 /* ------------------------------------------------------ personalised PR */
 /* Scratch bytes for pp_ppr_run / pp_ppr_adjoint with k columns processed in
  * tiles of k_tile (pp_ppr_run also takes k_tile = 1; 0 when an argument is

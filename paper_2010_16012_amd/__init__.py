@@ -135,6 +135,12 @@ class BfsRun:
     def run(self, root, policy=PP_SWITCH, alpha=14.0, beta=24.0, stream=None) -> BfsStats:
         return _lib.pp_bfs_run(self.g.handle, root, policy, alpha, beta, self.level, self.parent, self.state, stream)
 
+    def run_many(self, roots, policy=PP_SWITCH, alpha=14.0, beta=24.0, stream=None):
+        """``run`` from every root in turn with one host wait (per-root
+        stats; level and parent hold the last root's run)."""
+        return _lib.pp_bfs_run_many(self.g.handle, roots, policy, alpha, beta, self.level, self.parent, self.state,
+                                    stream)
+
     def run_logged(self, root, policy=PP_SWITCH, alpha=14.0, beta=24.0, stream=None):
         """``run`` with the whole per-level log: returns (stats, dirs, n_f, m_f),
         one entry per expanded frontier (numpy arrays)."""

@@ -79,6 +79,8 @@ _SIGS = {
     "pp_bfs_run": ([_P, _I32, ctypes.c_int, _F32, _F32, _P, _P, _P, _SZ, ctypes.POINTER(BfsStats), _P], ctypes.c_int),
     "pp_bfs_run_log": ([_P, _I32, ctypes.c_int, _F32, _F32, _P, _P, _P, _SZ, _P, _I32, ctypes.POINTER(BfsStats), _P],
                        ctypes.c_int),
+    "pp_bfs_run_many": ([_P, _I32, _P, ctypes.c_int, _F32, _F32, _P, _P, _P, _SZ, ctypes.POINTER(BfsStats), _P],
+                        ctypes.c_int),
     "pp_ppr_scratch_bytes": ([_P, _I32, _I32], _SZ),
     "pp_multi_workspace_bytes": ([_I32, _I64], _SZ),
     "pp_multi_run": ([_I32, _P, _P, _P, _P, _P, _P, ctypes.c_int, _I32, _F32, _P, _I32, _I32, _F32, _F32, _P, _P, _P,
@@ -235,6 +237,15 @@ def pp_bfs_run(h, root, policy, alpha, beta, level, parent, state, stream=None) 
     _check(_lib.pp_bfs_run(h, root, policy, alpha, beta, _ptr(level), _ptr(parent), _ptr(state), state.numel(),
                            ctypes.byref(st), _stream(stream)))
     return st
+
+
+def pp_bfs_run_many(h, roots, policy, alpha, beta, level, parent, state, stream=None):
+    import numpy as np
+    r = np.ascontiguousarray(roots, dtype=np.int32)
+    stats = (BfsStats * max(len(r), 1))()
+    _check(_lib.pp_bfs_run_many(h, len(r), r.ctypes.data_as(ctypes.c_void_p), policy, alpha, beta, _ptr(level),
+                                _ptr(parent), _ptr(state), state.numel(), stats, _stream(stream)))
+    return list(stats)[:len(r)]
 
 
 def pp_set_pull_slices(rows: int, width: int) -> None:

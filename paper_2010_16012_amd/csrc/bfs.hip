@@ -1563,6 +1563,33 @@ PP_EXPORT pp_status pp_bfs_run(pp_graph g, int32_t root, pp_dir policy, float al
     return pp_bfs_run_log(g, root, policy, alpha, beta, level, parent, state, state_bytes, nullptr, 0, stats, stream);
 }
 
+// A run's batches of levels: the first covers the most level-kernel launches
+// that found work in the recent runs with the policy on the graph (0: none
+// yet); batches are even (level kernels of parity 0, 1, 0, ...).
+constexpr int32_t kBfsMaxBatch = 256;  // deep graphs (grids) take long batches
+static int32_t bfs_even(int32_t b) { return std::min(kBfsMaxBatch, std::max<int32_t>(2, (b + 1) & ~1)); }
+static int32_t bfs_predicted(pp_graph g, int32_t policy) {
+    int32_t p = 0;
+    for (int i = 0; i < pp_graph_s::kBfsHist; ++i) p = std::max(p, g->bfs_hist[policy][i]);
+    return p;
+}
+static void bfs_record(pp_graph g, int32_t policy, int32_t busy) {
+    g->bfs_hist[policy][g->bfs_hist_pos[policy]] = busy;
+    g->bfs_hist_pos[policy] = (g->bfs_hist_pos[policy] + 1) % pp_graph_s::kBfsHist;
+}
+// The run is over when the newest frontier is empty (or a level kernel found
+// it so).
+static bool bfs_done(const BfsHdr& h) { return h.finished || h.slot[h.last % 3].n == 0; }
+static void bfs_fill_stats(const BfsHdr& h, pp_bfs_stats* stats) {
+    stats->levels = h.levels;
+    stats->reached = (int32_t)h.reached;
+    stats->edges_reached = h.edges;
+    for (int i = 0; i < PP_BFS_MAX_LOG; ++i) {
+        stats->dir[i] = (i < h.levels) ? h.log_dir[i] : (int8_t)-1;
+        stats->frontier[i] = (i < h.levels) ? h.log_n[i] : 0;
+    }
+}
+
 PP_EXPORT pp_status pp_bfs_run_log(pp_graph g, int32_t root, pp_dir policy, float alpha, float beta, int32_t* level,
                                    int32_t* parent, void* state, size_t state_bytes, pp_bfs_level* log,
                                    int32_t log_cap, pp_bfs_stats* stats, void* stream) {
@@ -1587,13 +1614,8 @@ PP_EXPORT pp_status pp_bfs_run_log(pp_graph g, int32_t root, pp_dir policy, floa
     // covers the most level-kernel launches that found work in the recent
     // runs with this policy on this graph, so a run of similar depth needs
     // one host read; a deeper run goes on in batches of 2, 4, 8, ...
-    static constexpr int32_t kMaxBatch = 256;  // deep graphs (grids) take long batches
-    int32_t* hist = g->bfs_hist[policy];
-    int32_t predicted = 0;
-    for (int i = 0; i < pp_graph_s::kBfsHist; ++i) predicted = std::max(predicted, hist[i]);
-    // batches are even (level kernels of parity 0, 1, 0, ...)
-    auto even = [](int32_t b) { return std::min(kMaxBatch, std::max<int32_t>(2, (b + 1) & ~1)); };
-    int32_t batch = predicted > 0 ? even(predicted) : 4;
+    const int32_t predicted = bfs_predicted(g, policy);
+    int32_t batch = predicted > 0 ? bfs_even(predicted) : 4;
     int32_t extra = 2;
     int32_t launched = 0;
     const int32_t max_levels = g->d.n + 1;  // at most n non-empty frontiers, then an empty one
@@ -1613,24 +1635,99 @@ PP_EXPORT pp_status pp_bfs_run_log(pp_graph g, int32_t root, pp_dir policy, floa
         }
         s = read_hdr(g, state, &h, st);
         if (s != PP_OK) return s;
-        if (h.finished || h.slot[h.last % 3].n == 0 || launched >= max_levels) break;
+        if (bfs_done(h) || launched >= max_levels) break;
         if (launched < predicted) {
-            batch = even(predicted - launched);
+            batch = bfs_even(predicted - launched);
         } else {
-            batch = even(extra);
-            extra = std::min(extra * 2, kMaxBatch);
+            batch = bfs_even(extra);
+            extra = std::min(extra * 2, kBfsMaxBatch);
         }
     }
-    hist[g->bfs_hist_pos[policy]] = h.busy;
-    g->bfs_hist_pos[policy] = (g->bfs_hist_pos[policy] + 1) % pp_graph_s::kBfsHist;
-    if (stats) {
-        stats->levels = h.levels;
-        stats->reached = (int32_t)h.reached;
-        stats->edges_reached = h.edges;
-        for (int i = 0; i < PP_BFS_MAX_LOG; ++i) {
-            stats->dir[i] = (i < h.levels) ? h.log_dir[i] : (int8_t)-1;
-            stats->frontier[i] = (i < h.levels) ? h.log_n[i] : 0;
+    bfs_record(g, policy, h.busy);
+    if (stats) bfs_fill_stats(h, stats);
+    return PP_OK;
+}
+
+// Many roots, one after another on the device: each root's init, one batch
+// of levels sized from the history and a copy of its header go out back to
+// back, and the host reads all the headers after one wait.  A root whose
+// batch fell short is run again on its own.
+PP_EXPORT pp_status pp_bfs_run_many(pp_graph g, int32_t k, const int32_t* roots, pp_dir policy, float alpha,
+                                    float beta, int32_t* level, int32_t* parent, void* state, size_t state_bytes,
+                                    pp_bfs_stats* stats, void* stream) {
+    clear_error();
+    if (!g) return set_error(PP_E_NULL, "graph handle is NULL");
+    if (k < 0) return set_error(PP_E_RANGE, "k must be >= 0");
+    if (policy != PP_PUSH && policy != PP_PULL && policy != PP_SWITCH)
+        return set_error(PP_E_RANGE, "policy must be PP_PUSH, PP_PULL or PP_SWITCH");
+    if (k == 0) return PP_OK;
+    if (!roots || !stats) return set_error(PP_E_NULL, "roots and stats are required");
+    for (int32_t i = 0; i < k; ++i)
+        if (roots[i] < 0 || roots[i] >= g->d.n) return set_error(PP_E_RANGE, "root out of range");
+    pp_status s = check_state(g, state, state_bytes);
+    if (s != PP_OK) return s;
+    if (!level || !parent) return set_error(PP_E_NULL, "level and parent are required");
+    if (!(alpha > 0.f)) alpha = 14.f;
+    if (!(beta > 0.f)) beta = 24.f;
+    auto one = [&](int32_t i) {
+        return pp_bfs_run_log(g, roots[i], policy, alpha, beta, level, parent, state, state_bytes, nullptr, 0,
+                              &stats[i], stream);
+    };
+    int32_t i0 = 0;
+    if (bfs_predicted(g, policy) == 0) {  // the first run with this policy sets the batch size
+        s = one(0);
+        if (s != PP_OK) return s;
+        i0 = 1;
+    }
+    // two levels more than the deepest recent run: an empty level pair costs
+    // a few microseconds, a root run again costs its whole run
+    const int32_t predicted = bfs_predicted(g, policy);
+    const int32_t batch = bfs_even(predicted + 2);
+    if (batch > g->d.n + 1 || predicted >= kBfsMaxBatch) {  // tiny or deep graphs: root by root
+        for (int32_t i = i0; i < k; ++i) {
+            s = one(i);
+            if (s != PP_OK) return s;
+        }
+        return PP_OK;
+    }
+    const size_t need = (size_t)(k - i0) * sizeof(BfsHdr);
+    if (need > g->bfs_hdrs_cap) {
+        if (g->bfs_hdrs_host) (void)hipHostFree(g->bfs_hdrs_host);
+        g->bfs_hdrs_host = nullptr;
+        g->bfs_hdrs_cap = 0;
+        PP_HIP(hipHostMalloc(&g->bfs_hdrs_host, need, hipHostMallocDefault));
+        g->bfs_hdrs_cap = need;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const BfsArgs a = bfs_args(g, state, level, parent);
+    hipGraphExec_t exec = nullptr;
+    s = bfs_graph(g, a, policy, alpha, beta, batch, state, &exec);
+    if (s != PP_OK) return s;
+    const char* hdr_dev = static_cast<const char*>(state) + bfs_layout(g).hdr;
+    BfsHdr* hdrs = static_cast<BfsHdr*>(g->bfs_hdrs_host);
+    for (int32_t i = i0; i < k; ++i) {
+        s = pp_bfs_init(g, roots[i], level, parent, state, state_bytes, stream);
+        if (s != PP_OK) return s;
+        PP_HIP(hipGraphLaunch(exec, st));
+        PP_HIP(hipMemcpyAsync(hdrs + (i - i0), hdr_dev, sizeof(BfsHdr), hipMemcpyDeviceToHost, st));
+    }
+    PP_HIP(hipStreamSynchronize(st));
+    bool again = false, last_again = false;
+    for (int32_t i = i0; i < k; ++i) {
+        BfsHdr h;
+        std::memcpy(&h, hdrs + (i - i0), sizeof(BfsHdr));
+        if (h.overflow) return set_error(PP_E_WORKSPACE, "BFS queue capacity exceeded");
+        if (bfs_done(h)) {
+            bfs_record(g, policy, h.busy);
+            bfs_fill_stats(h, &stats[i]);
+        } else {
+            s = one(i);
+            if (s != PP_OK) return s;
+            again = true;
+            last_again = (i == k - 1);
         }
     }
+    // level and parent hold the last root's run
+    if (again && !last_again) return one(k - 1);
     return PP_OK;
 }

@@ -275,9 +275,11 @@ struct pp_graph_s {
     // pageable memory goes through a staging buffer: slower per run)
     static constexpr size_t kBfsHdrHost = 4096;
     void* bfs_hdr_host = nullptr;
+    void* bfs_hdrs_host = nullptr;  // pinned headers of pp_bfs_run_many (grown on demand)
+    size_t bfs_hdrs_cap = 0;
     // level-kernel launches that found a frontier, per policy, over the last
     // kBfsHist runs on this graph (their maximum sizes a run's first batch)
-    static constexpr int kBfsHist = 8;
+    static constexpr int kBfsHist = 64;
     int32_t bfs_hist[3][kBfsHist] = {};
     int32_t bfs_hist_pos[3] = {};
     ~pp_graph_s() {
@@ -286,6 +288,7 @@ struct pp_graph_s {
             (void)hipGraphDestroy(e.graph);
         }
         if (bfs_hdr_host) (void)hipHostFree(bfs_hdr_host);
+        if (bfs_hdrs_host) (void)hipHostFree(bfs_hdrs_host);
     }
 };
 

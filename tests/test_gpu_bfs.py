@@ -309,3 +309,44 @@ def test_multi_level_launch_budget_and_retake():
         assert H.bfs_violations_fast(host, 0, lv, par) == []
         assert st.levels == nlev == 40000
         assert np.all(dirs == pp.PP_PUSH) and np.all(nf == 1)
+
+
+def _core_and_path():
+    """A connected random core (depth ~10) and, as a component of its own, a
+    60-vertex path (depth up to 59)."""
+    core = H.random_graph(3000, 9000, 31, symmetric=True, connected=True)
+    src = [np.repeat(np.arange(core.n), np.diff(core.off)), 3000 + np.arange(59)]
+    dst = [core.idx, 3001 + np.arange(59)]
+    host = gg.from_edges(3060, np.concatenate(src), np.concatenate(dst), True, "core_and_path")
+    return host
+
+
+@pytest.mark.parametrize("pol,name", list(zip(POLICIES, POL_IDS)), ids=POL_IDS)
+def test_run_many_matches_run(pol, name):
+    # Many roots with one host wait: each root's statistics are those of a
+    # run on its own, and level/parent hold the last root's run.  The first
+    # call runs its first root alone to size the batches; the path roots are
+    # deeper than that batch and run again on their own (also as the last
+    # root).
+    host = _core_and_path()
+    g = pp.Graph(host)
+    core = [5, 900, 2999, 17]
+    for roots in (core + [3000, 3030], core + [3059], [3059, 3000] + core, core):
+        announce(f"BFS run_many {name} roots={roots}")
+        r = pp.BfsRun(g)
+        many = r.run_many(roots, pol)
+        torch.cuda.synchronize()
+        lv, par = r.level.cpu().numpy(), r.parent.cpu().numpy()
+        want, _, nlev = oracle.bfs(host.off, host.idx, roots[-1])
+        assert np.array_equal(lv, want)
+        assert H.bfs_violations(host, roots[-1], lv, par) == []
+        for root, st in zip(roots, many):
+            one = pp.BfsRun(g).run(root, pol)
+            _, _, nl = oracle.bfs(host.off, host.idx, root)
+            assert st.levels == one.levels == nl
+            assert st.reached == one.reached and st.edges_reached == one.edges_reached
+            assert list(st.dir[:st.levels]) == list(one.dir[:one.levels])
+            assert list(st.frontier[:st.levels]) == list(one.frontier[:one.levels])
+    assert pp.BfsRun(g).run_many([], pol) == []
+    with pytest.raises(pp.PPError):
+        pp.BfsRun(g).run_many([0, host.n], pol)
