@@ -266,7 +266,10 @@ pp_status pp_bfs_frontier(pp_graph g, void* state, int32_t* size, void* stream);
  * frontier shrinks (m_f: out-edges of the frontier, m_u: out-edges of
  * unvisited vertices, n_f: frontier size).  alpha, beta > 0 (defaults 14, 24
  * when <= 0 is passed).  Levels do not depend on the policy; parents are
- * any valid BFS parents.  stats: host, nullable.  SYNC. */
+ * any valid BFS parents.  stats: host, nullable.  SYNC.  The graph keeps the
+ * recent runs' level counts, the instantiated level batches and a pinned
+ * header buffer: BFS calls on one graph must not overlap across host
+ * threads. */
 pp_status pp_bfs_run(pp_graph g, int32_t root, pp_dir policy, float alpha, float beta,
                      int32_t* level, int32_t* parent, void* state, size_t state_bytes,
                      pp_bfs_stats* stats, void* stream);
