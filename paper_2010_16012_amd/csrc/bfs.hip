@@ -798,9 +798,13 @@ __device__ __forceinline__ void level_bottom_up(const BfsArgs& a, int32_t lvl, c
 constexpr int kStreamQ = 8;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // a native vector: non-temporal loads take it
 
-__device__ __forceinline__ void level_bottom_up_stream(const BfsArgs& a, int32_t lvl, const FbView& fv, WaveLds& sl,
-                                                       int32_t* q_next, int32_t* fill_next, uint64_t* fb_next,
-                                                       BfsSlot* nxt, int32_t& cnt, int64_t& deg, Pager& pg) {
+// SINGLE: the frontier is one vertex, `single` (the root at level 0), so a
+// test is one compare (no bitmap, staged or not).
+template <bool SINGLE>
+__device__ __forceinline__ void level_bottom_up_stream(const BfsArgs& a, int32_t lvl, const FbView& fv, int32_t single,
+                                                       WaveLds& sl, int32_t* q_next, int32_t* fill_next,
+                                                       uint64_t* fb_next, BfsSlot* nxt, int32_t& cnt, int64_t& deg,
+                                                       Pager& pg) {
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
     const int64_t gwave = blockIdx.x * kBfsWaves + w;
@@ -866,7 +870,7 @@ __device__ __forceinline__ void level_bottom_up_stream(const BfsArgs& a, int32_t
             const int32_t s4[4] = {(int32_t)v[r].x, (int32_t)v[r].y, (int32_t)v[r].z, (int32_t)v[r].w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                hit[r][j] = (s4[j] >= 0) && fb_test(fv, s4[j]);
+                hit[r][j] = (s4[j] >= 0) && (SINGLE ? s4[j] == single : fb_test(fv, s4[j]));
                 any = any || hit[r][j];
             }
         }
@@ -891,7 +895,7 @@ __device__ __forceinline__ void level_bottom_up_stream(const BfsArgs& a, int32_t
         bool any = false;
 #pragma unroll
         for (int r = 0; r < kStreamU; ++r) {
-            hit[r] = (u[r] >= 0) && fb_test(fv, u[r]);
+            hit[r] = (u[r] >= 0) && (SINGLE ? u[r] == single : fb_test(fv, u[r]));
             any = any || hit[r];
         }
         if (__ballot(any) == 0) continue;
@@ -978,17 +982,25 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
         level_top_down(a, cx, s_wave, a.queue[lvl & 1], a.fill[lvl & 1], (cur.dir_prev == PP_PULL) ? 0 : a.static_pages,
                        min(cur.pages, a.page_cap), a.fb[sc], nf > a.words, cnt, deg, pg);
     } else {
-        // the summary pays on large levels only (each workgroup builds it)
-        const bool sum = sw && use_summary(a, nf);
-        uint64_t* s_sum = s_bits + a.stage_words;
-        if (sum) build_summary(s_sum, a.fb[sc], a.words, sw, a.sum_words);
-        if (sw) stage_bits(s_bits, a.fb[sc], sw);
-        const FbView fv{s_bits, sw, s_sum, sum ? min(a.words, a.sum_words * kWave) : 0, a.fb[sc]};
         // a sparse frontier while most in-edges still belong to unvisited
         // vertices: stream the in-edge array instead of scanning row by row
         // (its hits, the frontier's out-edges, must stay few)
-        if ((int64_t)nf * 8 < a.words && 2 * mu >= a.nnz && 256 * cur.m <= a.nnz)
-            level_bottom_up_stream(a, lvl, fv, s_wave, q_next, fill_next, a.fb[sn], &h->slot[sn], cnt, deg, pg);
+        const bool stream = (int64_t)nf * 8 < a.words && 2 * mu >= a.nnz && 256 * cur.m <= a.nnz;
+        // level 0: the frontier is the root alone, nothing to stage
+        const int32_t single = (lvl == 0 && stream) ? h->root : -1;
+        const int32_t sws = (single < 0) ? sw : 0;
+        // the summary pays on large levels only (each workgroup builds it)
+        const bool sum = sws && use_summary(a, nf);
+        uint64_t* s_sum = s_bits + a.stage_words;
+        if (sum) build_summary(s_sum, a.fb[sc], a.words, sws, a.sum_words);
+        if (sws) stage_bits(s_bits, a.fb[sc], sws);
+        const FbView fv{s_bits, sws, s_sum, sum ? min(a.words, a.sum_words * kWave) : 0, a.fb[sc]};
+        if (single >= 0)
+            level_bottom_up_stream<true>(a, lvl, fv, single, s_wave, q_next, fill_next, a.fb[sn], &h->slot[sn], cnt,
+                                         deg, pg);
+        else if (stream)
+            level_bottom_up_stream<false>(a, lvl, fv, -1, s_wave, q_next, fill_next, a.fb[sn], &h->slot[sn], cnt,
+                                          deg, pg);
         else
             level_bottom_up(a, lvl, fv, q_next, fill_next, a.fb[sn], &h->slot[sn], cnt, deg, pg);
     }
