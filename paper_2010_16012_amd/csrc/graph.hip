@@ -773,6 +773,16 @@ static pp_status build_slices(pp_graph g, const WsLayout& L, char* base, hipStre
         sp.list_skip[b] = k;
         counts[b] = pp_.count[b] - k;
     }
+    // rows past the last one with in-edges: the list is ascending within a
+    // bin, so they are bin 0's last entries (checked entry by entry)
+    int32_t tail = std::min(n - g->in_active, counts[0]);
+    for (int32_t i = 0; i < tail; ++i)
+        if (list[pp_.list_off[0] + pp_.count[0] - tail + i] != n - tail + i) {
+            tail = 0;
+            break;
+        }
+    counts[0] -= tail;
+    sp.tail = tail;
     sp.fix0 = sp.list_skip[5];
     sp.tab0 = first[sp.fix0];
     sp.nsplit = pp_.count[5] - sp.fix0;

@@ -131,6 +131,9 @@ struct SlicePlan {
     int32_t wave_off[PP_NUM_BINS + 1] = {};
     int32_t units = 0;
     int32_t nsplit = 0;
+    // rows [n - tail, n) have no in-edges and close bin 0's list: the combine
+    // kernel gives them the teleport term instead of a wavefront unit each
+    int32_t tail = 0;
 };
 
 // Binned push (pr.hip).  Updates to targets past the privatised ones (ids >=

@@ -119,6 +119,8 @@ struct PullArgs {
     float tele;            // (1-f) added to row tele_v
     float f;
     int32_t skip_below;    // rows u < skip_below are left to the hybrid's push part (0: none)
+    int32_t tail_beg;      // rows [tail_beg, tail_end) have no in-edges and no unit:
+    int32_t tail_end;      // the tiled combine finishes them
 };
 
 // Teleport term of row u.
@@ -510,8 +512,16 @@ __global__ __launch_bounds__(1024) void k_pr_tiled(TileArgs t, PullArgs a) {
 
 // Rows [0, R): y = teleport + the S slice partials in slice order (eight
 // loads in flight) + the row's chunk partials in order, then the next
-// contribution.
+// contribution.  Blocks past those of [0, R) take the rows without in-edges
+// at the end of the id range: y = teleport term (an empty sum, as a unit of
+// the plain pull would give them).
 __global__ __launch_bounds__(256) void k_pr_tiled_combine(TileArgs t, PullArgs a) {
+    const int32_t rb = (t.R + 255) / 256;
+    if ((int32_t)blockIdx.x >= rb) {
+        const int32_t v = a.tail_beg + ((int32_t)blockIdx.x - rb) * 256 + threadIdx.x;
+        if (v < a.tail_end) pull_finish(a, v, 0.f);
+        return;
+    }
     const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= t.R) return;
     const float* p = t.part + u;
@@ -733,6 +743,9 @@ pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float
             a.list_beg[b] = pp_.list_off[b] + sl.list_skip[b];
             a.list_cnt[b] = pp_.count[b] - sl.list_skip[b];
         }
+        a.list_cnt[0] -= sl.tail;
+        a.tail_beg = g->d.n - sl.tail;
+        a.tail_end = g->d.n;
         for (int b = 0; b <= PP_NUM_BINS; ++b) a.wave_off[b] = sl.wave_off[b];
         a.units = sl.units;
         a.tab0 = sl.tab0;
@@ -762,7 +775,8 @@ pp_status launch_pull(pp_graph g, const float* c, float* c_next, float* y, float
             allow_dynamic_lds(reinterpret_cast<const void*>(&k_pr_tiled<false>), lds);
             hipLaunchKernelGGL((k_pr_tiled<false>), dim3(sl.groups), dim3(tpb), lds, st, t, a);
         }
-        hipLaunchKernelGGL(k_pr_tiled_combine, dim3(ceil_div(sl.rows, 256)), dim3(256), 0, st, t, a);
+        hipLaunchKernelGGL(k_pr_tiled_combine, dim3(ceil_div(sl.rows, 256) + ceil_div(sl.tail, 256)), dim3(256), 0,
+                           st, t, a);
         if (sl.nsplit > 0)
             hipLaunchKernelGGL(k_pr_pull_fix, dim3(ceil_div(sl.nsplit, 64)), dim3(64), 0, st, a, sl.nsplit, sl.fix0);
         PP_LAUNCH_CHECK("k_pr_tiled");

@@ -372,6 +372,40 @@ def test_tiled_pull_directed_and_split_rest_rows(seed):
     assert np.abs(got - want).sum() <= PR_L1_TOL
 
 
+def test_tiled_pull_rows_without_in_edges_at_the_end():
+    # Rows past the last vertex with in-edges get the teleport term from the
+    # combine kernel instead of a unit of the plain part.  3,000 of them have
+    # an out-edge into an R-MAT core, so their contributions feed the next
+    # step and a wrong tail value shows in the core's ranks; the rest are
+    # isolated.  Personalised runs (k_tile = 1: the same sweep) seeded on tail
+    # rows put the teleport mass there.
+    core = gg.rmat(12, 16, seed=5)
+    K, M, Z = core.n, 3000, 500
+    n = K + M + Z
+    rng = np.random.default_rng(5)
+    src = np.concatenate([np.repeat(np.arange(K), np.diff(core.off)), np.arange(K, K + M)])
+    dst = np.concatenate([core.idx, rng.integers(0, K, M)])
+    host = gg.from_edges(n, src, dst, False, "rmat12_core_plus_sources")
+    host.ensure_transpose()
+    _lib.pp_set_pull_slices(512, 256)
+    g = pp.Graph(host)
+    assert g.slices()[0] > 0
+    # the premise: in internal ids the out-only vertices follow every vertex with in-edges
+    perm = g.relabel_map().cpu().numpy().astype(np.int64)
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)
+    indeg = np.bincount(host.idx, minlength=n)
+    assert inv[K:K + M].min() > inv[indeg > 0].max()
+    announce(f"tiled pull tail rows={n - 1 - inv[indeg > 0].max()} R={g.slices()[0]}")
+    want = oracle.pagerank(host.off, host.idx, F, 20)
+    got = pr_gpu(g, pp.PP_PULL, 20).astype(np.float64)
+    assert np.abs(got - want).sum() <= PR_L1_TOL
+    seeds = np.array([K + 7, n - 1, int(np.argmax(indeg))], dtype=np.int32)
+    wantp, _ = oracle.ppr(host.off, host.idx, seeds, F, T=20)
+    X, _ = pp.ppr(g, seeds, iters=20, f=F, k_tile=1, direction=pp.PP_PULL)
+    assert np.abs(X.cpu().numpy().astype(np.float64) - wantp).sum(axis=0).max() <= 1e-6
+
+
 def test_tiled_pull_off_for_weighted_and_unrelabelled_graphs():
     host = gg.workload("rmat14")
     _lib.pp_set_pull_slices(4096, 1024)
