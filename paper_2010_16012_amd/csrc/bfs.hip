@@ -53,9 +53,9 @@ constexpr int32_t kStaticLds = 16384;  // LDS bytes kept for the kernels' own ar
 // bitmap word (set if the word is nonzero): a test of a vertex whose word is
 // empty then needs no global load.  At most kSumMax summary words (8 KB).
 constexpr int32_t kSumMax = 1024;
-// Visited words the chunk kernel's top-down items test in LDS (60 KB: two
-// workgroups of it still share a compute unit).
-constexpr int32_t kChunkStage = 7680;
+// Visited words the chunk kernel's top-down items test in LDS (120 KB; one
+// workgroup of it per compute unit).
+constexpr int32_t kChunkStage = 15360;
 
 struct BfsSlot {
     int32_t n;         // frontier size (accumulated by the level that builds it)
@@ -117,7 +117,7 @@ static BfsLayout bfs_layout(pp_graph g) {
     const int32_t waves = L.blocks * kBfsWaves;
     // the reserved pages (one per level-kernel wavefront); full pages hold at
     // most n entries; each wavefront of the level kernel and of the chunk
-    // kernel (twice as many wavefronts) leaves at most one partial page
+    // kernel (at most twice as many wavefronts) leaves at most one partial page
     L.page_cap = waves + ceil_div(n, kPage) + 3 * waves + 2;
     L.item_cap = (int32_t)std::min<int64_t>(2 * nnz / std::min(kBigRow, kBigInRow) + 64, INT32_MAX / 4);
     L.hdr = take(sizeof(BfsHdr));
@@ -181,7 +181,8 @@ static BfsArgs bfs_args(pp_graph g, void* state, int32_t* level, int32_t* parent
     a.item_cap = L.item_cap;
     a.stage_words = L.stage_words;
     a.sum_words = L.sum_words;
-    a.chunk_stage = std::min(L.words, kChunkStage);
+    // never more than the level kernel stages: the LDS allowance covers both
+    a.chunk_stage = std::min(std::min(L.words, kChunkStage), L.stage_words);
     a.static_pages = L.blocks * kBfsWaves;
     // copying costs each workgroup stage_words loads; pay it only when the
     // level has at least two edges per staged word per workgroup
@@ -1042,8 +1043,6 @@ __global__ __launch_bounds__(kBfsBlock, 8) void k_bfs_chunks(BfsArgs a) {
     Pager pg{-1, 0};
     int32_t* q_next = a.queue[(lvl + 1) & 1];
     int32_t* fill_next = a.fill[(lvl + 1) & 1];
-    // LDS stays at most 60 KB, so two workgroups share a compute unit (more
-    // chunk chains in flight)
     if (dir == PP_PUSH) {
         // top-down items test the hottest visited words in LDS when the items
         // bring at least two edges per staged word
@@ -1405,8 +1404,10 @@ static void allow_stage_lds(const BfsArgs& a) {
 // visited stage.
 static size_t chunk_lds(const BfsArgs& a) { return (size_t)std::max(a.sum_words, a.chunk_stage) * 8; }
 
-// Workgroups of the chunk kernel: two per compute unit (its LDS is small).
-static int32_t chunk_blocks(pp_graph g) { return std::max(1, std::min(ceil_div(g->d.n, 4096), 2 * g->num_cu)); }
+// Workgroups of the chunk kernel: one per compute unit.  Two per unit, each
+// staging half as many visited words, ran top-down runs about 1.4% slower at
+// R-MAT scale 22; half a workgroup per unit about 18% slower.
+static int32_t chunk_blocks(pp_graph g) { return std::max(1, std::min(ceil_div(g->d.n, 4096), g->num_cu)); }
 
 // Frontier sets of the one-workgroup launch: vertices per set (qcap) and
 // out-edges per level (ecap) it takes on; 0 when it is off for this policy.
