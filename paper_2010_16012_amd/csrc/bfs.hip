@@ -45,6 +45,16 @@ constexpr int32_t kPage = 256;      // queue entries per page
 // Rows longer than one chunk are cut into chunk items that the whole grid
 // shares, so no wavefront walks a long row alone while the others idle.
 constexpr int32_t kBigRow = 256;    // top-down (out-rows)
+// Top-down levels with fewer frontier out-edges than nnz >> kSmallLevelShift
+// cut rows into chunks of kBigRowSmall: the few hub rows of such a level then
+// spread over many more wavefronts of the chunk kernel.  At R-MAT scale 22
+// (64 roots) push runs went from 1.482 to 1.41 ms per root and switch runs
+// from 0.382 to 0.361; 16-, 64- and 128-edge chunks, and bounds of nnz/4,
+// nnz/8 or nnz/128, were slower.
+constexpr int32_t kBigRowSmall = 32;
+constexpr int kSmallLevelShift = 5;
+// the item buffer sized for kBigRow-edge chunks then also holds a small level's
+static_assert((1 << kSmallLevelShift) * kBigRowSmall >= kBigRow && kBigRowSmall <= kBigRow, "chunk item bound");
 constexpr int32_t kBigInRow = 256;  // bottom-up (in-rows)
 constexpr int kBfsBlock = 1024;    // threads per workgroup of the level kernels
 constexpr int kBfsWaves = kBfsBlock / kWave;
@@ -119,6 +129,9 @@ static BfsLayout bfs_layout(pp_graph g) {
     // most n entries; each wavefront of the level kernel and of the chunk
     // kernel (at most twice as many wavefronts) leaves at most one partial page
     L.page_cap = waves + ceil_div(n, kPage) + 3 * waves + 2;
+    // a row cut into chunks of c edges (longer than c) gives at most 2 len / c
+    // items: a level queues at most 2 m / 256 of 256 edges, or, on a level
+    // with m < nnz / 32, at most 2 m / 32 < nnz / 512 of kBigRowSmall edges
     L.item_cap = (int32_t)std::min<int64_t>(2 * nnz / std::min(kBigRow, kBigInRow) + 64, INT32_MAX / 4);
     L.hdr = take(sizeof(BfsHdr));
     L.queue0 = take((size_t)L.page_cap * kPage * 4);
@@ -147,6 +160,10 @@ struct BfsArgs {
     int32_t stage_words;    // bitmap words a workgroup may stage in LDS
     int32_t sum_words;      // LDS summary words (after the staged words; 0 = none)
     int32_t chunk_stage;    // visited words the chunk kernel may stage
+    // chunk length of out-rows on small top-down levels: kBigRowSmall when
+    // rows longer than kBigRow exist (the chunk kernel then follows every
+    // level of a policy with top-down levels), else kBigRow (no items)
+    int32_t td_small_row;
     int32_t static_pages;   // queue pages owned one per wavefront of the level kernel
     int64_t stage_min;      // stage only when the level examines at least this many edges
     const int32_t* csr_off;
@@ -183,6 +200,7 @@ static BfsArgs bfs_args(pp_graph g, void* state, int32_t* level, int32_t* parent
     a.sum_words = L.sum_words;
     // never more than the level kernel stages: the LDS allowance covers both
     a.chunk_stage = std::min(std::min(L.words, kChunkStage), L.stage_words);
+    a.td_small_row = (g->max_out_deg > kBigRow) ? kBigRowSmall : kBigRow;
     a.static_pages = L.blocks * kBfsWaves;
     // copying costs each workgroup stage_words loads; pay it only when the
     // level has at least two edges per staged word per workgroup
@@ -468,6 +486,7 @@ struct TdCtx {
     // which pays on large levels; small levels go straight to the atomic and
     // save a round trip
     bool probe;
+    int32_t big_row;  // out-rows longer than this become chunk items
 };
 
 // Below this many frontier out-edges a level claims without probing first.
@@ -575,9 +594,9 @@ __device__ __forceinline__ void td_unit(const BfsArgs& a, const TdCtx& cx, WaveL
     const int32_t re = (v >= 0) ? a.csr_off[v + 1] : 0;
     int32_t len = re - rb;
     // very long rows: queue chunks for the second kernel
-    const bool huge = len > kBigRow;
+    const bool huge = len > cx.big_row;
     if (__ballot(huge)) {
-        queue_chunks(a, huge, v, rb, re, kBigRow, cx.nxt, lane);
+        queue_chunks(a, huge, v, rb, re, cx.big_row, cx.nxt, lane);
         if (huge) len = 0;
     }
     // medium rows: the whole wave walks one row at a time
@@ -978,7 +997,8 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_level(BfsArgs a, int32_t lvl_
     const int32_t sw = ((dir == PP_PUSH ? cur.m : mu) >= a.stage_min) ? a.stage_words : 0;
     if (dir == PP_PUSH) {
         if (sw) stage_bits(s_bits, a.visited, sw);
-        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw, cur.m >= kProbeMin};
+        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw, cur.m >= kProbeMin,
+                 (cur.m < (a.nnz >> kSmallLevelShift)) ? a.td_small_row : kBigRow};
         // a frontier built top-down left the reserved pages unused
         level_top_down(a, cx, s_wave, a.queue[lvl & 1], a.fill[lvl & 1], (cur.dir_prev == PP_PULL) ? 0 : a.static_pages,
                        min(cur.pages, a.page_cap), a.fb[sc], nf > a.words, cnt, deg, pg);
@@ -1048,7 +1068,7 @@ __global__ __launch_bounds__(kBfsBlock, 8) void k_bfs_chunks(BfsArgs a) {
         // bring at least two edges per staged word
         const int32_t sw = ((int64_t)items * kBigRow >= 2 * (int64_t)gridDim.x * a.chunk_stage) ? a.chunk_stage : 0;
         if (sw) stage_bits(s_bits, a.visited, sw);
-        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw, true};
+        TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw, true, kBigRow};
         for (int32_t it = gwave; it < items; it += nwaves)
             td_row(a, cx, pg, a.items[3 * it], a.items[3 * it + 1], a.items[3 * it + 2], cnt, deg, lane);
     } else {

@@ -350,3 +350,37 @@ def test_run_many_matches_run(pol, name):
     assert pp.BfsRun(g).run_many([], pol) == []
     with pytest.raises(pp.PPError):
         pp.BfsRun(g).run_many([0, host.n], pol)
+
+
+def _star_of_stars(centres, leaves):
+    """A hub joined to `centres` centres with `leaves` leaves each: rows of
+    centres (hub), leaves + 1 (centre) and 1 (leaf) edges."""
+    c = np.arange(1, centres + 1)
+    first_leaf = centres + 1
+    n = first_leaf + centres * leaves
+    src = np.concatenate([np.zeros(centres, dtype=np.int64), np.repeat(c, leaves)])
+    dst = np.concatenate([c, np.arange(first_leaf, n)])
+    return gg.from_edges(n, src, dst, True, f"star_of_stars_{centres}x{leaves}")
+
+
+@pytest.mark.parametrize("centres", [300, 200], ids=["hub300", "hub200"])
+def test_small_levels_cut_rows_into_short_chunks(centres):
+    # Top-down levels with fewer frontier out-edges than nnz/32 cut every row
+    # longer than 32 edges into chunk items, when rows longer than 256 edges
+    # exist (the chunk kernel then follows every level).  From a leaf, level 1
+    # (its centre's 101-edge row) and level 2 (the hub's row) are such levels,
+    # level 3 (the other centres) is not.  With 200 centres no row passes 256
+    # edges, there is no chunk kernel and rows stay whole.  The one-workgroup
+    # launch is off in one pass, so the level kernel takes the small levels.
+    host = _star_of_stars(centres, 100)
+    leaf = centres + 1 + 5 * 100 + 7
+    want, _, nlev = oracle.bfs(host.off, host.idx, leaf)
+    assert nlev == 5
+    for pol, name in ((pp.PP_PUSH, "push"), (pp.PP_SWITCH, "switch")):
+        for caps in ((0, 0), MULTI_CAPS[0]):
+            announce(f"BFS {host.name} root={leaf} {name} caps={caps}")
+            lv, par, st, dirs, nf, mf = _run_caps(host, leaf, pol, caps)
+            assert np.array_equal(lv, want), f"{name} caps {caps}: levels differ"
+            assert H.bfs_violations(host, leaf, lv, par) == []
+            assert st.levels == nlev
+            assert st.reached == host.n
