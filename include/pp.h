@@ -243,10 +243,14 @@ pp_status pp_bfs_init(pp_graph g, int32_t root, int32_t* level, int32_t* parent,
  * bitmap per claim, wave-aggregated queue appends).  pull = bottom-up: every
  * unvisited vertex scans its in-neighbours in stored order and stops at the
  * first frontier member, which becomes its parent (no atomics on vertex
- * state; one counter update per wavefront).  Rows longer than 256 edges are
- * cut into 256-edge chunks that the whole grid shares; a bottom-up vertex
- * whose in-row is chunked takes the first frontier member of whichever chunk
- * claims it first (one atomic OR).  A bottom-up level with a sparse frontier
+ * state; one counter update per wavefront).  Out-rows longer than 256 edges
+ * are cut into 256-edge chunks that the whole grid shares (into 32-edge
+ * chunks, rows past 32 edges, on a level with fewer than nnz/32 frontier
+ * out-edges, when the graph has rows past 256); an in-row longer than 128
+ * edges is scanned over its first 128 and its rest is cut into 128-edge
+ * chunks.  A bottom-up vertex whose in-row is chunked takes the first frontier
+ * member of whichever chunk claims it first (one atomic OR): rows of up to
+ * 256 in-edges still take the first in stored order.  A bottom-up level with a sparse frontier
  * (8 |F| < ceil(n/64), its out-edges at most nnz/256) while at least half the
  * edges leave unvisited vertices streams the whole in-edge array instead, and
  * a vertex takes whichever frontier in-neighbour claims it first.  Either step may follow the other.  level/parent must be the arrays given to pp_bfs_init.  Enqueue

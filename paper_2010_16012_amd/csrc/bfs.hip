@@ -55,7 +55,12 @@ constexpr int32_t kBigRowSmall = 32;
 constexpr int kSmallLevelShift = 5;
 // the item buffer sized for kBigRow-edge chunks then also holds a small level's
 static_assert((1 << kSmallLevelShift) * kBigRowSmall >= kBigRow && kBigRowSmall <= kBigRow, "chunk item bound");
-constexpr int32_t kBigInRow = 256;  // bottom-up (in-rows)
+// bottom-up (in-rows): the level kernel scans the first kBigInRow entries of
+// a longer in-row (the whole wavefront, as kCoopRow allows) and queues the
+// rest as chunk items.  256 ran pull 3.5% and switch 10% slower at R-MAT
+// scale 22; 64, 96 and 192 were slower too.  A row of up to 2 kBigInRow
+// in-edges is scanned in stored order (prefix, then at most one chunk).
+constexpr int32_t kBigInRow = 128;
 constexpr int kBfsBlock = 1024;    // threads per workgroup of the level kernels
 constexpr int kBfsWaves = kBfsBlock / kWave;
 constexpr int32_t kStaticLds = 16384;  // LDS bytes kept for the kernels' own arrays
@@ -130,8 +135,9 @@ static BfsLayout bfs_layout(pp_graph g) {
     // kernel (at most twice as many wavefronts) leaves at most one partial page
     L.page_cap = waves + ceil_div(n, kPage) + 3 * waves + 2;
     // a row cut into chunks of c edges (longer than c) gives at most 2 len / c
-    // items: a level queues at most 2 m / 256 of 256 edges, or, on a level
-    // with m < nnz / 32, at most 2 m / 32 < nnz / 512 of kBigRowSmall edges
+    // items: a level queues at most 2 nnz / min(kBigRow, kBigInRow), and a
+    // top-down level with m < nnz / 32 at most 2 m / 32 < nnz / 512 of
+    // kBigRowSmall edges
     L.item_cap = (int32_t)std::min<int64_t>(2 * nnz / std::min(kBigRow, kBigInRow) + 64, INT32_MAX / 4);
     L.hdr = take(sizeof(BfsHdr));
     L.queue0 = take((size_t)L.page_cap * kPage * 4);
