@@ -164,16 +164,19 @@ def tune_pagerank(host, iters=5, log=print, base=None) -> dict:
 
 
 def tune_bfs_switch(host, roots, log=print) -> dict:
-    """alpha/beta of the direction switch with the best harmonic-mean rate."""
+    """alpha/beta of the direction switch with the least time over the roots,
+    run through the many-roots call as a batch of roots is run (one host
+    wait; root-by-root runs also pay a host round trip per level batch, which
+    favours other constants)."""
     g = Graph(host)
     r = BfsRun(g)
+    roots = [int(x) for x in roots]
     best = None
     for alpha in (8.0, 14.0, 24.0, 48.0, 96.0, 192.0, 384.0):
-        for beta in (24.0, 64.0, 128.0, 256.0):
+        for beta in (24.0, 64.0, 128.0, 256.0, 512.0, 1024.0):
             def f():
-                for root in roots:
-                    r.run(int(root), PP_SWITCH, alpha, beta)
-            t = _time(f, reps=2)
+                r.run_many(roots, PP_SWITCH, alpha, beta)
+            t = _time(f, reps=3)
             log(f"bfs alpha={alpha} beta={beta}: {t / len(roots):.3f} ms/root")
             if best is None or t < best[0]:
                 best = (t, alpha, beta)
