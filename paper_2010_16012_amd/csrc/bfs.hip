@@ -1049,11 +1049,13 @@ __global__ __launch_bounds__(kBfsBlock, 8) void k_bfs_chunks(BfsArgs a) {
     BfsHdr* h = a.hdr;
     // slot fields read in the same round trip as the level index
     int32_t bigs[3], dirs[3], ns[3];
+    int64_t ms[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         bigs[i] = h->slot[i].big;
         dirs[i] = h->slot[i].dir_prev;
         ns[i] = h->slot[i].n;
+        ms[i] = h->slot[i].m;
     }
     const int32_t lvl = h->c_lvl;
     if (lvl < 0) return;
@@ -1071,8 +1073,11 @@ __global__ __launch_bounds__(kBfsBlock, 8) void k_bfs_chunks(BfsArgs a) {
     int32_t* fill_next = a.fill[(lvl + 1) & 1];
     if (dir == PP_PUSH) {
         // top-down items test the hottest visited words in LDS when the items
-        // bring at least two edges per staged word
-        const int32_t sw = ((int64_t)items * kBigRow >= 2 * (int64_t)gridDim.x * a.chunk_stage) ? a.chunk_stage : 0;
+        // bring at least two edges per staged word (items of the chunk length
+        // the level kernel used: the same rule on the frontier's out-edges)
+        const int64_t m = (sc == 0) ? ms[0] : ((sc == 1) ? ms[1] : ms[2]);
+        const int32_t clen = (m < (a.nnz >> kSmallLevelShift)) ? a.td_small_row : kBigRow;
+        const int32_t sw = ((int64_t)items * clen >= 2 * (int64_t)gridDim.x * a.chunk_stage) ? a.chunk_stage : 0;
         if (sw) stage_bits(s_bits, a.visited, sw);
         TdCtx cx{lvl, q_next, fill_next, a.fb[sn], &h->slot[sn], s_bits, sw, true, kBigRow};
         for (int32_t it = gwave; it < items; it += nwaves)
