@@ -53,7 +53,8 @@ constexpr int32_t kBigRow = 256;    // top-down (out-rows)
 // nnz/8 or nnz/128, were slower.
 constexpr int32_t kBigRowSmall = 32;
 constexpr int kSmallLevelShift = 5;
-// the item buffer sized for kBigRow-edge chunks then also holds a small level's
+// the item buffer, sized for chunks of min(kBigRow, kBigInRow) edges, then also
+// holds a small top-down level's kBigRowSmall-edge items
 static_assert((1 << kSmallLevelShift) * kBigRowSmall >= kBigRow && kBigRowSmall <= kBigRow, "chunk item bound");
 // bottom-up (in-rows): the level kernel scans the first kBigInRow entries of
 // a longer in-row (the whole wavefront, as kCoopRow allows) and queues the

@@ -516,9 +516,10 @@ __global__ __launch_bounds__(1024) void k_pr_tiled(TileArgs t, PullArgs a) {
 // at the end of the id range: y = teleport term (an empty sum, as a unit of
 // the plain pull would give them).
 __global__ __launch_bounds__(256) void k_pr_tiled_combine(TileArgs t, PullArgs a) {
-    const int32_t rb = (t.R + 255) / 256;
+    const int32_t bd = blockDim.x;
+    const int32_t rb = (t.R + bd - 1) / bd;
     if ((int32_t)blockIdx.x >= rb) {
-        const int32_t v = a.tail_beg + ((int32_t)blockIdx.x - rb) * 256 + threadIdx.x;
+        const int32_t v = a.tail_beg + ((int32_t)blockIdx.x - rb) * bd + (int32_t)threadIdx.x;
         if (v < a.tail_end) pull_finish(a, v, 0.f);
         return;
     }
