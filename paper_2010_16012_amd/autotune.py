@@ -35,7 +35,11 @@ TUNE_ROOT_SEED = 11  # BFS roots the switch constants are tuned on
 DEFAULTS = {"upper": [4, 16, 64, 1024, 4096], "split_chunk": 4096, "hot": 8192, "push_blocks": 1024,
             "pull_hot": 32768, "pull_block": 1024, "slice_rows": 0, "slice_width": 32768, "alpha": 14.0,
             "beta": 24.0, "k_tile": 32, "multi_big": 512, "multi_mid": 64, "multi_pull_group": 2,
-            "multi_mid_lanes": 16}
+            "multi_mid_lanes": 16, "bfs_multi_n": 256, "bfs_multi_m": 1024}
+
+# one-workgroup BFS launch caps (frontier vertices, out-edges per level) the
+# switch search tries: the default, smaller, and off
+BFS_MULTI_CAPS = ((256, 1024), (64, 256), (0, 0))
 
 TUNE_BATCH_SEED = 11  # many-graph batch the launch mapping is tuned on
 
@@ -64,6 +68,7 @@ def apply(cfg: dict) -> None:
     _lib.pp_set_pull_tuning(c["pull_hot"], c["pull_block"])
     _lib.pp_set_pull_slices(c["slice_rows"], c["slice_width"])
     _lib.pp_set_multi_tuning(c["multi_big"], c["multi_mid"], c["multi_pull_group"], c["multi_mid_lanes"])
+    _lib.pp_set_bfs_multi(c["bfs_multi_n"], c["bfs_multi_m"])
 
 
 def load(path: str, n: int, nnz: int, gpu_arch: str | None = None) -> dict:
@@ -164,24 +169,28 @@ def tune_pagerank(host, iters=5, log=print, base=None) -> dict:
 
 
 def tune_bfs_switch(host, roots, log=print) -> dict:
-    """alpha/beta of the direction switch with the least time over the roots,
-    run through the many-roots call as a batch of roots is run (one host
-    wait; root-by-root runs also pay a host round trip per level batch, which
-    favours other constants)."""
-    g = Graph(host)
-    r = BfsRun(g)
+    """alpha/beta of the direction switch, and the one-workgroup launch caps,
+    with the least time over the roots, run through the many-roots call as a
+    batch of roots is run (one host wait; root-by-root runs also pay a host
+    round trip per level batch, which favours other constants).  The caps
+    take effect at registration: one graph per setting."""
     roots = [int(x) for x in roots]
     best = None
-    for alpha in (8.0, 14.0, 24.0, 48.0, 96.0, 192.0, 384.0):
-        for beta in (24.0, 64.0, 128.0, 256.0, 512.0, 1024.0):
-            def f():
-                r.run_many(roots, PP_SWITCH, alpha, beta)
-            t = _time(f, reps=3)
-            log(f"bfs alpha={alpha} beta={beta}: {t / len(roots):.3f} ms/root")
-            if best is None or t < best[0]:
-                best = (t, alpha, beta)
-    g.close()
-    return {"alpha": best[1], "beta": best[2]}
+    for caps in BFS_MULTI_CAPS:
+        _lib.pp_set_bfs_multi(*caps)
+        g = Graph(host)
+        r = BfsRun(g)
+        for alpha in (8.0, 14.0, 24.0, 48.0, 96.0, 192.0, 384.0):
+            for beta in (24.0, 64.0, 128.0, 256.0, 512.0, 1024.0):
+                def f():
+                    r.run_many(roots, PP_SWITCH, alpha, beta)
+                t = _time(f, reps=3)
+                log(f"bfs caps={caps} alpha={alpha} beta={beta}: {t / len(roots):.3f} ms/root")
+                if best is None or t < best[0]:
+                    best = (t, alpha, beta, caps)
+        g.close()
+    _lib.pp_set_bfs_multi(*best[3])
+    return {"alpha": best[1], "beta": best[2], "bfs_multi_n": best[3][0], "bfs_multi_m": best[3][1]}
 
 
 def tune_ppr_tile(host, k, iters=3, log=print) -> dict:
