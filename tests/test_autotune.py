@@ -55,3 +55,16 @@ def test_multi_key_and_mapping_settings():
         with pytest.raises(_lib.PPError):
             autotune.apply(bad)
     autotune.apply({})
+
+
+def test_bfs_multi_caps_candidates_and_range():
+    # every caps setting the switch search tries is accepted (0 switches the
+    # one-workgroup launch off); negative caps are rejected
+    for n_cap, m_cap in autotune.BFS_MULTI_CAPS:
+        assert n_cap >= 0 and m_cap >= 0
+        autotune.apply({"bfs_multi_n": n_cap, "bfs_multi_m": m_cap})
+    assert (autotune.DEFAULTS["bfs_multi_n"], autotune.DEFAULTS["bfs_multi_m"]) in autotune.BFS_MULTI_CAPS
+    for bad in ({"bfs_multi_n": -1}, {"bfs_multi_m": -5}):
+        with pytest.raises(_lib.PPError):
+            autotune.apply(bad)
+    autotune.apply({})
