@@ -238,8 +238,18 @@ __global__ __launch_bounds__(256) void k_pr_push_hot_reduce(int32_t hot, int32_t
     const int32_t u = blockIdx.x * 64 + (threadIdx.x & 63);
     const int r = threadIdx.x >> 6;
     float acc = 0.f;
-    if (u < hot)
-        for (int32_t b = r; b < parts; b += 4) acc += hot_part[(size_t)b * hot + u];
+    if (u < hot) {
+        // partials b = r, r + 4, ... in that order, eight loads in flight
+        int32_t b = r;
+        for (; b + 28 < parts; b += 32) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = hot_part[(size_t)(b + 4 * k) * hot + u];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc += v[k];
+        }
+        for (; b < parts; b += 4) acc += hot_part[(size_t)b * hot + u];
+    }
     s[r][threadIdx.x & 63] = acc;
     __syncthreads();
     if (r == 0 && u < hot) y[u] += (s[0][threadIdx.x] + s[1][threadIdx.x]) + (s[2][threadIdx.x] + s[3][threadIdx.x]);
