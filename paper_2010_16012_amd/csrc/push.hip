@@ -224,9 +224,19 @@ __global__ __launch_bounds__(256) void k_pr_push_bin_combine(int32_t n, int32_t 
     if (u >= n) return;
     const int32_t r = u - hot;
     const int32_t b = r >> kPushBinShift, ul = r & (kPushBinW - 1);
+    const int32_t k0 = ulo[b], k1 = ulo[b + 1];
+    const float y0 = y[u];
+    // the unit partials in order, four loads in flight; a missing one adds
+    // +0, which leaves the sum (never -0: it starts at +0) unchanged
     float acc = 0.f;
-    for (int32_t k = ulo[b]; k < ulo[b + 1]; ++k) acc += part[(size_t)k * kPushBinW + ul];
-    y[u] += acc;
+    for (int32_t k = k0; k < k1; k += 4) {
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = (k + j < k1) ? part[(size_t)(k + j) * kPushBinW + ul] : 0.f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc += v[j];
+    }
+    y[u] = y0 + acc;
 }
 
 // y[u] += sum over workgroups of their LDS partials, u < hot (one writer per
